@@ -1,0 +1,277 @@
+"""Leverage scores, exact and estimated, in FP64 on the CPU.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Exact scores (Section 1): theta_i is the i-th diagonal entry of the hat
+matrix H = A (A^T A)^+ A^T, equivalently the squared norm of row i of any
+orthonormal basis of range(A) (H is the unique orthogonal projector onto
+range(A)).  The routes below are independent computations of that one
+quantity and the tests check them against each other.
+
+Estimator LS-HRN-approx (Algorithm 10):
+  1. Algorithm 4 (CountGaussSRRQR): sketch A~ = G (S A) (Algorithm 3), then a
+     rank-revealing QR of A~ giving the permutation P_k, R_k and the rank k.
+     The paper's implementation replaces the strong RRQR by the classical
+     column-pivoted QR of LAPACK xGEQP3 (Section 7); so does this oracle,
+     through scipy.linalg.qr(pivoting=True), which calls DGEQP3.
+  2. Keep A_{:,K} = A P_k.
+  3. Algorithm 8 on A_{:,K} with Pi_1 = G S: R~ from a QR of Pi_1 A_{:,K},
+     X = R~^{-1} Pi_2, theta~_i = ||e_i^T A_{:,K} X||^2.
+
+Readings of points the paper leaves open (listed with their reasons in the
+design notes of the repository):
+  * G is scaled by 1/sqrt(m) and Pi_2 by 1/sqrt(k) (Gaussian embeddings,
+    Section 3.3); the bare N(0,1) of Algorithm 3 would scale theta~ by 1/m.
+  * R is sign-normalised to a non-negative diagonal (the QR factor with a
+    positive diagonal is unique; Z = R^{-1} Pi_2 depends on the signs).
+  * Rank rule: k = #{ j : R_jj > zeta * R_00 } on the normalised QRCP
+    diagonal, the cutoff test of Section 7 (|R~_kk| < c |R~_11|).
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import conventions as conv
+
+
+# ==========================================================================
+# Exact leverage scores
+# ==========================================================================
+def exact_theta_svd(A: np.ndarray, tol: float) -> tuple[np.ndarray, int]:
+    """theta_i = sum_{j <= rho} U_ij^2 from the thin SVD A = U S V^T, with
+    the numerical rank rho = #{ sigma_j > tol * sigma_1 } (Section 1: row
+    norms of an orthonormal basis of range(A))."""
+    A = np.asarray(A, dtype=np.float64)
+    U, s, _ = np.linalg.svd(A, full_matrices=False)
+    if s.size == 0 or s[0] == 0.0:
+        return np.zeros(A.shape[0]), 0
+    rho = int(np.sum(s > tol * s[0]))
+    return np.sum(U[:, :rho] ** 2, axis=1), rho
+
+
+def hat_diagonal_bruteforce(A: np.ndarray, tol: float) -> np.ndarray:
+    """diag(A (A^T A)^+ A^T), the hat-matrix definition of Section 1 written
+    out literally (forms the n x n matrix: small n only).  The pseudoinverse
+    drops eigenvalues of A^T A below tol^2 * lambda_max, i.e. singular values
+    of A below tol * sigma_1."""
+    A = np.asarray(A, dtype=np.float64)
+    gram = A.T @ A
+    pinv = np.linalg.pinv(gram, rcond=tol ** 2, hermitian=True)
+    H = A @ pinv @ A.T
+    return np.diag(H).copy()
+
+
+def theta_householder_qr(A: np.ndarray) -> np.ndarray:
+    """Q, R = qr(A); theta = sum(Q .* Q, dims=2) -- the QR one-liner of
+    Section 1 (valid for full column rank A)."""
+    Q, _ = np.linalg.qr(np.asarray(A, dtype=np.float64), mode="reduced")
+    return np.sum(Q * Q, axis=1)
+
+
+def theta_least_squares(A: np.ndarray) -> np.ndarray:
+    """theta_i = ||e_i^T A X||^2 with X = argmin_Y ||A Y - I_n||_F (the least
+    squares form of Section 1; small n only)."""
+    A = np.asarray(A, dtype=np.float64)
+    X, *_ = np.linalg.lstsq(A, np.eye(A.shape[0]), rcond=None)
+    return np.sum((A @ X) ** 2, axis=1)
+
+
+def theta_gram(A, tol: float) -> tuple[np.ndarray, int]:
+    """Algorithm 5 (Gram pseudoinverse): B = A^T A as a sum of row outer
+    products (Lemma on the Gram complexity), B = V S^2 V^T, keep the rank-k
+    part, theta_i = ||e_i^T A V_k S_k^{-1}||^2.  Accepts dense or scipy
+    sparse A."""
+    if sp.issparse(A):
+        A = A.tocsr().astype(np.float64)
+        B = (A.T @ A).toarray()
+    else:
+        A = np.asarray(A, dtype=np.float64)
+        B = A.T @ A
+    w, V = np.linalg.eigh(B)
+    order = np.argsort(w)[::-1]
+    w, V = w[order], V[:, order]
+    sig = np.sqrt(np.clip(w, 0.0, None))
+    if sig.size == 0 or sig[0] == 0.0:
+        return np.zeros(A.shape[0]), 0
+    k = int(np.sum(sig > tol * sig[0]))
+    W = V[:, :k] / sig[:k]
+    Y = A @ W
+    Y = np.asarray(Y)
+    return np.sum(Y * Y, axis=1), k
+
+
+# ==========================================================================
+# Algorithm 3: CountGaussSketch
+# ==========================================================================
+def countsketch_dense_S(rnd: conv.SketchRandomness) -> np.ndarray:
+    """S as a dense r_cs x n matrix: S[h(i), i] = s(i) (tiny n only)."""
+    S = np.zeros((rnd.r_cs, rnd.n))
+    for i in range(rnd.n):
+        S[conv.bucket_of(rnd, i), i] = conv.sign_of(rnd, i)
+    return S
+
+
+def countsketch_apply(rnd: conv.SketchRandomness, A, chunk: int = 1 << 16) -> np.ndarray:
+    """S A (r_cs x d, FP64), with S the CountSketch of Section 3.3, applied
+    as a sparse matrix over row chunks of A (dense ndarray or scipy sparse)."""
+    h, cols, s = conv.countsketch_matrix_entries(rnd)
+    S = sp.csr_matrix((s, (h, cols)), shape=(rnd.r_cs, rnd.n))
+    d = A.shape[1]
+    SA = np.zeros((rnd.r_cs, d))
+    for lo in range(0, rnd.n, chunk):
+        hi = min(rnd.n, lo + chunk)
+        blk = A[lo:hi]
+        if sp.issparse(blk):
+            SA += np.asarray((S[:, lo:hi] @ blk.astype(np.float64)).todense())
+        else:
+            SA += S[:, lo:hi] @ np.asarray(blk, dtype=np.float64)
+    return SA
+
+
+def count_gauss_sketch(rnd: conv.SketchRandomness, A, m: int):
+    """Algorithm 3: A~ = G (S A), with G = G_m / sqrt(m).  Returns (A~, SA)."""
+    SA = countsketch_apply(rnd, A)
+    G = conv.gaussian_transform(rnd, m)
+    return G @ SA, SA
+
+
+# ==========================================================================
+# Algorithm 4: CountGaussSRRQR (QRCP in place of SRRQR, as in Section 7)
+# ==========================================================================
+@dataclass
+class RankRevealing:
+    perm: np.ndarray      # int64[d]: column j of A~ P is column perm[j] of A~
+    R: np.ndarray         # d x d upper triangular, non-negative diagonal
+    rank: int             # k = #{ j : R_jj > zeta R_00 }
+
+
+def qrcp_sign_normalised(At: np.ndarray, zeta: float) -> RankRevealing:
+    """Column-pivoted QR of A~ (LAPACK DGEQP3, the routine of Section 7),
+    R's rows flipped so diag(R) >= 0, and the cutoff rank rule."""
+    At = np.asarray(At, dtype=np.float64)
+    _, R, perm = sla.qr(At, mode="economic", pivoting=True)
+    sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+    R = R * sgn[:, None]
+    dg = np.diag(R)
+    if dg.size == 0 or dg[0] <= 0.0:
+        rank = 0
+    else:
+        rank = int(np.sum(dg > zeta * dg[0]))
+    return RankRevealing(np.asarray(perm, dtype=np.int64), R, rank)
+
+
+def count_gauss_srrqr(rnd: conv.SketchRandomness, A, m: int, zeta: float):
+    """Algorithm 4: returns (P_k as column ids, R_k, k) plus the sketch."""
+    At, SA = count_gauss_sketch(rnd, A, m)
+    rr = qrcp_sign_normalised(At, zeta)
+    k = rr.rank
+    return rr.perm[:k], rr.R[:k, :k], k, At, SA, rr
+
+
+# ==========================================================================
+# Algorithm 8 on A_{:,K}, and Algorithm 10
+# ==========================================================================
+def r_from_qr_of_sketch(AtK: np.ndarray) -> np.ndarray:
+    """Algorithm 8 step 3 with Pi_1 = G S: R~ from an (unpivoted) QR of
+    Pi_1 A_{:,K} = A~[:, K], sign-normalised to a non-negative diagonal."""
+    _, R = np.linalg.qr(AtK, mode="reduced")
+    sgn = np.where(np.diag(R) < 0, -1.0, 1.0)
+    return R * sgn[:, None]
+
+
+def jl_orthogonalizer(R: np.ndarray, Pi2: np.ndarray) -> np.ndarray:
+    """Algorithm 8 step 4: X = R~^{-1} Pi_2 (back substitution)."""
+    return sla.solve_triangular(R, Pi2, lower=False)
+
+
+def row_norms_sq(AK, X: np.ndarray, rows=None, chunk: int = 1 << 16) -> np.ndarray:
+    """Algorithm 8 step 5: theta~_i = ||e_i^T A_{:,K} X||^2 (rows subset
+    optional)."""
+    if rows is not None:
+        blk = AK[rows]
+        Y = blk @ X
+        Y = np.asarray(Y.todense() if sp.issparse(Y) else Y)
+        return np.sum(Y * Y, axis=1)
+    n = AK.shape[0]
+    out = np.empty(n)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        blk = AK[lo:hi]
+        if sp.issparse(blk):
+            Y = np.asarray(blk.astype(np.float64) @ X)
+        else:
+            Y = np.asarray(blk, dtype=np.float64) @ X
+        out[lo:hi] = np.sum(Y * Y, axis=1)
+    return out
+
+
+@dataclass
+class Estimate:
+    theta: np.ndarray | None   # theta~ (None when only sampled rows were asked)
+    theta_rows: np.ndarray | None
+    perm: np.ndarray           # full QRCP permutation of the sketch
+    rank: int
+    R11: np.ndarray            # k x k orthogonalizer R~ of A_{:,K}
+    Z: np.ndarray              # X = R~^{-1} Pi_2, k x k_jl
+    At: np.ndarray             # A~ = G S A
+    SA: np.ndarray
+    R_full: np.ndarray         # sign-normalised QRCP R of A~
+    G_k: np.ndarray            # d x k_jl JL Gaussian (rows used: 0..rank-1)
+
+
+def ls_hrn_approx(A, seed: int, r_cs: int, m: int, k_jl: int, zeta: float, rows=None) -> Estimate:
+    """Algorithm 10 (LS-HRN-approx) with the readings listed in the module
+    docstring.  ``rows`` restricts the final row-norm step to a subset (the
+    sketch still uses all of A)."""
+    n, d = A.shape
+    rnd = conv.derive(seed, n, r_cs)
+    K, _, k, At, SA, rr = count_gauss_srrqr(rnd, A, m, zeta)
+    Gk = conv.jl_gaussian(rnd, d, k_jl)
+    if k == 0:
+        th = np.zeros(n) if rows is None else None
+        thr = np.zeros(len(rows)) if rows is not None else None
+        return Estimate(th, thr, rr.perm, 0, np.zeros((0, 0)), np.zeros((0, k_jl)), At, SA, rr.R, Gk)
+    R11 = r_from_qr_of_sketch(At[:, K])
+    Z = jl_orthogonalizer(R11, Gk[:k])
+    AK = A[:, K]
+    if rows is None:
+        return Estimate(row_norms_sq(AK, Z), None, rr.perm, k, R11, Z, At, SA, rr.R, Gk)
+    return Estimate(None, row_norms_sq(AK, Z, rows=rows), rr.perm, k, R11, Z, At, SA, rr.R, Gk)
+
+
+def theta_prime(A, K: np.ndarray, R11: np.ndarray, rows=None) -> np.ndarray:
+    """The estimate without the JL step: ||e_i^T A_{:,K} R~^{-1}||^2."""
+    X = sla.solve_triangular(R11, np.eye(R11.shape[0]), lower=False)
+    return row_norms_sq(A[:, K], X, rows=rows)
+
+
+def qrcp_reference_small(At: np.ndarray) -> np.ndarray:
+    """Businger-Golub column pivoting written out (tiny inputs): at each step
+    the pivot is the remaining column of largest residual norm, recomputed
+    exactly by projecting out the columns already chosen.  Returns the
+    permutation; used to pin the LAPACK route."""
+    At = np.asarray(At, dtype=np.float64)
+    d = At.shape[1]
+    chosen: list[int] = []
+    Q = np.zeros((At.shape[0], 0))
+    for _ in range(d):
+        best, best_norm = -1, -1.0
+        for c in range(d):
+            if c in chosen:
+                continue
+            resid = At[:, c] - Q @ (Q.T @ At[:, c])
+            nrm = float(resid @ resid)
+            if nrm > best_norm:
+                best, best_norm = c, nrm
+        chosen.append(best)
+        resid = At[:, best] - Q @ (Q.T @ At[:, best])
+        nr = math.sqrt(max(best_norm, 0.0))
+        q = resid / nr if nr > 0 else resid * 0.0
+        Q = np.column_stack([Q, q])
+    return np.asarray(chosen, dtype=np.int64)

@@ -1,0 +1,361 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle:
+published test vectors of the generators, the paper's definitions of the
+leverage scores (several independent routes and their invariants), theorems
+with explicit constants, and brute force on tiny inputs."""
+
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.stats as st
+
+from oracle import conventions as C
+from oracle import leverage as L
+
+GOLDEN = Path(__file__).parent / "golden"
+
+
+def _rows(name):
+    out = []
+    for line in (GOLDEN / name).read_text().splitlines():
+        line = line.strip()
+        if line and not line.startswith("#"):
+            out.append(line.split())
+    return out
+
+
+# ---------------------------------------------------------------- generators
+def test_splitmix64_reference_outputs():
+    for seed, *words in _rows("splitmix64.txt"):
+        assert C.splitmix64_words(int(seed), len(words)) == [int(w, 16) for w in words]
+
+
+def test_philox_known_answers():
+    for row in _rows("philox4x32_10_kat.txt"):
+        vals = [int(x, 16) for x in row]
+        ctr, key, expect = vals[:4], vals[4:6], vals[6:]
+        out = C.philox4x32_10(tuple([c] for c in ctr), tuple(key))
+        assert [int(o[0]) for o in out] == expect
+
+
+def test_gaussian_is_standard_normal():
+    z = C.gaussian_matrix((12345, 678), 300, 400)
+    assert z.shape == (300, 400)
+    # KS test against N(0,1); moments
+    assert st.kstest(z.ravel(), "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 0.01 and abs(z.var() - 1) < 0.02
+    # even/odd elements (cos/sin branches of one counter) are uncorrelated
+    flat = z.ravel()
+    assert abs(np.corrcoef(flat[0::2], flat[1::2])[0, 1]) < 0.02
+
+
+def test_gaussian_scaling_and_determinism():
+    rnd = C.derive(99, 1000, 64)
+    G = C.gaussian_transform(rnd, 37)
+    assert G.shape == (37, 64)
+    raw = C.gaussian_matrix(rnd.key_m, 37, 64)
+    np.testing.assert_array_equal(G, raw * (1.0 / math.sqrt(37)))
+    np.testing.assert_array_equal(G, C.gaussian_transform(C.derive(99, 5, 64), 37))
+    Gk = C.jl_gaussian(rnd, 10, 8)
+    np.testing.assert_array_equal(Gk, C.gaussian_matrix(rnd.key_k, 10, 8) * (1.0 / math.sqrt(8)))
+
+
+# ---------------------------------------------------------------- hashing
+def test_prime_modulus():
+    for n in [0, 1, 2, 3, 4, 100, 4096, 65536, 1 << 20, (1 << 23) + 5]:
+        rnd = C.derive(1, n, 8)
+        assert rnd.P >= max(n, 2) and C.is_prime(rnd.P)
+        assert all(not C.is_prime(x) for x in range(max(n, 2), rnd.P))
+        assert 1 <= rnd.a <= rnd.P - 1 and 0 <= rnd.c < rnd.P
+
+
+def test_vectorised_hash_matches_definition():
+    rng = np.random.default_rng(0)
+    for seed, n, r in [(3, 5000, 97), (2 ** 63 + 11, 100003, 4096), (0, 17, 1), (5, 20, 64)]:
+        rnd = C.derive(seed, n, r)
+        h, s = C.buckets(rnd), C.signs(rnd)
+        rows = np.unique(np.concatenate([rng.integers(0, n, 300), [0, n - 1]]))
+        for i in rows:
+            assert h[i] == C.bucket_of(rnd, int(i))
+            assert s[i] == C.sign_of(rnd, int(i))
+        assert h.min() >= 0 and h.max() < r
+
+
+def test_bucket_hash_uniform_and_pairwise():
+    n, r = 200000, 256
+    rnd = C.derive(7, n, r)
+    counts = np.bincount(C.buckets(rnd), minlength=r)
+    chi2 = ((counts - n / r) ** 2 / (n / r)).sum()
+    # (P is the next prime after n, so the hash is a permutation of [0, P)
+    # reduced mod r: counts differ by at most about one sweep.)
+    assert chi2 < st.chi2.ppf(0.999, r - 1)
+    # collision probability of a fixed pair over random seeds ~ 1/r
+    pairs = [(0, 1), (5, 77777), (123, 199999)]
+    trials = 4000
+    for i, j in pairs:
+        coll = sum(C.bucket_of(C.derive(s, n, r), i) == C.bucket_of(C.derive(s, n, r), j)
+                   for s in range(trials))
+        assert coll / trials < 3.0 / r + 3 * math.sqrt(1 / r / trials)
+
+
+def test_signs_balanced_and_fourwise():
+    n = 100000
+    s = C.signs(C.derive(11, n, 8))
+    assert abs(s.mean()) < 4 / math.sqrt(n)
+    # E over seeds of s_a s_b s_c s_d ~ 0 for distinct rows (4-wise independence)
+    rows = [3, 10, 500, 9999]
+    prods = [np.prod([C.sign_of(C.derive(sd, n, 8), i) for i in rows]) for sd in range(3000)]
+    assert abs(np.mean(prods)) < 4 / math.sqrt(3000)
+
+
+def test_countsketch_apply_matches_dense_definition():
+    rng = np.random.default_rng(1)
+    A = rng.integers(-50, 50, size=(300, 7)).astype(np.float64)
+    rnd = C.derive(42, 300, 16)
+    S = L.countsketch_dense_S(rnd)
+    assert np.all(np.count_nonzero(S, axis=0) == 1)  # one +-1 per column
+    np.testing.assert_array_equal(L.countsketch_apply(rnd, A, chunk=64), S @ A)
+
+
+# ---------------------------------------------------------------- exact theta
+def _full_rank(n=400, d=12, seed=0):
+    return np.random.default_rng(seed).standard_normal((n, d))
+
+
+def test_exact_routes_agree_full_rank():
+    A = _full_rank()
+    t_svd, rho = L.exact_theta_svd(A, 1e-12)
+    assert rho == A.shape[1]
+    np.testing.assert_allclose(L.hat_diagonal_bruteforce(A, 1e-12), t_svd, atol=1e-13)
+    np.testing.assert_allclose(L.theta_householder_qr(A), t_svd, atol=1e-13)
+    np.testing.assert_allclose(L.theta_least_squares(A), t_svd, atol=1e-12)
+    t_gram, k = L.theta_gram(A, 1e-7)
+    assert k == A.shape[1]
+    np.testing.assert_allclose(t_gram, t_svd, atol=1e-12)
+
+
+def test_exact_invariants_and_special_cases():
+    A = _full_rank(500, 9, 3)
+    t, rho = L.exact_theta_svd(A, 1e-12)
+    assert np.all(t >= -1e-15) and np.all(t <= 1 + 1e-12)
+    assert abs(t.sum() - rho) < 1e-10                   # trace of a projector = rank
+    T = np.random.default_rng(4).standard_normal((9, 9))
+    np.testing.assert_allclose(L.exact_theta_svd(3.7 * A, 1e-12)[0], t, atol=1e-13)
+    np.testing.assert_allclose(L.exact_theta_svd(A @ T, 1e-12)[0], t, atol=1e-11)  # range unchanged
+    Q, _ = np.linalg.qr(A)
+    np.testing.assert_allclose(L.exact_theta_svd(Q, 1e-12)[0], np.sum(Q * Q, 1), atol=1e-13)
+    E = np.vstack([np.eye(5), np.zeros((20, 5))])
+    np.testing.assert_allclose(L.exact_theta_svd(E, 1e-12)[0], np.r_[np.ones(5), np.zeros(20)], atol=1e-15)
+    Z = np.zeros((10, 3))
+    tz, rz = L.exact_theta_svd(Z, 1e-12)
+    assert rz == 0 and np.all(tz == 0)
+    # coherence is the largest score
+    assert L.exact_theta_svd(A, 1e-12)[0].max() == t.max()
+
+
+def test_sherman_morrison_leave_one_out():
+    """Section 1: deleting row i changes (A^T A)^{-1} by
+    G^{-1} a_i a_i^T G^{-1} / (1 - theta_i)."""
+    A = _full_rank(60, 5, 7)
+    t, _ = L.exact_theta_svd(A, 1e-12)
+    G = A.T @ A
+    Gi = np.linalg.inv(G)
+    for i in [0, 17, 59]:
+        a = A[i]
+        lhs = np.linalg.inv(G - np.outer(a, a))
+        rhs = Gi + Gi @ np.outer(a, a) @ Gi / (1 - t[i])
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-10, atol=1e-12)
+
+
+def test_rank_deficient_routes():
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((300, 6)) @ rng.standard_normal((6, 10))  # rank 6
+    t, rho = L.exact_theta_svd(A, 1e-8)
+    assert rho == 6 and abs(t.sum() - 6) < 1e-10
+    np.testing.assert_allclose(L.hat_diagonal_bruteforce(A, 1e-6), t, atol=1e-10)
+    tg, kg = L.theta_gram(A, 1e-6)
+    assert kg == 6
+    np.testing.assert_allclose(tg, t, atol=1e-9)
+    # a maximal independent column subset has the same scores (Theorem on
+    # QR vs SVD with k = rank: sigma_{k+1} = 0)
+    rr = L.qrcp_sign_normalised(A, 1e-8)
+    assert rr.rank == 6
+    np.testing.assert_allclose(L.exact_theta_svd(A[:, rr.perm[:6]], 1e-12)[0], t, atol=1e-10)
+
+
+def test_theorem_qr_vs_svd_bound():
+    """|theta_i(A_k) - theta_i(A_K)| <= (sqrt th(A_k) + sqrt th(A_K)) sigma_{k+1}(A)/sigma_k(R11)
+    on a fixed-spectrum matrix (Section 7 recipe) with k below the rank."""
+    rng = np.random.default_rng(8)
+    n, d, k = 2000, 20, 10
+    U, _ = np.linalg.qr(rng.standard_normal((n, d)))
+    V, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    sig = np.r_[np.ones(10), 1e-3 * np.ones(10)]
+    A = (U * sig) @ V.T
+    _, R, perm = sla.qr(A, mode="economic", pivoting=True)
+    AK = A[:, perm[:k]]
+    Uu, s, _ = np.linalg.svd(A, full_matrices=False)
+    th_k = np.sum(Uu[:, :k] ** 2, 1)
+    th_K, _ = L.exact_theta_svd(AK, 1e-14)
+    smin_R11 = np.linalg.svd(R[:k, :k], compute_uv=False)[-1]
+    bound = (np.sqrt(th_k) + np.sqrt(th_K)) * s[k] / smin_R11
+    assert np.all(np.abs(th_k - th_K) <= bound + 1e-14)
+    assert np.max(np.abs(th_k - th_K)) > 0  # the bound is not vacuous here
+
+
+# ---------------------------------------------------------------- QRCP / rank
+def test_qrcp_matches_businger_golub_and_is_a_factorisation():
+    rng = np.random.default_rng(9)
+    for trial in range(5):
+        At = rng.standard_normal((40, 12)) * rng.uniform(0.1, 10, 12)
+        rr = L.qrcp_sign_normalised(At, 0.0)
+        np.testing.assert_array_equal(rr.perm, L.qrcp_reference_small(At))
+        dg = np.diag(rr.R)
+        assert np.all(dg >= 0) and np.all(np.diff(dg) <= 1e-12 * dg[0])
+        Q = At[:, rr.perm] @ np.linalg.inv(rr.R)
+        np.testing.assert_allclose(Q.T @ Q, np.eye(12), atol=1e-10)
+
+
+def test_rank_rule_cutoff():
+    rng = np.random.default_rng(10)
+    B = rng.standard_normal((50, 5)) @ rng.standard_normal((5, 9))
+    B += 1e-9 * rng.standard_normal(B.shape)
+    assert L.qrcp_sign_normalised(B, 1e-6).rank == 5
+    assert L.qrcp_sign_normalised(B, 1e-12).rank == 9
+    assert L.qrcp_sign_normalised(np.zeros((8, 4)), 1e-6).rank == 0
+
+
+# ---------------------------------------------------------------- estimator
+def test_orthogonalizer_is_leading_block_of_qrcp():
+    """Algorithm 8 step 3 on A_{:,K} with Pi_1 = GS re-derives R11: a QR of
+    A~[:, K] equals the leading block of the pivoted QR (uniqueness of the
+    positive-diagonal factor)."""
+    A = _full_rank(3000, 16, 12)
+    est = L.ls_hrn_approx(A, 5, 256, 48, 8, 1e-10)
+    np.testing.assert_allclose(est.R11, est.R_full[:est.rank, :est.rank], rtol=1e-10, atol=1e-12)
+
+
+def test_no_jl_estimate_within_deterministic_sketch_bound():
+    """theta'_i = ||a_K R11^{-1}||^2 = a^T (A~_K^T A~_K)^{-1} a lies between
+    theta_i(A_K)/sigma_max(GS U_K)^2 and theta_i(A_K)/sigma_min(GS U_K)^2."""
+    rng = np.random.default_rng(13)
+    A = rng.standard_normal((4000, 10)) @ rng.standard_normal((10, 14))
+    est = L.ls_hrn_approx(A, 21, 512, 40, 8, 1e-8)
+    K = est.perm[:est.rank]
+    tp = L.theta_prime(A, K, est.R11)
+    AK = A[:, K]
+    th, _ = L.exact_theta_svd(AK, 1e-12)
+    U, _ = np.linalg.qr(AK)
+    rnd = C.derive(21, A.shape[0], 512)
+    GSU = C.gaussian_transform(rnd, 40) @ L.countsketch_apply(rnd, U)
+    sv = np.linalg.svd(GSU, compute_uv=False)
+    assert np.all(tp >= th / sv[0] ** 2 * (1 - 1e-9))
+    assert np.all(tp <= th / sv[-1] ** 2 * (1 + 1e-9))
+
+
+def test_jl_ratio_is_chi_square_over_k():
+    """Given the sketch, theta~_i / theta'_i ~ chi^2_k / k (Pi_2 Gaussian)."""
+    A = _full_rank(2000, 6, 14)
+    k = 8
+    est = L.ls_hrn_approx(A, 3, 128, 24, k, 1e-10)
+    K = est.perm[:est.rank]
+    tp = L.theta_prime(A, K, est.R11)
+    ratios = []
+    for seed in range(40):
+        rnd = C.derive(1000 + seed, A.shape[0], 128)
+        Pi2 = C.jl_gaussian(rnd, 6, k)[: est.rank]
+        X = sla.solve_triangular(est.R11, Pi2)
+        ratios.append(L.row_norms_sq(A[:, K], X)[:50] / tp[:50])
+    r = np.concatenate(ratios) * k
+    assert st.kstest(r, st.chi2(k).cdf).pvalue > 1e-3
+
+
+def test_countsketch_is_an_ose_at_the_theorem_size():
+    """CountSketch OSE theorem (Section 3.3): r >= (d^2+d)/(delta (2 eps -
+    eps^2)^2) rows give sigma(S U) in [1-eps, 1+eps] with probability
+    >= 1 - delta, for any fixed orthonormal U."""
+    n, d, eps, delta = 3000, 3, 0.5, 1 / 3
+    r = math.ceil((d * d + d) / (delta * (2 * eps - eps ** 2) ** 2))
+    U, _ = np.linalg.qr(np.random.default_rng(17).standard_normal((n, d)))
+    fails = 0
+    seeds = 60
+    for seed in range(seeds):
+        sv = np.linalg.svd(L.countsketch_apply(C.derive(seed, n, r), U), compute_uv=False)
+        fails += int(sv[0] > 1 + eps or sv[-1] < 1 - eps)
+    assert fails / seeds <= delta
+
+
+def test_gaussian_spectrum_lemma():
+    """Gaussian lemma of Section 3.3 (Davidson-Szarek): for G m x n Gaussian
+    and U n x k orthonormal, sigma_1(GU) < (1+a) sqrt(m) + sqrt(k) and
+    sigma_k(GU) > (1-a) sqrt(m) - sqrt(k), each with probability
+    >= 1 - exp(-a^2 m / 2)."""
+    n, k, m, a = 500, 6, 60, 0.35
+    U, _ = np.linalg.qr(np.random.default_rng(18).standard_normal((n, k)))
+    viol_hi = viol_lo = 0
+    trials = 200
+    for t in range(trials):
+        G = C.gaussian_matrix((t, 77), m, n)
+        sv = np.linalg.svd(G @ U, compute_uv=False)
+        viol_hi += sv[0] >= (1 + a) * math.sqrt(m) + math.sqrt(k)
+        viol_lo += sv[-1] <= (1 - a) * math.sqrt(m) - math.sqrt(k)
+    p = math.exp(-a * a * m / 2)
+    assert viol_hi / trials <= p + 0.05 and viol_lo / trials <= p + 0.05
+
+
+def test_jl_step_meets_its_bound_given_the_sketch():
+    """Given the sketch, Algorithm 8's JL step with r_2 >= 4 ln n / (eps^2/2 -
+    eps^3/3) columns (Gaussian JLT lemma) keeps every theta~_i within
+    (1 +- eps) of theta'_i, and theta'_i within the deterministic interval
+    [theta_i(A_K)/sigma_max(GSU_K)^2, theta_i(A_K)/sigma_min(GSU_K)^2]."""
+    n, d, eps = 4096, 5, 0.5
+    rng = np.random.default_rng(15)
+    A = rng.standard_normal((n, d)) * rng.lognormal(0, 1, (n, 1))
+    k = math.ceil(4 * math.log(n) / (eps ** 2 / 2 - eps ** 3 / 3))
+    th, _ = L.exact_theta_svd(A, 1e-12)
+    U, _ = np.linalg.qr(A)
+    for seed in range(3):
+        est = L.ls_hrn_approx(A, seed, 256, 40, k, 1e-10)
+        assert est.rank == d
+        rnd = C.derive(seed, n, 256)
+        sv = np.linalg.svd(C.gaussian_transform(rnd, 40) @ L.countsketch_apply(rnd, U), compute_uv=False)
+        tp = L.theta_prime(A, est.perm[:d], est.R11)
+        assert np.all(tp >= th / sv[0] ** 2 * (1 - 1e-9)) and np.all(tp <= th / sv[-1] ** 2 * (1 + 1e-9))
+        ratio = est.theta / tp
+        assert np.all(np.abs(ratio - 1) <= eps)
+
+
+def test_estimator_handles_zero_and_zero_rows():
+    A = np.zeros((100, 5))
+    est = L.ls_hrn_approx(A, 1, 16, 10, 4, 1e-8)
+    assert est.rank == 0 and np.all(est.theta == 0)
+    B = _full_rank(500, 5, 16)
+    B[[3, 77]] = 0
+    est = L.ls_hrn_approx(B, 1, 64, 10, 4, 1e-8)
+    assert est.theta[3] == 0 and est.theta[77] == 0
+
+
+# ---------------------------------------------------------------- planted mistakes
+def test_pins_catch_a_dropped_sign_normalisation(monkeypatch):
+    """A plausible oracle bug (no sign normalisation of R) must break a pin."""
+    A = _full_rank(3000, 16, 12)
+    good = L.ls_hrn_approx(A, 5, 256, 48, 8, 1e-10)
+
+    def bad_r(AtK):
+        _, R = np.linalg.qr(AtK, mode="reduced")
+        return R
+    monkeypatch.setattr(L, "r_from_qr_of_sketch", bad_r)
+    bad = L.ls_hrn_approx(A, 5, 256, 48, 8, 1e-10)
+    assert not np.allclose(bad.R11, bad.R_full[:bad.rank, :bad.rank])
+    assert not np.allclose(bad.theta, good.theta)
+
+
+def test_pins_catch_a_transposed_sketch(monkeypatch):
+    A = np.random.default_rng(1).integers(-50, 50, size=(300, 7)).astype(np.float64)
+    rnd = C.derive(42, 300, 16)
+    S = L.countsketch_dense_S(rnd)
+    orig = C.buckets
+    monkeypatch.setattr(C, "buckets", lambda r: (orig(r) + 1) % r.r_cs)  # off-by-one bucket
+    assert not np.array_equal(L.countsketch_apply(rnd, A), S @ A)
