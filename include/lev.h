@@ -1,0 +1,196 @@
+/*
+ * lev.h -- C interface of liblev, an MI355X (gfx950) implementation of the
+ * randomized row-leverage-score estimator LS-HRN-approx of Sobczyk &
+ * Gallopoulos, "Estimating leverage scores via rank revealing methods and
+ * randomization" (Algorithm 10: Algorithm 4 followed by Algorithm 8 on the
+ * selected columns).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - All matrix/vector pointers are DEVICE pointers (hipMalloc'd or owned by
+ *   a framework such as PyTorch) unless a comment says "host".  The caller
+ *   owns every buffer; the library never allocates, frees or synchronises.
+ *   Work is enqueued on the caller's stream and completes in stream order.
+ * - Dense matrices are row-major with a leading dimension `ld` (elements
+ *   between consecutive rows, ld >= d).
+ * - Scratch memory comes from a caller-provided workspace `ws` of
+ *   `ws_bytes` bytes; query the size with lev_workspace_size().  The
+ *   workspace must be 256-byte aligned.
+ * - Return value: LEV_OK (0) or a negative lev_status.  All argument
+ *   validation happens on the host BEFORE anything is enqueued; on error
+ *   nothing has been launched and the outputs are untouched.  Faults inside
+ *   kernels surface at the caller's next synchronisation.  A readable
+ *   message for the most recent error of the calling thread is returned by
+ *   lev_last_error().
+ * - Random draws (the CountSketch hash and signs, the Gaussian transform
+ *   G_m and the JL Gaussian G_k) are all derived from params->seed, so two
+ *   calls with the same seed and shapes use the same sketch.  Their exact
+ *   definitions (SplitMix64 seed expansion, Carter-Wegman bucket hash over
+ *   the smallest prime P >= n, cubic sign polynomial over GF(2^61-1),
+ *   Philox4x32-10 + Box-Muller) are documented in the repository's design
+ *   notes.
+ */
+#ifndef LEV_H
+#define LEV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int lev_status;
+enum {
+  LEV_OK = 0,
+  LEV_ERR_ARG = -1,           /* null pointer, bad enum, bad parameter value */
+  LEV_ERR_SHAPE = -2,         /* inconsistent or unsupported sizes */
+  LEV_ERR_DTYPE = -3,         /* dtype not supported by this call */
+  LEV_ERR_FORMAT = -4,        /* malformed CSR (checked only where stated) */
+  LEV_ERR_WORKSPACE = -5,     /* ws too small or misaligned */
+  LEV_ERR_HIP = -6,           /* a HIP runtime call failed at launch */
+  LEV_ERR_NOT_SUPPORTED = -7  /* valid request this build does not handle */
+};
+
+enum { LEV_DENSE_ROWMAJOR = 0, LEV_CSR = 1 };
+enum { LEV_F64 = 0, LEV_F32 = 1, LEV_BF16 = 2 };
+
+/* Arithmetic of the pass that forms A_{:,K} Z and its squared row norms
+ * (Algorithm 8, last step).  NATIVE: F64 input -> FP64 MFMA, F32 input ->
+ * FP32 MFMA, BF16 input -> BF16 MFMA with Z rounded to BF16.  FP32: FP32
+ * MFMA whatever the storage type.  BF16: BF16 MFMA, Z in BF16 (BF16 input
+ * only).  BF16X2: BF16 MFMA with Z split into a BF16 high and low part
+ * (BF16 input only).  All MFMA forms accumulate in FP32 (FP64 for F64). */
+enum { LEV_AZ_NATIVE = 0, LEV_AZ_FP32 = 1, LEV_AZ_BF16 = 2, LEV_AZ_BF16X2 = 3 };
+
+/* The tall input A (n x d, n >> d).
+ *  DENSE_ROWMAJOR: values points at n*ld elements of `dtype`; row_ptr and
+ *    col_idx are ignored.  values must be 16-byte aligned and ld*sizeof(elt)
+ *    a multiple of 16 bytes (d itself may be anything <= ld).
+ *  CSR: row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing, row_ptr[n] =
+ *    nnz), col_idx int32[nnz] strictly increasing within each row and < d,
+ *    values[nnz] of `dtype`; ld is ignored.  The CSR invariants are the
+ *    caller's responsibility (they are not checked on the device). */
+typedef struct {
+  int32_t format;
+  int32_t dtype;
+  int64_t n, d, ld, nnz;
+  const void* values;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+} lev_matrix;
+
+/* Parameters of the estimator.
+ *  seed  -- 64-bit seed of all random draws.
+ *  r_cs  -- rows of the CountSketch S (Algorithm 3's r).  >= 1.
+ *  m     -- rows of the Gaussian transform G (Algorithm 3's m = ceil(gamma d)).
+ *           d <= m required.
+ *  k     -- columns of the JL Gaussian Pi_2 (Algorithm 8's r_2).  1..64.
+ *  zeta  -- rank tolerance: the revealed rank is r = #{ j : R_jj > zeta R_00 }
+ *           on the column-pivoted factor of the sketch (the cutoff rule of
+ *           Section 7).  0 <= zeta < 1.
+ *  az_precision -- LEV_AZ_* above. */
+typedef struct {
+  uint64_t seed;
+  int64_t r_cs, m, k;
+  double zeta;
+  int32_t az_precision;
+  int32_t reserved;
+} lev_params;
+
+/* Workspace bytes needed by lev_sketch (which = LEV_WS_SKETCH),
+ * lev_estimate (LEV_WS_ESTIMATE) or lev_estimate_backward (LEV_WS_BACKWARD)
+ * for this A and p; lev_rank_workspace_size gives lev_rank_estimate's.
+ * Both return 0 when the arguments are invalid. */
+enum { LEV_WS_SKETCH = 0, LEV_WS_ESTIMATE = 2, LEV_WS_BACKWARD = 3 };
+size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which);
+size_t lev_rank_workspace_size(int64_t m, int64_t d);
+
+/* Bytes of the state blob written by lev_estimate for lev_estimate_backward. */
+size_t lev_state_size(int64_t d, int64_t m, int64_t k);
+
+/* Algorithm 3 (CountGaussSketch): A~ = G (S A), with S the r_cs x n
+ * CountSketch (S[h(i), i] = s(i), Section 3.3) and G = G_m / sqrt(m) an
+ * m x r_cs Gaussian embedding (Section 3.3, Gaussian embeddings).
+ *  At_out     -- m x d, FP64, row-major (ld = d).
+ *  SA_out     -- optional (NULL to skip): r_cs x d FP64 copy of S A.
+ * S A is accumulated in FP64 in a fixed order (deterministic bits).
+ * Supported: dense F64/F32/BF16 and CSR F32/F64. */
+lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out,
+                      double* SA_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Algorithm 4, steps 2-3, on an m x d FP64 sketch At (row-major, ld = d):
+ * column-pivoted QR of At (Businger-Golub pivoting: the next pivot is the
+ * remaining column of largest residual norm; exact ties go to the lowest
+ * column index), R sign-normalised to a non-negative diagonal, and the rank
+ * r = #{ j : R_jj > zeta R_00 }.  Pivoting stops at r.
+ *  perm_out -- int32[d]: perm_out[j] = original column at pivot position j;
+ *              entries j >= r list the unselected columns in ascending order.
+ *  R_out    -- d x d FP64 row-major; rows j < r hold row j of the pivoted,
+ *              upper-triangular factor (R_out[j][t] for t >= j, zeros left of
+ *              the diagonal); rows j >= r are zero.
+ *  rank_out -- device int64 scalar r.
+ * The factor is obtained as the pivoted Cholesky factor of A~^T A~ (equal to
+ * the QRCP factor with positive diagonal in exact arithmetic); see the
+ * design notes for its accuracy range.  Requires d <= 1024 and d <= m. */
+lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta,
+                             int32_t* perm_out, double* R_out, int64_t* rank_out,
+                             void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Algorithm 10 (LS-HRN-approx): sketch, rank-revealing QR, then Algorithm 8
+ * on the selected columns K = perm[0..r): theta~_i = || A[i, K] Z ||^2 with
+ * Z = R11^{-1} G_k[0:r, :], R11 the leading r x r block of R and G_k the
+ * d x k JL Gaussian scaled by 1/sqrt(k) (row j of G_k pairs with pivot
+ * position j).
+ *  theta_out -- n entries: FP64 when A is F64, else FP32.
+ *  state_out -- optional (NULL to skip): lev_state_size(d, m, k) bytes that
+ *               lev_estimate_backward needs (perm, rank, R, Z, A~).
+ * r = 0 (e.g. A = 0) gives theta~ = 0.  Zero rows give theta~_i = 0. */
+lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_out,
+                        void* state_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of f(A) = sum_i w_i theta~_i with the sketch (S, G_m, G_k), the
+ * pivots and the rank held fixed: gradA_out = df/dA, n x ld dense, FP32 for
+ * F32 input (FP64 for F64 input).  `state` is the blob lev_estimate wrote
+ * for the same A and params.  Dense F32/F64 only. */
+lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const void* state,
+                                 const void* w, void* gradA_out, void* ws, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/* ---- inspection helpers (used by the tests) -------------------------------- */
+
+/* h(i) and s(i) of the CountSketch for every row i < n (int64 h_out[n],
+ * int8 s_out[n], device). */
+lev_status lev_debug_hash(uint64_t seed, int64_t n, int64_t r_cs, int64_t* h_out,
+                          int8_t* s_out, hipStream_t stream);
+
+/* S in compressed form, as pass 1 enumerates it: bucket_off int64[r_cs+1]
+ * and bucket_rows int32[n] (rows of bucket b in bucket_rows[bucket_off[b] ..
+ * bucket_off[b+1]), in the order pass 1 accumulates them). */
+lev_status lev_debug_buckets(uint64_t seed, int64_t n, int64_t r_cs, int64_t* bucket_off,
+                             int32_t* bucket_rows, hipStream_t stream);
+
+/* The Gaussian matrices of a seed: which = 0 -> G_m / sqrt(m) (rows = m,
+ * cols = r_cs), which = 1 -> G_k / sqrt(k) (rows = d, cols = k).  out is
+ * rows x cols FP64 row-major. */
+lev_status lev_debug_gaussian(uint64_t seed, int which, int64_t rows, int64_t cols,
+                              double* out, hipStream_t stream);
+
+/* Phase timing.  Registers `count` caller-created HIP events (count must be
+ * LEV_PHASES, or 0 / NULL to stop) for the calling thread; each following
+ * lev_estimate call on that thread records them on its stream at the phase
+ * boundaries: [0] start, [1] after the Gaussian draws, [2] after pass 1
+ * (S A), [3] after A~ = G (S A), [4] after the rank-revealing factorisation,
+ * [5] after Z is formed, [6] after pass 2 (theta~).  The events stay owned
+ * by the caller. */
+#define LEV_PHASES 7
+lev_status lev_set_phase_events(hipEvent_t* events, int count);
+
+const char* lev_status_string(lev_status s);
+const char* lev_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LEV_H */

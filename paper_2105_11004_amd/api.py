@@ -1,0 +1,316 @@
+"""ctypes binding of liblev (include/lev.h), same names as the C calls.
+
+Argument marshalling only: every step of the estimator runs in the HIP
+kernels of liblev.  PyTorch provides device memory (inputs, outputs,
+workspace) and the stream (the current stream of the input's device).
+There is no fallback: if liblev.so is missing, or a call returns an error,
+an exception is raised.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_uint64, c_void_p
+from dataclasses import dataclass
+from pathlib import Path
+
+import torch
+
+LIB_PATH = Path(__file__).resolve().parent / "liblev.so"
+
+LEV_OK = 0
+STATUS_NAMES = {0: "LEV_OK", -1: "LEV_ERR_ARG", -2: "LEV_ERR_SHAPE", -3: "LEV_ERR_DTYPE",
+                -4: "LEV_ERR_FORMAT", -5: "LEV_ERR_WORKSPACE", -6: "LEV_ERR_HIP",
+                -7: "LEV_ERR_NOT_SUPPORTED"}
+DENSE, CSR = 0, 1
+F64, F32, BF16 = 0, 1, 2
+AZ = {"native": 0, "fp32": 1, "bf16": 2, "bf16x2": 3}
+WS_SKETCH, WS_ESTIMATE, WS_BACKWARD = 0, 2, 3
+
+# Every symbol the header declares (checked by the CPU tests).
+EXPORTED = ["lev_workspace_size", "lev_rank_workspace_size", "lev_state_size", "lev_sketch",
+            "lev_rank_estimate", "lev_estimate", "lev_estimate_backward", "lev_debug_hash",
+            "lev_debug_buckets", "lev_debug_gaussian", "lev_set_phase_events", "lev_status_string",
+            "lev_last_error"]
+LEV_PHASES = 7
+PHASE_NAMES = ["gaussian_draws", "pass1_countsketch", "gaussian_transform", "rank_revealing_qr",
+               "form_z", "pass2_rownorm"]
+
+
+class LevMatrix(ctypes.Structure):
+    _fields_ = [("format", c_int32), ("dtype", c_int32), ("n", c_int64), ("d", c_int64),
+                ("ld", c_int64), ("nnz", c_int64), ("values", c_void_p), ("row_ptr", c_void_p),
+                ("col_idx", c_void_p)]
+
+
+class LevParams(ctypes.Structure):
+    _fields_ = [("seed", c_uint64), ("r_cs", c_int64), ("m", c_int64), ("k", c_int64),
+                ("zeta", c_double), ("az_precision", c_int32), ("reserved", c_int32)]
+
+
+class LevError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: Path | None = None):
+    """Loads liblev.so once (torch is imported first so that the HIP runtime
+    it ships is the one liblev binds to)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = Path(path) if path is not None else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2105_11004_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(str(p))
+    vp = c_void_p
+    lib.lev_workspace_size.argtypes = [POINTER(LevMatrix), POINTER(LevParams), c_int]
+    lib.lev_workspace_size.restype = c_size_t
+    lib.lev_rank_workspace_size.argtypes = [c_int64, c_int64]
+    lib.lev_rank_workspace_size.restype = c_size_t
+    lib.lev_state_size.argtypes = [c_int64, c_int64, c_int64]
+    lib.lev_state_size.restype = c_size_t
+    lib.lev_sketch.argtypes = [POINTER(LevMatrix), POINTER(LevParams), vp, vp, vp, c_size_t, vp]
+    lib.lev_rank_estimate.argtypes = [vp, c_int64, c_int64, c_double, vp, vp, vp, vp, c_size_t, vp]
+    lib.lev_estimate.argtypes = [POINTER(LevMatrix), POINTER(LevParams), vp, vp, vp, c_size_t, vp]
+    lib.lev_estimate_backward.argtypes = [POINTER(LevMatrix), POINTER(LevParams), vp, vp, vp, vp,
+                                          c_size_t, vp]
+    lib.lev_debug_hash.argtypes = [c_uint64, c_int64, c_int64, vp, vp, vp]
+    lib.lev_debug_buckets.argtypes = [c_uint64, c_int64, c_int64, vp, vp, vp]
+    lib.lev_debug_gaussian.argtypes = [c_uint64, c_int, c_int64, c_int64, vp, vp]
+    lib.lev_set_phase_events.argtypes = [vp, c_int]
+    lib.lev_set_phase_events.restype = c_int
+    lib.lev_status_string.argtypes = [c_int]
+    lib.lev_status_string.restype = ctypes.c_char_p
+    lib.lev_last_error.argtypes = []
+    lib.lev_last_error.restype = ctypes.c_char_p
+    for name in ("lev_sketch", "lev_rank_estimate", "lev_estimate", "lev_estimate_backward",
+                 "lev_debug_hash", "lev_debug_buckets", "lev_debug_gaussian"):
+        getattr(lib, name).restype = c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != LEV_OK:
+        raise LevError(status, load_library().lev_last_error().decode())
+
+
+def _stream(device: torch.device) -> c_void_p:
+    return c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None) -> c_void_p:
+    return c_void_p(t.data_ptr()) if t is not None else c_void_p(None)
+
+
+_DTYPES = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+
+def _matrix(A: torch.Tensor) -> LevMatrix:
+    if not A.is_cuda:
+        raise ValueError("A must be a device (cuda) tensor")
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor with unit column stride")
+    if A.dtype not in _DTYPES:
+        raise ValueError(f"unsupported dtype {A.dtype}")
+    ld = A.stride(0)
+    return LevMatrix(DENSE, _DTYPES[A.dtype], A.shape[0], A.shape[1], ld, 0, A.data_ptr(), None, None)
+
+
+def _params(seed, r_cs, m, k, zeta, precision) -> LevParams:
+    if precision not in AZ:
+        raise ValueError(f"precision must be one of {list(AZ)}")
+    return LevParams(int(seed) & ((1 << 64) - 1), int(r_cs), int(m), int(k), float(zeta), AZ[precision], 0)
+
+
+def _workspace(nbytes: int, device) -> tuple[torch.Tensor, c_void_p]:
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    base = buf.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    return buf, c_void_p(aligned)
+
+
+@dataclass
+class State:
+    """Device blob lev_estimate writes for lev_estimate_backward, plus views
+    of its fields (perm, rank, R, Z, A~)."""
+    blob: torch.Tensor
+    d: int
+    m: int
+    k: int
+
+    def _f64(self, offset: int, count: int) -> torch.Tensor:
+        return self.blob[offset:offset + 8 * count].view(torch.float64)
+
+    @staticmethod
+    def layout(d: int, m: int, k: int):
+        al = lambda x: (x + 255) // 256 * 256  # noqa: E731
+        off = {}
+        pos = 0
+        for name, nbytes in (("header", 64), ("perm", 4 * d), ("R", 8 * d * d), ("Z", 8 * d * k),
+                             ("At", 8 * m * d)):
+            off[name] = pos
+            pos += al(nbytes)
+        return off
+
+    @property
+    def rank(self) -> torch.Tensor:
+        off = self.layout(self.d, self.m, self.k)["header"]
+        return self.blob[off + 32:off + 40].view(torch.int64)
+
+    @property
+    def perm(self) -> torch.Tensor:
+        off = self.layout(self.d, self.m, self.k)["perm"]
+        return self.blob[off:off + 4 * self.d].view(torch.int32)
+
+    @property
+    def R(self) -> torch.Tensor:
+        off = self.layout(self.d, self.m, self.k)["R"]
+        return self._f64(off, self.d * self.d).view(self.d, self.d)
+
+    @property
+    def Z(self) -> torch.Tensor:
+        off = self.layout(self.d, self.m, self.k)["Z"]
+        return self._f64(off, self.d * self.k).view(self.d, self.k)
+
+    @property
+    def At(self) -> torch.Tensor:
+        off = self.layout(self.d, self.m, self.k)["At"]
+        return self._f64(off, self.m * self.d).view(self.m, self.d)
+
+
+def _aligned_blob(nbytes: int, device) -> torch.Tensor:
+    """A uint8 tensor of nbytes whose data pointer is 256-byte aligned."""
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + int(nbytes)]
+
+
+def lev_workspace_size(A: torch.Tensor, seed, r_cs, m, k, zeta, precision="native", which=WS_ESTIMATE) -> int:
+    lib = load_library()
+    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
+    return int(lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), which))
+
+
+def lev_sketch(A: torch.Tensor, seed: int, r_cs: int, m: int, return_sa: bool = False):
+    """Algorithm 3: A~ = G (S A) (m x d, FP64); optionally also S A."""
+    lib = load_library()
+    mat, par = _matrix(A), _params(seed, r_cs, m, 1, 0.0, "fp32" if A.dtype == torch.bfloat16 else "native")
+    nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_SKETCH)
+    if nbytes == 0:
+        _check(lib.lev_sketch(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))
+    _, ws = _workspace(nbytes, A.device)
+    At = torch.empty(m, A.shape[1], dtype=torch.float64, device=A.device)
+    SA = torch.empty(r_cs, A.shape[1], dtype=torch.float64, device=A.device) if return_sa else None
+    _check(lib.lev_sketch(ctypes.byref(mat), ctypes.byref(par), _ptr(At), _ptr(SA), ws, nbytes,
+                          _stream(A.device)))
+    return (At, SA) if return_sa else At
+
+
+def lev_rank_estimate(At: torch.Tensor, zeta: float):
+    """Algorithm 4 steps 2-3 on an m x d FP64 sketch: (perm int32[d],
+    R d x d, rank int64[1]), all on the device."""
+    lib = load_library()
+    if At.dtype != torch.float64 or At.dim() != 2 or not At.is_contiguous() or not At.is_cuda:
+        raise ValueError("At must be a contiguous m x d float64 device tensor")
+    m, d = At.shape
+    nbytes = lib.lev_rank_workspace_size(m, d)
+    if nbytes == 0:
+        raise LevError(-2, f"invalid sketch shape {m} x {d}")
+    _, ws = _workspace(nbytes, At.device)
+    perm = torch.empty(d, dtype=torch.int32, device=At.device)
+    R = torch.empty(d, d, dtype=torch.float64, device=At.device)
+    rank = torch.empty(1, dtype=torch.int64, device=At.device)
+    _check(lib.lev_rank_estimate(_ptr(At), m, d, float(zeta), _ptr(perm), _ptr(R), _ptr(rank), ws, nbytes,
+                                 _stream(At.device)))
+    return perm, R, rank
+
+
+def lev_estimate(A: torch.Tensor, seed: int, r_cs: int, m: int, k: int, zeta: float,
+                 precision: str = "native", return_state: bool = False):
+    """Algorithm 10 (LS-HRN-approx): theta~ (FP64 for FP64 A, else FP32)."""
+    lib = load_library()
+    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
+    nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_ESTIMATE)
+    if nbytes == 0:
+        _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))
+    _, ws = _workspace(nbytes, A.device)
+    out_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
+    theta = torch.empty(A.shape[0], dtype=out_dtype, device=A.device)
+    state = None
+    if return_state:
+        d = A.shape[1]
+        state = State(_aligned_blob(lib.lev_state_size(d, m, k), A.device), d, m, k)
+    _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), _ptr(theta),
+                            _ptr(state.blob) if state is not None else None, ws, nbytes, _stream(A.device)))
+    return (theta, state) if return_state else theta
+
+
+class EstimatePlan:
+    """Pre-allocated workspace and outputs for repeated lev_estimate calls on
+    same-shaped inputs (what the benchmark times)."""
+
+    def __init__(self, A: torch.Tensor, seed, r_cs, m, k, zeta, precision="native"):
+        self.lib = load_library()
+        self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
+        self.nbytes = self.lib.lev_workspace_size(ctypes.byref(self.mat), ctypes.byref(self.par), WS_ESTIMATE)
+        if self.nbytes == 0:
+            _check(self.lib.lev_estimate(ctypes.byref(self.mat), ctypes.byref(self.par), None, None, None, 0,
+                                         None))
+        self._buf, self.ws = _workspace(self.nbytes, A.device)
+        out_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
+        self.theta = torch.empty(A.shape[0], dtype=out_dtype, device=A.device)
+        self.device = A.device
+        self.A = A
+
+    def run(self, stream=None):
+        s = c_void_p(stream.cuda_stream) if stream is not None else _stream(self.device)
+        _check(self.lib.lev_estimate(ctypes.byref(self.mat), ctypes.byref(self.par), _ptr(self.theta), None,
+                                     self.ws, self.nbytes, s))
+        return self.theta
+
+
+def lev_set_phase_events(events):
+    """Registers LEV_PHASES torch.cuda.Event objects (already recorded once,
+    so that they exist) for the phase boundaries of following lev_estimate
+    calls on this thread; None stops recording."""
+    lib = load_library()
+    if events is None:
+        _check(lib.lev_set_phase_events(None, 0))
+        return
+    if len(events) != LEV_PHASES:
+        raise ValueError(f"need {LEV_PHASES} events")
+    arr = (c_void_p * LEV_PHASES)(*[c_void_p(e.cuda_event) for e in events])
+    _check(lib.lev_set_phase_events(arr, LEV_PHASES))
+
+
+def lev_debug_hash(seed: int, n: int, r_cs: int, device="cuda"):
+    lib = load_library()
+    h = torch.empty(n, dtype=torch.int64, device=device)
+    s = torch.empty(n, dtype=torch.int8, device=device)
+    _check(lib.lev_debug_hash(int(seed) & ((1 << 64) - 1), n, r_cs, _ptr(h), _ptr(s),
+                              _stream(torch.device(device))))
+    return h, s
+
+
+def lev_debug_buckets(seed: int, n: int, r_cs: int, device="cuda"):
+    lib = load_library()
+    off = torch.empty(r_cs + 1, dtype=torch.int64, device=device)
+    rows = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    _check(lib.lev_debug_buckets(int(seed) & ((1 << 64) - 1), n, r_cs, _ptr(off), _ptr(rows),
+                                 _stream(torch.device(device))))
+    return off, rows[:n]
+
+
+def lev_debug_gaussian(seed: int, which: int, rows: int, cols: int, device="cuda"):
+    lib = load_library()
+    out = torch.empty(rows, cols, dtype=torch.float64, device=device)
+    _check(lib.lev_debug_gaussian(int(seed) & ((1 << 64) - 1), which, rows, cols, _ptr(out),
+                                  _stream(torch.device(device))))
+    return out

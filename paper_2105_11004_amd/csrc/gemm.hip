@@ -1,0 +1,164 @@
+// FP64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Used for the n-independent contractions of the estimator: the Gaussian
+// transform A~ = G (S A) of Algorithm 3, the Gram A~^T A~ that drives the
+// column-pivoted factorisation, and the rank-nb Schur complement updates of
+// that factorisation.  All are small next to the passes over A, so this is a
+// plain LDS-tiled kernel: 64 x 64 output tile per workgroup of 4 waves
+// (each wave a 32 x 32 quadrant = 2 x 2 MFMA blocks), K in steps of 16,
+// optional split-K with a fixed-order reduction (deterministic bits).
+//
+// MFMA operand layout (16x16x4 f64, wave64): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; accumulator element v of lane l is
+// C[(l / 16) + 4 * v][l % 16] (measured on gfx950; the f32 and bf16 forms
+// use row 4 * (l / 16) + v instead).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "lev_internal.h"
+
+namespace lev {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+__global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                    const double* __restrict__ A, int64_t sai,
+                                                    int64_t sak, const double* __restrict__ B,
+                                                    int64_t sbk, int64_t sbj, double beta,
+                                                    double* __restrict__ C, int64_t ldc, int splits,
+                                                    int64_t kchunk, double* __restrict__ partial,
+                                                    const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int64_t n0 = (int64_t)blockIdx.y * BN;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = std::min<int64_t>(K, kb + kchunk);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const bool a_kfast = (sak == 1);
+  const bool b_jfast = (sbj == 1);
+
+  v4d acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      int kk, ii;
+      if (a_kfast) {
+        kk = e % BK;
+        ii = e / BK;
+      } else {
+        kk = e / BM;
+        ii = e % BM;
+      }
+      const int64_t gi = m0 + ii, gk = k0 + kk;
+      As[kk][ii] = (gi < M && gk < ke) ? A[gi * sai + gk * sak] : 0.0;
+      int kb2, jj;
+      if (b_jfast) {
+        kb2 = e / BN;
+        jj = e % BN;
+      } else {
+        kb2 = e % BK;
+        jj = e / BK;
+      }
+      const int64_t gj = n0 + jj, gk2 = k0 + kb2;
+      Bs[kb2][jj] = (gj < N && gk2 < ke) ? B[gk2 * sbk + gj * sbj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k4 = 0; k4 < BK; k4 += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = As[k4 + (lane >> 4)][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Bs[k4 + (lane >> 4)][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = m0 + wm + 16 * i + (lane >> 4) + 4 * v;
+        const int64_t gj = n0 + wn + 16 * j + (lane & 15);
+        if (gi < M && gj < N) {
+          if (splits == 1) {
+            const double prev = (beta != 0.0) ? beta * C[gi * ldc + gj] : 0.0;
+            C[gi * ldc + gj] = alpha * acc[i][j][v] + prev;
+          } else {
+            partial[((int64_t)blockIdx.z * M + gi) * N + gj] = acc[i][j][v];
+          }
+        }
+      }
+}
+
+__global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, const double* __restrict__ partial,
+                                     double alpha, double beta, double* __restrict__ C, int64_t ldc,
+                                     const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  const int64_t i = idx / N, j = idx % N;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * M * N + idx];
+  const double prev = (beta != 0.0) ? beta * C[i * ldc + j] : 0.0;
+  C[i * ldc + j] = alpha * s + prev;
+}
+
+}  // namespace
+
+int dgemm_choose_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int splits = 1;
+  // Aim for >= 512 workgroups (2 per CU) while each split keeps >= 256 of K.
+  while (tiles * splits < 512 && K / (splits * 2) >= 256 && splits < 64) splits *= 2;
+  return splits;
+}
+
+size_t dgemm_partial_elems(int64_t M, int64_t N, int splits) {
+  return splits > 1 ? (size_t)splits * (size_t)M * (size_t)N : 0;
+}
+
+hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sai,
+                        int64_t sak, const double* B, int64_t sbk, int64_t sbj, double beta,
+                        double* C, int64_t ldc, int splits, double* partial, const int32_t* skip,
+                        hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (splits < 1) splits = 1;
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  if (kchunk == 0) kchunk = BK;
+  dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
+  dgemm_kernel<<<grid, 256, 0, s>>>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc, splits,
+                                    kchunk, partial, skip);
+  if (splits > 1) {
+    const int64_t total = M * N;
+    splitk_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, partial, alpha,
+                                                                          beta, C, ldc, skip);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lev

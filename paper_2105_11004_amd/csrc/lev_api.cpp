@@ -1,0 +1,477 @@
+// C interface of liblev (declarations and contracts in include/lev.h):
+// argument validation, seed expansion, workspace carving and the launch
+// sequence of Algorithm 10 (LS-HRN-approx) = Algorithm 4 + Algorithm 8.
+#include "lev.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "lev_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local hipEvent_t g_phase_events[LEV_PHASES];
+thread_local bool g_phase_on = false;
+
+hipError_t mark_phase(int i, hipStream_t s) {
+  return g_phase_on ? hipEventRecord(g_phase_events[i], s) : hipSuccess;
+}
+
+lev_status fail(lev_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+lev_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(LEV_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return LEV_OK;
+}
+
+#define LEV_TRY(expr)                          \
+  do {                                         \
+    lev_status _st = (expr);                   \
+    if (_st != LEV_OK) return _st;             \
+  } while (0)
+
+#define LEV_HIP(expr) LEV_TRY(hip_check((expr), #expr))
+
+// ---- seed expansion (SplitMix64, Steele-Lea-Flood 2014) --------------------
+uint64_t splitmix64_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+bool is_prime_u64(uint64_t x) {
+  if (x < 2) return false;
+  if (x % 2 == 0) return x == 2;
+  for (uint64_t f = 3; f * f <= x; f += 2)
+    if (x % f == 0) return false;
+  return true;
+}
+
+uint64_t next_prime_u64(uint64_t x) {
+  uint64_t p = x < 2 ? 2 : x;
+  while (!is_prime_u64(p)) ++p;
+  return p;
+}
+
+// a^{-1} mod p (p prime, 0 < a < p), extended Euclid.
+uint64_t modinv(uint64_t a, uint64_t p) {
+  int64_t t = 0, new_t = 1;
+  int64_t r = (int64_t)p, new_r = (int64_t)a;
+  while (new_r != 0) {
+    const int64_t q = r / new_r;
+    int64_t tmp = t - q * new_t;
+    t = new_t;
+    new_t = tmp;
+    tmp = r - q * new_r;
+    r = new_r;
+    new_r = tmp;
+  }
+  if (t < 0) t += (int64_t)p;
+  return (uint64_t)t;
+}
+
+constexpr uint64_t kP61 = (1ull << 61) - 1;
+constexpr int64_t kMaxRows = (1ll << 31) - 2;  // row ids + sign bit in 32 bits
+constexpr int64_t kMaxD = 1024;
+constexpr int64_t kMaxK = 64;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Bump allocator over the caller's workspace (or a sizing pass when base is null).
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+size_t elem_size(int dtype) {
+  switch (dtype) {
+    case LEV_F64: return 8;
+    case LEV_F32: return 4;
+    case LEV_BF16: return 2;
+    default: return 0;
+  }
+}
+
+// pass-2 variant from the storage type and the requested precision
+int az_variant(int dtype, int az) {
+  if (dtype == LEV_F64) return az == LEV_AZ_NATIVE ? 0 : -1;
+  if (dtype == LEV_F32) return (az == LEV_AZ_NATIVE || az == LEV_AZ_FP32) ? 1 : -1;
+  if (dtype == LEV_BF16) {
+    switch (az) {
+      case LEV_AZ_NATIVE: return 2;
+      case LEV_AZ_FP32: return 1;
+      case LEV_AZ_BF16: return 2;
+      case LEV_AZ_BF16X2: return 3;
+      default: return -1;
+    }
+  }
+  return -1;
+}
+
+lev_status check_matrix(const lev_matrix* A) {
+  if (A == nullptr) return fail(LEV_ERR_ARG, "A is null");
+  if (A->format != LEV_DENSE_ROWMAJOR && A->format != LEV_CSR)
+    return fail(LEV_ERR_ARG, "unknown format %d", A->format);
+  if (elem_size(A->dtype) == 0) return fail(LEV_ERR_DTYPE, "unknown dtype %d", A->dtype);
+  if (A->n < 0 || A->n > kMaxRows) return fail(LEV_ERR_SHAPE, "n = %lld out of range", (long long)A->n);
+  if (A->d < 1 || A->d > kMaxD)
+    return fail(LEV_ERR_SHAPE, "d = %lld outside [1, %lld]", (long long)A->d, (long long)kMaxD);
+  if (A->format == LEV_DENSE_ROWMAJOR) {
+    if (A->ld < A->d) return fail(LEV_ERR_SHAPE, "ld = %lld < d", (long long)A->ld);
+    if (A->n > 0 && A->values == nullptr) return fail(LEV_ERR_ARG, "A->values is null");
+    if ((reinterpret_cast<uintptr_t>(A->values) & 15) != 0)
+      return fail(LEV_ERR_ARG, "A->values must be 16-byte aligned");
+    if ((A->ld * (int64_t)elem_size(A->dtype)) % 16 != 0)
+      return fail(LEV_ERR_ARG, "ld * sizeof(element) must be a multiple of 16 bytes");
+  } else {
+    return fail(LEV_ERR_NOT_SUPPORTED, "CSR input is not supported by this build yet");
+  }
+  return LEV_OK;
+}
+
+lev_status check_params(const lev_matrix* A, const lev_params* p) {
+  if (p == nullptr) return fail(LEV_ERR_ARG, "params is null");
+  if (p->r_cs < 1 || p->r_cs > kMaxRows) return fail(LEV_ERR_ARG, "r_cs = %lld out of range", (long long)p->r_cs);
+  if (p->m < A->d) return fail(LEV_ERR_SHAPE, "m = %lld < d = %lld", (long long)p->m, (long long)A->d);
+  if (p->m > (1ll << 24)) return fail(LEV_ERR_SHAPE, "m too large");
+  if (p->k < 1 || p->k > kMaxK) return fail(LEV_ERR_ARG, "k = %lld outside [1, 64]", (long long)p->k);
+  if (!(p->zeta >= 0.0 && p->zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
+  if (az_variant(A->dtype, p->az_precision) < 0)
+    return fail(LEV_ERR_ARG, "az_precision %d not valid for dtype %d", p->az_precision, A->dtype);
+  return LEV_OK;
+}
+
+lev_status check_ws(const void* ws, size_t have, size_t need) {
+  if (need > have) return fail(LEV_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", have, need);
+  if (need > 0 && ws == nullptr) return fail(LEV_ERR_WORKSPACE, "workspace is null");
+  if ((reinterpret_cast<uintptr_t>(ws) & (kAlign - 1)) != 0)
+    return fail(LEV_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  return LEV_OK;
+}
+
+// ---- state blob ---------------------------------------------------------------
+struct StateView {
+  int64_t* header;  // [0] magic, [1] d, [2] m, [3] k, [4] rank
+  int32_t* perm;
+  double* R;
+  double* Z64;
+  double* At;
+};
+constexpr int64_t kStateMagic = 0x4C45565354415431ll;
+
+size_t state_bytes(int64_t d, int64_t m, int64_t k) {
+  Carver c(nullptr);
+  c.take<int64_t>(8);
+  c.take<int32_t>((size_t)d);
+  c.take<double>((size_t)(d * d));
+  c.take<double>((size_t)(d * k));
+  c.take<double>((size_t)(m * d));
+  return c.used;
+}
+
+StateView carve_state(void* base, int64_t d, int64_t m, int64_t k) {
+  Carver c(base);
+  StateView v;
+  v.header = c.take<int64_t>(8);
+  v.perm = c.take<int32_t>((size_t)d);
+  v.R = c.take<double>((size_t)(d * d));
+  v.Z64 = c.take<double>((size_t)(d * k));
+  v.At = c.take<double>((size_t)(m * d));
+  return v;
+}
+
+// ---- workspace plans -------------------------------------------------------------
+struct SketchBufs {
+  double* Gm;
+  double* SA;
+  double* partial;
+};
+
+int gm_splits(int64_t m, int64_t d, int64_t r_cs) { return lev::dgemm_choose_splits(m, d, r_cs); }
+
+SketchBufs carve_sketch(Carver& c, int64_t n, int64_t d, int64_t m, int64_t r_cs, bool need_sa) {
+  (void)n;
+  SketchBufs b;
+  b.Gm = c.take<double>((size_t)(m * r_cs));
+  b.SA = need_sa ? c.take<double>((size_t)(r_cs * d)) : nullptr;
+  b.partial = c.take<double>(lev::dgemm_partial_elems(m, d, gm_splits(m, d, r_cs)));
+  return b;
+}
+
+struct RankBufs {
+  double* B;
+  double* partial;
+  lev::PivCholState pc;
+};
+
+RankBufs carve_rank(Carver& c, int64_t m, int64_t d) {
+  RankBufs b;
+  b.B = c.take<double>((size_t)(d * d));
+  b.partial = c.take<double>(lev::dgemm_partial_elems(d, d, lev::dgemm_choose_splits(d, d, m)));
+  b.pc.diag = c.take<double>((size_t)d);
+  b.pc.Rrows = c.take<double>((size_t)(d * d));
+  b.pc.piv = c.take<int32_t>((size_t)d);
+  b.pc.flags = c.take<int32_t>(64);
+  b.pc.r00 = c.take<double>(1);
+  return b;
+}
+
+lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::SeedDraws& dr,
+                          const SketchBufs& b, double* SA, double* At, hipStream_t s) {
+  const int64_t d = A->d, m = p->m, r_cs = p->r_cs;
+  LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, 1.0 / std::sqrt((double)m), b.Gm, s));
+  LEV_HIP(mark_phase(1, s));
+  if (A->n > 0) {
+    LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, s));
+  } else {
+    LEV_HIP(lev::launch_fill_zero(SA, sizeof(double) * (size_t)(r_cs * d), s));
+  }
+  LEV_HIP(mark_phase(2, s));
+  // A~ = G_m (S A): (m x r_cs) (r_cs x d)
+  const int splits = gm_splits(m, d, r_cs);
+  LEV_HIP(lev::launch_dgemm(m, d, r_cs, 1.0, b.Gm, r_cs, 1, SA, d, 1, 0.0, At, d, splits, b.partial,
+                            nullptr, s));
+  LEV_HIP(mark_phase(3, s));
+  return LEV_OK;
+}
+
+lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, const RankBufs& b,
+                        int32_t* perm, double* R, int64_t* rank, hipStream_t s) {
+  // Gram B = A~^T A~ (d x d)
+  const int splits = lev::dgemm_choose_splits(d, d, m);
+  LEV_HIP(lev::launch_dgemm(d, d, m, 1.0, At, 1, d, At, d, 1, 0.0, b.B, d, splits, b.partial, nullptr, s));
+  LEV_HIP(lev::launch_fill_zero(b.pc.flags, 64 * sizeof(int32_t), s));
+  LEV_HIP(lev::launch_pivchol(b.B, d, zeta, b.pc, rank, b.partial, s));
+  LEV_HIP(lev::launch_pivchol_finalize(d, b.pc, rank, perm, R, s));
+  return LEV_OK;
+}
+
+}  // namespace
+
+namespace lev {
+
+SeedDraws derive_draws(uint64_t seed, int64_t n, int64_t r_cs) {
+  uint64_t st = seed;
+  uint64_t w[8];
+  for (int i = 0; i < 8; ++i) w[i] = splitmix64_next(st);
+  SeedDraws dr;
+  HashParams& h = dr.hash;
+  h.n = n;
+  h.r_cs = r_cs;
+  h.P = next_prime_u64((uint64_t)(n < 2 ? 2 : n));
+  h.a = 1 + w[0] % (h.P - 1);
+  h.c = w[1] % h.P;
+  h.ainv = modinv(h.a, h.P);
+  h.delta = (h.ainv * ((uint64_t)r_cs % h.P)) % h.P;
+  h.c0 = w[2] % kP61;
+  h.c1 = w[3] % kP61;
+  h.c2 = w[4] % kP61;
+  h.c3 = w[5] % kP61;
+  dr.key_m = PhiloxKey{(uint32_t)(w[6] & 0xFFFFFFFFu), (uint32_t)(w[6] >> 32)};
+  dr.key_k = PhiloxKey{(uint32_t)(w[7] & 0xFFFFFFFFu), (uint32_t)(w[7] >> 32)};
+  return dr;
+}
+
+}  // namespace lev
+
+extern "C" {
+
+const char* lev_status_string(lev_status s) {
+  switch (s) {
+    case LEV_OK: return "LEV_OK";
+    case LEV_ERR_ARG: return "LEV_ERR_ARG";
+    case LEV_ERR_SHAPE: return "LEV_ERR_SHAPE";
+    case LEV_ERR_DTYPE: return "LEV_ERR_DTYPE";
+    case LEV_ERR_FORMAT: return "LEV_ERR_FORMAT";
+    case LEV_ERR_WORKSPACE: return "LEV_ERR_WORKSPACE";
+    case LEV_ERR_HIP: return "LEV_ERR_HIP";
+    case LEV_ERR_NOT_SUPPORTED: return "LEV_ERR_NOT_SUPPORTED";
+    default: return "LEV_ERR_UNKNOWN";
+  }
+}
+
+const char* lev_last_error(void) { return g_last_error.c_str(); }
+
+lev_status lev_set_phase_events(hipEvent_t* events, int count) {
+  if (events == nullptr || count == 0) {
+    g_phase_on = false;
+    return LEV_OK;
+  }
+  if (count != LEV_PHASES) return fail(LEV_ERR_ARG, "count must be %d", LEV_PHASES);
+  for (int i = 0; i < LEV_PHASES; ++i) {
+    if (events[i] == nullptr) return fail(LEV_ERR_ARG, "event %d is null", i);
+    g_phase_events[i] = events[i];
+  }
+  g_phase_on = true;
+  return LEV_OK;
+}
+
+size_t lev_state_size(int64_t d, int64_t m, int64_t k) {
+  if (d < 1 || m < d || k < 1) return 0;
+  return state_bytes(d, m, k);
+}
+
+size_t lev_rank_workspace_size(int64_t m, int64_t d) {
+  if (d < 1 || d > kMaxD || m < d) return 0;
+  Carver c(nullptr);
+  carve_rank(c, m, d);
+  return c.used;
+}
+
+size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
+  if (check_matrix(A) != LEV_OK || check_params(A, p) != LEV_OK) return 0;
+  const int64_t d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
+  Carver c(nullptr);
+  if (which == LEV_WS_SKETCH) {
+    carve_sketch(c, A->n, d, m, r_cs, true);
+    return c.used;
+  }
+  if (which == LEV_WS_ESTIMATE) {
+    carve_sketch(c, A->n, d, m, r_cs, true);
+    carve_rank(c, m, d);
+    c.take<char>(state_bytes(d, m, k));
+    c.take<double>((size_t)(d * k));  // G_k
+    c.take<char>(lev::pack_z_bytes(az_variant(A->dtype, p->az_precision), d, k));
+    return c.used;
+  }
+  return 0;
+}
+
+lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out, double* SA_out, void* ws,
+                      size_t ws_bytes, hipStream_t stream) {
+  LEV_TRY(check_matrix(A));
+  LEV_TRY(check_params(A, p));
+  if (At_out == nullptr) return fail(LEV_ERR_ARG, "At_out is null");
+  Carver sizing(nullptr);
+  carve_sketch(sizing, A->n, A->d, p->m, p->r_cs, true);
+  LEV_TRY(check_ws(ws, ws_bytes, sizing.used));
+  Carver c(ws);
+  SketchBufs b = carve_sketch(c, A->n, A->d, p->m, p->r_cs, true);
+  const lev::SeedDraws dr = lev::derive_draws(p->seed, A->n, p->r_cs);
+  double* SA = SA_out != nullptr ? SA_out : b.SA;
+  return enqueue_sketch(A, p, dr, b, SA, At_out, stream);
+}
+
+lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta, int32_t* perm_out,
+                             double* R_out, int64_t* rank_out, void* ws, size_t ws_bytes,
+                             hipStream_t stream) {
+  if (At == nullptr || perm_out == nullptr || R_out == nullptr || rank_out == nullptr)
+    return fail(LEV_ERR_ARG, "null pointer argument");
+  if (d < 1 || d > kMaxD) return fail(LEV_ERR_SHAPE, "d = %lld outside [1, 1024]", (long long)d);
+  if (m < d) return fail(LEV_ERR_SHAPE, "m = %lld < d = %lld", (long long)m, (long long)d);
+  if (!(zeta >= 0.0 && zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
+  const size_t need = lev_rank_workspace_size(m, d);
+  LEV_TRY(check_ws(ws, ws_bytes, need));
+  Carver c(ws);
+  RankBufs b = carve_rank(c, m, d);
+  return enqueue_rank(At, m, d, zeta, b, perm_out, R_out, rank_out, stream);
+}
+
+lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_out, void* state_out, void* ws,
+                        size_t ws_bytes, hipStream_t stream) {
+  LEV_TRY(check_matrix(A));
+  LEV_TRY(check_params(A, p));
+  if (theta_out == nullptr && A->n > 0) return fail(LEV_ERR_ARG, "theta_out is null");
+  const size_t need = lev_workspace_size(A, p, LEV_WS_ESTIMATE);
+  LEV_TRY(check_ws(ws, ws_bytes, need));
+  if (state_out != nullptr && (reinterpret_cast<uintptr_t>(state_out) & (kAlign - 1)) != 0)
+    return fail(LEV_ERR_ARG, "state_out must be 256-byte aligned");
+
+  const int64_t n = A->n, d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
+  const int variant = az_variant(A->dtype, p->az_precision);
+  Carver c(ws);
+  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
+  RankBufs rb = carve_rank(c, m, d);
+  void* state_ws = c.take<char>(state_bytes(d, m, k));
+  double* Gk = c.take<double>((size_t)(d * k));
+  void* Zpack = c.take<char>(lev::pack_z_bytes(variant, d, k));
+  StateView sv = carve_state(state_out != nullptr ? state_out : state_ws, d, m, k);
+  int64_t* rank = sv.header + 4;
+
+  const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
+  LEV_HIP(mark_phase(0, stream));
+  LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, stream));
+  LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, stream));
+  LEV_HIP(mark_phase(4, stream));
+  LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, 1.0 / std::sqrt((double)k), Gk, stream));
+  LEV_HIP(lev::launch_trsm_z(d, k, sv.R, rank, Gk, sv.Z64, stream));
+  LEV_HIP(lev::launch_pack_z(variant, d, k, sv.perm, rank, sv.Z64, Zpack, stream));
+  LEV_HIP(mark_phase(5, stream));
+  if (n > 0) {
+    LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, k, Zpack, rank, theta_out,
+                                      stream));
+  }
+  LEV_HIP(mark_phase(6, stream));
+  if (state_out != nullptr) {
+    LEV_HIP(lev::launch_store_i64x4(sv.header, kStateMagic, d, m, k, stream));
+  }
+  return LEV_OK;
+}
+
+lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const void* state, const void* w,
+                                 void* gradA_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  (void)A;
+  (void)p;
+  (void)state;
+  (void)w;
+  (void)gradA_out;
+  (void)ws;
+  (void)ws_bytes;
+  (void)stream;
+  return fail(LEV_ERR_NOT_SUPPORTED, "backward is not implemented in this build yet");
+}
+
+lev_status lev_debug_hash(uint64_t seed, int64_t n, int64_t r_cs, int64_t* h_out, int8_t* s_out,
+                          hipStream_t stream) {
+  if (n < 0 || n > kMaxRows || r_cs < 1 || r_cs > kMaxRows) return fail(LEV_ERR_SHAPE, "bad n or r_cs");
+  if (n > 0 && (h_out == nullptr || s_out == nullptr)) return fail(LEV_ERR_ARG, "null output");
+  const lev::SeedDraws dr = lev::derive_draws(seed, n, r_cs);
+  LEV_HIP(lev::launch_hash_rows(dr.hash, h_out, s_out, stream));
+  return LEV_OK;
+}
+
+lev_status lev_debug_buckets(uint64_t seed, int64_t n, int64_t r_cs, int64_t* bucket_off, int32_t* bucket_rows,
+                             hipStream_t stream) {
+  if (n < 0 || n > kMaxRows || r_cs < 1 || r_cs > kMaxRows) return fail(LEV_ERR_SHAPE, "bad n or r_cs");
+  if (bucket_off == nullptr || (n > 0 && bucket_rows == nullptr)) return fail(LEV_ERR_ARG, "null output");
+  const lev::SeedDraws dr = lev::derive_draws(seed, n, r_cs);
+  LEV_HIP(lev::launch_bucket_lists(dr.hash, bucket_off, bucket_rows, stream));
+  return LEV_OK;
+}
+
+lev_status lev_debug_gaussian(uint64_t seed, int which, int64_t rows, int64_t cols, double* out,
+                              hipStream_t stream) {
+  if (rows < 1 || cols < 1) return fail(LEV_ERR_SHAPE, "rows and cols must be >= 1");
+  if (out == nullptr) return fail(LEV_ERR_ARG, "out is null");
+  if (which != 0 && which != 1) return fail(LEV_ERR_ARG, "which must be 0 or 1");
+  const lev::SeedDraws dr = lev::derive_draws(seed, 2, 1);
+  const double scale = 1.0 / std::sqrt((double)(which == 0 ? rows : cols));
+  LEV_HIP(lev::launch_gaussian(which == 0 ? dr.key_m : dr.key_k, rows, cols, scale, out, stream));
+  return LEV_OK;
+}
+
+}  // extern "C"

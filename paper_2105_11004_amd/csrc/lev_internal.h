@@ -1,0 +1,112 @@
+// Internal interface between the C API (lev_api.cpp) and the kernels.
+// Not installed; nothing outside csrc/ includes it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lev {
+
+// Parameters of the CountSketch S, expanded from the user seed on the host.
+// Bucket hash: h(i) = ((a*i + c) mod P) mod r_cs with P the smallest prime
+// >= max(n, 2) (P < 2^32 since n < 2^31).  Pass 1 walks bucket b by
+// inverting the permutation x = (a*i + c) mod P: the rows of bucket b are
+// i = ainv * (x - c) mod P for x = b, b + r_cs, b + 2 r_cs, ... < P, kept
+// when i < n, i.e. the arithmetic progression i_t = i_0 + t*delta (mod P)
+// with delta = ainv * r_cs mod P.
+// Sign: s(i) = +1 if (c3 i^3 + c2 i^2 + c1 i + c0) mod (2^61 - 1) is even.
+struct HashParams {
+  uint64_t P, a, c, ainv, delta;
+  uint64_t c0, c1, c2, c3;
+  int64_t n, r_cs;
+};
+
+struct PhiloxKey {
+  uint32_t k0, k1;
+};
+
+struct SeedDraws {
+  HashParams hash;
+  PhiloxKey key_m;  // Gaussian transform G_m
+  PhiloxKey key_k;  // JL Gaussian G_k
+};
+
+// Host-side expansion of a seed (SplitMix64 words w0..w7).
+SeedDraws derive_draws(uint64_t seed, int64_t n, int64_t r_cs);
+
+// ---- launch wrappers (all enqueue on `s`, return hipError_t of the launch) ----
+
+// h(i), s(i) for all rows (debug/inspection).
+hipError_t launch_hash_rows(const HashParams& hp, int64_t* h_out, int8_t* s_out, hipStream_t s);
+// bucket_off[r_cs+1], bucket_rows[n] in pass-1 order (debug/inspection).
+hipError_t launch_bucket_lists(const HashParams& hp, int64_t* off, int32_t* rows, hipStream_t s);
+
+// Pass 1, dense: SA (r_cs x d, FP64, ld = d) = S A.
+// dtype: 0 = f64, 1 = f32, 2 = bf16.
+hipError_t launch_countsketch_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
+                                    const HashParams& hp, double* SA, hipStream_t s);
+// Pass 1, CSR.
+hipError_t launch_countsketch_csr(int dtype, const void* vals, const int64_t* row_ptr,
+                                  const int32_t* col_idx, int64_t n, int64_t d,
+                                  const HashParams& hp, double* SA, hipStream_t s);
+
+// rows x cols FP64 Gaussian matrix, Philox4x32-10 + Box-Muller, times scale.
+hipError_t launch_gaussian(PhiloxKey key, int64_t rows, int64_t cols, double scale, double* out,
+                           hipStream_t s);
+
+// FP64 GEMM on MFMA: C = alpha * op(A) op(B) + beta * C with arbitrary
+// element strides: op(A)(i,k) = A[i*sai + k*sak], op(B)(k,j) = B[k*sbk + j*sbj],
+// C(i,j) = C[i*ldc + j].  If `skip` is non-null and *skip != 0 on the device,
+// the kernel does nothing.  `partial` (splits * M * N doubles) is used when
+// splits > 1 (split-K, reduced in fixed order).
+hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sai,
+                        int64_t sak, const double* B, int64_t sbk, int64_t sbj, double beta,
+                        double* C, int64_t ldc, int splits, double* partial, const int32_t* skip,
+                        hipStream_t s);
+size_t dgemm_partial_elems(int64_t M, int64_t N, int splits);
+int dgemm_choose_splits(int64_t M, int64_t N, int64_t K);
+
+// Pivoted Cholesky of the d x d Gram B (overwritten with Schur complements).
+struct PivCholState {
+  double* diag;        // d
+  double* Rrows;       // d x d: row J = row J of R in original column order
+  int32_t* piv;        // d: pivot at position J
+  int32_t* flags;      // [0] = done, [1] = pivots so far, [2..] scratch
+  double* r00;         // 1
+};
+hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState& st, int64_t* rank_out,
+                          double* gemm_partial, hipStream_t s);
+// Writes perm (int32[d], unpivoted columns ascending after the rank) and
+// R_out (d x d, pivoted order, zero below the diagonal and below the rank).
+hipError_t launch_pivchol_finalize(int64_t d, const PivCholState& st, const int64_t* rank,
+                                   int32_t* perm_out, double* R_out, hipStream_t s);
+
+// Z = R11^{-1} G_k[0:r, 0:k] in FP64 (R pivoted d x d, ld = d), r read from
+// the device.  Z64 is d x k (rows >= r zeroed).
+hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, const double* Gk,
+                         double* Z64, hipStream_t s);
+
+// Prepares the operand of pass 2: Z_full (d x k, rows indexed by original
+// column, zero off K) converted to the pass-2 compute type and laid out for
+// the MFMA B-operand; see rownorm.hip for the layouts.
+// variant: 0 = FP64, 1 = FP32, 2 = BF16, 3 = BF16 hi/lo.
+hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
+                         const double* Z64, void* Zpack, hipStream_t s);
+size_t pack_z_bytes(int variant, int64_t d, int64_t k);
+
+// Pass 2, dense: theta[i] = || A[i, :] Z_full ||^2.
+// variant as above; dtype = storage type of A (0 f64, 1 f32, 2 bf16).
+hipError_t launch_rownorm_dense(int variant, int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
+                                int64_t k, const void* Zpack, const int64_t* rank, void* theta,
+                                hipStream_t s);
+hipError_t launch_rownorm_csr(int variant, int dtype, const void* vals, const int64_t* row_ptr,
+                              const int32_t* col_idx, int64_t n, int64_t d, int64_t k,
+                              const void* Zpack, const int64_t* rank, void* theta, hipStream_t s);
+
+// dst[0..3] = (a, b, c, e) from a kernel (capture-safe small header write).
+hipError_t launch_store_i64x4(int64_t* dst, int64_t a, int64_t b, int64_t c, int64_t e, hipStream_t s);
+
+// Zero-fill helper (a kernel, so it is safe under graph capture).
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace lev

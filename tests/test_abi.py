@@ -1,0 +1,115 @@
+"""The C-ABI library loads and exports every symbol include/lev.h declares;
+host-side validation rejects bad arguments before anything is launched.
+No compute call here reaches a kernel, so these run without a GPU."""
+
+import ctypes
+import re
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch  # noqa: F401  (binds liblev to the HIP runtime torch ships)
+    from paper_2105_11004_amd import api
+    if not api.LIB_PATH.exists():
+        from paper_2105_11004_amd import build
+        build.build()
+    return api.load_library()
+
+
+def _declared_functions():
+    text = (ROOT / "include" / "lev.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lev_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary_calls():
+    names = _declared_functions()
+    for call in ("lev_sketch", "lev_rank_estimate", "lev_estimate", "lev_estimate_backward"):
+        assert call in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2105_11004_amd import api
+    names = _declared_functions()
+    assert set(names) == set(api.EXPORTED)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    from paper_2105_11004_amd import api
+    for code, name in api.STATUS_NAMES.items():
+        assert lib.lev_status_string(code).decode() == name
+
+
+def _mat(api, **kw):
+    base = dict(format=api.DENSE, dtype=api.F32, n=1000, d=16, ld=16, nnz=0, values=4096,
+                row_ptr=None, col_idx=None)
+    base.update(kw)
+    return api.LevMatrix(base["format"], base["dtype"], base["n"], base["d"], base["ld"], base["nnz"],
+                         base["values"], base["row_ptr"], base["col_idx"])
+
+
+def _par(api, **kw):
+    base = dict(seed=1, r_cs=64, m=32, k=8, zeta=1e-5, az=0)
+    base.update(kw)
+    return api.LevParams(base["seed"], base["r_cs"], base["m"], base["k"], base["zeta"], base["az"], 0)
+
+
+@pytest.mark.parametrize("mat_kw,par_kw,expected", [
+    ({"format": 7}, {}, -1),
+    ({"dtype": 9}, {}, -3),
+    ({"d": 0}, {}, -2),
+    ({"d": 2048, "ld": 2048}, {"m": 4096}, -2),
+    ({"ld": 8}, {}, -2),
+    ({"values": 4100}, {}, -1),                 # misaligned
+    ({"ld": 17}, {}, -1),                        # row pitch not a multiple of 16 bytes
+    ({"n": -1}, {}, -2),
+    ({}, {"m": 8}, -2),                          # m < d
+    ({}, {"k": 0}, -1),
+    ({}, {"k": 65}, -1),
+    ({}, {"r_cs": 0}, -1),
+    ({}, {"zeta": 1.5}, -1),
+    ({}, {"az": 2}, -1),                         # BF16 products need BF16 storage
+    ({"dtype": 0, "ld": 16}, {"az": 1}, -1),     # FP64 input only in FP64
+    ({"format": 1}, {}, -7),                     # CSR not in this build yet
+])
+def test_estimate_rejects_bad_arguments(lib, mat_kw, par_kw, expected):
+    from paper_2105_11004_amd import api
+    A, p = _mat(api, **mat_kw), _par(api, **par_kw)
+    st = lib.lev_estimate(ctypes.byref(A), ctypes.byref(p), ctypes.c_void_p(8192), None,
+                          ctypes.c_void_p(1 << 20), 1 << 40, None)
+    assert st == expected, lib.lev_last_error().decode()
+    assert lib.lev_last_error().decode() != ""
+
+
+def test_workspace_checks(lib):
+    from paper_2105_11004_amd import api
+    A, p = _mat(api), _par(api)
+    need = lib.lev_workspace_size(ctypes.byref(A), ctypes.byref(p), api.WS_ESTIMATE)
+    assert need > 0
+    st = lib.lev_estimate(ctypes.byref(A), ctypes.byref(p), ctypes.c_void_p(8192), None,
+                          ctypes.c_void_p(1 << 20), need - 1, None)
+    assert st == -5
+    st = lib.lev_estimate(ctypes.byref(A), ctypes.byref(p), ctypes.c_void_p(8192), None,
+                          ctypes.c_void_p((1 << 20) + 8), need, None)
+    assert st == -5  # misaligned workspace
+    assert lib.lev_workspace_size(None, ctypes.byref(p), api.WS_ESTIMATE) == 0
+    assert lib.lev_state_size(16, 32, 8) > 16 * 32 * 8
+    assert lib.lev_state_size(16, 8, 8) == 0
+    assert lib.lev_rank_workspace_size(32, 16) > 0
+    assert lib.lev_rank_workspace_size(8, 16) == 0
+
+
+def test_other_calls_validate(lib):
+    vp = ctypes.c_void_p
+    assert lib.lev_rank_estimate(None, 32, 16, 1e-5, vp(8), vp(8), vp(8), vp(1 << 20), 1 << 30, None) == -1
+    assert lib.lev_rank_estimate(vp(8), 8, 16, 1e-5, vp(8), vp(8), vp(8), vp(1 << 20), 1 << 30, None) == -2
+    assert lib.lev_debug_hash(1, -5, 8, vp(8), vp(8), None) == -2
+    assert lib.lev_debug_gaussian(1, 2, 4, 4, vp(8), None) == -1
+    assert lib.lev_debug_buckets(1, 10, 0, vp(8), vp(8), None) == -2

@@ -1,0 +1,263 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Every comparison feeds both sides the same seeded inputs; the oracle never
+sees a GPU output.  Bars: bit-exact for integer work (hash, buckets, and the
+sketch of integer-valued matrices), 1e-4 relative per theta~_i for the FP32
+estimator, tighter for FP64, reported error for BF16."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import conventions as C
+from oracle import leverage as L
+from paper_2105_11004_amd import api
+from paper_2105_11004_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------ hashing
+@pytest.mark.parametrize("seed,n,r_cs", [(1, 10007, 97), (2 ** 64 - 3, 65536, 4096), (5, 100, 1),
+                                         (7, 50, 200), (9, 1, 3)])
+def test_hash_bit_exact(gpu, seed, n, r_cs):
+    _log("hash", seed, n, r_cs)
+    h, s = api.lev_debug_hash(seed, n, r_cs, device=gpu)
+    rnd = C.derive(seed, n, r_cs)
+    np.testing.assert_array_equal(h.cpu().numpy(), C.buckets(rnd))
+    np.testing.assert_array_equal(s.cpu().numpy().astype(np.float64), C.signs(rnd))
+
+
+@pytest.mark.parametrize("seed,n,r_cs", [(3, 20011, 64), (4, 3000, 4096), (11, 4096, 1)])
+def test_bucket_lists_are_the_hash_preimages(gpu, seed, n, r_cs):
+    _log("buckets", seed, n, r_cs)
+    off, rows = api.lev_debug_buckets(seed, n, r_cs, device=gpu)
+    off, rows = off.cpu().numpy(), rows.cpu().numpy()
+    rnd = C.derive(seed, n, r_cs)
+    h = C.buckets(rnd)
+    assert off[0] == 0 and off[-1] == n
+    np.testing.assert_array_equal(np.diff(off), np.bincount(h, minlength=r_cs))
+    for b in range(r_cs):
+        mine = rows[off[b]:off[b + 1]]
+        # the set is unique ...
+        np.testing.assert_array_equal(np.sort(mine), np.nonzero(h == b)[0])
+        # ... and the order pass 1 uses is ascending x = (a i + c) mod P
+        x = (rnd.a * mine.astype(object) + rnd.c) % rnd.P
+        assert all(x[j] < x[j + 1] for j in range(len(x) - 1))
+
+
+# ------------------------------------------------------------------ Gaussians
+@pytest.mark.parametrize("which,rows,cols", [(0, 257, 1031), (1, 64, 48), (0, 1, 1)])
+def test_gaussian_matches_oracle(gpu, which, rows, cols):
+    _log("gaussian", which, rows, cols)
+    g = api.lev_debug_gaussian(77, which, rows, cols, device=gpu).cpu().numpy()
+    rnd = C.derive(77, 2, 1)
+    o = C.gaussian_matrix(rnd.key_m if which == 0 else rnd.key_k, rows, cols,
+                          1.0 / math.sqrt(rows if which == 0 else cols))
+    # same Philox bits; Box-Muller's log/sqrt/sincos may differ by a few ulp
+    np.testing.assert_allclose(g, o, rtol=1e-14, atol=1e-15)
+
+
+# ------------------------------------------------------------------ pass 1 + Gaussian transform
+@pytest.mark.parametrize("dtype,n,d", [(torch.float64, 5003, 64), (torch.float32, 20011, 256),
+                                       (torch.bfloat16, 9001, 1024), (torch.float32, 777, 20),
+                                       (torch.float32, 4099, 600)])
+def test_sketch_integer_matrix_bit_exact(gpu, dtype, n, d):
+    _log("sketch", dtype, n, d)
+    g = torch.Generator().manual_seed(n)
+    Ai = torch.randint(-8, 9, (n, d), generator=g).to(torch.float64)
+    A = Ai.to(dtype)
+    ld = d if (d * A.element_size()) % 16 == 0 else ((d * A.element_size() + 15) // 16 * 16) // A.element_size()
+    Ad = torch.zeros(n, ld, dtype=dtype, device=gpu)
+    Ad[:, :d] = A.to(gpu)
+    Ad = Ad[:, :d]
+    r_cs, m = 512, max(d, 96)
+    At, SA = api.lev_sketch(Ad, 31, r_cs, m, return_sa=True)
+    rnd = C.derive(31, n, r_cs)
+    SA_o = L.countsketch_apply(rnd, Ai.numpy())
+    np.testing.assert_array_equal(SA.cpu().numpy(), SA_o)   # integer sums are exact in FP64
+    G = C.gaussian_transform(rnd, m)
+    At_o = G @ SA_o
+    bound = 1e-13 * (np.abs(G) @ np.abs(SA_o)) + 1e-300
+    assert np.all(np.abs(At.cpu().numpy() - At_o) <= bound)
+
+
+def test_sketch_is_deterministic(gpu):
+    A = W.dense_gaussian(30000, 128, 5, dtype=torch.float32).to(gpu)
+    a1 = api.lev_sketch(A, 3, 1024, 256)
+    a2 = api.lev_sketch(A, 3, 1024, 256)
+    assert torch.equal(a1, a2)
+
+
+# ------------------------------------------------------------------ rank-revealing QR
+def _rank_check(gpu, At_np, zeta, expect_rank=None):
+    At = torch.from_numpy(At_np).to(gpu)
+    perm, R, rank = api.lev_rank_estimate(At, zeta)
+    r = int(rank.item())
+    o = L.qrcp_sign_normalised(At_np, zeta)
+    if expect_rank is not None:
+        assert o.rank == expect_rank
+    assert r == o.rank
+    perm = perm.cpu().numpy()
+    np.testing.assert_array_equal(perm[:r], o.perm[:r])
+    assert sorted(perm.tolist()) == list(range(At_np.shape[1]))
+    Rg = R.cpu().numpy()
+    scale = o.R[0, 0] if r else 1.0
+    # rows < r compared column by original id (past the rank the two
+    # permutations order the unselected columns differently)
+    d = At_np.shape[1]
+    by_id_g, by_id_o = np.empty((r, d)), np.empty((r, d))
+    by_id_g[:, perm] = Rg[:r]
+    by_id_o[:, o.perm] = o.R[:r]
+    np.testing.assert_allclose(by_id_g, by_id_o, atol=1e-9 * scale, rtol=0)
+    np.testing.assert_allclose(Rg[:r, :r], o.R[:r, :r], atol=1e-9 * scale, rtol=0)
+    assert np.all(Rg[r:] == 0)
+    return r
+
+
+def test_rank_estimate_full_rank(gpu):
+    rng = np.random.default_rng(0)
+    for m, d in [(256, 64), (512, 256), (70, 33), (2048, 1024)]:
+        _log("qrcp", m, d)
+        _rank_check(gpu, rng.standard_normal((m, d)) * rng.uniform(0.5, 2, d), 1e-10, expect_rank=d)
+
+
+def test_rank_estimate_rank_deficient_and_zero(gpu):
+    rng = np.random.default_rng(1)
+    B = rng.standard_normal((300, 40)) @ rng.standard_normal((40, 100))
+    B += 1e-9 * rng.standard_normal(B.shape)
+    _rank_check(gpu, B, 1e-6, expect_rank=40)
+    Z = np.zeros((64, 32))
+    Z[:, 5] = rng.standard_normal(64)
+    _rank_check(gpu, Z, 1e-6, expect_rank=1)
+    _rank_check(gpu, np.zeros((16, 8)), 1e-6, expect_rank=0)
+
+
+# ------------------------------------------------------------------ the estimator
+def _oracle_theta(A_host_f64, seed, r_cs, m, k, zeta, rows=None):
+    return L.ls_hrn_approx(A_host_f64, seed, r_cs, m, k, zeta, rows=rows)
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def test_estimate_fp64_dense_gaussian(gpu):
+    n, d, r_cs, m, k, zeta, seed = 4096, 64, 1024, 256, 32, 1e-10, 2001
+    A = W.dense_gaussian(n, d, 1001, dtype=torch.float64)
+    theta, state = api.lev_estimate(A.to(gpu), seed, r_cs, m, k, zeta, return_state=True)
+    o = _oracle_theta(A.numpy(), seed, r_cs, m, k, zeta)
+    assert int(state.rank.item()) == o.rank == d
+    np.testing.assert_array_equal(state.perm.cpu().numpy()[:d], o.perm[:d])
+    rel = _rel(theta.cpu().numpy(), o.theta)
+    _log("fp64 max rel", rel.max())
+    assert rel.max() < 1e-9
+
+
+@pytest.mark.parametrize("n", [65536 + 13, 1000])
+def test_estimate_fp32_low_rank_coherent(gpu, n):
+    d, rank, r_cs, m, k, zeta, seed = 256, 128, 4096, 512, 48, 1e-5, 2002
+    A = W.low_rank_coherent(n, d, rank, 1002)
+    theta, state = api.lev_estimate(A.to(gpu), seed, r_cs, m, k, zeta, return_state=True)
+    o = _oracle_theta(A.numpy().astype(np.float64), seed, r_cs, m, k, zeta)
+    r = int(state.rank.item())
+    assert r == o.rank == rank
+    np.testing.assert_array_equal(state.perm.cpu().numpy()[:r], o.perm[:r])
+    rel = _rel(theta.cpu().numpy().astype(np.float64), o.theta)
+    _log("fp32 n", n, "max rel", rel.max(), "p99", np.quantile(rel, 0.99))
+    assert rel.max() < 1e-4
+
+
+@pytest.mark.parametrize("precision,bar_max,bar_p99", [("fp32", 1e-4, 1e-5), ("bf16x2", 2e-4, 2e-5),
+                                                      ("bf16", 5e-2, 2e-2)])
+def test_estimate_bf16_storage(gpu, precision, bar_max, bar_p99):
+    n, d, r_cs, m, k, zeta, seed = 32768 + 5, 512, 8192, 1024, 64, 1e-3, 2004
+    A = W.row_scaled_bf16(n, d, 1004)
+    theta = api.lev_estimate(A.to(gpu), seed, r_cs, m, k, zeta, precision=precision)
+    o = _oracle_theta(A.to(torch.float64).numpy(), seed, r_cs, m, k, zeta)
+    rel = _rel(theta.cpu().numpy().astype(np.float64), o.theta)
+    _log("bf16", precision, "max rel", rel.max(), "p99", np.quantile(rel, 0.99))
+    assert rel.max() < bar_max and np.quantile(rel, 0.99) < bar_p99
+
+
+def test_estimate_full_size_sampled(gpu):
+    """The benchmark's workload (2^20 x 256 FP32, rank 128, 1% rows x 1e3) in
+    the benchmark's launch configuration, checked on sampled rows."""
+    cfg = W.CONFIGS["dense_f32_1Mx256_rank128"]
+    n, d = cfg["n"], cfg["d"]
+    _log("full size: generating")
+    A = W.low_rank_coherent(n, d, cfg["rank"], W.data_seed(2), device=gpu)
+    plan = api.EstimatePlan(A, W.sketch_seed(2), cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+    theta = plan.run().cpu().numpy().astype(np.float64)
+    rows = np.sort(np.random.default_rng(0).choice(n, 3000, replace=False))
+    A_host = A.cpu().numpy()
+    _log("full size: oracle")
+    o = _oracle_theta(A_host, W.sketch_seed(2), cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows)
+    assert o.rank == cfg["rank"]
+    rel = _rel(theta[rows], o.theta_rows)
+    _log("full size max rel", rel.max())
+    assert rel.max() < 1e-4
+    # properties that hold at any size
+    assert np.all(theta >= 0) and np.all(np.isfinite(theta))
+
+
+# ------------------------------------------------------------------ edge cases
+def test_zero_matrix_and_zero_rows(gpu):
+    A = torch.zeros(1000, 32, dtype=torch.float32, device=gpu)
+    theta, st = api.lev_estimate(A, 1, 64, 64, 8, 1e-5, return_state=True)
+    assert int(st.rank.item()) == 0 and torch.all(theta == 0)
+    B = W.dense_gaussian(2000, 32, 3, dtype=torch.float32)
+    B[[0, 999, 1999]] = 0
+    theta = api.lev_estimate(B.to(gpu), 1, 256, 64, 8, 1e-5).cpu()
+    assert theta[0] == 0 and theta[999] == 0 and theta[1999] == 0
+
+
+@pytest.mark.parametrize("n,d,k,r_cs,m", [(1, 4, 1, 1, 4), (15, 8, 17, 3, 8), (33, 64, 64, 7, 64),
+                                          (5000, 36, 5, 1, 40), (300, 12, 16, 5000, 12)])
+def test_small_and_degenerate_shapes(gpu, n, d, k, r_cs, m):
+    _log("shape", n, d, k, r_cs, m)
+    A = W.dense_gaussian(n, d, n + d, dtype=torch.float32)
+    theta, st = api.lev_estimate(A.to(gpu), 5, r_cs, m, k, 1e-5, return_state=True)
+    o = _oracle_theta(A.numpy().astype(np.float64), 5, r_cs, m, k, 1e-5)
+    r = int(st.rank.item())
+    assert r == o.rank
+    np.testing.assert_array_equal(st.perm.cpu().numpy()[:r], o.perm[:r])
+    rel = _rel(theta.cpu().numpy().astype(np.float64), o.theta)
+    assert rel.max() < 1e-4
+
+
+def test_padded_rows_and_odd_width(gpu):
+    n, d, ld = 3000, 13, 16
+    A = W.dense_gaussian(n, d, 9, dtype=torch.float32)
+    buf = torch.full((n, ld), float("nan"), dtype=torch.float32, device=gpu)
+    buf[:, :d] = A.to(gpu)
+    theta = api.lev_estimate(buf[:, :d], 8, 256, 32, 16, 1e-5).cpu().numpy()
+    o = _oracle_theta(A.numpy().astype(np.float64), 8, 256, 32, 16, 1e-5)
+    assert np.all(np.isfinite(theta))
+    assert _rel(theta.astype(np.float64), o.theta).max() < 1e-4
+
+
+def test_estimate_is_deterministic(gpu):
+    A = W.low_rank_coherent(50000, 128, 64, 4).to(gpu)
+    t1 = api.lev_estimate(A, 9, 2048, 256, 32, 1e-5)
+    t2 = api.lev_estimate(A, 9, 2048, 256, 32, 1e-5)
+    assert torch.equal(t1, t2)
+
+
+def test_accuracy_against_exact_theta_is_reported(gpu):
+    """Reported, with the paper's loose guarantee: theta~ / theta concentrates
+    around the predicted sketch bias; sum theta~ ~ rank."""
+    n, d, r_cs, m, k = 65536, 64, 1024, 256, 32
+    A = W.dense_gaussian(n, d, 123, dtype=torch.float64)
+    theta = api.lev_estimate(A.to(gpu), 1, r_cs, m, k, 1e-10).cpu().numpy()
+    th, rho = L.exact_theta_svd(A.numpy(), 1e-10)
+    ratio = theta / th
+    bias = W.expected_bias(m, d, r_cs)
+    _log("median ratio", np.median(ratio), "pred bias", bias, "within 0.5", np.mean(np.abs(ratio - 1) < 0.5))
+    assert abs(np.median(ratio) / bias - 1) < 0.25
