@@ -239,10 +239,10 @@ def ls_hrn_approx(A, seed: int, r_cs: int, m: int, k_jl: int, zeta: float, rows=
         return Estimate(th, thr, rr.perm, 0, np.zeros((0, 0)), np.zeros((0, k_jl)), At, SA, rr.R, Gk)
     R11 = r_from_qr_of_sketch(At[:, K])
     Z = jl_orthogonalizer(R11, Gk[:k])
-    AK = A[:, K]
     if rows is None:
-        return Estimate(row_norms_sq(AK, Z), None, rr.perm, k, R11, Z, At, SA, rr.R, Gk)
-    return Estimate(None, row_norms_sq(AK, Z, rows=rows), rr.perm, k, R11, Z, At, SA, rr.R, Gk)
+        return Estimate(row_norms_sq(A[:, K], Z), None, rr.perm, k, R11, Z, At, SA, rr.R, Gk)
+    AK_rows = A[np.asarray(rows)][:, K]
+    return Estimate(None, row_norms_sq(AK_rows, Z), rr.perm, k, R11, Z, At, SA, rr.R, Gk)
 
 
 def theta_prime(A, K: np.ndarray, R11: np.ndarray, rows=None) -> np.ndarray:
