@@ -111,8 +111,8 @@ size_t lev_rank_workspace_size(int64_t m, int64_t d);
 size_t lev_state_size(int64_t d, int64_t m, int64_t k);
 
 /* Algorithm 3 (CountGaussSketch): A~ = G (S A), with S the r_cs x n
- * CountSketch (S[h(i), i] = s(i), Section 3.3) and G = G_m / sqrt(m) an
- * m x r_cs Gaussian embedding (Section 3.3, Gaussian embeddings).
+ * CountSketch (S[h(i), i] = s(i), Section 3.4) and G = G_m / sqrt(m) an
+ * m x r_cs Gaussian embedding (Section 3.4, Gaussian embeddings).
  *  At_out     -- m x d, FP64, row-major (ld = d).
  *  SA_out     -- optional (NULL to skip): r_cs x d FP64 copy of S A.
  * S A is accumulated in FP64 in a fixed order (deterministic bits).

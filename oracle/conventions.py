@@ -4,11 +4,11 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper fixes only the distributions:
 
-* CountSketch (Section 3.3, "CountSketch" paragraph, and the OSE theorem cited
+* CountSketch (Section 3.4, "CountSketch" paragraph, and the OSE theorem cited
   there): S in R^{r x n} has exactly one nonzero per column, at row h(i), with
   value s_i = +-1; h must be 2-wise independent and the signs 4-wise
   independent.
-* Gaussian embeddings (Section 3.3, "Gaussian embeddings"): S = G / sqrt(r)
+* Gaussian embeddings (Section 3.4, "Gaussian embeddings"): S = G / sqrt(r)
   with G i.i.d. N(0,1).  Algorithm 3 applies G (m x r) to SA; Algorithm 8
   applies a JL Gaussian Pi_2 to R^{-1}.
 
@@ -156,7 +156,7 @@ def _mulmod_p61_vec(x: np.ndarray, y: np.ndarray) -> np.ndarray:
 
 
 def countsketch_matrix_entries(rnd: SketchRandomness):
-    """(rows, cols, vals) of S: S[h(i), i] = s(i) (Section 3.3)."""
+    """(rows, cols, vals) of S: S[h(i), i] = s(i) (Section 3.4)."""
     return buckets(rnd), np.arange(rnd.n, dtype=np.int64), signs(rnd)
 
 
@@ -212,7 +212,7 @@ def gaussian_matrix(key, rows: int, cols: int, scale: float = 1.0) -> np.ndarray
 
 def gaussian_transform(rnd: SketchRandomness, m: int) -> np.ndarray:
     """G_m / sqrt(m), m x r_cs (the Gaussian of Algorithm 3, scaled as a
-    Gaussian embedding of Section 3.3)."""
+    Gaussian embedding of Section 3.4)."""
     return gaussian_matrix(rnd.key_m, m, rnd.r_cs, 1.0 / math.sqrt(m))
 
 

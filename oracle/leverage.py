@@ -21,7 +21,7 @@ Estimator LS-HRN-approx (Algorithm 10):
 Readings of points the paper leaves open (listed with their reasons in the
 design notes of the repository):
   * G is scaled by 1/sqrt(m) and Pi_2 by 1/sqrt(k) (Gaussian embeddings,
-    Section 3.3); the bare N(0,1) of Algorithm 3 would scale theta~ by 1/m.
+    Section 3.4); the bare N(0,1) of Algorithm 3 would scale theta~ by 1/m.
   * R is sign-normalised to a non-negative diagonal (the QR factor with a
     positive diagonal is unique; Z = R^{-1} Pi_2 depends on the signs).
   * Rank rule: k = #{ j : R_jj > zeta * R_00 } on the normalised QRCP
@@ -118,7 +118,7 @@ def countsketch_dense_S(rnd: conv.SketchRandomness) -> np.ndarray:
 
 
 def countsketch_apply(rnd: conv.SketchRandomness, A, chunk: int = 1 << 16) -> np.ndarray:
-    """S A (r_cs x d, FP64), with S the CountSketch of Section 3.3, applied
+    """S A (r_cs x d, FP64), with S the CountSketch of Section 3.4, applied
     as a sparse matrix over row chunks of A (dense ndarray or scipy sparse)."""
     h, cols, s = conv.countsketch_matrix_entries(rnd)
     S = sp.csr_matrix((s, (h, cols)), shape=(rnd.r_cs, rnd.n))

@@ -1,4 +1,4 @@
-// Gaussian matrices of the estimator (Section 3.3, Gaussian embeddings):
+// Gaussian matrices of the estimator (Section 3.4, Gaussian embeddings):
 // G_m / sqrt(m) of Algorithm 3 and the JL Gaussian Pi_2 / sqrt(k) of
 // Algorithm 8.  Element e (row-major) uses Philox4x32-10 counter floor(e/2);
 // the two uniforms of that counter feed Box-Muller, whose cosine branch is

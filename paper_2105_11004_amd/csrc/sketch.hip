@@ -1,5 +1,5 @@
 // Pass 1 of the estimator: the CountSketch product S A (Algorithm 3, first
-// factor; CountSketch as defined in Section 3.3).
+// factor; CountSketch as defined in Section 3.4).
 //
 // Design.  S has one +-1 per column, so (S A)[b, :] = sum_{h(i) = b} s(i) A[i, :].
 // Scatter-adding rows into S A with atomics would make the result depend on

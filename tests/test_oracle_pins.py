@@ -273,7 +273,7 @@ def test_jl_ratio_is_chi_square_over_k():
 
 
 def test_countsketch_is_an_ose_at_the_theorem_size():
-    """CountSketch OSE theorem (Section 3.3): r >= (d^2+d)/(delta (2 eps -
+    """CountSketch OSE theorem (Section 3.4): r >= (d^2+d)/(delta (2 eps -
     eps^2)^2) rows give sigma(S U) in [1-eps, 1+eps] with probability
     >= 1 - delta, for any fixed orthonormal U."""
     n, d, eps, delta = 3000, 3, 0.5, 1 / 3
@@ -288,7 +288,7 @@ def test_countsketch_is_an_ose_at_the_theorem_size():
 
 
 def test_gaussian_spectrum_lemma():
-    """Gaussian lemma of Section 3.3 (Davidson-Szarek): for G m x n Gaussian
+    """Gaussian lemma of Section 3.4 (Davidson-Szarek): for G m x n Gaussian
     and U n x k orthonormal, sigma_1(GU) < (1+a) sqrt(m) + sqrt(k) and
     sigma_k(GU) > (1-a) sqrt(m) - sqrt(k), each with probability
     >= 1 - exp(-a^2 m / 2)."""
