@@ -57,12 +57,18 @@ enum { LEV_DENSE_ROWMAJOR = 0, LEV_CSR = 1 };
 enum { LEV_F64 = 0, LEV_F32 = 1, LEV_BF16 = 2 };
 
 /* Arithmetic of the pass that forms A_{:,K} Z and its squared row norms
- * (Algorithm 8, last step).  NATIVE: F64 input -> FP64 MFMA, F32 input ->
- * FP32 MFMA, BF16 input -> BF16 MFMA with Z rounded to BF16.  FP32: FP32
- * MFMA whatever the storage type.  BF16: BF16 MFMA, Z in BF16 (BF16 input
- * only).  BF16X2: BF16 MFMA with Z split into a BF16 high and low part
- * (BF16 input only).  All MFMA forms accumulate in FP32 (FP64 for F64). */
-enum { LEV_AZ_NATIVE = 0, LEV_AZ_FP32 = 1, LEV_AZ_BF16 = 2, LEV_AZ_BF16X2 = 3 };
+ * (Algorithm 8, last step).
+ *  NATIVE: F64 input -> FP64 MFMA; F32 input -> BF16X3; BF16 input -> BF16.
+ *  FP32:   FP32 MFMA (16x16x4), any storage type but F64.
+ *  BF16:   BF16 MFMA with Z rounded to BF16 (BF16 input only).
+ *  BF16X2: BF16 MFMA, Z split into a BF16 high and low part (BF16 input only).
+ *  BF16X3: FP32 input only.  A and Z are each split exactly into three BF16
+ *          parts (24 significant bits, like FP32) and the six products above
+ *          2^-24 relative run on the BF16 matrix cores: FP32-level accuracy at
+ *          a fraction of the FP32 matrix-core time.
+ * MFMA accumulators are FP32 (FP64 for F64 input) and are flushed into FP64
+ * after every contraction chunk of 8-32 columns. */
+enum { LEV_AZ_NATIVE = 0, LEV_AZ_FP32 = 1, LEV_AZ_BF16 = 2, LEV_AZ_BF16X2 = 3, LEV_AZ_BF16X3 = 4 };
 
 /* The tall input A (n x d, n >> d).
  *  DENSE_ROWMAJOR: values points at n*ld elements of `dtype`; row_ptr and

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "LEV_OK", -1: "LEV_ERR_ARG", -2: "LEV_ERR_SHAPE", -3: "LEV_ER
                 -7: "LEV_ERR_NOT_SUPPORTED"}
 DENSE, CSR = 0, 1
 F64, F32, BF16 = 0, 1, 2
-AZ = {"native": 0, "fp32": 1, "bf16": 2, "bf16x2": 3}
+AZ = {"native": 0, "fp32": 1, "bf16": 2, "bf16x2": 3, "bf16x3": 4}
 WS_SKETCH, WS_ESTIMATE, WS_BACKWARD = 0, 2, 3
 
 # Every symbol the header declares (checked by the CPU tests).

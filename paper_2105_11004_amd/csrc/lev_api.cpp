@@ -119,7 +119,10 @@ size_t elem_size(int dtype) {
 // pass-2 variant from the storage type and the requested precision
 int az_variant(int dtype, int az) {
   if (dtype == LEV_F64) return az == LEV_AZ_NATIVE ? 0 : -1;
-  if (dtype == LEV_F32) return (az == LEV_AZ_NATIVE || az == LEV_AZ_FP32) ? 1 : -1;
+  if (dtype == LEV_F32) {
+    if (az == LEV_AZ_NATIVE || az == LEV_AZ_BF16X3) return 4;
+    return az == LEV_AZ_FP32 ? 1 : -1;
+  }
   if (dtype == LEV_BF16) {
     switch (az) {
       case LEV_AZ_NATIVE: return 2;

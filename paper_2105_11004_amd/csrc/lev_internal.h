@@ -89,10 +89,13 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
 // Prepares the operand of pass 2: Z_full (d x k, rows indexed by original
 // column, zero off K) converted to the pass-2 compute type and laid out for
 // the MFMA B-operand; see rownorm.hip for the layouts.
-// variant: 0 = FP64, 1 = FP32, 2 = BF16, 3 = BF16 hi/lo.
+// variant: 0 = FP64, 1 = FP32, 2 = BF16, 3 = BF16 hi/lo, 4 = BF16x3 (FP32 A).
+// pack_z_bytes: workspace needed (operand + an inverse permutation);
+// pack_z_operand_bytes: the operand alone (what pass 2 reads).
 hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
                          const double* Z64, void* Zpack, hipStream_t s);
 size_t pack_z_bytes(int variant, int64_t d, int64_t k);
+size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k);
 
 // Pass 2, dense: theta[i] = || A[i, :] Z_full ||^2.
 // variant as above; dtype = storage type of A (0 f64, 1 f32, 2 bf16).

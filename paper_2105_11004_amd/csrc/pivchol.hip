@@ -16,6 +16,10 @@
 //
 // Rank rule (the cutoff test of Section 7): pivoting stops at the first J
 // with R_JJ <= zeta * R_00 (or a non-positive Schur diagonal); r = J.
+//
+// Two implementations: d <= 256 runs entirely in one workgroup with the
+// Schur complement in registers (below); larger d uses panels of NB pivots
+// (one workgroup) and rank-NB Schur updates on the matrix cores.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -137,6 +141,229 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
   }
 }
 
+// ---------------------------------------------------------------------------
+// d <= 256: the whole factorisation in one workgroup with the symmetric
+// Schur complement resident in registers (right-looking pivoted Cholesky).
+//
+// The d x d matrix is tiled by 64 x 64 squares that cover its lower triangle
+// (10 for d = 256); wave w owns square (a, b) and lane l of that wave holds
+// row 64a + l, columns 64b .. 64b + 63 in 128 registers (at most 3 waves per
+// SIMD, so up to 170 registers per lane).  The waves with b = 0 own the
+// diagonal too: row i's Schur diagonal sits in a register of lane i % 64,
+// updated as d_i -= l_i^2.
+//
+// Per pivot step (two barriers): every wave reads the four per-band
+// candidates (value, index, sqrt, 1/sqrt) left by the previous step and takes
+// the best, p; the owners of column p (rows i >= p) and of row p (columns
+// j < p) publish l = S[:, p] / sqrt(S_pp) to LDS; after the barrier every lane
+// applies S -= l l^T to its entries, the diagonal owners update their d_i and
+// leave their band's argmax (DPP wave reduction) for the next step.  No global
+// memory is read inside the loop; the row R[J, :] = l is stored.
+constexpr int kSmallD = 256;
+constexpr int kBandR = 64, kBandC = 64;
+constexpr int kLvec = 256;  // >= 64 * ceil(256 / 64)
+
+__host__ __device__ inline int small_bands(int a, int d) {
+  const int by_tri = (kBandR * a + kBandR - 1) / kBandC + 1;
+  const int by_d = (d + kBandC - 1) / kBandC;
+  return by_tri < by_d ? by_tri : by_d;
+}
+
+__host__ __device__ inline int small_rects(int d) {
+  int cnt = 0;
+  for (int a = 0; a * kBandR < d; ++a) cnt += small_bands(a, d);
+  return cnt;
+}
+
+__device__ inline void small_rect(int w, int d, int& a_out, int& b_out) {
+  int idx = 0;
+  for (int a = 0; a * kBandR < d; ++a) {
+    const int nb = small_bands(a, d);
+    if (w < idx + nb) {
+      a_out = a;
+      b_out = w - idx;
+      return;
+    }
+    idx += nb;
+  }
+  a_out = 0;
+  b_out = 0;
+}
+
+typedef double v16d __attribute__((ext_vector_type(16)));
+
+// One DPP step of a wave max over doubles (identity -inf).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_max_step(double v) {
+  const int olo = 0, ohi = (int)0xFFF00000;  // -inf
+  const int slo = __builtin_amdgcn_update_dpp(olo, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int shi = __builtin_amdgcn_update_dpp(ohi, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return fmax(v, __hiloint2double(shi, slo));
+}
+
+// Max over the 64 lanes (row shifts within 16-lane rows, then row broadcasts;
+// lane 63 ends with the total), returned to every lane.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = dpp_max_step<0x111, 0xF>(v);  // row_shr:1
+  v = dpp_max_step<0x112, 0xF>(v);  // row_shr:2
+  v = dpp_max_step<0x114, 0xF>(v);  // row_shr:4
+  v = dpp_max_step<0x118, 0xF>(v);  // row_shr:8
+  v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15
+  v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// waits for every outstanding global store to be acknowledged; inside the
+// pivot loop the waves exchange data through LDS alone, and the R rows they
+// store to global memory are not read back before the kernel ends.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+struct Cand {
+  double v, rpp, inv;
+  int idx;
+};
+
+__global__ __launch_bounds__(640) void pivchol_small_kernel(const double* __restrict__ B, int d, double zeta,
+                                                            PivCholState st, int64_t* __restrict__ rank_out) {
+  __shared__ __align__(16) double lvec[kLvec];
+  __shared__ Cand cand[4];
+
+  const int lane = threadIdx.x & 63;
+  // wave-uniform values kept scalar (the compiler cannot infer it)
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int a, b;
+  small_rect(wave, d, a, b);
+  a = __builtin_amdgcn_readfirstlane(a);
+  b = __builtin_amdgcn_readfirstlane(b);
+  const int i = kBandR * a + lane;  // my row
+  const int j0 = kBandC * b;        // my first column
+  const bool row_ok = i < d;
+  const int nbands = (d + kBandR - 1) / kBandR;
+
+  v16d s0, s1, s2, s3;
+  {
+    // unconditional loads from clamped addresses, then a select: no
+    // per-element branches
+    // entry (i, j) is read from the lower triangle, B[max(i,j)][min(i,j)], so
+    // S is bitwise symmetric from the start and stays so (the update
+    // fma(-l_i, l_j, s) is symmetric in i and j)
+    const int ic = row_ok ? i : 0;
+#define LEV_LOAD16(V, OFF)                                                  \
+  _Pragma("unroll") for (int e = 0; e < 16; ++e) {                          \
+    const int j = j0 + (OFF) + e;                                           \
+    const int jc = j < d ? j : 0;                                           \
+    const int hi = ic > jc ? ic : jc, lo = ic > jc ? jc : ic;               \
+    const double x = B[(int64_t)hi * d + lo];                               \
+    V[e] = (row_ok && j < d) ? x : 0.0;                                     \
+  }                                                                         \
+  __builtin_amdgcn_sched_barrier(0);
+    LEV_LOAD16(s0, 0) LEV_LOAD16(s1, 16) LEV_LOAD16(s2, 32) LEV_LOAD16(s3, 48)
+#undef LEV_LOAD16
+  }
+  for (int q = threadIdx.x; q < kLvec; q += blockDim.x) lvec[q] = 0.0;
+
+  // diagonal owners: d_i in a register; leave the band's candidate
+  double dg = -INFINITY;
+  auto publish_candidate = [&]() {
+    const double m = wave_max_f64(dg);
+    const unsigned long long hit = __ballot(dg == m && dg != -INFINITY);
+    if (lane == 0) {
+      Cand cd;
+      cd.v = m;
+      cd.idx = hit ? kBandR * a + __builtin_ctzll(hit) : 0x7fffffff;
+      // 1/sqrt(m): hardware estimate + two Newton steps (~1 ulp); sqrt = m/sqrt
+      double y = __builtin_amdgcn_rsq(m);
+      y = y * fma(-0.5 * m * y, y, 1.5);
+      y = y * fma(-0.5 * m * y, y, 1.5);
+      cd.inv = m > 0.0 ? y : 0.0;
+      cd.rpp = m > 0.0 ? m * y : 0.0;
+      cand[a] = cd;
+    }
+  };
+  if (b == 0) {
+    if (row_ok) dg = B[(int64_t)i * d + i];
+    publish_candidate();
+  }
+  __syncthreads();
+
+  double r00 = 0.0;
+  int J = 0;
+  for (; J < d; ++J) {
+    Cand best = cand[0];
+    for (int t = 1; t < nbands; ++t) {
+      const Cand c2 = cand[t];
+      if (c2.v > best.v || (c2.v == best.v && c2.idx < best.idx)) best = c2;
+    }
+    const double pv = best.v;
+    const int p = __builtin_amdgcn_readfirstlane(best.idx);
+    if (J == 0) r00 = best.rpp;
+    if (!(pv > 0.0) || !(best.rpp > zeta * r00)) break;  // uniform
+    const double rpp = best.rpp, inv = best.inv;
+    // row p: the lane holding row p in each rectangle with b <= b_p writes
+    // its 64 entries (columns >= p duplicate the column-p owners' writes
+    // below with identical bits, S being symmetric)
+    if (a == p / kBandR && lane == (p & (kBandR - 1)) && b <= p / kBandC) {
+      double2* dst = reinterpret_cast<double2*>(&lvec[j0]);
+#define LEV_PUT16(V, OFF) \
+  _Pragma("unroll") for (int e = 0; e < 16; e += 2) dst[((OFF) + e) / 2] = make_double2(V[e] * inv, V[e + 1] * inv);
+      LEV_PUT16(s0, 0) LEV_PUT16(s1, 16) LEV_PUT16(s2, 32) LEV_PUT16(s3, 48)
+#undef LEV_PUT16
+    }
+    // column p, rows i >= p; the entry is picked with a uniform-index
+    // register extract
+    if (b == p / kBandC) {
+      const int cp = __builtin_amdgcn_readfirstlane(p - j0);
+      const int e = cp & 15, blk = cp >> 4;
+      const double v0 = s0[e], v1 = s1[e], v2 = s2[e], v3 = s3[e];
+      const double v = blk == 0 ? v0 : (blk == 1 ? v1 : (blk == 2 ? v2 : v3));
+      if (row_ok && i >= p) lvec[i] = v * inv;
+    }
+    lds_barrier();
+    const double li = row_ok ? lvec[i] : 0.0;
+    // 8 groups of 8 columns; the LDS reads of group g + 1 are issued before
+    // the FMAs of group g, and each FMA result is pinned in place so the
+    // compiler neither sinks the FMAs nor hoists every read of the step
+    double lj[2][8];
+#define LEV_READ8(buf, OFF) \
+  _Pragma("unroll") for (int e = 0; e < 8; ++e) lj[buf][e] = lvec[j0 + (OFF) + e];
+#define LEV_FMA8(buf, V, E0)                                               \
+  _Pragma("unroll") for (int e = 0; e < 8; ++e) {                          \
+    double t = fma(-li, lj[buf][e], V[(E0) + e]);                          \
+    asm volatile("" : "+v"(t));                                            \
+    V[(E0) + e] = t;                                                       \
+  }
+    LEV_READ8(0, 0)
+    LEV_READ8(1, 8) LEV_FMA8(0, s0, 0)
+    LEV_READ8(0, 16) LEV_FMA8(1, s0, 8)
+    LEV_READ8(1, 24) LEV_FMA8(0, s1, 0)
+    LEV_READ8(0, 32) LEV_FMA8(1, s1, 8)
+    LEV_READ8(1, 40) LEV_FMA8(0, s2, 0)
+    LEV_READ8(0, 48) LEV_FMA8(1, s2, 8)
+    LEV_READ8(1, 56) LEV_FMA8(0, s3, 0)
+    LEV_FMA8(1, s3, 8)
+#undef LEV_READ8
+#undef LEV_FMA8
+    if (b == 0) {
+      dg = (i == p) ? -INFINITY : fma(-li, li, dg);
+      if (row_ok) st.Rrows[(int64_t)J * d + i] = li;
+      publish_candidate();
+    }
+    if (threadIdx.x == 0) st.piv[J] = p;
+    lds_barrier();
+  }
+  if (threadIdx.x == 0) {
+    *st.r00 = r00;
+    st.flags[0] = 1;
+    st.flags[1] = J;
+    *rank_out = J;
+  }
+}
+
 // perm: pivots, then the unselected columns ascending.  R_out: pivoted,
 // upper triangular, rows >= r zero.  One workgroup of kMaxD threads for the
 // permutation, then the R gather.
@@ -182,6 +409,11 @@ hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState&
                           double* gemm_partial, hipStream_t s) {
   (void)gemm_partial;
   if (d <= 0 || d > kMaxD) return hipErrorInvalidValue;
+  if (d <= kSmallD) {
+    const int waves = small_rects((int)d);
+    pivchol_small_kernel<<<1, 64 * waves, 0, s>>>(B, (int)d, zeta, st, rank_out);
+    return hipGetLastError();
+  }
   const int threads = (int)(((d + 63) / 64) * 64);
   for (int64_t J0 = 0; J0 < d; J0 += NB) {
     pivchol_panel_kernel<<<1, threads, 0, s>>>(B, d, zeta, J0, st, rank_out);

@@ -15,8 +15,13 @@
 // are summed per lane and across the 16 lanes of a row with shuffles.
 //
 // Variants (LEV_AZ_*): FP64 (16x16x4f64, EL 2), FP32 (16x16x4f32, EL 4; A
-// may be stored as FP32 or BF16), BF16 (16x16x32bf16, EL 8, Z in BF16) and
-// BF16 hi/lo (two BF16 products, Z = Z_hi + Z_lo).
+// may be stored as FP32 or BF16), BF16 (16x16x32bf16, EL 8, Z in BF16),
+// BF16 hi/lo (two BF16 products, Z = Z_hi + Z_lo) and BF16x3 for FP32 A:
+// A and Z are each split exactly into three BF16 parts (hi + mid + lo, 24
+// significant bits, like FP32) and the six products above 2^-24 relative
+// (hh, hm, mh, hl, mm, lh) run on the BF16 matrix cores, which on gfx950
+// deliver 16x the FP32 matrix rate: the FP32-accurate pass becomes bound by
+// HBM instead of by FP32 MFMA throughput.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -31,14 +36,13 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // ---- per-variant traits ----------------------------------------------------
-// Load one lane's A fragment for chunk t; returns it in the MFMA input type.
 template <int VAR, typename TA>
 struct Frag;
 
 // FP64: two doubles per lane, 16-byte load.
 template <>
 struct Frag<0, double> {
-  static constexpr int EL = 2, CW = 8;
+  static constexpr int EL = 2, CW = 8, NZ = 1;
   using T = uint4;
   __device__ static T load(const double* row, int64_t col, int64_t d, bool ok) {
     if (!ok || col >= d) return make_uint4(0u, 0u, 0u, 0u);
@@ -51,7 +55,7 @@ struct Frag<0, double> {
 // FP32 from FP32 storage: four floats, 16-byte load.
 template <>
 struct Frag<1, float> {
-  static constexpr int EL = 4, CW = 16;
+  static constexpr int EL = 4, CW = 16, NZ = 1;
   using T = uint4;
   __device__ static T load(const float* row, int64_t col, int64_t d, bool ok) {
     if (!ok || col >= d) return make_uint4(0u, 0u, 0u, 0u);
@@ -68,7 +72,7 @@ struct Frag<1, float> {
 // FP32 from BF16 storage: four bf16 (8-byte load), widened exactly.
 template <>
 struct Frag<1, __hip_bfloat16> {
-  static constexpr int EL = 4, CW = 16;
+  static constexpr int EL = 4, CW = 16, NZ = 1;
   using T = uint4;
   __device__ static T load(const __hip_bfloat16* row, int64_t col, int64_t d, bool ok) {
     if (!ok || col >= d) return make_uint4(0u, 0u, 0u, 0u);
@@ -83,28 +87,60 @@ struct Frag<1, __hip_bfloat16> {
   }
 };
 
-// BF16: eight bf16, 16-byte load.
-template <int VAR>
-struct FragBf16 {
-  static constexpr int EL = 8, CW = 32;
+// BF16 storage: eight bf16, 16-byte load.
+__device__ __forceinline__ uint4 load_bf16x8(const __hip_bfloat16* row, int64_t col, int64_t d, bool ok) {
+  if (!ok || col >= d) return make_uint4(0u, 0u, 0u, 0u);
+  uint4 v = *reinterpret_cast<const uint4*>(row + col);
+  if (col + 7 >= d) {
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      if (col + e >= d) w[e >> 1] &= (e & 1) ? 0x0000FFFFu : 0xFFFF0000u;
+    v = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  return v;
+}
+template <>
+struct Frag<2, __hip_bfloat16> {
+  static constexpr int EL = 8, CW = 32, NZ = 1;
   using T = uint4;
   __device__ static T load(const __hip_bfloat16* row, int64_t col, int64_t d, bool ok) {
-    if (!ok || col >= d) return make_uint4(0u, 0u, 0u, 0u);
-    uint4 v = *reinterpret_cast<const uint4*>(row + col);
-    if (col + 7 >= d) {
-      uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-      for (int e = 0; e < 8; ++e)
-        if (col + e >= d) w[e >> 1] &= (e & 1) ? 0x0000FFFFu : 0xFFFF0000u;
-      v = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-    return v;
+    return load_bf16x8(row, col, d, ok);
   }
 };
 template <>
-struct Frag<2, __hip_bfloat16> : FragBf16<2> {};
+struct Frag<3, __hip_bfloat16> {
+  static constexpr int EL = 8, CW = 32, NZ = 2;
+  using T = uint4;
+  __device__ static T load(const __hip_bfloat16* row, int64_t col, int64_t d, bool ok) {
+    return load_bf16x8(row, col, d, ok);
+  }
+};
+
+// BF16x3 from FP32 storage: eight floats (two 16-byte loads).
+struct F8 {
+  uint4 lo, hi;
+};
 template <>
-struct Frag<3, __hip_bfloat16> : FragBf16<3> {};
+struct Frag<4, float> {
+  static constexpr int EL = 8, CW = 32, NZ = 3;
+  using T = F8;
+  __device__ static T load(const float* row, int64_t col, int64_t d, bool ok) {
+    F8 f{make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u)};
+    if (!ok || col >= d) return f;
+    f.lo = *reinterpret_cast<const uint4*>(row + col);
+    if (col + 4 < d) f.hi = *reinterpret_cast<const uint4*>(row + col + 4);
+    if (col + 7 >= d) {
+      uint32_t w[8] = {f.lo.x, f.lo.y, f.lo.z, f.lo.w, f.hi.x, f.hi.y, f.hi.z, f.hi.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e)
+        if (col + e >= d) w[e] = 0u;
+      f.lo = make_uint4(w[0], w[1], w[2], w[3]);
+      f.hi = make_uint4(w[4], w[5], w[6], w[7]);
+    }
+    return f;
+  }
+};
 
 template <int VAR>
 struct Acc {
@@ -115,36 +151,53 @@ struct Acc<0> {
   using T = v4d;
 };
 
-// acc += A_frag * Z_frag over one chunk of the contraction.
-template <int VAR>
-__device__ __forceinline__ void mma(typename Acc<VAR>::T& acc, const uint4& a, const uint4& b,
-                                    const uint4& b_lo);
+typedef float v8f __attribute__((ext_vector_type(8)));
+
+// x = h + m + l exactly (for normal numbers): each part is the
+// round-to-nearest BF16 of what the previous parts left over.
+__device__ __forceinline__ void split3(const F8& f, v8bf& h, v8bf& m, v8bf& l) {
+  const v8f x = {__uint_as_float(f.lo.x), __uint_as_float(f.lo.y), __uint_as_float(f.lo.z),
+                 __uint_as_float(f.lo.w), __uint_as_float(f.hi.x), __uint_as_float(f.hi.y),
+                 __uint_as_float(f.hi.z), __uint_as_float(f.hi.w)};
+  h = __builtin_convertvector(x, v8bf);
+  const v8f r1 = x - __builtin_convertvector(h, v8f);
+  m = __builtin_convertvector(r1, v8bf);
+  const v8f r2 = r1 - __builtin_convertvector(m, v8f);
+  l = __builtin_convertvector(r2, v8bf);
+}
+
+__device__ __forceinline__ v4f mfma_bf16(const v8bf& a, const v8bf& b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v8bf as_bf(const uint4& u) { return __builtin_bit_cast(v8bf, u); }
+
+// acc += A_frag * Z_frag over one chunk of the contraction; z[p] is the
+// p-th part of Z's fragment (NZ parts).
+template <int VAR, typename TF>
+__device__ __forceinline__ void mma(typename Acc<VAR>::T& acc, const TF& a, const uint4* z);
 
 template <>
-__device__ __forceinline__ void mma<0>(v4d& acc, const uint4& a, const uint4& b, const uint4&) {
+__device__ __forceinline__ void mma<0, uint4>(v4d& acc, const uint4& a, const uint4* z) {
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double((int)a.y, (int)a.x),
-                                             __hiloint2double((int)b.y, (int)b.x), acc, 0, 0, 0);
+                                             __hiloint2double((int)z[0].y, (int)z[0].x), acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double((int)a.w, (int)a.z),
-                                             __hiloint2double((int)b.w, (int)b.z), acc, 0, 0, 0);
+                                             __hiloint2double((int)z[0].w, (int)z[0].z), acc, 0, 0, 0);
 }
 template <>
-__device__ __forceinline__ void mma<1>(v4f& acc, const uint4& a, const uint4& b, const uint4&) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), acc, 0, 0, 0);
+__device__ __forceinline__ void mma<1, uint4>(v4f& acc, const uint4& a, const uint4* z) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(z[0].x), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(z[0].y), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(z[0].z), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(z[0].w), acc, 0, 0, 0);
 }
 template <>
-__device__ __forceinline__ void mma<2>(v4f& acc, const uint4& a, const uint4& b, const uint4&) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b),
-                                                acc, 0, 0, 0);
+__device__ __forceinline__ void mma<2, uint4>(v4f& acc, const uint4& a, const uint4* z) {
+  acc = mfma_bf16(as_bf(a), as_bf(z[0]), acc);
 }
 template <>
-__device__ __forceinline__ void mma<3>(v4f& acc, const uint4& a, const uint4& b, const uint4& b_lo) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b),
-                                                acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
-                                                __builtin_bit_cast(v8bf, b_lo), acc, 0, 0, 0);
+__device__ __forceinline__ void mma<3, uint4>(v4f& acc, const uint4& a, const uint4* z) {
+  acc = mfma_bf16(as_bf(a), as_bf(z[0]), acc);
+  acc = mfma_bf16(as_bf(a), as_bf(z[1]), acc);
 }
 
 template <typename T>
@@ -155,16 +208,15 @@ __device__ __forceinline__ T sum16(T x) {
   return x;
 }
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kBatch = 8;  // chunks loaded per batch (loads in flight per lane)
 
-// Zpack: ((t*CB + cb)*64 + l) 16-byte vectors (BF16 hi/lo: lo part follows
-// the hi part, `lo_off` vectors later).
+// Zpack: part p of vector (t, cb, lane) at index p * part_vecs + (t*CB + cb)*64 + lane.
 template <int VAR, typename TA, int CB, bool ZLDS>
 __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __restrict__ A, int64_t n,
                                                                  int64_t d, int64_t ld, int64_t nt,
                                                                  const uint4* __restrict__ Zg,
-                                                                 int64_t zvecs, int64_t lo_off,
+                                                                 int64_t zvecs, int64_t part_vecs,
                                                                  void* __restrict__ theta) {
   using F = Frag<VAR, TA>;
   using AccT = typename Acc<VAR>::T;
@@ -205,13 +257,31 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
       for (int u = 0; u < kBatch; ++u) {
         const int64_t t = t0 + u;
         if (t < nt) {
+          if constexpr (VAR == 4) {
+            v8bf ah, am, al;
+            split3(a[u], ah, am, al);
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            const int64_t zi = (t * CB + cb) * 64 + lane;
-            const uint4 b = Z[zi];
-            uint4 blo = make_uint4(0u, 0u, 0u, 0u);
-            if constexpr (VAR == 3) blo = Z[zi + lo_off];
-            mma<VAR>(acc[cb], a[u], b, blo);
+            for (int cb = 0; cb < CB; ++cb) {
+              const int64_t zi = (t * CB + cb) * 64 + lane;
+              const v8bf zh = as_bf(Z[zi]), zm = as_bf(Z[zi + part_vecs]), zl = as_bf(Z[zi + 2 * part_vecs]);
+              v4f c = acc[cb];
+              c = mfma_bf16(al, zh, c);  // smallest terms first
+              c = mfma_bf16(am, zm, c);
+              c = mfma_bf16(ah, zl, c);
+              c = mfma_bf16(am, zh, c);
+              c = mfma_bf16(ah, zm, c);
+              c = mfma_bf16(ah, zh, c);
+              acc[cb] = c;
+            }
+          } else {
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+              const int64_t zi = (t * CB + cb) * 64 + lane;
+              uint4 zp[F::NZ];
+#pragma unroll
+              for (int p = 0; p < F::NZ; ++p) zp[p] = Z[zi + p * part_vecs];
+              mma<VAR, typename F::T>(acc[cb], a[u], zp);
+            }
           }
           if constexpr (VAR != 0) {
 #pragma unroll
@@ -253,24 +323,32 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
   }
 }
 
+constexpr size_t kMaxLdsZ = 144 * 1024;
+
 template <int VAR, typename TA, int CB>
 hipError_t launch_cb(const void* A, int64_t n, int64_t d, int64_t ld, int64_t nt, const void* Zpack,
                      size_t zbytes, void* theta, hipStream_t s) {
+  using F = Frag<VAR, TA>;
   const int64_t zvecs = (int64_t)(zbytes / 16);
-  const int64_t lo_off = (VAR == 3) ? zvecs / 2 : 0;
+  const int64_t part_vecs = zvecs / F::NZ;
   const int64_t ntiles = (n + 15) / 16;
-  int64_t blocks = (ntiles + 3) / 4;
-  const int64_t max_blocks = 256 * 8;
+  int64_t blocks = (ntiles + (kThreads / 64) - 1) / (kThreads / 64);
+  const int64_t max_blocks = 256 * 4;
   if (blocks > max_blocks) blocks = max_blocks;
   if (blocks < 1) blocks = 1;
   const TA* a = static_cast<const TA*>(A);
   const uint4* z = static_cast<const uint4*>(Zpack);
-  if (zbytes <= 64 * 1024) {
-    rownorm_dense_kernel<VAR, TA, CB, true><<<(unsigned)blocks, kThreads, zbytes, s>>>(
-        a, n, d, ld, nt, z, zvecs, lo_off, theta);
+  if (zbytes <= kMaxLdsZ) {
+    auto kern = rownorm_dense_kernel<VAR, TA, CB, true>;
+    if (zbytes > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)zbytes);
+      if (e != hipSuccess) return e;
+    }
+    kern<<<(unsigned)blocks, kThreads, zbytes, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta);
   } else {
     rownorm_dense_kernel<VAR, TA, CB, false><<<(unsigned)blocks, kThreads, 0, s>>>(a, n, d, ld, nt, z, zvecs,
-                                                                                   lo_off, theta);
+                                                                                   part_vecs, theta);
   }
   return hipGetLastError();
 }
@@ -280,7 +358,7 @@ hipError_t launch_var(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k
                       void* theta, hipStream_t s) {
   using F = Frag<VAR, TA>;
   const int64_t nt = (d + F::CW - 1) / F::CW;
-  const size_t zbytes = pack_z_bytes(VAR, d, k);
+  const size_t zbytes = pack_z_operand_bytes(VAR, d, k);
   switch ((k + 15) / 16) {
     case 1: return launch_cb<VAR, TA, 1>(A, n, d, ld, nt, Zpack, zbytes, theta, s);
     case 2: return launch_cb<VAR, TA, 2>(A, n, d, ld, nt, Zpack, zbytes, theta, s);
@@ -302,6 +380,7 @@ hipError_t launch_rownorm_dense(int variant, int dtype, const void* A, int64_t n
   if (variant == 1 && dtype == 2) return launch_var<1, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, s);
   if (variant == 2 && dtype == 2) return launch_var<2, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, s);
   if (variant == 3 && dtype == 2) return launch_var<3, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, s);
+  if (variant == 4 && dtype == 1) return launch_var<4, float>(A, n, d, ld, k, Zpack, theta, s);
   return hipErrorInvalidValue;
 }
 

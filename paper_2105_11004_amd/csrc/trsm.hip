@@ -43,15 +43,90 @@ __global__ __launch_bounds__(64) void trsm_z_kernel(int64_t d, int64_t k, const 
   }
 }
 
+// r <= 256, k <= 64: one workgroup of 16 waves.  Lane c of wave q holds
+// column c of the right-hand side for rows t = 16 s + q (s < 16) in
+// registers.  Column-oriented back substitution: at step j the owner of row
+// j (wave j % 16) finishes z_j = g'_j / R_jj and publishes it through LDS;
+// after one barrier every lane applies g'_t -= R[t][j] z_j to its rows
+// t < j.  R11 is staged through LDS 16 columns at a time (double-buffered),
+// so the loop reads no global memory.
+constexpr int kTrsmR = 256;
+typedef double v16d __attribute__((ext_vector_type(16)));
+constexpr int kTrsmCols = 16;
+
+__global__ __launch_bounds__(1024) void trsm_small_kernel(int64_t d, int64_t k, const double* __restrict__ R,
+                                                          const int64_t* __restrict__ rank,
+                                                          const double* __restrict__ Gk,
+                                                          double* __restrict__ Z64) {
+  __shared__ double rblk[2][kTrsmR][kTrsmCols];  // 64 KB: R[0:r, 16-column block]
+  __shared__ double zrow[2][64];
+  const int c = threadIdx.x & 63;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = (int)*rank;
+  const bool col_ok = c < k;
+
+  v16d g;  // SSA vector: uniform-index access becomes an indexed register move
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int t = 16 * s + q;
+    g[s] = (col_ok && t < r) ? Gk[(int64_t)t * k + c] : 0.0;
+  }
+  // rows >= r of Z are zero
+  for (int64_t t = r + q; t < d; t += 16)
+    if (col_ok) Z64[t * k + c] = 0.0;
+  if (r == 0) return;
+
+  // stage the 16-column block holding column j (blocks descend)
+  auto stage = [&](int blk, int buf) {
+    for (int e = threadIdx.x; e < r * kTrsmCols; e += blockDim.x) {
+      const int t = e / kTrsmCols, cc = e % kTrsmCols;
+      const int col = blk * kTrsmCols + cc;
+      rblk[buf][t][cc] = (col < r) ? R[(int64_t)t * d + col] : 0.0;
+    }
+  };
+  int blk = (r - 1) / kTrsmCols;
+  stage(blk, blk & 1);
+  __syncthreads();
+  for (int j = r - 1; j >= 0; --j) {
+    const int jb = j / kTrsmCols;
+    if (jb != blk) {  // uniform: next block was prefetched at the previous step
+      blk = jb;
+      __syncthreads();
+    }
+    if (j % kTrsmCols == 0 && jb > 0) stage(jb - 1, (jb - 1) & 1);  // prefetch next block
+    const int buf = jb & 1, cj = j % kTrsmCols;
+    if (q == (j & 15)) {
+      const int sj = __builtin_amdgcn_readfirstlane(j >> 4);
+      const double zj = g[sj] / rblk[buf][j][cj];
+      g[sj] = zj;
+      zrow[j & 1][c] = zj;
+    }
+    __syncthreads();
+    const double zj = zrow[j & 1][c];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int t = 16 * s + q;
+      if (t < j) g[s] = fma(-rblk[buf][t][cj], zj, g[s]);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int t = 16 * s + q;
+    if (col_ok && t < r) Z64[(int64_t)t * k + c] = g[s];
+  }
+}
+
 // Pass-2 operand layouts (see rownorm.hip).  For chunk t of the contraction
 // (CW columns), column tile cb (16 output columns), lane l and element e:
 //   value = Z_full[t*CW + EL*(l/16) + e][16*cb + (l%16)]
 // stored at ((t*CB + cb)*64 + l)*EL + e, CB = ceil(k/16).
-//   FP64: EL = 2, CW = 8.   FP32: EL = 4, CW = 16.   BF16: EL = 8, CW = 32.
-template <typename OUT, int EL>
-__global__ void pack_z_kernel(int64_t d, int64_t k, const int32_t* __restrict__ perm,
-                              const int64_t* __restrict__ rank, const double* __restrict__ Z64,
-                              OUT* __restrict__ out, OUT* __restrict__ out_lo, int64_t nt, int64_t cbn) {
+//   FP64: EL = 2, CW = 8.   FP32: EL = 4, CW = 16.   BF16 forms: EL = 8, CW = 32.
+// BF16 forms store NP parts one after the other: part 0 = RNE(v), part p =
+// RNE(v - parts 0..p-1) (NP = 1 BF16, 2 BF16 hi/lo, 3 BF16x3).
+template <typename OUT, int EL, int NP>
+__global__ void pack_z_kernel(int64_t d, int64_t k, const int32_t* __restrict__ inv_perm,
+                              const double* __restrict__ Z64, OUT* __restrict__ out, int64_t nt,
+                              int64_t cbn) {
   constexpr int CW = 4 * EL;
   const int64_t total = nt * cbn * 64 * EL;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -62,76 +137,94 @@ __global__ void pack_z_kernel(int64_t d, int64_t k, const int32_t* __restrict__ 
   const int64_t t = idx / (EL * 64 * cbn);
   const int64_t row = t * CW + EL * (l / 16) + e;  // original column id of A
   const int64_t col = 16 * cb + (l % 16);
-  const int64_t r = *rank;
   double v = 0.0;
   if (row < d && col < k) {
-    // position of column `row` among the pivots (linear scan; d <= 1024)
-    for (int64_t j = 0; j < r; ++j) {
-      if (perm[j] == row) {
-        v = Z64[j * k + col];
-        break;
-      }
-    }
+    const int32_t j = inv_perm[row];  // pivot position, or -1 when not selected
+    if (j >= 0) v = Z64[(int64_t)j * k + col];
   }
   if constexpr (sizeof(OUT) == 2) {
-    const __hip_bfloat16 hi = __double2bfloat16(v);
-    out[idx] = hi;
-    if (out_lo != nullptr) out_lo[idx] = __double2bfloat16(v - (double)__bfloat162float(hi));
+    double rest = v;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const __hip_bfloat16 part = __double2bfloat16(rest);
+      out[p * total + idx] = part;
+      rest -= (double)__bfloat162float(part);
+    }
   } else {
     out[idx] = (OUT)v;
   }
 }
 
+// inv_perm[c] = pivot position of column c (-1 when c is not among the r
+// selected columns).
+__global__ void inverse_perm_kernel(int64_t d, const int32_t* __restrict__ perm, const int64_t* __restrict__ rank,
+                                    int32_t* __restrict__ inv_perm) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d) return;
+  const int64_t r = *rank;
+  inv_perm[perm[j]] = j < r ? (int32_t)j : -1;
+}
+
 constexpr int64_t chunk_cols(int variant) { return variant == 0 ? 8 : (variant == 1 ? 16 : 32); }
+constexpr int parts(int variant) { return variant == 3 ? 2 : (variant == 4 ? 3 : 1); }
 
 }  // namespace
 
 hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, const double* Gk,
                          double* Z64, hipStream_t s) {
-  trsm_z_kernel<<<(unsigned)k, 64, (size_t)d * sizeof(double), s>>>(d, k, R, rank, Gk, Z64);
+  if (d <= kTrsmR && k <= 64) {
+    trsm_small_kernel<<<1, 1024, 0, s>>>(d, k, R, rank, Gk, Z64);
+  } else {
+    trsm_z_kernel<<<(unsigned)k, 64, (size_t)d * sizeof(double), s>>>(d, k, R, rank, Gk, Z64);
+  }
   return hipGetLastError();
 }
 
-size_t pack_z_bytes(int variant, int64_t d, int64_t k) {
+size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k) {
+  if (variant < 0 || variant > 4) return 0;
   const int64_t cw = chunk_cols(variant);
   const int64_t nt = (d + cw - 1) / cw;
   const int64_t cbn = (k + 15) / 16;
   const int64_t elems = nt * cbn * 64 * (cw / 4);
-  switch (variant) {
-    case 0: return (size_t)elems * 8;
-    case 1: return (size_t)elems * 4;
-    case 2: return (size_t)elems * 2;
-    case 3: return (size_t)elems * 4;  // hi then lo
-    default: return 0;
-  }
+  const size_t esize = variant == 0 ? 8 : (variant == 1 ? 4 : 2);
+  return (size_t)elems * esize * (size_t)parts(variant);
 }
 
+size_t pack_z_bytes(int variant, int64_t d, int64_t k) {
+  if (variant < 0 || variant > 4) return 0;
+  return pack_z_operand_bytes(variant, d, k) + (size_t)d * sizeof(int32_t);
+}
+
+// Zpack layout: the packed operand (as above) followed by inv_perm[d].
 hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
                          const double* Z64, void* Zpack, hipStream_t s) {
   const int64_t cw = chunk_cols(variant);
   const int64_t nt = (d + cw - 1) / cw;
   const int64_t cbn = (k + 15) / 16;
   const int64_t total = nt * cbn * 64 * (cw / 4);
+  const size_t esize = variant == 0 ? 8 : (variant == 1 ? 4 : 2);
+  int32_t* inv = reinterpret_cast<int32_t*>(static_cast<char*>(Zpack) + (size_t)total * esize * parts(variant));
+  inverse_perm_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(d, perm, rank, inv);
   const unsigned blocks = (unsigned)((total + 255) / 256);
   switch (variant) {
     case 0:
-      pack_z_kernel<double, 2><<<blocks, 256, 0, s>>>(d, k, perm, rank, Z64, static_cast<double*>(Zpack),
-                                                      nullptr, nt, cbn);
+      pack_z_kernel<double, 2, 1><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<double*>(Zpack), nt, cbn);
       break;
     case 1:
-      pack_z_kernel<float, 4><<<blocks, 256, 0, s>>>(d, k, perm, rank, Z64, static_cast<float*>(Zpack),
-                                                     nullptr, nt, cbn);
+      pack_z_kernel<float, 4, 1><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<float*>(Zpack), nt, cbn);
       break;
     case 2:
-      pack_z_kernel<__hip_bfloat16, 8><<<blocks, 256, 0, s>>>(
-          d, k, perm, rank, Z64, static_cast<__hip_bfloat16*>(Zpack), nullptr, nt, cbn);
+      pack_z_kernel<__hip_bfloat16, 8, 1><<<blocks, 256, 0, s>>>(d, k, inv, Z64,
+                                                                 static_cast<__hip_bfloat16*>(Zpack), nt, cbn);
       break;
-    case 3: {
-      __hip_bfloat16* hi = static_cast<__hip_bfloat16*>(Zpack);
-      pack_z_kernel<__hip_bfloat16, 8><<<blocks, 256, 0, s>>>(d, k, perm, rank, Z64, hi, hi + total, nt,
-                                                              cbn);
+    case 3:
+      pack_z_kernel<__hip_bfloat16, 8, 2><<<blocks, 256, 0, s>>>(d, k, inv, Z64,
+                                                                 static_cast<__hip_bfloat16*>(Zpack), nt, cbn);
       break;
-    }
+    case 4:
+      pack_z_kernel<__hip_bfloat16, 8, 3><<<blocks, 256, 0, s>>>(d, k, inv, Z64,
+                                                                 static_cast<__hip_bfloat16*>(Zpack), nt, cbn);
+      break;
     default:
       return hipErrorInvalidValue;
   }

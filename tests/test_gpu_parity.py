@@ -160,17 +160,18 @@ def test_estimate_fp64_dense_gaussian(gpu):
     assert rel.max() < 1e-9
 
 
+@pytest.mark.parametrize("precision", ["native", "fp32"])
 @pytest.mark.parametrize("n", [65536 + 13, 1000])
-def test_estimate_fp32_low_rank_coherent(gpu, n):
+def test_estimate_fp32_low_rank_coherent(gpu, n, precision):
     d, rank, r_cs, m, k, zeta, seed = 256, 128, 4096, 512, 48, 1e-5, 2002
     A = W.low_rank_coherent(n, d, rank, 1002)
-    theta, state = api.lev_estimate(A.to(gpu), seed, r_cs, m, k, zeta, return_state=True)
+    theta, state = api.lev_estimate(A.to(gpu), seed, r_cs, m, k, zeta, precision=precision, return_state=True)
     o = _oracle_theta(A.numpy().astype(np.float64), seed, r_cs, m, k, zeta)
     r = int(state.rank.item())
     assert r == o.rank == rank
     np.testing.assert_array_equal(state.perm.cpu().numpy()[:r], o.perm[:r])
     rel = _rel(theta.cpu().numpy().astype(np.float64), o.theta)
-    _log("fp32 n", n, "max rel", rel.max(), "p99", np.quantile(rel, 0.99))
+    _log("fp32", precision, "n", n, "max rel", rel.max(), "p99", np.quantile(rel, 0.99))
     assert rel.max() < 1e-4
 
 
