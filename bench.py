@@ -49,20 +49,34 @@ def make_workload(name: str, device):
         A = W.dense_gaussian(cfg["n"], cfg["d"], W.data_seed(idx), dtype=torch.float64, device=device)
     elif name.startswith("dense_bf16"):
         A = W.row_scaled_bf16(cfg["n"], cfg["d"], W.data_seed(idx), device=device)
+    elif name.startswith("csr_f32"):
+        A = W.sparse_power_law(cfg["n"], cfg["d"], cfg["zero_cols"], W.data_seed(idx), device=device)
     else:
-        raise SystemExit(f"workload {name} is not a dense single-GPU bench workload")
+        raise SystemExit(f"unknown workload {name}")
     return A, cfg, W.sketch_seed(idx)
 
 
-def bytes_per_launch(A: torch.Tensor, cfg) -> dict:
-    n, d = A.shape
-    es = A.element_size()
-    theta_es = 8 if A.dtype == torch.float64 else 4
+def _is_csr(A) -> bool:
+    return not isinstance(A, torch.Tensor)
+
+
+def a_bytes(A) -> int:
+    """Bytes of A as stored (dense: n*d elements; CSR: row_ptr, col_idx, values)."""
+    if _is_csr(A):
+        return A.row_ptr.numel() * 8 + A.col_idx.numel() * 4 + A.values.numel() * A.values.element_size()
+    return A.shape[0] * A.shape[1] * A.element_size()
+
+
+def bytes_per_launch(A, cfg) -> dict:
+    vals = A.values if _is_csr(A) else A
+    n = A.n if _is_csr(A) else A.shape[0]
+    d = cfg["d"]
+    theta_es = 8 if vals.dtype == torch.float64 else 4
     return {
         # pass 2 reads A once and writes theta~ (Z is ~KB, read from cache)
-        "pass2_rownorm": n * d * es + n * theta_es,
+        "pass2_rownorm": a_bytes(A) + n * theta_es,
         # pass 1 reads A once and writes S A (FP64)
-        "pass1_countsketch": n * d * es + cfg["r_cs"] * d * 8,
+        "pass1_countsketch": a_bytes(A) + cfg["r_cs"] * d * 8,
     }
 
 
@@ -75,10 +89,14 @@ def cpu_baseline(A: torch.Tensor, cfg, seed, target_s: float = 12.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    n = A.shape[0]
+    n = A.n if _is_csr(A) else A.shape[0]
     ns = min(n, 1 << 15)
+    S = A.to_scipy() if _is_csr(A) else None
     while True:
-        Ah = A[:ns].to(torch.float64).cpu().numpy() if A.dtype == torch.bfloat16 else A[:ns].cpu().numpy()
+        if S is not None:
+            Ah = S[:ns]
+        else:
+            Ah = A[:ns].to(torch.float64).cpu().numpy() if A.dtype == torch.bfloat16 else A[:ns].cpu().numpy()
         t0 = time.perf_counter()
         L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
         dt = time.perf_counter() - t0
@@ -150,7 +168,8 @@ def main():
     for i, name in enumerate(api.PHASE_NAMES):
         vals = [ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(args.steps)]
         phases[name] = float(np.mean(vals))
-    n = A.shape[0]
+    n = A.n if _is_csr(A) else A.shape[0]
+    vals = A.values if _is_csr(A) else A
     bpl = bytes_per_launch(A, cfg)
     dom = "pass2_rownorm"
     achieved = bpl[dom] / (phases[dom] * 1e-3) / 1e9
@@ -166,9 +185,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[str(A.dtype).split(".")[1]],
+        "dtype": {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[str(vals.dtype).split(".")[1]],
         "data": "synthetic (seeded, generated on the GPU)",
-        "config": {"workload": args.workload, "n": n, "d": A.shape[1], "r_cs": cfg["r_cs"], "m": cfg["m"],
+        "config": {"workload": args.workload, "n": n, "d": cfg["d"], "r_cs": cfg["r_cs"], "m": cfg["m"],
                    "k": cfg["k"], "zeta": cfg["zeta"], "precision": args.precision},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom), "kernel": dom},

@@ -121,7 +121,7 @@ def countsketch_apply(rnd: conv.SketchRandomness, A, chunk: int = 1 << 16) -> np
     """S A (r_cs x d, FP64), with S the CountSketch of Section 3.4, applied
     as a sparse matrix over row chunks of A (dense ndarray or scipy sparse)."""
     h, cols, s = conv.countsketch_matrix_entries(rnd)
-    S = sp.csr_matrix((s, (h, cols)), shape=(rnd.r_cs, rnd.n))
+    S = sp.csc_matrix((s, (h, cols)), shape=(rnd.r_cs, rnd.n))  # column slices below
     d = A.shape[1]
     SA = np.zeros((rnd.r_cs, d))
     for lo in range(0, rnd.n, chunk):

@@ -112,7 +112,62 @@ def _ptr(t: torch.Tensor | None) -> c_void_p:
 _DTYPES = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
 
 
-def _matrix(A: torch.Tensor) -> LevMatrix:
+@dataclass
+class Csr:
+    """A CSR matrix on the device: row_ptr int64[n+1], col_idx int32[nnz]
+    (strictly increasing within each row, < d), values[nnz] (float64,
+    float32 or bfloat16).  Any object with these five attributes is accepted
+    where a Csr is."""
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    values: torch.Tensor
+    n: int
+    d: int
+
+
+def _is_csr(A) -> bool:
+    return not isinstance(A, torch.Tensor) and all(hasattr(A, a) for a in ("row_ptr", "col_idx", "values", "n", "d"))
+
+
+def _as_csr(A):
+    if isinstance(A, torch.Tensor) and A.layout == torch.sparse_csr:
+        # torch keeps both index arrays in one dtype; the ABI takes int64
+        # row pointers and int32 column ids
+        return Csr(A.crow_indices().to(torch.int64), A.col_indices().to(torch.int32), A.values(), A.shape[0],
+                   A.shape[1])
+    return A
+
+
+def _device(A) -> torch.device:
+    A = _as_csr(A)
+    return A.values.device if _is_csr(A) else A.device
+
+
+def _shape(A) -> tuple[int, int]:
+    A = _as_csr(A)
+    return (int(A.n), int(A.d)) if _is_csr(A) else (A.shape[0], A.shape[1])
+
+
+def _dtype(A) -> torch.dtype:
+    A = _as_csr(A)
+    return A.values.dtype if _is_csr(A) else A.dtype
+
+
+def _matrix(A) -> LevMatrix:
+    A = _as_csr(A)
+    if _is_csr(A):
+        rp, ci, va = A.row_ptr, A.col_idx, A.values
+        for name, t in (("row_ptr", rp), ("col_idx", ci), ("values", va)):
+            if not t.is_cuda or t.dim() != 1 or not t.is_contiguous():
+                raise ValueError(f"CSR {name} must be a contiguous 1-D device tensor")
+        if rp.dtype != torch.int64 or ci.dtype != torch.int32:
+            raise ValueError("CSR row_ptr must be int64 and col_idx int32")
+        if va.dtype not in _DTYPES:
+            raise ValueError(f"unsupported dtype {va.dtype}")
+        if rp.numel() != int(A.n) + 1 or ci.numel() != va.numel():
+            raise ValueError("CSR sizes are inconsistent (row_ptr must have n + 1 entries)")
+        return LevMatrix(CSR, _DTYPES[va.dtype], int(A.n), int(A.d), 0, va.numel(), va.data_ptr(), rp.data_ptr(),
+                         ci.data_ptr())
     if not A.is_cuda:
         raise ValueError("A must be a device (cuda) tensor")
     if A.dim() != 2 or A.stride(1) != 1:
@@ -192,24 +247,29 @@ def _aligned_blob(nbytes: int, device) -> torch.Tensor:
     return buf[off:off + int(nbytes)]
 
 
-def lev_workspace_size(A: torch.Tensor, seed, r_cs, m, k, zeta, precision="native", which=WS_ESTIMATE) -> int:
+def lev_workspace_size(A, seed, r_cs, m, k, zeta, precision="native", which=WS_ESTIMATE) -> int:
     lib = load_library()
+    A = _as_csr(A)
     mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
     return int(lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), which))
 
 
-def lev_sketch(A: torch.Tensor, seed: int, r_cs: int, m: int, return_sa: bool = False):
-    """Algorithm 3: A~ = G (S A) (m x d, FP64); optionally also S A."""
+def lev_sketch(A, seed: int, r_cs: int, m: int, return_sa: bool = False):
+    """Algorithm 3: A~ = G (S A) (m x d, FP64); optionally also S A.  A is a
+    dense device tensor or a CSR matrix (Csr, or a torch sparse_csr tensor
+    with int64 row pointers and int32 column indices)."""
     lib = load_library()
-    mat, par = _matrix(A), _params(seed, r_cs, m, 1, 0.0, "fp32" if A.dtype == torch.bfloat16 else "native")
+    A = _as_csr(A)  # held until the call returns: it owns converted index arrays
+    dev, (_, d) = _device(A), _shape(A)
+    prec = "fp32" if (_dtype(A) == torch.bfloat16 and not _is_csr(_as_csr(A))) else "native"
+    mat, par = _matrix(A), _params(seed, r_cs, m, 1, 0.0, prec)
     nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_SKETCH)
     if nbytes == 0:
         _check(lib.lev_sketch(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))
-    _, ws = _workspace(nbytes, A.device)
-    At = torch.empty(m, A.shape[1], dtype=torch.float64, device=A.device)
-    SA = torch.empty(r_cs, A.shape[1], dtype=torch.float64, device=A.device) if return_sa else None
-    _check(lib.lev_sketch(ctypes.byref(mat), ctypes.byref(par), _ptr(At), _ptr(SA), ws, nbytes,
-                          _stream(A.device)))
+    _, ws = _workspace(nbytes, dev)
+    At = torch.empty(m, d, dtype=torch.float64, device=dev)
+    SA = torch.empty(r_cs, d, dtype=torch.float64, device=dev) if return_sa else None
+    _check(lib.lev_sketch(ctypes.byref(mat), ctypes.byref(par), _ptr(At), _ptr(SA), ws, nbytes, _stream(dev)))
     return (At, SA) if return_sa else At
 
 
@@ -232,23 +292,25 @@ def lev_rank_estimate(At: torch.Tensor, zeta: float):
     return perm, R, rank
 
 
-def lev_estimate(A: torch.Tensor, seed: int, r_cs: int, m: int, k: int, zeta: float,
+def lev_estimate(A, seed: int, r_cs: int, m: int, k: int, zeta: float,
                  precision: str = "native", return_state: bool = False):
-    """Algorithm 10 (LS-HRN-approx): theta~ (FP64 for FP64 A, else FP32)."""
+    """Algorithm 10 (LS-HRN-approx): theta~ (FP64 for FP64 A, else FP32).
+    A is a dense device tensor or a CSR matrix (see lev_sketch)."""
     lib = load_library()
+    A = _as_csr(A)  # held until the call returns: it owns converted index arrays
+    dev, (n, d), dt = _device(A), _shape(A), _dtype(A)
     mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
     nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_ESTIMATE)
     if nbytes == 0:
         _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))
-    _, ws = _workspace(nbytes, A.device)
-    out_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
-    theta = torch.empty(A.shape[0], dtype=out_dtype, device=A.device)
+    _, ws = _workspace(nbytes, dev)
+    out_dtype = torch.float64 if dt == torch.float64 else torch.float32
+    theta = torch.empty(n, dtype=out_dtype, device=dev)
     state = None
     if return_state:
-        d = A.shape[1]
-        state = State(_aligned_blob(lib.lev_state_size(d, m, k), A.device), d, m, k)
+        state = State(_aligned_blob(lib.lev_state_size(d, m, k), dev), d, m, k)
     _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), _ptr(theta),
-                            _ptr(state.blob) if state is not None else None, ws, nbytes, _stream(A.device)))
+                            _ptr(state.blob) if state is not None else None, ws, nbytes, _stream(dev)))
     return (theta, state) if return_state else theta
 
 
@@ -256,17 +318,18 @@ class EstimatePlan:
     """Pre-allocated workspace and outputs for repeated lev_estimate calls on
     same-shaped inputs (what the benchmark times)."""
 
-    def __init__(self, A: torch.Tensor, seed, r_cs, m, k, zeta, precision="native"):
+    def __init__(self, A, seed, r_cs, m, k, zeta, precision="native"):
         self.lib = load_library()
+        A = _as_csr(A)  # kept in self.A: the pointers below refer to its arrays
         self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
         self.nbytes = self.lib.lev_workspace_size(ctypes.byref(self.mat), ctypes.byref(self.par), WS_ESTIMATE)
         if self.nbytes == 0:
             _check(self.lib.lev_estimate(ctypes.byref(self.mat), ctypes.byref(self.par), None, None, None, 0,
                                          None))
-        self._buf, self.ws = _workspace(self.nbytes, A.device)
-        out_dtype = torch.float64 if A.dtype == torch.float64 else torch.float32
-        self.theta = torch.empty(A.shape[0], dtype=out_dtype, device=A.device)
-        self.device = A.device
+        self.device = _device(A)
+        self._buf, self.ws = _workspace(self.nbytes, self.device)
+        out_dtype = torch.float64 if _dtype(A) == torch.float64 else torch.float32
+        self.theta = torch.empty(_shape(A)[0], dtype=out_dtype, device=self.device)
         self.A = A
 
     def run(self, stream=None):

@@ -116,8 +116,13 @@ size_t elem_size(int dtype) {
   }
 }
 
-// pass-2 variant from the storage type and the requested precision
-int az_variant(int dtype, int az) {
+// pass-2 variant from the format, the storage type and the requested precision
+int az_variant(int format, int dtype, int az) {
+  if (format == LEV_CSR) {
+    // CSR pass 2 runs on the vector ALUs: FP64 for F64 values, else FP32
+    if (dtype == LEV_F64) return az == LEV_AZ_NATIVE ? 6 : -1;
+    return (az == LEV_AZ_NATIVE || az == LEV_AZ_FP32) ? 5 : -1;
+  }
   if (dtype == LEV_F64) return az == LEV_AZ_NATIVE ? 0 : -1;
   if (dtype == LEV_F32) {
     if (az == LEV_AZ_NATIVE || az == LEV_AZ_BF16X3) return 4;
@@ -151,7 +156,10 @@ lev_status check_matrix(const lev_matrix* A) {
     if ((A->ld * (int64_t)elem_size(A->dtype)) % 16 != 0)
       return fail(LEV_ERR_ARG, "ld * sizeof(element) must be a multiple of 16 bytes");
   } else {
-    return fail(LEV_ERR_NOT_SUPPORTED, "CSR input is not supported by this build yet");
+    if (A->nnz < 0) return fail(LEV_ERR_SHAPE, "nnz = %lld < 0", (long long)A->nnz);
+    if (A->row_ptr == nullptr) return fail(LEV_ERR_ARG, "A->row_ptr is null");
+    if (A->nnz > 0 && (A->col_idx == nullptr || A->values == nullptr))
+      return fail(LEV_ERR_ARG, "A->col_idx or A->values is null");
   }
   return LEV_OK;
 }
@@ -163,7 +171,7 @@ lev_status check_params(const lev_matrix* A, const lev_params* p) {
   if (p->m > (1ll << 24)) return fail(LEV_ERR_SHAPE, "m too large");
   if (p->k < 1 || p->k > kMaxK) return fail(LEV_ERR_ARG, "k = %lld outside [1, 64]", (long long)p->k);
   if (!(p->zeta >= 0.0 && p->zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
-  if (az_variant(A->dtype, p->az_precision) < 0)
+  if (az_variant(A->format, A->dtype, p->az_precision) < 0)
     return fail(LEV_ERR_ARG, "az_precision %d not valid for dtype %d", p->az_precision, A->dtype);
   return LEV_OK;
 }
@@ -248,7 +256,10 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
   const int64_t d = A->d, m = p->m, r_cs = p->r_cs;
   LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, 1.0 / std::sqrt((double)m), b.Gm, s));
   LEV_HIP(mark_phase(1, s));
-  if (A->n > 0) {
+  if (A->n > 0 && A->format == LEV_CSR) {
+    LEV_HIP(lev::launch_countsketch_csr(A->dtype, A->values, A->row_ptr, A->col_idx, A->n, d, A->nnz, dr.hash,
+                                        SA, s));
+  } else if (A->n > 0) {
     LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, s));
   } else {
     LEV_HIP(lev::launch_fill_zero(SA, sizeof(double) * (size_t)(r_cs * d), s));
@@ -358,7 +369,7 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
     carve_rank(c, m, d);
     c.take<char>(state_bytes(d, m, k));
     c.take<double>((size_t)(d * k));  // G_k
-    c.take<char>(lev::pack_z_bytes(az_variant(A->dtype, p->az_precision), d, k));
+    c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, k));
     return c.used;
   }
   return 0;
@@ -405,7 +416,7 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
     return fail(LEV_ERR_ARG, "state_out must be 256-byte aligned");
 
   const int64_t n = A->n, d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
-  const int variant = az_variant(A->dtype, p->az_precision);
+  const int variant = az_variant(A->format, A->dtype, p->az_precision);
   Carver c(ws);
   SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
   RankBufs rb = carve_rank(c, m, d);
@@ -424,7 +435,10 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   LEV_HIP(lev::launch_trsm_z(d, k, sv.R, rank, Gk, sv.Z64, stream));
   LEV_HIP(lev::launch_pack_z(variant, d, k, sv.perm, rank, sv.Z64, Zpack, stream));
   LEV_HIP(mark_phase(5, stream));
-  if (n > 0) {
+  if (n > 0 && A->format == LEV_CSR) {
+    LEV_HIP(lev::launch_rownorm_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, Zpack, theta_out,
+                                    stream));
+  } else if (n > 0) {
     LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, k, Zpack, rank, theta_out,
                                       stream));
   }

@@ -45,9 +45,10 @@ hipError_t launch_bucket_lists(const HashParams& hp, int64_t* off, int32_t* rows
 // dtype: 0 = f64, 1 = f32, 2 = bf16.
 hipError_t launch_countsketch_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
                                     const HashParams& hp, double* SA, hipStream_t s);
-// Pass 1, CSR.
+// Pass 1, CSR (row_ptr int64[n+1], col_idx int32[nnz], vals[nnz]).  Row
+// extents are clamped to [0, nnz] and to d entries, column ids >= d skipped.
 hipError_t launch_countsketch_csr(int dtype, const void* vals, const int64_t* row_ptr,
-                                  const int32_t* col_idx, int64_t n, int64_t d,
+                                  const int32_t* col_idx, int64_t n, int64_t d, int64_t nnz,
                                   const HashParams& hp, double* SA, hipStream_t s);
 
 // rows x cols FP64 Gaussian matrix, Philox4x32-10 + Box-Muller, times scale.
@@ -89,7 +90,8 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
 // Prepares the operand of pass 2: Z_full (d x k, rows indexed by original
 // column, zero off K) converted to the pass-2 compute type and laid out for
 // the MFMA B-operand; see rownorm.hip for the layouts.
-// variant: 0 = FP64, 1 = FP32, 2 = BF16, 3 = BF16 hi/lo, 4 = BF16x3 (FP32 A).
+// variant: 0 = FP64, 1 = FP32, 2 = BF16, 3 = BF16 hi/lo, 4 = BF16x3 (FP32 A),
+// 5 = FP32 row-major d x 64 (CSR pass 2), 6 = FP64 row-major d x 64 (CSR).
 // pack_z_bytes: workspace needed (operand + an inverse permutation);
 // pack_z_operand_bytes: the operand alone (what pass 2 reads).
 hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
@@ -102,9 +104,13 @@ size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k);
 hipError_t launch_rownorm_dense(int variant, int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
                                 int64_t k, const void* Zpack, const int64_t* rank, void* theta,
                                 hipStream_t s);
-hipError_t launch_rownorm_csr(int variant, int dtype, const void* vals, const int64_t* row_ptr,
-                              const int32_t* col_idx, int64_t n, int64_t d, int64_t k,
-                              const void* Zpack, const int64_t* rank, void* theta, hipStream_t s);
+// Pass 2, CSR: theta[i] = || A[i, :] Z_full ||^2 with Z_full packed by
+// launch_pack_z as variant 5 (FP32, for F32/BF16 values) or 6 (FP64, for
+// F64 values): d rows of 64 elements (columns >= k zero).  theta is FP64 for
+// F64 values, else FP32.
+hipError_t launch_rownorm_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
+                              int64_t n, int64_t d, int64_t nnz, const void* Zpack, void* theta,
+                              hipStream_t s);
 
 // dst[0..3] = (a, b, c, e) from a kernel (capture-safe small header write).
 hipError_t launch_store_i64x4(int64_t* dst, int64_t a, int64_t b, int64_t c, int64_t e, hipStream_t s);

@@ -210,6 +210,146 @@ hipError_t launch_dense_typed(const void* A, int64_t n, int64_t d, int64_t ld, c
   return hipGetLastError();
 }
 
+// ---- CSR input -------------------------------------------------------------
+// Same bucket-major gather as the dense kernel.  A wave takes the staged
+// row list 64 entries at a time (lane j <-> entry j: its row's extent from
+// row_ptr), then walks those rows U at a time: the first 64 nonzeros of U
+// rows are loaded together (lane t <-> nonzero t of a row) and then added,
+// row after row, into the wave's private FP64 accumulator in LDS with
+// ds_add_f64.  Within one row the column ids are distinct, so one add
+// instruction never hits an address twice, and the adds of one wave execute
+// in program order: the accumulation order is a fixed function of the input
+// and S A is bitwise reproducible.  The four wave accumulators are summed in
+// a fixed order at the end.
+template <typename T>
+__device__ __forceinline__ double load_as_double(const T* p);
+template <>
+__device__ __forceinline__ double load_as_double<double>(const double* p) { return *p; }
+template <>
+__device__ __forceinline__ double load_as_double<float>(const float* p) { return (double)*p; }
+template <>
+__device__ __forceinline__ double load_as_double<__hip_bfloat16>(const __hip_bfloat16* p) {
+  const uint16_t bits = *reinterpret_cast<const uint16_t*>(p);
+  return (double)__uint_as_float((uint32_t)bits << 16);
+}
+
+constexpr int kCsrU = 8;  // rows whose first 64 nonzeros are in flight together
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void countsketch_csr_kernel(const T* __restrict__ vals,
+                                                                   const int64_t* __restrict__ row_ptr,
+                                                                   const int32_t* __restrict__ col_idx,
+                                                                   int64_t d, int64_t nnz, HashParams hp,
+                                                                   double* __restrict__ SA) {
+  extern __shared__ double acc[];  // [kWaves][d]
+  __shared__ uint32_t entries[kChunk];
+  const int64_t b = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* my = acc + (int64_t)wave * d;
+  for (int64_t c = threadIdx.x; c < kWaves * d; c += kThreads) acc[c] = 0.0;
+
+  const int64_t T_b = bucket_len(hp, b);
+  const uint64_t i0 = T_b > 0 ? bucket_start(hp, b) : 0;
+  for (int64_t t0 = 0; t0 < T_b; t0 += kChunk) {
+    const int cnt = (int)min<int64_t>(kChunk, T_b - t0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < cnt; q += kThreads) {
+      const uint64_t i = bucket_row(hp, i0, (uint64_t)(t0 + q));
+      uint32_t e = kInvalid;
+      if (i < (uint64_t)hp.n) e = (uint32_t)i | (sign_negative(hp, i) ? 0x80000000u : 0u);
+      entries[q] = e;
+    }
+    __syncthreads();
+    for (int q0 = wave * 64; q0 < cnt; q0 += kWaves * 64) {
+      const int q = q0 + lane;
+      const uint32_t ent = q < cnt ? entries[q] : kInvalid;
+      int64_t start = 0;
+      int len = 0;
+      int neg = 0;
+      if (ent != kInvalid) {
+        const int64_t row = (int64_t)(ent & 0x7FFFFFFFu);
+        // a well-formed row lies in [0, nnz) and has at most d nonzeros; the
+        // clamps keep a malformed row_ptr from reading out of bounds
+        start = min(max(row_ptr[row], (int64_t)0), nnz);
+        const int64_t end = min(max(row_ptr[row + 1], start), nnz);
+        len = (int)min<int64_t>(end - start, d);
+        neg = (ent >> 31) != 0;
+      }
+      const int rows_here = min(64, cnt - q0);
+      for (int g = 0; g < rows_here; g += kCsrU) {
+        int32_t cv[kCsrU];
+        double xv[kCsrU];
+        int64_t st[kCsrU];
+        int ln[kCsrU];
+#pragma unroll
+        for (int u = 0; u < kCsrU; ++u) {
+          const int j = g + u;  // uniform
+          const int jj = j < 64 ? j : 63;
+          st[u] = ((int64_t)__builtin_amdgcn_readlane((int)(start >> 32), jj) << 32) |
+                  (uint32_t)__builtin_amdgcn_readlane((int)start, jj);
+          ln[u] = j < rows_here ? __builtin_amdgcn_readlane(len, jj) : 0;
+          const int sg = __builtin_amdgcn_readlane(neg, jj);
+          cv[u] = 0;
+          xv[u] = 0.0;
+          if (lane < ln[u]) {
+            cv[u] = col_idx[st[u] + lane];
+            const double x = load_as_double<T>(vals + st[u] + lane);
+            xv[u] = sg ? -x : x;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kCsrU; ++u) {
+          if (lane < ln[u] && (uint32_t)cv[u] < (uint32_t)d)
+            __hip_atomic_fetch_add(my + cv[u], xv[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        // nonzeros beyond the first 64 of a row: row by row, up to 8 chunks
+        // of 64 loaded together before they are added
+#pragma unroll
+        for (int u = 0; u < kCsrU; ++u) {
+          const int sg = __builtin_amdgcn_readlane(neg, (g + u) < 64 ? g + u : 63);
+          for (int off0 = 64; off0 < ln[u]; off0 += 8 * 64) {
+            int32_t c8[8];
+            double x8[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              const int off = off0 + 64 * v + lane;
+              c8[v] = 0;
+              x8[v] = 0.0;
+              if (off < ln[u]) {
+                c8[v] = col_idx[st[u] + off];
+                const double x = load_as_double<T>(vals + st[u] + off);
+                x8[v] = sg ? -x : x;
+              }
+            }
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+              if (off0 + 64 * v + lane < ln[u] && (uint32_t)c8[v] < (uint32_t)d)
+                __hip_atomic_fetch_add(my + c8[v], x8[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int64_t c = threadIdx.x; c < d; c += kThreads) {
+    double s = acc[c];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) s += acc[(int64_t)w * d + c];
+    SA[b * d + c] = s;
+  }
+}
+
+template <typename T>
+hipError_t launch_csr_typed(const void* vals, const int64_t* row_ptr, const int32_t* col_idx, int64_t d,
+                            int64_t nnz, const HashParams& hp, double* SA, hipStream_t s) {
+  const size_t lds = (size_t)kWaves * (size_t)d * sizeof(double);
+  countsketch_csr_kernel<T><<<(unsigned)hp.r_cs, kThreads, lds, s>>>(static_cast<const T*>(vals), row_ptr,
+                                                                      col_idx, d, nnz, hp, SA);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_hash_rows(const HashParams& hp, int64_t* h_out, int8_t* s_out, hipStream_t s) {
@@ -234,6 +374,18 @@ hipError_t launch_countsketch_dense(int dtype, const void* A, int64_t n, int64_t
     case 0: return launch_dense_typed<double>(A, n, d, ld, hp, SA, s);
     case 1: return launch_dense_typed<float>(A, n, d, ld, hp, SA, s);
     case 2: return launch_dense_typed<__hip_bfloat16>(A, n, d, ld, hp, SA, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_countsketch_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
+                                  int64_t n, int64_t d, int64_t nnz, const HashParams& hp, double* SA,
+                                  hipStream_t s) {
+  (void)n;
+  switch (dtype) {
+    case 0: return launch_csr_typed<double>(vals, row_ptr, col_idx, d, nnz, hp, SA, s);
+    case 1: return launch_csr_typed<float>(vals, row_ptr, col_idx, d, nnz, hp, SA, s);
+    case 2: return launch_csr_typed<__hip_bfloat16>(vals, row_ptr, col_idx, d, nnz, hp, SA, s);
     default: return hipErrorInvalidValue;
   }
 }

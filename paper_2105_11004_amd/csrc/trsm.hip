@@ -165,6 +165,21 @@ __global__ void inverse_perm_kernel(int64_t d, const int32_t* __restrict__ perm,
   inv_perm[perm[j]] = j < r ? (int32_t)j : -1;
 }
 
+// CSR operand: Z_full row-major with rows padded to 64 columns.
+template <typename OUT>
+__global__ void pack_z_rowmajor_kernel(int64_t d, int64_t k, const int32_t* __restrict__ inv_perm,
+                                       const double* __restrict__ Z64, OUT* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * 64) return;
+  const int64_t row = idx / 64, col = idx % 64;
+  double v = 0.0;
+  if (col < k) {
+    const int32_t j = inv_perm[row];
+    if (j >= 0) v = Z64[(int64_t)j * k + col];
+  }
+  out[idx] = (OUT)v;
+}
+
 constexpr int64_t chunk_cols(int variant) { return variant == 0 ? 8 : (variant == 1 ? 16 : 32); }
 constexpr int parts(int variant) { return variant == 3 ? 2 : (variant == 4 ? 3 : 1); }
 
@@ -181,6 +196,7 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
 }
 
 size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k) {
+  if (variant == 5 || variant == 6) return (size_t)d * 64 * (variant == 5 ? 4 : 8);
   if (variant < 0 || variant > 4) return 0;
   const int64_t cw = chunk_cols(variant);
   const int64_t nt = (d + cw - 1) / cw;
@@ -191,13 +207,23 @@ size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k) {
 }
 
 size_t pack_z_bytes(int variant, int64_t d, int64_t k) {
-  if (variant < 0 || variant > 4) return 0;
+  if (variant < 0 || variant > 6) return 0;
   return pack_z_operand_bytes(variant, d, k) + (size_t)d * sizeof(int32_t);
 }
 
 // Zpack layout: the packed operand (as above) followed by inv_perm[d].
 hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
                          const double* Z64, void* Zpack, hipStream_t s) {
+  if (variant == 5 || variant == 6) {
+    int32_t* inv = reinterpret_cast<int32_t*>(static_cast<char*>(Zpack) + pack_z_operand_bytes(variant, d, k));
+    inverse_perm_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(d, perm, rank, inv);
+    const unsigned blocks = (unsigned)((d * 64 + 255) / 256);
+    if (variant == 5)
+      pack_z_rowmajor_kernel<float><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<float*>(Zpack));
+    else
+      pack_z_rowmajor_kernel<double><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<double*>(Zpack));
+    return hipGetLastError();
+  }
   const int64_t cw = chunk_cols(variant);
   const int64_t nt = (d + cw - 1) / cw;
   const int64_t cbn = (k + 15) / 16;

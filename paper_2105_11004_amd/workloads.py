@@ -14,14 +14,15 @@ Recipes (sizes as in the workload table of the design notes):
     in BF16 (round to nearest even).
   * fixed_spectrum   -- A = U diag(sigma) V^T with Haar-like U, V and a
     prescribed singular value list (the fixed_svd matrices of Section 7).
-  * sparse_power_law -- CSR rows with power-law lengths on [1, live], the
-    columns of each row uniform without replacement over the live columns
-    (all but a seeded set of zero columns), values N(0,1).
+  * sparse_power_law -- CSR rows with power-law lengths on [1, live] (mean
+    16 nonzeros), the columns of each row uniform without replacement over
+    the live columns (all but a seeded set of zero columns), values N(0,1).
 """
 
 from __future__ import annotations
 
 import math
+from dataclasses import dataclass
 
 import numpy as np
 import torch
@@ -76,45 +77,81 @@ def fixed_spectrum(n: int, sigma, seed: int, dtype=torch.float64, device="cpu") 
     return ((U * sigma) @ V.T).to(dtype)
 
 
-def power_law_lengths(n: int, live: int, alpha: float, seed: int) -> np.ndarray:
-    """Row lengths l in [1, live] with P(l) proportional to l^-alpha."""
-    rng = np.random.default_rng(seed)
+def power_law_alpha(live: int, mean: float) -> float:
+    """Exponent alpha of P(l) ~ l^-alpha on [1, live] whose mean is `mean`
+    (bisection; the mean decreases monotonically in alpha)."""
     ell = np.arange(1, live + 1, dtype=np.float64)
-    p = ell ** (-alpha)
-    p /= p.sum()
-    return rng.choice(np.arange(1, live + 1), size=n, p=p).astype(np.int64)
+    lo, hi = 0.0, 8.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        w = ell ** (-mid)
+        if (ell * w).sum() / w.sum() > mean:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
 
 
-def sparse_power_law(n: int, d: int, n_zero_cols: int, alpha: float, seed: int,
-                     dtype=np.float32):
-    """CSR (row_ptr int64, col_idx int32 sorted per row, values) on the host.
+@dataclass
+class CsrHost:
+    """CSR matrix as torch tensors (row_ptr int64[n+1], col_idx int32[nnz],
+    values[nnz]) on one device."""
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    values: torch.Tensor
+    n: int
+    d: int
+    zero_cols: torch.Tensor
 
-    Each row draws its length from the truncated power law, then that many
-    distinct columns uniformly from the live columns (random keys, take the
-    smallest), sorted ascending.
-    """
-    rng = np.random.default_rng(seed + 1)
-    zero_cols = np.sort(rng.choice(d, size=n_zero_cols, replace=False))
-    live = np.setdiff1d(np.arange(d), zero_cols).astype(np.int32)
-    lengths = power_law_lengths(n, live.size, alpha, seed)
-    row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(lengths, out=row_ptr[1:])
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    def to(self, device) -> "CsrHost":
+        return CsrHost(self.row_ptr.to(device), self.col_idx.to(device), self.values.to(device), self.n, self.d,
+                       self.zero_cols.to(device))
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.values.cpu().to(torch.float64).numpy(), self.col_idx.cpu().numpy(),
+                              self.row_ptr.cpu().numpy()), shape=(self.n, self.d))
+
+
+def sparse_power_law(n: int, d: int, n_zero_cols: int, seed: int, mean_nnz: float = 16.0,
+                     dtype=torch.float32, device="cpu", chunk: int = 1 << 15) -> CsrHost:
+    """CSR with a seeded set of n_zero_cols all-zero columns; row lengths l in
+    [1, live] (live = d - n_zero_cols) with P(l) ~ l^-alpha, alpha set so the
+    mean is mean_nnz; each row's columns are l distinct live columns drawn
+    uniformly (the l smallest of live random keys), sorted; values N(0,1)."""
+    g = _gen(seed, device)
+    perm = torch.randperm(d, generator=g, device=device)
+    zero_cols = torch.sort(perm[:n_zero_cols]).values
+    is_live = torch.ones(d, dtype=torch.bool, device=device)
+    is_live[zero_cols] = False
+    live = torch.nonzero(is_live).flatten().to(torch.int32)
+    n_live = int(live.numel())
+    alpha = power_law_alpha(n_live, mean_nnz)
+    w = torch.arange(1, n_live + 1, dtype=torch.float64, device=device) ** (-alpha)
+    cdf = torch.cumsum(w / w.sum(), 0)
+    cdf[-1] = 1.0
+    u = torch.rand(n, generator=g, dtype=torch.float64, device=device)
+    lengths = torch.searchsorted(cdf, u, right=True).clamp_(max=n_live - 1) + 1
+    row_ptr = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    torch.cumsum(lengths, 0, out=row_ptr[1:])
     nnz = int(row_ptr[-1])
-    col_idx = np.empty(nnz, dtype=np.int32)
-    # group rows by length so each group is one vectorised draw
-    for ell in np.unique(lengths):
-        rows = np.nonzero(lengths == ell)[0]
-        for lo in range(0, rows.size, 1 << 16):
-            rr = rows[lo:lo + (1 << 16)]
-            keys = rng.random((rr.size, live.size), dtype=np.float32)
-            pick = np.argpartition(keys, ell - 1, axis=1)[:, :ell] if ell < live.size else \
-                np.tile(np.arange(live.size), (rr.size, 1))
-            cols = np.sort(live[pick], axis=1)
-            starts = row_ptr[rr]
-            idx = starts[:, None] + np.arange(ell)[None, :]
-            col_idx[idx.ravel()] = cols.ravel()
-    values = rng.standard_normal(nnz, dtype=np.float64).astype(dtype)
-    return row_ptr, col_idx, values, zero_cols
+    col_idx = torch.empty(nnz, dtype=torch.int32, device=device)
+    ar = torch.arange(n_live, device=device)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        keys = torch.rand(hi - lo, n_live, generator=g, dtype=torch.float64, device=device)
+        order = torch.argsort(keys, dim=1)
+        sel = ar[None, :] < lengths[lo:hi, None]
+        mask = torch.zeros_like(sel)
+        mask.scatter_(1, order, sel)  # exactly l_i columns per row
+        cols = torch.nonzero(mask)[:, 1]  # row-major: ascending within a row
+        col_idx[int(row_ptr[lo]):int(row_ptr[hi])] = live[cols]
+    values = torch.randn(nnz, generator=g, dtype=torch.float32, device=device).to(dtype)
+    return CsrHost(row_ptr, col_idx, values, n, d, zero_cols)
 
 
 # Workload table: the shapes of the paper's sketches at the sizes the tests
@@ -122,7 +159,7 @@ def sparse_power_law(n: int, d: int, n_zero_cols: int, alpha: float, seed: int,
 CONFIGS = {
     "dense_f64_4096x64": dict(n=4096, d=64, dtype="f64", r_cs=1024, m=256, k=32, zeta=1e-10),
     "dense_f32_1Mx256_rank128": dict(n=1 << 20, d=256, rank=128, dtype="f32", r_cs=4096, m=512, k=48, zeta=1e-5),
-    "csr_f32_8Mx512": dict(n=1 << 23, d=512, dtype="f32", r_cs=8192, m=1024, k=64, zeta=1e-5),
+    "csr_f32_8Mx512": dict(n=1 << 23, d=512, zero_cols=64, dtype="f32", r_cs=8192, m=1024, k=64, zeta=1e-5),
     "dense_bf16_4Mx1024": dict(n=1 << 22, d=1024, dtype="bf16", r_cs=16384, m=2048, k=64, zeta=1e-3),
     "dense_f32_1Mx256_rank192_bwd": dict(n=1 << 20, d=256, rank=192, dtype="f32", r_cs=4096, m=512, k=48, zeta=1e-5),
 }

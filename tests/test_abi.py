@@ -77,7 +77,11 @@ def _par(api, **kw):
     ({}, {"zeta": 1.5}, -1),
     ({}, {"az": 2}, -1),                         # BF16 products need BF16 storage
     ({"dtype": 0, "ld": 16}, {"az": 1}, -1),     # FP64 input only in FP64
-    ({"format": 1}, {}, -7),                     # CSR not in this build yet
+    ({"format": 1}, {}, -1),                     # CSR without row_ptr
+    ({"format": 1, "row_ptr": 8192, "nnz": -1}, {}, -2),
+    ({"format": 1, "row_ptr": 8192, "nnz": 10}, {}, -1),            # nnz > 0 without col_idx
+    ({"format": 1, "row_ptr": 8192, "dtype": 0}, {"az": 1}, -1),    # FP64 CSR runs in FP64 only
+    ({"format": 1, "row_ptr": 8192, "nnz": 5, "col_idx": 16384}, {"az": 2}, -1),  # no BF16 products on CSR
 ])
 def test_estimate_rejects_bad_arguments(lib, mat_kw, par_kw, expected):
     from paper_2105_11004_amd import api

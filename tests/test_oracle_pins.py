@@ -337,6 +337,28 @@ def test_estimator_handles_zero_and_zero_rows():
     assert est.theta[3] == 0 and est.theta[77] == 0
 
 
+def test_sparse_input_takes_the_same_steps_as_dense():
+    """The oracle's sparse branches (CountSketch of a CSR block, column
+    selection and row norms of a sparse A) against its dense branches on
+    the same matrix, zero columns included (they sketch to exact zeros and
+    drop out of the rank)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((700, 24)) * (rng.random((700, 24)) < 0.2)
+    A[:, [4, 17]] = 0.0
+    S = sp.csr_matrix(A)
+    np.testing.assert_array_equal(L.countsketch_apply(C.derive(5, 700, 64), S, chunk=128),
+                                  L.countsketch_apply(C.derive(5, 700, 64), A, chunk=128))
+    ed = L.ls_hrn_approx(A, 5, 64, 48, 6, 1e-8)
+    es = L.ls_hrn_approx(S, 5, 64, 48, 6, 1e-8)
+    assert ed.rank == es.rank == 22
+    np.testing.assert_array_equal(ed.perm, es.perm)
+    np.testing.assert_allclose(es.theta, ed.theta, rtol=1e-12, atol=0)
+    rows = np.array([0, 5, 699])
+    np.testing.assert_allclose(L.ls_hrn_approx(S, 5, 64, 48, 6, 1e-8, rows=rows).theta_rows, ed.theta[rows],
+                               rtol=1e-12)
+
+
 # ---------------------------------------------------------------- planted mistakes
 def test_pins_catch_a_dropped_sign_normalisation(monkeypatch):
     """A plausible oracle bug (no sign normalisation of R) must break a pin."""
