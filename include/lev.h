@@ -57,7 +57,7 @@ enum { LEV_DENSE_ROWMAJOR = 0, LEV_CSR = 1 };
 enum { LEV_F64 = 0, LEV_F32 = 1, LEV_BF16 = 2 };
 
 /* Arithmetic of the pass that forms A_{:,K} Z and its squared row norms
- * (Algorithm 8, last step).
+ * (Algorithm 8, last step).  Dense A:
  *  NATIVE: F64 input -> FP64 MFMA; F32 input -> BF16X3; BF16 input -> BF16.
  *  FP32:   FP32 MFMA (16x16x4), any storage type but F64.
  *  BF16:   BF16 MFMA with Z rounded to BF16 (BF16 input only).
@@ -67,7 +67,9 @@ enum { LEV_F64 = 0, LEV_F32 = 1, LEV_BF16 = 2 };
  *          2^-24 relative run on the BF16 matrix cores: FP32-level accuracy at
  *          a fraction of the FP32 matrix-core time.
  * MFMA accumulators are FP32 (FP64 for F64 input) and are flushed into FP64
- * after every contraction chunk of 8-32 columns. */
+ * after every contraction chunk of 8-32 columns.
+ * CSR A (no dense tile for the matrix cores): NATIVE or FP32 -> FP32 vector
+ * FMAs (FP64 for F64 values, NATIVE only). */
 enum { LEV_AZ_NATIVE = 0, LEV_AZ_FP32 = 1, LEV_AZ_BF16 = 2, LEV_AZ_BF16X2 = 3, LEV_AZ_BF16X3 = 4 };
 
 /* The tall input A (n x d, n >> d).
@@ -77,7 +79,9 @@ enum { LEV_AZ_NATIVE = 0, LEV_AZ_FP32 = 1, LEV_AZ_BF16 = 2, LEV_AZ_BF16X2 = 3, L
  *  CSR: row_ptr int64[n+1] (row_ptr[0] = 0, non-decreasing, row_ptr[n] =
  *    nnz), col_idx int32[nnz] strictly increasing within each row and < d,
  *    values[nnz] of `dtype`; ld is ignored.  The CSR invariants are the
- *    caller's responsibility (they are not checked on the device). */
+ *    caller's responsibility: the kernels clamp row extents to [0, nnz] and
+ *    skip column ids >= d, so a malformed matrix gives wrong scores but no
+ *    access outside the arrays (given a correct nnz). */
 typedef struct {
   int32_t format;
   int32_t dtype;
@@ -122,7 +126,7 @@ size_t lev_state_size(int64_t d, int64_t m, int64_t k);
  *  At_out     -- m x d, FP64, row-major (ld = d).
  *  SA_out     -- optional (NULL to skip): r_cs x d FP64 copy of S A.
  * S A is accumulated in FP64 in a fixed order (deterministic bits).
- * Supported: dense F64/F32/BF16 and CSR F32/F64. */
+ * Supported: dense and CSR, F64/F32/BF16 values. */
 lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out,
                       double* SA_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
@@ -151,15 +155,31 @@ lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta
  * position j).
  *  theta_out -- n entries: FP64 when A is F64, else FP32.
  *  state_out -- optional (NULL to skip): lev_state_size(d, m, k) bytes that
- *               lev_estimate_backward needs (perm, rank, R, Z, A~).
+ *               lev_estimate_backward needs (perm, rank, R, Z, A~); 256-byte
+ *               aligned.
+ * Dense (F64/F32/BF16) and CSR (F64/F32/BF16 values) input.
  * r = 0 (e.g. A = 0) gives theta~ = 0.  Zero rows give theta~_i = 0. */
 lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_out,
                         void* state_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of f(A) = sum_i w_i theta~_i with the sketch (S, G_m, G_k), the
- * pivots and the rank held fixed: gradA_out = df/dA, n x ld dense, FP32 for
- * F32 input (FP64 for F64 input).  `state` is the blob lev_estimate wrote
- * for the same A and params.  Dense F32/F64 only. */
+ * pivots K and the rank r held fixed (the paper differentiates nothing; this
+ * is the reverse of Algorithms 3, 4 and 8 step by step):
+ *   Y = A_K Z,  C = A_K^T diag(w) Y,  Zbar = 2 C,
+ *   Rbar = -triu(R11^{-T} Zbar Z^T),  A~_K bar = Q copyltu(R11 Rbar^T) R11^{-T}
+ *   (Q = A~_K R11^{-1}),  H = G^T A~_K bar,
+ *   gradA[i, K] = 2 w_i Y_i Z^T + s_i H[h(i), :],  gradA[i, not K] = 0.
+ *  A         -- the same dense matrix lev_estimate saw (F32 or F64 only;
+ *               CSR gives LEV_ERR_NOT_SUPPORTED, BF16 LEV_ERR_DTYPE).
+ *  p         -- the same parameters.
+ *  state     -- the blob lev_estimate wrote for this A and p (256-byte
+ *               aligned); it is read, not modified.  A blob from another A
+ *               or other parameters gives a meaningless gradient (its header
+ *               is not checked on the host, which would need a sync).
+ *  w         -- n weights of A's type.
+ *  gradA_out -- n x ld, A's type; columns >= d are not written.
+ * Workspace: lev_workspace_size(A, p, LEV_WS_BACKWARD).  Two passes over A
+ * (Y is recomputed in each, never stored), FP64 for the d x d core. */
 lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const void* state,
                                  const void* w, void* gradA_out, void* ws, size_t ws_bytes,
                                  hipStream_t stream);

@@ -377,3 +377,54 @@ def lev_debug_gaussian(seed: int, which: int, rows: int, cols: int, device="cuda
     _check(lib.lev_debug_gaussian(int(seed) & ((1 << 64) - 1), which, rows, cols, _ptr(out),
                                   _stream(torch.device(device))))
     return out
+
+
+def lev_estimate_backward(A, state: State, w: torch.Tensor, seed: int, r_cs: int, m: int, k: int, zeta: float,
+                          precision: str = "native") -> torch.Tensor:
+    """d(w^T theta~)/dA at the sketch, pivots and rank recorded in `state`
+    (the blob lev_estimate returned for the same A and parameters).  Dense
+    FP32/FP64 A; w has A's dtype and n entries; the gradient has A's dtype
+    and shape."""
+    lib = load_library()
+    A = _as_csr(A)
+    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
+    nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_BACKWARD)
+    if nbytes == 0:
+        _check(lib.lev_estimate_backward(ctypes.byref(mat), ctypes.byref(par), None, None, None, None, 0, None))
+    n, d = _shape(A)
+    dev = _device(A)
+    if not isinstance(w, torch.Tensor) or w.device != dev or w.dtype != _dtype(A) or w.numel() != n:
+        raise ValueError("w must be a device tensor of A's dtype with n entries")
+    w = w.contiguous()
+    _, ws = _workspace(nbytes, dev)
+    ld = A.stride(0)
+    g = torch.empty(n, ld, dtype=A.dtype, device=dev)
+    _check(lib.lev_estimate_backward(ctypes.byref(mat), ctypes.byref(par), _ptr(state.blob), _ptr(w), _ptr(g), ws,
+                                     nbytes, _stream(dev)))
+    return g[:, :d]
+
+
+class LevEstimate(torch.autograd.Function):
+    """theta~ = LS-HRN-approx(A) as a differentiable op: the forward keeps the
+    state blob (pivots, rank, R, Z, A~), the backward calls the adjoint
+    kernels with w = the incoming gradient (sketch, pivots and rank fixed)."""
+
+    @staticmethod
+    def forward(ctx, A, seed, r_cs, m, k, zeta, precision="native"):
+        theta, state = lev_estimate(A, seed, r_cs, m, k, zeta, precision=precision, return_state=True)
+        ctx.save_for_backward(A)
+        ctx.state = state
+        ctx.params = (seed, r_cs, m, k, zeta, precision)
+        return theta
+
+    @staticmethod
+    def backward(ctx, grad_theta):
+        (A,) = ctx.saved_tensors
+        w = grad_theta.to(A.dtype).contiguous()
+        gA = lev_estimate_backward(A, ctx.state, w, *ctx.params)
+        return gA, None, None, None, None, None, None
+
+
+def estimate(A: torch.Tensor, seed: int, r_cs: int, m: int, k: int, zeta: float, precision: str = "native"):
+    """theta~ with autograd support (see LevEstimate)."""
+    return LevEstimate.apply(A, seed, r_cs, m, k, zeta, precision)

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -284,6 +285,69 @@ lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, con
   return LEV_OK;
 }
 
+// ---- backward plan ---------------------------------------------------------------
+struct BwdBufs {
+  void* Zpack;       // Z_full, variant 5/6 (d x 64 of the gradient's type) + inverse perm
+  void* partials;    // groups x d x 64 elements
+  double* C64;       // d x k
+  double* Zbar;      // d x k
+  double* sq[5];     // d x d scratch
+  double* AtK;       // m x d
+  double* Abar_t;    // m x d
+  double* Gm;        // m x r_cs
+  double* H;         // r_cs x d
+  void* Hf;          // r_cs x d, gradient type
+  double* gemm_partial;
+  int groups;
+};
+
+size_t bwd_gemm_partial_elems(int64_t d, int64_t m, int64_t k, int64_t r_cs) {
+  size_t mx = 0;
+  const int64_t shapes[4][3] = {{d, d, k}, {d, d, d}, {m, d, d}, {r_cs, d, m}};
+  for (const auto& sh : shapes) {
+    const int sp = lev::dgemm_choose_splits(sh[0], sh[1], sh[2]);
+    mx = std::max(mx, lev::dgemm_partial_elems(sh[0], sh[1], sp));
+  }
+  return mx;
+}
+
+BwdBufs carve_bwd(Carver& c, const lev_matrix* A, const lev_params* p) {
+  const int64_t n = A->n, d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
+  const int dt = A->dtype == LEV_F64 ? 0 : 1;
+  const size_t es = lev::bwd_elem_size(dt);
+  BwdBufs b;
+  b.groups = lev::bwd_groups(dt, n, d, k);
+  b.Zpack = c.take<char>(lev::pack_z_bytes(dt == 0 ? 6 : 5, d, k));
+  b.partials = c.take<char>((size_t)b.groups * (size_t)d * 64 * es);
+  b.C64 = c.take<double>((size_t)(d * k));
+  b.Zbar = c.take<double>((size_t)(d * k));
+  for (int i = 0; i < 5; ++i) b.sq[i] = c.take<double>((size_t)(d * d));
+  b.AtK = c.take<double>((size_t)(m * d));
+  b.Abar_t = c.take<double>((size_t)(m * d));
+  b.Gm = c.take<double>((size_t)(m * r_cs));
+  b.H = c.take<double>((size_t)(r_cs * d));
+  b.Hf = c.take<char>((size_t)(r_cs * d) * es);
+  b.gemm_partial = c.take<double>(bwd_gemm_partial_elems(d, m, k, r_cs));
+  return b;
+}
+
+lev_status check_backward_input(const lev_matrix* A) {
+  if (A->format != LEV_DENSE_ROWMAJOR)
+    return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass takes dense A only");
+  if (A->dtype != LEV_F32 && A->dtype != LEV_F64)
+    return fail(LEV_ERR_DTYPE, "the backward pass takes FP32 or FP64 A");
+  return LEV_OK;
+}
+
+// C = alpha op(A) op(B) with the strides of launch_dgemm and the split the
+// shape calls for.
+lev_status gemm(int64_t M, int64_t N, int64_t K, const double* A, int64_t sai, int64_t sak, const double* B,
+                int64_t sbk, int64_t sbj, double* C, double* partial, hipStream_t s) {
+  const int sp = lev::dgemm_choose_splits(M, N, K);
+  return hip_check(lev::launch_dgemm(M, N, K, 1.0, A, sai, sak, B, sbk, sbj, 0.0, C, N, sp, partial, nullptr, s),
+                   "dgemm");
+}
+
 }  // namespace
 
 namespace lev {
@@ -372,6 +436,11 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
     c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, k));
     return c.used;
   }
+  if (which == LEV_WS_BACKWARD) {
+    if (check_backward_input(A) != LEV_OK) return 0;
+    carve_bwd(c, A, p);
+    return c.used;
+  }
   return 0;
 }
 
@@ -451,15 +520,58 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
 
 lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const void* state, const void* w,
                                  void* gradA_out, void* ws, size_t ws_bytes, hipStream_t stream) {
-  (void)A;
-  (void)p;
-  (void)state;
-  (void)w;
-  (void)gradA_out;
-  (void)ws;
-  (void)ws_bytes;
-  (void)stream;
-  return fail(LEV_ERR_NOT_SUPPORTED, "backward is not implemented in this build yet");
+  LEV_TRY(check_matrix(A));
+  LEV_TRY(check_params(A, p));
+  LEV_TRY(check_backward_input(A));
+  if (state == nullptr) return fail(LEV_ERR_ARG, "state is null");
+  if ((reinterpret_cast<uintptr_t>(state) & (kAlign - 1)) != 0)
+    return fail(LEV_ERR_ARG, "state must be 256-byte aligned");
+  if (A->n > 0 && (w == nullptr || gradA_out == nullptr)) return fail(LEV_ERR_ARG, "w or gradA_out is null");
+  const size_t need = lev_workspace_size(A, p, LEV_WS_BACKWARD);
+  LEV_TRY(check_ws(ws, ws_bytes, need));
+
+  const int64_t n = A->n, d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
+  const int dt = A->dtype == LEV_F64 ? 0 : 1;
+  Carver c(ws);
+  BwdBufs b = carve_bwd(c, A, p);
+  const StateView sv = carve_state(const_cast<void*>(state), d, m, k);
+  const int64_t* rank = sv.header + 4;
+  const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
+  hipStream_t s = stream;
+
+  // Z_full in the gradient's type (rows by column id, zero off K)
+  LEV_HIP(lev::launch_pack_z(dt == 0 ? 6 : 5, d, k, sv.perm, rank, sv.Z64, b.Zpack, s));
+  // C = A^T diag(w) A Z_full
+  if (n > 0) {
+    LEV_HIP(lev::launch_bwd_gram(dt, A->values, n, d, A->ld, k, w, b.Zpack, b.partials, b.groups, b.C64, s));
+  } else {
+    LEV_HIP(lev::launch_fill_zero(b.C64, sizeof(double) * (size_t)(d * k), s));
+  }
+  // The FP64 core, at d x d with zeros past the rank (the rank stays on the
+  // device): Zbar = 2 C[K]; Rbar = -triu(R11^{-T} Zbar Z^T);
+  // N = R11^{-1} copyltu(R11 Rbar^T) R11^{-T}; Abar~_K = A~_K N; H = G^T Abar~_K.
+  double *I = b.sq[0], *Rinv = b.sq[1], *T1 = b.sq[2], *X = b.sq[3], *Msym = b.sq[4];
+  LEV_HIP(lev::launch_gather_zbar(d, k, sv.perm, rank, b.C64, b.Zbar, s));
+  LEV_TRY(gemm(d, d, k, b.Zbar, k, 1, sv.Z64, 1, k, T1, b.gemm_partial, s));          // Zbar Z^T
+  LEV_HIP(lev::launch_identity(d, I, s));
+  LEV_HIP(lev::launch_trsm_z(d, d, sv.R, rank, I, Rinv, s));                           // R11^{-1}
+  LEV_TRY(gemm(d, d, d, Rinv, 1, d, T1, d, 1, X, b.gemm_partial, s));                 // R11^{-T} T1
+  LEV_HIP(lev::launch_neg_triu(d, X, s));                                              // Rbar
+  double* M1 = I;
+  LEV_TRY(gemm(d, d, d, sv.R, d, 1, X, 1, d, M1, b.gemm_partial, s));                 // R11 Rbar^T
+  LEV_HIP(lev::launch_copyltu(d, M1, Msym, s));
+  double* N1 = T1;
+  LEV_TRY(gemm(d, d, d, Rinv, d, 1, Msym, d, 1, N1, b.gemm_partial, s));              // R11^{-1} Msym
+  double* N = X;
+  LEV_TRY(gemm(d, d, d, N1, d, 1, Rinv, 1, d, N, b.gemm_partial, s));                 // ... R11^{-T}
+  LEV_HIP(lev::launch_gather_cols(m, d, sv.perm, rank, sv.At, b.AtK, s));
+  LEV_TRY(gemm(m, d, d, b.AtK, d, 1, N, d, 1, b.Abar_t, b.gemm_partial, s));          // A~_K N
+  LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, 1.0 / std::sqrt((double)m), b.Gm, s));
+  LEV_TRY(gemm(r_cs, d, m, b.Gm, 1, r_cs, b.Abar_t, d, 1, b.H, b.gemm_partial, s));   // G^T Abar~_K
+  LEV_HIP(lev::launch_scatter_h(dt, r_cs, d, sv.perm, rank, b.H, b.Hf, s));
+  // Abar = 2 diag(w) A Z_full Z_full^T + S^T H_full
+  LEV_HIP(lev::launch_bwd_grad(dt, A->values, n, d, A->ld, k, w, b.Zpack, b.Hf, dr.hash, gradA_out, A->ld, s));
+  return LEV_OK;
 }
 
 lev_status lev_debug_hash(uint64_t seed, int64_t n, int64_t r_cs, int64_t* h_out, int8_t* s_out,

@@ -112,6 +112,28 @@ hipError_t launch_rownorm_csr(int dtype, const void* vals, const int64_t* row_pt
                               int64_t n, int64_t d, int64_t nnz, const void* Zpack, void* theta,
                               hipStream_t s);
 
+// ---- backward (adjoint of w^T theta~ at a fixed sketch) ----------------------
+// dtype 0 = FP64, 1 = FP32 (A, w, Z_full, H_full and the gradient share it).
+// Z_full is the variant-5/6 packing (d rows of 64).
+int bwd_groups(int dtype, int64_t n, int64_t d, int64_t k);
+size_t bwd_elem_size(int dtype);
+// C64 (d x k, FP64) = A^T diag(w) A Z_full; partials: groups x d x 64 elements.
+hipError_t launch_bwd_gram(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, int64_t k, const void* w,
+                           const void* Zfull, void* partials, int groups, double* C64, hipStream_t s);
+// G (n x ldg) = 2 diag(w) A Z_full Z_full^T + S^T H_full (H_full r_cs x d).
+hipError_t launch_bwd_grad(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, int64_t k, const void* w,
+                           const void* Zfull, const void* Hfull, const HashParams& hp, void* G, int64_t ldg,
+                           hipStream_t s);
+hipError_t launch_gather_zbar(int64_t d, int64_t k, const int32_t* perm, const int64_t* rank, const double* C64,
+                              double* Zbar, hipStream_t s);
+hipError_t launch_neg_triu(int64_t d, double* X, hipStream_t s);
+hipError_t launch_copyltu(int64_t d, const double* M, double* out, hipStream_t s);
+hipError_t launch_identity(int64_t d, double* I, hipStream_t s);
+hipError_t launch_gather_cols(int64_t m, int64_t d, const int32_t* perm, const int64_t* rank, const double* At,
+                              double* AtK, hipStream_t s);
+hipError_t launch_scatter_h(int dtype, int64_t rows, int64_t d, const int32_t* perm, const int64_t* rank,
+                            const double* H, void* Hf, hipStream_t s);
+
 // dst[0..3] = (a, b, c, e) from a kernel (capture-safe small header write).
 hipError_t launch_store_i64x4(int64_t* dst, int64_t a, int64_t b, int64_t c, int64_t e, hipStream_t s);
 
