@@ -4,7 +4,8 @@
 
 One step = one lev_estimate call over the whole workload resident in HBM:
 Gaussian draws, pass 1 (CountSketch S A), the Gaussian transform, the
-rank-revealing factorisation, Z = R11^{-1} G_k and pass 2 (theta~).  Prints
+rank-revealing factorisation, Z = R11^{-1} G_k and pass 2 (theta~); for the
+backward workload (name ending in _bwd) also the adjoint of w^T theta~.  Prints
 one JSON line with rows/s, the per-phase times, the roofline of the
 dominant kernel (HBM-bound pass 2) measured live with HIP events, and the
 CPU oracle timed on a bounded sample of the same workload.
@@ -44,7 +45,8 @@ def make_workload(name: str, device):
     cfg = dict(W.CONFIGS[name])
     idx = list(W.CONFIGS).index(name) + 1
     if name.startswith("dense_f32"):
-        A = W.low_rank_coherent(cfg["n"], cfg["d"], cfg["rank"], W.data_seed(idx), device=device)
+        heavy = 0.0 if name.endswith("_bwd") else 0.01  # the backward workload has no heavy rows
+        A = W.low_rank_coherent(cfg["n"], cfg["d"], cfg["rank"], W.data_seed(idx), heavy_frac=heavy, device=device)
     elif name.startswith("dense_f64"):
         A = W.dense_gaussian(cfg["n"], cfg["d"], W.data_seed(idx), dtype=torch.float64, device=device)
     elif name.startswith("dense_bf16"):
@@ -138,8 +140,14 @@ def main():
     print(f"# generating workload {args.workload}", file=sys.stderr, flush=True)
     A, cfg, seed = make_workload(args.workload, dev)
     plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=args.precision)
+    backward = args.workload.endswith("_bwd")
+    if backward:
+        bwd = api.BackwardPlan(plan, torch.rand(A.shape[0], device=dev, dtype=A.dtype,
+                                                generator=torch.Generator(device=dev).manual_seed(5)))
     for _ in range(args.warmup):
         plan.run()
+        if backward:
+            bwd.run()
     torch.cuda.synchronize()
     print("# warmup done", file=sys.stderr, flush=True)
 
@@ -154,10 +162,15 @@ def main():
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    bwd_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     t_start.record(stream)
     for s in range(args.steps):
         api.lev_set_phase_events(ev[s])
         plan.run()
+        if backward:
+            bwd_ev[s][0].record(stream)
+            bwd.run()
+            bwd_ev[s][1].record(stream)
     t_end.record(stream)
     torch.cuda.synchronize()
     api.lev_set_phase_events(None)
@@ -195,6 +208,10 @@ def main():
         "pass1_hbm_gbs": pass1_gbs,
         "pass1_frac": pass1_gbs / HBM_PEAK_GBS,
     }
+    if backward:
+        bms = float(np.mean([e[0].elapsed_time(e[1]) for e in bwd_ev]))
+        out["backward_ms"] = bms
+        out["backward_hbm_gbs"] = 3 * a_bytes(A) / (bms * 1e-3) / 1e9  # two reads of A, one write of the gradient
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(A, cfg, seed)

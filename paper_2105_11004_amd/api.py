@@ -339,6 +339,36 @@ class EstimatePlan:
         return self.theta
 
 
+class BackwardPlan:
+    """Pre-allocated workspace, state and gradient for repeated
+    lev_estimate_backward calls after an EstimatePlan's forward (the
+    benchmark's backward step)."""
+
+    def __init__(self, plan: "EstimatePlan", w: torch.Tensor):
+        self.plan, self.lib = plan, plan.lib
+        A = plan.A
+        n, d = _shape(A)
+        p = plan.par
+        self.state = State(_aligned_blob(self.lib.lev_state_size(d, p.m, p.k), plan.device), d, p.m, p.k)
+        self.nbytes = self.lib.lev_workspace_size(ctypes.byref(plan.mat), ctypes.byref(p), WS_BACKWARD)
+        if self.nbytes == 0:
+            _check(self.lib.lev_estimate_backward(ctypes.byref(plan.mat), ctypes.byref(p), None, None, None, None,
+                                                  0, None))
+        self._buf, self.ws = _workspace(self.nbytes, plan.device)
+        self.w = w.contiguous()
+        self.grad = torch.empty(n, A.stride(0), dtype=A.dtype, device=plan.device)
+        # the forward that fills the state
+        _check(self.lib.lev_estimate(ctypes.byref(plan.mat), ctypes.byref(p), _ptr(plan.theta), _ptr(self.state.blob),
+                                     plan.ws, plan.nbytes, _stream(plan.device)))
+
+    def run(self):
+        p = self.plan
+        _check(self.lib.lev_estimate_backward(ctypes.byref(p.mat), ctypes.byref(p.par), _ptr(self.state.blob),
+                                              _ptr(self.w), _ptr(self.grad), self.ws, self.nbytes,
+                                              _stream(p.device)))
+        return self.grad
+
+
 def lev_set_phase_events(events):
     """Registers LEV_PHASES torch.cuda.Event objects (already recorded once,
     so that they exist) for the phase boundaries of following lev_estimate

@@ -5,8 +5,10 @@
 // column-pivoted factorisation, and the rank-nb Schur complement updates of
 // that factorisation.  All are small next to the passes over A, so this is a
 // plain LDS-tiled kernel: 64 x 64 output tile per workgroup of 4 waves
-// (each wave a 32 x 32 quadrant = 2 x 2 MFMA blocks), K in steps of 16,
-// optional split-K with a fixed-order reduction (deterministic bits).
+// (each wave a 32 x 32 quadrant = 2 x 2 MFMA blocks), K in steps of 32
+// through double-buffered LDS with the next step's global loads in flight
+// during the current step's MFMAs, optional split-K with a fixed-order
+// reduction (deterministic bits).
 //
 // MFMA operand layout (16x16x4 f64, wave64): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; accumulator element v of lane l is
@@ -24,18 +26,62 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int kThreads = 256;
+constexpr int kPerThread = BM * BK / kThreads;  // elements of each operand a thread stages per K step
 
-__global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                    const double* __restrict__ A, int64_t sai,
-                                                    int64_t sak, const double* __restrict__ B,
-                                                    int64_t sbk, int64_t sbj, double beta,
-                                                    double* __restrict__ C, int64_t ldc, int splits,
-                                                    int64_t kchunk, double* __restrict__ partial,
-                                                    const int32_t* __restrict__ skip) {
+// One K step of the A and B tiles held in registers between the global
+// loads and the LDS stores (the loads of step s + 1 are in flight while the
+// matrix cores work on step s).
+struct Stage {
+  double a[kPerThread];
+  double b[kPerThread];
+};
+
+__device__ __forceinline__ void load_stage(Stage& st, int tid, int64_t m0, int64_t n0, int64_t k0, int64_t ke,
+                                           int64_t M, int64_t N, const double* __restrict__ A, int64_t sai,
+                                           int64_t sak, const double* __restrict__ B, int64_t sbk, int64_t sbj) {
+  const bool a_kfast = (sak == 1);
+  const bool b_jfast = (sbj == 1);
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int e = tid + kThreads * q;
+    // consecutive threads walk the operand's contiguous index
+    const int kk = a_kfast ? e % BK : e / BM;
+    const int ii = a_kfast ? e / BK : e % BM;
+    const int64_t gi = m0 + ii, gk = k0 + kk;
+    st.a[q] = (gi < M && gk < ke) ? A[gi * sai + gk * sak] : 0.0;
+    const int kb = b_jfast ? e / BN : e % BK;
+    const int jj = b_jfast ? e % BN : e / BK;
+    const int64_t gj = n0 + jj, gk2 = k0 + kb;
+    st.b[q] = (gj < N && gk2 < ke) ? B[gk2 * sbk + gj * sbj] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void store_stage(const Stage& st, int tid, bool a_kfast, bool b_jfast,
+                                            double (*As)[BM + 1], double (*Bs)[BN + 1]) {
+#pragma unroll
+  for (int q = 0; q < kPerThread; ++q) {
+    const int e = tid + kThreads * q;
+    const int kk = a_kfast ? e % BK : e / BM;
+    const int ii = a_kfast ? e / BK : e % BM;
+    As[kk][ii] = st.a[q];
+    const int kb = b_jfast ? e / BN : e % BK;
+    const int jj = b_jfast ? e % BN : e / BK;
+    Bs[kb][jj] = st.b[q];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
+                                                         const double* __restrict__ A, int64_t sai,
+                                                         int64_t sak, const double* __restrict__ B,
+                                                         int64_t sbk, int64_t sbj, double beta,
+                                                         double* __restrict__ C, int64_t ldc, int splits,
+                                                         int64_t kchunk, double* __restrict__ partial,
+                                                         const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip != 0) return;
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  __shared__ double As[2][BK][BM + 1];
+  __shared__ double Bs[2][BK][BN + 1];
 
   const int64_t m0 = (int64_t)blockIdx.x * BM;
   const int64_t n0 = (int64_t)blockIdx.y * BN;
@@ -53,46 +99,33 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
+  Stage st;
+  int buf = 0;
+  if (kb < ke) {
+    load_stage(st, tid, m0, n0, kb, ke, M, N, A, sai, sak, B, sbk, sbj);
+    store_stage(st, tid, a_kfast, b_jfast, As[0], Bs[0]);
+  }
+  __syncthreads();
   for (int64_t k0 = kb; k0 < ke; k0 += BK) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = tid + 256 * q;
-      int kk, ii;
-      if (a_kfast) {
-        kk = e % BK;
-        ii = e / BK;
-      } else {
-        kk = e / BM;
-        ii = e % BM;
-      }
-      const int64_t gi = m0 + ii, gk = k0 + kk;
-      As[kk][ii] = (gi < M && gk < ke) ? A[gi * sai + gk * sak] : 0.0;
-      int kb2, jj;
-      if (b_jfast) {
-        kb2 = e / BN;
-        jj = e % BN;
-      } else {
-        kb2 = e % BK;
-        jj = e / BK;
-      }
-      const int64_t gj = n0 + jj, gk2 = k0 + kb2;
-      Bs[kb2][jj] = (gj < N && gk2 < ke) ? B[gk2 * sbk + gj * sbj] : 0.0;
-    }
-    __syncthreads();
+    const bool more = k0 + BK < ke;  // uniform
+    if (more) load_stage(st, tid, m0, n0, k0 + BK, ke, M, N, A, sai, sak, B, sbk, sbj);
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
       double a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[k4 + (lane >> 4)][wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < 2; ++i) a[i] = As[buf][k4 + (lane >> 4)][wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[k4 + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][k4 + (lane >> 4)][wn + 16 * j + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    // the other buffer was last read before the previous barrier
+    if (more) store_stage(st, tid, a_kfast, b_jfast, As[buf ^ 1], Bs[buf ^ 1]);
     __syncthreads();
+    buf ^= 1;
   }
 
 #pragma unroll
@@ -132,8 +165,9 @@ __global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, const dou
 int dgemm_choose_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   int splits = 1;
-  // Aim for >= 512 workgroups (2 per CU) while each split keeps >= 256 of K.
-  while (tiles * splits < 512 && K / (splits * 2) >= 256 && splits < 64) splits *= 2;
+  // Aim for >= 512 workgroups (2 per CU) while each split keeps >= 128 of K
+  // (four K steps, so the prefetch of the next step has work to hide behind).
+  while (tiles * splits < 512 && K / (splits * 2) >= 128 && splits < 64) splits *= 2;
   return splits;
 }
 
@@ -151,7 +185,7 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const dou
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   if (kchunk == 0) kchunk = BK;
   dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
-  dgemm_kernel<<<grid, 256, 0, s>>>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc, splits,
+  dgemm_kernel<<<grid, kThreads, 0, s>>>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc, splits,
                                     kchunk, partial, skip);
   if (splits > 1) {
     const int64_t total = M * N;

@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "lev_internal.h"
 
 namespace lev {
@@ -209,7 +211,15 @@ __device__ __forceinline__ T sum16(T x) {
 }
 
 constexpr int kThreads = 512;
-constexpr int kBatch = 8;  // chunks loaded per batch (loads in flight per lane)
+// Chunks loaded per batch (loads in flight per lane).  BF16x3 keeps its
+// batch at 4 so the kernel stays under 128 VGPRs (four waves per SIMD).
+template <int VAR>
+constexpr int batch_of() { return VAR == 4 ? 4 : 8; }
+// Chunks accumulated in FP32 before the flush into FP64 (one: flushing
+// every second chunk saves ~3% of the pass and triples the worst FP32
+// error on small coherent inputs).
+template <int VAR>
+constexpr int flush_of() { return 1; }
 
 // Zpack: part p of vector (t, cb, lane) at index p * part_vecs + (t*CB + cb)*64 + lane.
 template <int VAR, typename TA, int CB, bool ZLDS>
@@ -220,6 +230,7 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
                                                                  void* __restrict__ theta) {
   using F = Frag<VAR, TA>;
   using AccT = typename Acc<VAR>::T;
+  constexpr int kBatch = batch_of<VAR>();
   extern __shared__ uint4 zs[];
   const uint4* Z = Zg;
   if constexpr (ZLDS) {
@@ -238,7 +249,8 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
     const TA* rp = A + (ok ? row : 0) * ld;
     AccT acc[CB];
     // FP32 forms: the matrix-core accumulator is flushed into FP64 after
-    // every chunk, so FP32 rounding only ever sums one chunk's products.
+    // every flush_of<VAR>() chunks, so FP32 rounding only ever sums a few
+    // dozen products.
     double acc64[CB][4];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
@@ -284,11 +296,13 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
             }
           }
           if constexpr (VAR != 0) {
+            if ((u + 1) % flush_of<VAR>() == 0 || t + 1 == nt) {
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
+              for (int cb = 0; cb < CB; ++cb) {
 #pragma unroll
-              for (int v = 0; v < 4; ++v) acc64[cb][v] += (double)acc[cb][v];
-              acc[cb] = AccT{};
+                for (int v = 0; v < 4; ++v) acc64[cb][v] += (double)acc[cb][v];
+                acc[cb] = AccT{};
+              }
             }
           }
         }
@@ -332,23 +346,32 @@ hipError_t launch_cb(const void* A, int64_t n, int64_t d, int64_t ld, int64_t nt
   const int64_t zvecs = (int64_t)(zbytes / 16);
   const int64_t part_vecs = zvecs / F::NZ;
   const int64_t ntiles = (n + 15) / 16;
-  int64_t blocks = (ntiles + (kThreads / 64) - 1) / (kThreads / 64);
-  const int64_t max_blocks = 256 * 4;
-  if (blocks > max_blocks) blocks = max_blocks;
-  if (blocks < 1) blocks = 1;
+  const int64_t want = (ntiles + (kThreads / 64) - 1) / (kThreads / 64);
   const TA* a = static_cast<const TA*>(A);
   const uint4* z = static_cast<const uint4*>(Zpack);
+  int dev = 0, num_cu = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  // a persistent grid of exactly the resident workgroups: every wave strides
+  // over the 16-row tiles, so no tail of half-empty rounds
   if (zbytes <= kMaxLdsZ) {
     auto kern = rownorm_dense_kernel<VAR, TA, CB, true>;
     if (zbytes > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)zbytes);
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)zbytes);
       if (e != hipSuccess) return e;
     }
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, zbytes);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * std::max(per_cu, 1)));
     kern<<<(unsigned)blocks, kThreads, zbytes, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta);
   } else {
-    rownorm_dense_kernel<VAR, TA, CB, false><<<(unsigned)blocks, kThreads, 0, s>>>(a, n, d, ld, nt, z, zvecs,
-                                                                                   part_vecs, theta);
+    auto kern = rownorm_dense_kernel<VAR, TA, CB, false>;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * std::max(per_cu, 1)));
+    kern<<<(unsigned)blocks, kThreads, 0, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta);
   }
   return hipGetLastError();
 }
