@@ -43,75 +43,83 @@ __global__ __launch_bounds__(64) void trsm_z_kernel(int64_t d, int64_t k, const 
   }
 }
 
-// r <= 256, k <= 64: one workgroup of 16 waves.  Lane c of wave q holds
-// column c of the right-hand side for rows t = 16 s + q (s < 16) in
-// registers.  Column-oriented back substitution: at step j the owner of row
-// j (wave j % 16) finishes z_j = g'_j / R_jj and publishes it through LDS;
-// after one barrier every lane applies g'_t -= R[t][j] z_j to its rows
-// t < j.  R11 is staged through LDS 16 columns at a time (double-buffered),
-// so the loop reads no global memory.
+// r <= 256: one workgroup of 16 waves per group of 64 right-hand sides
+// (grid.y).  Wave w holds row block w (rows 16 w .. 16 w + 15) of the
+// right-hand side, lane c column c, in registers.  Blocked back
+// substitution from the last block: the owner wave of block b solves its
+// 16 x 16 diagonal triangle in-lane (no cross-lane traffic), publishes the
+// block of Z through LDS, and every wave above applies the 16 x 16 update
+// G_w -= R[w, b] Z_b.  R's 16-column panel of block b is staged in LDS
+// (double-buffered), so the loop reads no global memory; r / 16 block steps
+// instead of r row steps.
 constexpr int kTrsmR = 256;
 typedef double v16d __attribute__((ext_vector_type(16)));
-constexpr int kTrsmCols = 16;
 
-__global__ __launch_bounds__(1024) void trsm_small_kernel(int64_t d, int64_t k, const double* __restrict__ R,
-                                                          const int64_t* __restrict__ rank,
-                                                          const double* __restrict__ Gk,
-                                                          double* __restrict__ Z64) {
-  __shared__ double rblk[2][kTrsmR][kTrsmCols];  // 64 KB: R[0:r, 16-column block]
-  __shared__ double zrow[2][64];
-  const int c = threadIdx.x & 63;
-  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+__global__ __launch_bounds__(1024) void trsm_blocked_kernel(int64_t d, int64_t k, const double* __restrict__ R,
+                                                            const int64_t* __restrict__ rank,
+                                                            const double* __restrict__ Gk,
+                                                            double* __restrict__ Z64) {
+  __shared__ double rpan[2][kTrsmR][16];  // 64 KB: R[0:r, 16 b .. 16 b + 15]
+  __shared__ double zblk[2][16][64];      // the block of Z just solved
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t c = (int64_t)blockIdx.y * 64 + lane;
   const int r = (int)*rank;
   const bool col_ok = c < k;
 
-  v16d g;  // SSA vector: uniform-index access becomes an indexed register move
+  v16d g;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const int t = 16 * s + q;
+    const int t = 16 * w + s;
     g[s] = (col_ok && t < r) ? Gk[(int64_t)t * k + c] : 0.0;
   }
-  // rows >= r of Z are zero
-  for (int64_t t = r + q; t < d; t += 16)
+  for (int64_t t = r + w; t < d; t += 16)
     if (col_ok) Z64[t * k + c] = 0.0;
   if (r == 0) return;
 
-  // stage the 16-column block holding column j (blocks descend)
   auto stage = [&](int blk, int buf) {
-    for (int e = threadIdx.x; e < r * kTrsmCols; e += blockDim.x) {
-      const int t = e / kTrsmCols, cc = e % kTrsmCols;
-      const int col = blk * kTrsmCols + cc;
-      rblk[buf][t][cc] = (col < r) ? R[(int64_t)t * d + col] : 0.0;
+    const int rows = 16 * (blk + 1);  // rows 0 .. 16 blk + 15 use this panel
+    for (int e = threadIdx.x; e < rows * 16; e += blockDim.x) {
+      const int t = e / 16, cc = e % 16;
+      const int col = 16 * blk + cc;
+      rpan[buf][t][cc] = (t < r && col < r) ? R[(int64_t)t * d + col] : 0.0;
     }
   };
-  int blk = (r - 1) / kTrsmCols;
-  stage(blk, blk & 1);
+  const int nblk = (r + 15) / 16;
+  stage(nblk - 1, (nblk - 1) & 1);
   __syncthreads();
-  for (int j = r - 1; j >= 0; --j) {
-    const int jb = j / kTrsmCols;
-    if (jb != blk) {  // uniform: next block was prefetched at the previous step
-      blk = jb;
-      __syncthreads();
-    }
-    if (j % kTrsmCols == 0 && jb > 0) stage(jb - 1, (jb - 1) & 1);  // prefetch next block
-    const int buf = jb & 1, cj = j % kTrsmCols;
-    if (q == (j & 15)) {
-      const int sj = __builtin_amdgcn_readfirstlane(j >> 4);
-      const double zj = g[sj] / rblk[buf][j][cj];
-      g[sj] = zj;
-      zrow[j & 1][c] = zj;
-    }
-    __syncthreads();
-    const double zj = zrow[j & 1][c];
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const int buf = blk & 1;
+    if (w == blk) {
+      // rows past the rank stay zero (R has zero rows there)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const int t = 16 * s + q;
-      if (t < j) g[s] = fma(-rblk[buf][t][cj], zj, g[s]);
+      for (int s = 15; s >= 0; --s) {
+        double x = g[s];
+#pragma unroll
+        for (int e = s + 1; e < 16; ++e) x = fma(-rpan[buf][16 * blk + s][e], g[e], x);
+        g[s] = (16 * blk + s < r) ? x / rpan[buf][16 * blk + s][s] : 0.0;
+        zblk[buf][s][lane] = g[s];
+      }
     }
+    if (blk > 0) stage(blk - 1, buf ^ 1);
+    __syncthreads();
+    if (w < blk) {
+      double z[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) z[e] = zblk[buf][e][lane];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        double x = g[s];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x = fma(-rpan[buf][16 * w + s][e], z[e], x);
+        g[s] = x;
+      }
+    }
+    __syncthreads();  // rpan[buf] and zblk[buf] are rewritten two steps later
   }
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const int t = 16 * s + q;
+    const int t = 16 * w + s;
     if (col_ok && t < r) Z64[(int64_t)t * k + c] = g[s];
   }
 }
@@ -187,8 +195,8 @@ constexpr int parts(int variant) { return variant == 3 ? 2 : (variant == 4 ? 3 :
 
 hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, const double* Gk,
                          double* Z64, hipStream_t s) {
-  if (d <= kTrsmR && k <= 64) {
-    trsm_small_kernel<<<1, 1024, 0, s>>>(d, k, R, rank, Gk, Z64);
+  if (d <= kTrsmR) {
+    trsm_blocked_kernel<<<dim3(1, (unsigned)((k + 63) / 64)), 1024, 0, s>>>(d, k, R, rank, Gk, Z64);
   } else {
     trsm_z_kernel<<<(unsigned)k, 64, (size_t)d * sizeof(double), s>>>(d, k, R, rank, Gk, Z64);
   }
