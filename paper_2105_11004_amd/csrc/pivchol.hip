@@ -146,19 +146,20 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
 // Schur complement resident in registers (right-looking pivoted Cholesky).
 //
 // The d x d matrix is tiled by 64 x 64 squares that cover its lower triangle
-// (10 for d = 256); wave w owns square (a, b) and lane l of that wave holds
-// row 64a + l, columns 64b .. 64b + 63 in 128 registers (at most 3 waves per
-// SIMD, so up to 170 registers per lane).  The waves with b = 0 own the
-// diagonal too: row i's Schur diagonal sits in a register of lane i % 64,
-// updated as d_i -= l_i^2.
+// (10 for d = 256); "square" wave w owns square (a, b) and lane l of that wave
+// holds row 64a + l, columns 64b .. 64b + 63 in 128 registers.  Two more
+// "diagonal" waves own the Schur diagonal: lane l of diagonal wave q holds
+// d_i for rows i = 128 q + l and 128 q + 64 + l, updated as d_i -= l_i^2.
+// Twelve waves (three per SIMD) leave up to 170 registers per lane.
 //
-// Per pivot step (two barriers): every wave reads the four per-band
-// candidates (value, index, sqrt, 1/sqrt) left by the previous step and takes
-// the best, p; the owners of column p (rows i >= p) and of row p (columns
-// j < p) publish l = S[:, p] / sqrt(S_pp) to LDS; after the barrier every lane
-// applies S -= l l^T to its entries, the diagonal owners update their d_i and
-// leave their band's argmax (DPP wave reduction) for the next step.  No global
-// memory is read inside the loop; the row R[J, :] = l is stored.
+// Per pivot step (two barriers): every wave reads the per-diagonal-wave
+// candidates (value, index) left by the previous step and takes the best, p,
+// with 1/sqrt(S_pp) from the hardware estimate plus two Newton steps; the
+// owners of column p (rows i >= p) and of row p (columns j < p) publish
+// l = S[:, p] / sqrt(S_pp) to LDS; after the barrier the square waves apply
+// S -= l l^T to their entries while the diagonal waves, at the same time,
+// update d, store R[J, :] = l and leave their argmax (DPP wave reduction) for
+// the next step.  No global memory is read inside the loop.
 constexpr int kSmallD = 256;
 constexpr int kBandR = 64, kBandC = 64;
 constexpr int kLvec = 256;  // >= 64 * ceil(256 / 64)
@@ -224,26 +225,34 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 struct Cand {
-  double v, rpp, inv;
+  double v;
   int idx;
 };
+constexpr int kDiagRows = 128;  // rows per diagonal wave (two per lane)
 
-__global__ __launch_bounds__(640) void pivchol_small_kernel(const double* __restrict__ B, int d, double zeta,
+__host__ __device__ inline int small_diag_waves(int d) { return (d + kDiagRows - 1) / kDiagRows; }
+
+__global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __restrict__ B, int d, double zeta,
                                                             PivCholState st, int64_t* __restrict__ rank_out) {
   __shared__ __align__(16) double lvec[kLvec];
-  __shared__ Cand cand[4];
+  __shared__ Cand cand[kSmallD / kDiagRows];
 
   const int lane = threadIdx.x & 63;
   // wave-uniform values kept scalar (the compiler cannot infer it)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int a, b;
-  small_rect(wave, d, a, b);
+  const int nrect = small_rects(d);
+  const bool square = wave < nrect;  // uniform
+  const int ndiag = small_diag_waves(d);
+  int a = 0, b = 0;
+  if (square) small_rect(wave, d, a, b);
   a = __builtin_amdgcn_readfirstlane(a);
   b = __builtin_amdgcn_readfirstlane(b);
-  const int i = kBandR * a + lane;  // my row
+  const int i = kBandR * a + lane;  // my row (square waves)
   const int j0 = kBandC * b;        // my first column
-  const bool row_ok = i < d;
-  const int nbands = (d + kBandR - 1) / kBandR;
+  const bool row_ok = square && i < d;
+  const int q = wave - nrect;                  // diagonal wave index
+  const int i0 = kDiagRows * q + lane;         // my two diagonal rows
+  const int i1 = i0 + 64;
 
   v16d s0, s1, s2, s3;
   {
@@ -265,28 +274,25 @@ __global__ __launch_bounds__(640) void pivchol_small_kernel(const double* __rest
     LEV_LOAD16(s0, 0) LEV_LOAD16(s1, 16) LEV_LOAD16(s2, 32) LEV_LOAD16(s3, 48)
 #undef LEV_LOAD16
   }
-  for (int q = threadIdx.x; q < kLvec; q += blockDim.x) lvec[q] = 0.0;
+  for (int t = threadIdx.x; t < kLvec; t += blockDim.x) lvec[t] = 0.0;
 
-  // diagonal owners: d_i in a register; leave the band's candidate
-  double dg = -INFINITY;
+  // diagonal waves: d_i in registers; leave the wave's candidate
+  double dg0 = -INFINITY, dg1 = -INFINITY;
   auto publish_candidate = [&]() {
-    const double m = wave_max_f64(dg);
-    const unsigned long long hit = __ballot(dg == m && dg != -INFINITY);
+    const double m = wave_max_f64(fmax(dg0, dg1));
+    const unsigned long long h0 = __ballot(dg0 == m && dg0 != -INFINITY);
+    const unsigned long long h1 = __ballot(dg1 == m && dg1 != -INFINITY);
     if (lane == 0) {
       Cand cd;
       cd.v = m;
-      cd.idx = hit ? kBandR * a + __builtin_ctzll(hit) : 0x7fffffff;
-      // 1/sqrt(m): hardware estimate + two Newton steps (~1 ulp); sqrt = m/sqrt
-      double y = __builtin_amdgcn_rsq(m);
-      y = y * fma(-0.5 * m * y, y, 1.5);
-      y = y * fma(-0.5 * m * y, y, 1.5);
-      cd.inv = m > 0.0 ? y : 0.0;
-      cd.rpp = m > 0.0 ? m * y : 0.0;
-      cand[a] = cd;
+      cd.idx = h0 ? kDiagRows * q + __builtin_ctzll(h0)
+                  : (h1 ? kDiagRows * q + 64 + __builtin_ctzll(h1) : 0x7fffffff);
+      cand[q] = cd;
     }
   };
-  if (b == 0) {
-    if (row_ok) dg = B[(int64_t)i * d + i];
+  if (!square) {
+    if (i0 < d) dg0 = B[(int64_t)i0 * d + i0];
+    if (i1 < d) dg1 = B[(int64_t)i1 * d + i1];
     publish_candidate();
   }
   __syncthreads();
@@ -294,63 +300,107 @@ __global__ __launch_bounds__(640) void pivchol_small_kernel(const double* __rest
   double r00 = 0.0;
   int J = 0;
   for (; J < d; ++J) {
-    Cand best = cand[0];
-    for (int t = 1; t < nbands; ++t) {
-      const Cand c2 = cand[t];
-      if (c2.v > best.v || (c2.v == best.v && c2.idx < best.idx)) best = c2;
-    }
-    const double pv = best.v;
+    // the best candidate (larger value, ties to the lower index): all reads
+    // issued together
+    Cand cs[kSmallD / kDiagRows];
+#pragma unroll
+    for (int t = 0; t < kSmallD / kDiagRows; ++t) cs[t] = cand[t < ndiag ? t : 0];
+    Cand best = cs[0];
+#pragma unroll
+    for (int t = 1; t < kSmallD / kDiagRows; ++t)
+      if (t < ndiag && (cs[t].v > best.v || (cs[t].v == best.v && cs[t].idx < best.idx))) best = cs[t];
+    // uniform by construction: kept in scalar registers
+    const double pv = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(best.v)),
+                                       __builtin_amdgcn_readfirstlane(__double2loint(best.v)));
     const int p = __builtin_amdgcn_readfirstlane(best.idx);
-    if (J == 0) r00 = best.rpp;
-    if (!(pv > 0.0) || !(best.rpp > zeta * r00)) break;  // uniform
-    const double rpp = best.rpp, inv = best.inv;
-    // row p: the lane holding row p in each rectangle with b <= b_p writes
-    // its 64 entries (columns >= p duplicate the column-p owners' writes
-    // below with identical bits, S being symmetric)
-    if (a == p / kBandR && lane == (p & (kBandR - 1)) && b <= p / kBandC) {
-      double2* dst = reinterpret_cast<double2*>(&lvec[j0]);
+    // 1/sqrt(pv): hardware estimate + two Newton steps (~1 ulp); sqrt = pv/sqrt
+    double y = __builtin_amdgcn_rsq(pv);
+    y = y * fma(-0.5 * pv * y, y, 1.5);
+    y = y * fma(-0.5 * pv * y, y, 1.5);
+    y = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(y)),
+                         __builtin_amdgcn_readfirstlane(__double2loint(y)));
+    const double inv = pv > 0.0 ? y : 0.0;
+    const double rpp = pv > 0.0 ? pv * y : 0.0;
+    if (J == 0) r00 = rpp;
+    if (!(pv > 0.0) || !(rpp > zeta * r00)) break;  // uniform
+    if (square) {
+      // row p: the lane holding row p in each square with b <= b_p writes
+      // its 64 entries (columns >= p duplicate the column-p owners' writes
+      // below with identical bits, S being symmetric)
+      if (a == p / kBandR && lane == (p & (kBandR - 1)) && b <= p / kBandC) {
+        double2* dst = reinterpret_cast<double2*>(&lvec[j0]);
 #define LEV_PUT16(V, OFF) \
   _Pragma("unroll") for (int e = 0; e < 16; e += 2) dst[((OFF) + e) / 2] = make_double2(V[e] * inv, V[e + 1] * inv);
-      LEV_PUT16(s0, 0) LEV_PUT16(s1, 16) LEV_PUT16(s2, 32) LEV_PUT16(s3, 48)
+        LEV_PUT16(s0, 0) LEV_PUT16(s1, 16) LEV_PUT16(s2, 32) LEV_PUT16(s3, 48)
 #undef LEV_PUT16
-    }
-    // column p, rows i >= p; the entry is picked with a uniform-index
-    // register extract
-    if (b == p / kBandC) {
-      const int cp = __builtin_amdgcn_readfirstlane(p - j0);
-      const int e = cp & 15, blk = cp >> 4;
-      const double v0 = s0[e], v1 = s1[e], v2 = s2[e], v3 = s3[e];
-      const double v = blk == 0 ? v0 : (blk == 1 ? v1 : (blk == 2 ? v2 : v3));
-      if (row_ok && i >= p) lvec[i] = v * inv;
+      }
+      // column p, rows i >= p; the entry is picked with a uniform-index
+      // register extract
+      if (b == p / kBandC) {
+        const int cp = __builtin_amdgcn_readfirstlane(p - j0);
+        const int e = cp & 15, blk = cp >> 4;
+        const double v0 = s0[e], v1 = s1[e], v2 = s2[e], v3 = s3[e];
+        const double v = blk == 0 ? v0 : (blk == 1 ? v1 : (blk == 2 ? v2 : v3));
+        if (row_ok && i >= p) lvec[i] = v * inv;
+      }
     }
     lds_barrier();
-    const double li = row_ok ? lvec[i] : 0.0;
-    // 8 groups of 8 columns; the LDS reads of group g + 1 are issued before
-    // the FMAs of group g, and each FMA result is pinned in place so the
-    // compiler neither sinks the FMAs nor hoists every read of the step
-    double lj[2][8];
-#define LEV_READ8(buf, OFF) \
-  _Pragma("unroll") for (int e = 0; e < 8; ++e) lj[buf][e] = lvec[j0 + (OFF) + e];
-#define LEV_FMA8(buf, V, E0)                                               \
-  _Pragma("unroll") for (int e = 0; e < 8; ++e) {                          \
+    if (square) {
+      const double li = row_ok ? lvec[i] : 0.0;
+      // 32 groups of 2 columns; the LDS reads of group g + 1 are issued
+      // before the FMAs of group g, and each FMA result is pinned in place so
+      // the compiler neither sinks the FMAs nor hoists every read of the step
+      double lj[2][2];
+#define LEV_READ2(buf, OFF) \
+  _Pragma("unroll") for (int e = 0; e < 2; ++e) lj[buf][e] = lvec[j0 + (OFF) + e];
+#define LEV_FMA2(buf, V, E0)                                               \
+  _Pragma("unroll") for (int e = 0; e < 2; ++e) {                          \
     double t = fma(-li, lj[buf][e], V[(E0) + e]);                          \
     asm volatile("" : "+v"(t));                                            \
     V[(E0) + e] = t;                                                       \
   }
-    LEV_READ8(0, 0)
-    LEV_READ8(1, 8) LEV_FMA8(0, s0, 0)
-    LEV_READ8(0, 16) LEV_FMA8(1, s0, 8)
-    LEV_READ8(1, 24) LEV_FMA8(0, s1, 0)
-    LEV_READ8(0, 32) LEV_FMA8(1, s1, 8)
-    LEV_READ8(1, 40) LEV_FMA8(0, s2, 0)
-    LEV_READ8(0, 48) LEV_FMA8(1, s2, 8)
-    LEV_READ8(1, 56) LEV_FMA8(0, s3, 0)
-    LEV_FMA8(1, s3, 8)
-#undef LEV_READ8
-#undef LEV_FMA8
-    if (b == 0) {
-      dg = (i == p) ? -INFINITY : fma(-li, li, dg);
-      if (row_ok) st.Rrows[(int64_t)J * d + i] = li;
+      LEV_READ2(0, 0)
+      LEV_READ2(1, 2) LEV_FMA2(0, s0, 0)
+      LEV_READ2(0, 4) LEV_FMA2(1, s0, 2)
+      LEV_READ2(1, 6) LEV_FMA2(0, s0, 4)
+      LEV_READ2(0, 8) LEV_FMA2(1, s0, 6)
+      LEV_READ2(1, 10) LEV_FMA2(0, s0, 8)
+      LEV_READ2(0, 12) LEV_FMA2(1, s0, 10)
+      LEV_READ2(1, 14) LEV_FMA2(0, s0, 12)
+      LEV_READ2(0, 16) LEV_FMA2(1, s0, 14)
+      LEV_READ2(1, 18) LEV_FMA2(0, s1, 0)
+      LEV_READ2(0, 20) LEV_FMA2(1, s1, 2)
+      LEV_READ2(1, 22) LEV_FMA2(0, s1, 4)
+      LEV_READ2(0, 24) LEV_FMA2(1, s1, 6)
+      LEV_READ2(1, 26) LEV_FMA2(0, s1, 8)
+      LEV_READ2(0, 28) LEV_FMA2(1, s1, 10)
+      LEV_READ2(1, 30) LEV_FMA2(0, s1, 12)
+      LEV_READ2(0, 32) LEV_FMA2(1, s1, 14)
+      LEV_READ2(1, 34) LEV_FMA2(0, s2, 0)
+      LEV_READ2(0, 36) LEV_FMA2(1, s2, 2)
+      LEV_READ2(1, 38) LEV_FMA2(0, s2, 4)
+      LEV_READ2(0, 40) LEV_FMA2(1, s2, 6)
+      LEV_READ2(1, 42) LEV_FMA2(0, s2, 8)
+      LEV_READ2(0, 44) LEV_FMA2(1, s2, 10)
+      LEV_READ2(1, 46) LEV_FMA2(0, s2, 12)
+      LEV_READ2(0, 48) LEV_FMA2(1, s2, 14)
+      LEV_READ2(1, 50) LEV_FMA2(0, s3, 0)
+      LEV_READ2(0, 52) LEV_FMA2(1, s3, 2)
+      LEV_READ2(1, 54) LEV_FMA2(0, s3, 4)
+      LEV_READ2(0, 56) LEV_FMA2(1, s3, 6)
+      LEV_READ2(1, 58) LEV_FMA2(0, s3, 8)
+      LEV_READ2(0, 60) LEV_FMA2(1, s3, 10)
+      LEV_READ2(1, 62) LEV_FMA2(0, s3, 12)
+      LEV_FMA2(1, s3, 14)
+#undef LEV_READ2
+#undef LEV_FMA2
+    } else {
+      const double l0 = i0 < d ? lvec[i0] : 0.0;
+      const double l1 = i1 < d ? lvec[i1] : 0.0;
+      dg0 = (i0 == p) ? -INFINITY : fma(-l0, l0, dg0);
+      dg1 = (i1 == p) ? -INFINITY : fma(-l1, l1, dg1);
+      if (i0 < d) st.Rrows[(int64_t)J * d + i0] = l0;
+      if (i1 < d) st.Rrows[(int64_t)J * d + i1] = l1;
       publish_candidate();
     }
     if (threadIdx.x == 0) st.piv[J] = p;
@@ -410,7 +460,7 @@ hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState&
   (void)gemm_partial;
   if (d <= 0 || d > kMaxD) return hipErrorInvalidValue;
   if (d <= kSmallD) {
-    const int waves = small_rects((int)d);
+    const int waves = small_rects((int)d) + small_diag_waves((int)d);
     pivchol_small_kernel<<<1, 64 * waves, 0, s>>>(B, (int)d, zeta, st, rank_out);
     return hipGetLastError();
   }
