@@ -147,17 +147,21 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
 //
 // The d x d matrix is tiled by 64 x 64 squares that cover its lower triangle
 // (10 for d = 256); "square" wave w owns square (a, b) and lane l of that wave
-// holds row 64a + l, columns 64b .. 64b + 63 in 128 registers.  Two more
+// holds the 8 x 8 block of rows 64a + 8 (l / 8) + 0..7 and columns
+// 64b + 8 (l % 8) + 0..7 in 128 registers, so a row and a column of the square
+// are both spread over 8 lanes.  Two more
 // "diagonal" waves own the Schur diagonal: lane l of diagonal wave q holds
 // d_i for rows i = 128 q + l and 128 q + 64 + l, updated as d_i -= l_i^2.
 // Twelve waves (three per SIMD) leave up to 170 registers per lane.
 //
 // Per pivot step (two barriers): every wave reads the per-diagonal-wave
 // candidates (value, index) left by the previous step and takes the best, p,
-// with 1/sqrt(S_pp) from the hardware estimate plus two Newton steps; the
-// owners of column p (rows i >= p) and of row p (columns j < p) publish
-// l = S[:, p] / sqrt(S_pp) to LDS; after the barrier the square waves apply
-// S -= l l^T to their entries while the diagonal waves, at the same time,
+// with 1/sqrt(S_pp) from the hardware estimate plus two Newton steps; column p
+// of the squares (a, b_p) gives l for the bands >= b_p and row p of the squares
+// (b_p, b), b < b_p, gives it for the bands below (each entry written once,
+// 8 lanes x 8 values per square), l = S[:, p] / sqrt(S_pp) going to LDS; after
+// the barrier the square waves apply S -= l l^T to their entries (8 + 8
+// values of l per lane, 64 FMAs) while the diagonal waves, at the same time,
 // update d, store R[J, :] = l and leave their argmax (DPP wave reduction) for
 // the next step.  No global memory is read inside the loop.
 constexpr int kSmallD = 256;
@@ -247,11 +251,14 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
   if (square) small_rect(wave, d, a, b);
   a = __builtin_amdgcn_readfirstlane(a);
   b = __builtin_amdgcn_readfirstlane(b);
-  const int i = kBandR * a + lane;  // my row (square waves)
-  const int j0 = kBandC * b;        // my first column
-  const bool row_ok = square && i < d;
-  const int q = wave - nrect;                  // diagonal wave index
-  const int i0 = kDiagRows * q + lane;         // my two diagonal rows
+  // square waves: lane l holds the 8 x 8 block rows ri0 .. ri0 + 7, columns
+  // cj0 .. cj0 + 7 of the square (a, b); entry (r, c) is element (r % 2) * 8 + c
+  // of vector r / 2
+  const int gr = lane >> 3, gc = lane & 7;
+  const int ri0 = kBandR * a + 8 * gr;
+  const int cj0 = kBandC * b + 8 * gc;
+  const int q = wave - nrect;           // diagonal wave index
+  const int i0 = kDiagRows * q + lane;  // its two diagonal rows
   const int i1 = i0 + 64;
 
   v16d s0, s1, s2, s3;
@@ -261,17 +268,17 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
     // entry (i, j) is read from the lower triangle, B[max(i,j)][min(i,j)], so
     // S is bitwise symmetric from the start and stays so (the update
     // fma(-l_i, l_j, s) is symmetric in i and j)
-    const int ic = row_ok ? i : 0;
-#define LEV_LOAD16(V, OFF)                                                  \
+#define LEV_LOAD16(V, R0)                                                   \
   _Pragma("unroll") for (int e = 0; e < 16; ++e) {                          \
-    const int j = j0 + (OFF) + e;                                           \
-    const int jc = j < d ? j : 0;                                           \
+    const int i = ri0 + (R0) + e / 8, j = cj0 + e % 8;                      \
+    const bool ok = square && i < d && j < d;                               \
+    const int ic = ok ? i : 0, jc = ok ? j : 0;                             \
     const int hi = ic > jc ? ic : jc, lo = ic > jc ? jc : ic;               \
     const double x = B[(int64_t)hi * d + lo];                               \
-    V[e] = (row_ok && j < d) ? x : 0.0;                                     \
+    V[e] = ok ? x : 0.0;                                                    \
   }                                                                         \
   __builtin_amdgcn_sched_barrier(0);
-    LEV_LOAD16(s0, 0) LEV_LOAD16(s1, 16) LEV_LOAD16(s2, 32) LEV_LOAD16(s3, 48)
+    LEV_LOAD16(s0, 0) LEV_LOAD16(s1, 2) LEV_LOAD16(s2, 4) LEV_LOAD16(s3, 6)
 #undef LEV_LOAD16
   }
   for (int t = threadIdx.x; t < kLvec; t += blockDim.x) lvec[t] = 0.0;
@@ -324,76 +331,75 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
     if (J == 0) r00 = rpp;
     if (!(pv > 0.0) || !(rpp > zeta * r00)) break;  // uniform
     if (square) {
-      // row p: the lane holding row p in each square with b <= b_p writes
-      // its 64 entries (columns >= p duplicate the column-p owners' writes
-      // below with identical bits, S being symmetric)
-      if (a == p / kBandR && lane == (p & (kBandR - 1)) && b <= p / kBandC) {
-        double2* dst = reinterpret_cast<double2*>(&lvec[j0]);
-#define LEV_PUT16(V, OFF) \
-  _Pragma("unroll") for (int e = 0; e < 16; e += 2) dst[((OFF) + e) / 2] = make_double2(V[e] * inv, V[e + 1] * inv);
-        LEV_PUT16(s0, 0) LEV_PUT16(s1, 16) LEV_PUT16(s2, 32) LEV_PUT16(s3, 48)
-#undef LEV_PUT16
-      }
-      // column p, rows i >= p; the entry is picked with a uniform-index
-      // register extract
-      if (b == p / kBandC) {
-        const int cp = __builtin_amdgcn_readfirstlane(p - j0);
-        const int e = cp & 15, blk = cp >> 4;
-        const double v0 = s0[e], v1 = s1[e], v2 = s2[e], v3 = s3[e];
-        const double v = blk == 0 ? v0 : (blk == 1 ? v1 : (blk == 2 ? v2 : v3));
-        if (row_ok && i >= p) lvec[i] = v * inv;
+      const int bp = p / kBandC;
+      const int pl = p - kBandC * bp;  // p's position inside its band
+      if (b == bp) {
+        // column p of the squares (a, b_p), a >= b_p: rows of bands >= b_p;
+        // the 8 lanes of column group pl / 8 each hold 8 rows of it, picked
+        // with uniform-index register extracts
+        if (gc == (pl >> 3)) {
+          const int e = __builtin_amdgcn_readfirstlane(pl & 7);
+          const double v0 = s0[e], v1 = s0[8 + e], v2 = s1[e], v3 = s1[8 + e];
+          const double v4 = s2[e], v5 = s2[8 + e], v6 = s3[e], v7 = s3[8 + e];
+          double2* dst = reinterpret_cast<double2*>(&lvec[ri0]);
+          dst[0] = make_double2(v0 * inv, v1 * inv);
+          dst[1] = make_double2(v2 * inv, v3 * inv);
+          dst[2] = make_double2(v4 * inv, v5 * inv);
+          dst[3] = make_double2(v6 * inv, v7 * inv);
+        }
+      } else if (a == bp) {
+        // row p of the squares (b_p, b), b < b_p: columns of bands < b_p,
+        // by symmetry the entries of column p there
+        if (gr == (pl >> 3)) {
+          const int rr = pl & 7;
+          const int e = __builtin_amdgcn_readfirstlane((rr & 1) * 8);
+          const int vs = __builtin_amdgcn_readfirstlane(rr >> 1);
+          double w[8];
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            const double u0 = s0[e + c], u1 = s1[e + c], u2 = s2[e + c], u3 = s3[e + c];
+            w[c] = vs == 0 ? u0 : (vs == 1 ? u1 : (vs == 2 ? u2 : u3));
+          }
+          double2* dst = reinterpret_cast<double2*>(&lvec[cj0]);
+#pragma unroll
+          for (int c = 0; c < 8; c += 2) dst[c / 2] = make_double2(w[c] * inv, w[c + 1] * inv);
+        }
       }
     }
     lds_barrier();
     if (square) {
-      const double li = row_ok ? lvec[i] : 0.0;
-      // 32 groups of 2 columns; the LDS reads of group g + 1 are issued
-      // before the FMAs of group g, and each FMA result is pinned in place so
-      // the compiler neither sinks the FMAs nor hoists every read of the step
-      double lj[2][2];
-#define LEV_READ2(buf, OFF) \
-  _Pragma("unroll") for (int e = 0; e < 2; ++e) lj[buf][e] = lvec[j0 + (OFF) + e];
-#define LEV_FMA2(buf, V, E0)                                               \
-  _Pragma("unroll") for (int e = 0; e < 2; ++e) {                          \
-    double t = fma(-li, lj[buf][e], V[(E0) + e]);                          \
-    asm volatile("" : "+v"(t));                                            \
-    V[(E0) + e] = t;                                                       \
+      // S -= l l^T on the lane's 8 x 8 block: 8 column values and 8 row
+      // values of l, 64 FMAs (each result pinned so that the compiler keeps
+      // the FMAs where they are)
+      double lc[8], lr[4];
+      {
+        const double2* src = reinterpret_cast<const double2*>(&lvec[cj0]);
+#pragma unroll
+        for (int c = 0; c < 8; c += 2) {
+          const double2 t = src[c / 2];
+          lc[c] = t.x;
+          lc[c + 1] = t.y;
+        }
+      }
+      const double2* srr = reinterpret_cast<const double2*>(&lvec[ri0]);
+#define LEV_ROWS4(R0)                                                      \
+  {                                                                        \
+    const double2 t0 = srr[(R0) / 2], t1 = srr[(R0) / 2 + 1];              \
+    lr[0] = t0.x;                                                          \
+    lr[1] = t0.y;                                                          \
+    lr[2] = t1.x;                                                          \
+    lr[3] = t1.y;                                                          \
   }
-      LEV_READ2(0, 0)
-      LEV_READ2(1, 2) LEV_FMA2(0, s0, 0)
-      LEV_READ2(0, 4) LEV_FMA2(1, s0, 2)
-      LEV_READ2(1, 6) LEV_FMA2(0, s0, 4)
-      LEV_READ2(0, 8) LEV_FMA2(1, s0, 6)
-      LEV_READ2(1, 10) LEV_FMA2(0, s0, 8)
-      LEV_READ2(0, 12) LEV_FMA2(1, s0, 10)
-      LEV_READ2(1, 14) LEV_FMA2(0, s0, 12)
-      LEV_READ2(0, 16) LEV_FMA2(1, s0, 14)
-      LEV_READ2(1, 18) LEV_FMA2(0, s1, 0)
-      LEV_READ2(0, 20) LEV_FMA2(1, s1, 2)
-      LEV_READ2(1, 22) LEV_FMA2(0, s1, 4)
-      LEV_READ2(0, 24) LEV_FMA2(1, s1, 6)
-      LEV_READ2(1, 26) LEV_FMA2(0, s1, 8)
-      LEV_READ2(0, 28) LEV_FMA2(1, s1, 10)
-      LEV_READ2(1, 30) LEV_FMA2(0, s1, 12)
-      LEV_READ2(0, 32) LEV_FMA2(1, s1, 14)
-      LEV_READ2(1, 34) LEV_FMA2(0, s2, 0)
-      LEV_READ2(0, 36) LEV_FMA2(1, s2, 2)
-      LEV_READ2(1, 38) LEV_FMA2(0, s2, 4)
-      LEV_READ2(0, 40) LEV_FMA2(1, s2, 6)
-      LEV_READ2(1, 42) LEV_FMA2(0, s2, 8)
-      LEV_READ2(0, 44) LEV_FMA2(1, s2, 10)
-      LEV_READ2(1, 46) LEV_FMA2(0, s2, 12)
-      LEV_READ2(0, 48) LEV_FMA2(1, s2, 14)
-      LEV_READ2(1, 50) LEV_FMA2(0, s3, 0)
-      LEV_READ2(0, 52) LEV_FMA2(1, s3, 2)
-      LEV_READ2(1, 54) LEV_FMA2(0, s3, 4)
-      LEV_READ2(0, 56) LEV_FMA2(1, s3, 6)
-      LEV_READ2(1, 58) LEV_FMA2(0, s3, 8)
-      LEV_READ2(0, 60) LEV_FMA2(1, s3, 10)
-      LEV_READ2(1, 62) LEV_FMA2(0, s3, 12)
-      LEV_FMA2(1, s3, 14)
-#undef LEV_READ2
-#undef LEV_FMA2
+#define LEV_UPD16(V, R)                                                    \
+  _Pragma("unroll") for (int e = 0; e < 16; ++e) {                         \
+    double t = fma(-lr[(R) + e / 8], lc[e % 8], V[e]);                     \
+    asm volatile("" : "+v"(t));                                            \
+    V[e] = t;                                                              \
+  }
+      LEV_ROWS4(0) LEV_UPD16(s0, 0) LEV_UPD16(s1, 2)
+      LEV_ROWS4(4) LEV_UPD16(s2, 0) LEV_UPD16(s3, 2)
+#undef LEV_ROWS4
+#undef LEV_UPD16
     } else {
       const double l0 = i0 < d ? lvec[i0] : 0.0;
       const double l1 = i1 < d ? lvec[i1] : 0.0;
