@@ -279,7 +279,9 @@ lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, con
   // Gram B = A~^T A~ (d x d)
   const int splits = lev::dgemm_choose_splits(d, d, m);
   LEV_HIP(lev::launch_dgemm(d, d, m, 1.0, At, 1, d, At, d, 1, 0.0, b.B, d, splits, b.partial, nullptr, s));
-  LEV_HIP(lev::launch_fill_zero(b.pc.flags, 64 * sizeof(int32_t), s));
+  // the panel path (d > 256) tracks progress in flags; the single-workgroup
+  // path does not read them
+  if (d > 256) LEV_HIP(lev::launch_fill_zero(b.pc.flags, 64 * sizeof(int32_t), s));
   LEV_HIP(lev::launch_pivchol(b.B, d, zeta, b.pc, rank, b.partial, s));
   LEV_HIP(lev::launch_pivchol_finalize(d, b.pc, rank, perm, R, s));
   return LEV_OK;
@@ -497,12 +499,11 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
 
   const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
   LEV_HIP(mark_phase(0, stream));
+  LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, 1.0 / std::sqrt((double)k), Gk, stream));
   LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, stream));
   LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, stream));
   LEV_HIP(mark_phase(4, stream));
-  LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, 1.0 / std::sqrt((double)k), Gk, stream));
-  LEV_HIP(lev::launch_trsm_z(d, k, sv.R, rank, Gk, sv.Z64, stream));
-  LEV_HIP(lev::launch_pack_z(variant, d, k, sv.perm, rank, sv.Z64, Zpack, stream));
+  LEV_HIP(lev::launch_form_z(variant, d, k, sv.R, rank, sv.perm, Gk, sv.Z64, Zpack, stream));
   LEV_HIP(mark_phase(5, stream));
   if (n > 0 && A->format == LEV_CSR) {
     LEV_HIP(lev::launch_rownorm_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, Zpack, theta_out,

@@ -97,6 +97,10 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
 hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
                          const double* Z64, void* Zpack, hipStream_t s);
 size_t pack_z_bytes(int variant, int64_t d, int64_t k);
+// trsm + pack in one launch where it fits (r <= 256, k <= 64), else the two
+// launches above.  Zpack as for launch_pack_z.
+hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, const int64_t* rank,
+                         const int32_t* perm, const double* Gk, double* Z64, void* Zpack, hipStream_t s);
 size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k);
 
 // Pass 2, dense: theta[i] = || A[i, :] Z_full ||^2.

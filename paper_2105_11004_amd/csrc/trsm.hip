@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lev_internal.h"
 
 namespace lev {
@@ -131,23 +133,23 @@ __global__ __launch_bounds__(1024) void trsm_blocked_kernel(int64_t d, int64_t k
 //   FP64: EL = 2, CW = 8.   FP32: EL = 4, CW = 16.   BF16 forms: EL = 8, CW = 32.
 // BF16 forms store NP parts one after the other: part 0 = RNE(v), part p =
 // RNE(v - parts 0..p-1) (NP = 1 BF16, 2 BF16 hi/lo, 3 BF16x3).
+// Value of packed element idx (see the layout above); inv maps a column id
+// to its pivot position (-1 off K), Z64 is r x k by pivot position.
+// (32-bit index arithmetic: the operand has at most 2^18 elements.)
 template <typename OUT, int EL, int NP>
-__global__ void pack_z_kernel(int64_t d, int64_t k, const int32_t* __restrict__ inv_perm,
-                              const double* __restrict__ Z64, OUT* __restrict__ out, int64_t nt,
-                              int64_t cbn) {
+__device__ __forceinline__ void pack_element(int idx, int total, int d, int k, int cbn, const int32_t* inv,
+                                             const double* __restrict__ Z64, OUT* out) {
   constexpr int CW = 4 * EL;
-  const int64_t total = nt * cbn * 64 * EL;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int e = (int)(idx % EL);
-  const int l = (int)((idx / EL) % 64);
-  const int64_t cb = (idx / (EL * 64)) % cbn;
-  const int64_t t = idx / (EL * 64 * cbn);
-  const int64_t row = t * CW + EL * (l / 16) + e;  // original column id of A
-  const int64_t col = 16 * cb + (l % 16);
+  const int e = idx % EL;
+  const int l = (idx / EL) % 64;
+  const int q = idx / (EL * 64);
+  const int cb = q % cbn;
+  const int t = q / cbn;
+  const int row = t * CW + EL * (l / 16) + e;  // original column id of A
+  const int col = 16 * cb + (l % 16);
   double v = 0.0;
   if (row < d && col < k) {
-    const int32_t j = inv_perm[row];  // pivot position, or -1 when not selected
+    const int32_t j = inv[row];  // pivot position, or -1 when not selected
     if (j >= 0) v = Z64[(int64_t)j * k + col];
   }
   if constexpr (sizeof(OUT) == 2) {
@@ -161,6 +163,29 @@ __global__ void pack_z_kernel(int64_t d, int64_t k, const int32_t* __restrict__ 
   } else {
     out[idx] = (OUT)v;
   }
+}
+
+template <typename OUT, int EL, int NP>
+__global__ void pack_z_kernel(int64_t d, int64_t k, const int32_t* __restrict__ inv_perm,
+                              const double* __restrict__ Z64, OUT* __restrict__ out, int64_t nt,
+                              int64_t cbn) {
+  const int total = (int)(nt * cbn * 64 * EL);
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  pack_element<OUT, EL, NP>(idx, total, (int)d, (int)k, (int)cbn, inv_perm, Z64, out);
+}
+
+// CSR operand value of element idx of the d x 64 row-major Z_full.
+template <typename OUT>
+__device__ __forceinline__ void pack_rowmajor_element(int idx, int k, const int32_t* inv,
+                                                      const double* __restrict__ Z64, OUT* out) {
+  const int row = idx / 64, col = idx % 64;
+  double v = 0.0;
+  if (col < k) {
+    const int32_t j = inv[row];
+    if (j >= 0) v = Z64[(int64_t)j * k + col];
+  }
+  out[idx] = (OUT)v;
 }
 
 // inv_perm[c] = pivot position of column c (-1 when c is not among the r
@@ -177,19 +202,134 @@ __global__ void inverse_perm_kernel(int64_t d, const int32_t* __restrict__ perm,
 template <typename OUT>
 __global__ void pack_z_rowmajor_kernel(int64_t d, int64_t k, const int32_t* __restrict__ inv_perm,
                                        const double* __restrict__ Z64, OUT* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d * 64) return;
-  const int64_t row = idx / 64, col = idx % 64;
-  double v = 0.0;
-  if (col < k) {
-    const int32_t j = inv_perm[row];
-    if (j >= 0) v = Z64[(int64_t)j * k + col];
-  }
-  out[idx] = (OUT)v;
+  pack_rowmajor_element<OUT>(idx, (int)k, inv_perm, Z64, out);
 }
 
 constexpr int64_t chunk_cols(int variant) { return variant == 0 ? 8 : (variant == 1 ? 16 : 32); }
 constexpr int parts(int variant) { return variant == 3 ? 2 : (variant == 4 ? 3 : 1); }
+
+// Z = R11^{-1} G_k, then Z_full packed for pass 2, in one workgroup (r <= 256,
+// k <= 64): the blocked back substitution of trsm_blocked_kernel with the R
+// panel of the next block prefetched into registers during the current
+// block's solve, Z stored (state), the inverse permutation built in LDS and
+// the packed operand written from the just-stored Z (L2-resident).
+template <int VARIANT>
+__global__ __launch_bounds__(1024) void form_z_kernel(int64_t d, int64_t k, const double* __restrict__ R,
+                                                      const int64_t* __restrict__ rank,
+                                                      const int32_t* __restrict__ perm,
+                                                      const double* __restrict__ Gk, double* __restrict__ Z64,
+                                                      void* __restrict__ Zpack, int64_t nt, int64_t cbn) {
+  __shared__ double rpan[2][kTrsmR][16];  // 64 KB: R[0:r, 16 b .. 16 b + 15]
+  __shared__ double zblk[2][16][64];      // the block of Z just solved
+  __shared__ int32_t inv[kTrsmR];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int c = lane;
+  const int r = (int)*rank;
+  const bool col_ok = c < k;
+
+  v16d g;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int t = 16 * w + s;
+    g[s] = (col_ok && t < r) ? Gk[(int64_t)t * k + c] : 0.0;
+  }
+  for (int64_t t = r + w; t < d; t += 16)
+    if (col_ok) Z64[t * k + c] = 0.0;
+  for (int j = threadIdx.x; j < d; j += blockDim.x) inv[perm[j]] = j < r ? j : -1;
+
+  // panel b: rows 0 .. 16 b + 15 of columns 16 b .. 16 b + 15 (4 per thread)
+  double pre[4];
+  auto load_panel = [&](int blk) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 1024 * q;
+      const int t = e / 16, cc = e % 16;
+      const int col = 16 * blk + cc;
+      pre[q] = (t < 16 * (blk + 1) && t < r && col < r) ? R[(int64_t)t * d + col] : 0.0;
+    }
+  };
+  auto store_panel = [&](int blk) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 1024 * q;
+      rpan[blk & 1][e / 16][e % 16] = pre[q];
+    }
+  };
+  const int nblk = (r + 15) / 16;
+  if (nblk > 0) {
+    load_panel(nblk - 1);
+    store_panel(nblk - 1);
+    if (nblk > 1) load_panel(nblk - 2);
+  }
+  __syncthreads();
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const int buf = blk & 1;
+    if (w == blk) {
+#pragma unroll
+      for (int s = 15; s >= 0; --s) {
+        double x = g[s];
+#pragma unroll
+        for (int e = s + 1; e < 16; ++e) x = fma(-rpan[buf][16 * blk + s][e], g[e], x);
+        g[s] = (16 * blk + s < r) ? x / rpan[buf][16 * blk + s][s] : 0.0;
+        zblk[buf][s][lane] = g[s];
+      }
+    }
+    if (blk > 0) {
+      store_panel(blk - 1);  // loaded during the previous block
+      if (blk > 1) load_panel(blk - 2);
+    }
+    __syncthreads();
+    if (w < blk) {
+      double z[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) z[e] = zblk[buf][e][lane];
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        double x = g[s];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x = fma(-rpan[buf][16 * w + s][e], z[e], x);
+        g[s] = x;
+      }
+    }
+    __syncthreads();  // rpan[buf] and zblk[buf] are rewritten two steps later
+  }
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int t = 16 * w + s;
+    if (col_ok && t < r) Z64[(int64_t)t * k + c] = g[s];
+  }
+  __syncthreads();  // Z64 and inv visible to the whole workgroup
+  // eight elements per thread and round, so their reads of Z overlap
+  constexpr int U = 8;
+  const int di = (int)d, ki = (int)k;
+  if constexpr (VARIANT == 5 || VARIANT == 6) {
+    using OUT = typename std::conditional<VARIANT == 5, float, double>::type;
+    for (int i0 = threadIdx.x; i0 < di * 64; i0 += 1024 * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = i0 + 1024 * u;
+        if (idx < di * 64) pack_rowmajor_element<OUT>(idx, ki, inv, Z64, static_cast<OUT*>(Zpack));
+      }
+    }
+  } else {
+    constexpr int EL = VARIANT == 0 ? 2 : (VARIANT == 1 ? 4 : 8);
+    constexpr int NP = VARIANT == 3 ? 2 : (VARIANT == 4 ? 3 : 1);
+    using OUT = typename std::conditional<VARIANT == 0, double,
+                typename std::conditional<VARIANT == 1, float, __hip_bfloat16>::type>::type;
+    const int total = (int)(nt * cbn * 64 * EL);
+    const int cbi = (int)cbn;
+    for (int i0 = threadIdx.x; i0 < total; i0 += 1024 * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = i0 + 1024 * u;
+        if (idx < total) pack_element<OUT, EL, NP>(idx, total, di, ki, cbi, inv, Z64, static_cast<OUT*>(Zpack));
+      }
+    }
+  }
+}
 
 }  // namespace
 
@@ -262,6 +402,28 @@ hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm,
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, const int64_t* rank,
+                         const int32_t* perm, const double* Gk, double* Z64, void* Zpack, hipStream_t s) {
+  if (variant < 0 || variant > 6) return hipErrorInvalidValue;
+  if (d > kTrsmR || k > 64) {
+    hipError_t e = launch_trsm_z(d, k, R, rank, Gk, Z64, s);
+    if (e != hipSuccess) return e;
+    return launch_pack_z(variant, d, k, perm, rank, Z64, Zpack, s);
+  }
+  const int64_t cw = variant >= 5 ? 1 : chunk_cols(variant);
+  const int64_t nt = (d + cw - 1) / cw;
+  const int64_t cbn = (k + 15) / 16;
+#define LEV_FZ(V)                                                                                      \
+  case V:                                                                                              \
+    form_z_kernel<V><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn);                  \
+    break;
+  switch (variant) {
+    LEV_FZ(0) LEV_FZ(1) LEV_FZ(2) LEV_FZ(3) LEV_FZ(4) LEV_FZ(5) LEV_FZ(6)
+  }
+#undef LEV_FZ
   return hipGetLastError();
 }
 
