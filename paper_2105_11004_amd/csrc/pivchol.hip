@@ -149,21 +149,22 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
 // (10 for d = 256); "square" wave w owns square (a, b) and lane l of that wave
 // holds the 8 x 8 block of rows 64a + 8 (l / 8) + 0..7 and columns
 // 64b + 8 (l % 8) + 0..7 in 128 registers, so a row and a column of the square
-// are both spread over 8 lanes.  Two more
-// "diagonal" waves own the Schur diagonal: lane l of diagonal wave q holds
-// d_i for rows i = 128 q + l and 128 q + 64 + l, updated as d_i -= l_i^2.
-// Twelve waves (three per SIMD) leave up to 170 registers per lane.
+// are both spread over 8 lanes.  One more, the "diagonal" wave, owns the
+// Schur diagonal: lane l holds d_i for rows i = l + 64 t (t < 4), updated as
+// d_i -= l_i^2.  Eleven waves (at most three per SIMD) leave up to 170
+// registers per lane.
 //
-// Per pivot step (two barriers): every wave reads the per-diagonal-wave
-// candidates (value, index) left by the previous step and takes the best, p,
-// with 1/sqrt(S_pp) from the hardware estimate plus two Newton steps; column p
-// of the squares (a, b_p) gives l for the bands >= b_p and row p of the squares
-// (b_p, b), b < b_p, gives it for the bands below (each entry written once,
-// 8 lanes x 8 values per square), l = S[:, p] / sqrt(S_pp) going to LDS; after
-// the barrier the square waves apply S -= l l^T to their entries (8 + 8
-// values of l per lane, 64 FMAs) while the diagonal waves, at the same time,
-// update d, store R[J, :] = l and leave their argmax (DPP wave reduction) for
-// the next step.  No global memory is read inside the loop.
+// Per pivot step (two barriers): the square waves read the pivot p and
+// 1/sqrt(S_pp) that the diagonal wave posted; column p of the squares
+// (a, b_p) gives l for the bands >= b_p and row p of the squares (b_p, b),
+// b < b_p, gives it for the bands below (each entry written once, 8 lanes x
+// 8 values per square), l = S[:, p] / sqrt(S_pp) going to LDS; after the
+// barrier the square waves apply S -= l l^T to their entries (8 + 8 values of
+// l per lane, 64 FMAs) while the diagonal wave, at the same time and first in
+// issue, updates d, stores R[J, :] = l and posts the next pivot: the argmax of
+// d (DPP wave reduction, ties to the lower index) and its 1/sqrt from the
+// hardware estimate plus two Newton steps.  No global memory is read inside
+// the loop.
 constexpr int kSmallD = 256;
 constexpr int kBandR = 64, kBandC = 64;
 constexpr int kLvec = 256;  // >= 64 * ceil(256 / 64)
@@ -228,25 +229,23 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-struct Cand {
-  double v;
-  int idx;
+// The pivot of the next step, posted by the diagonal wave.
+struct PivotMsg {
+  double inv;  // 1 / sqrt(S_pp)
+  int p;
+  int ok;  // 0: the factorization stops here
 };
-constexpr int kDiagRows = 128;  // rows per diagonal wave (two per lane)
-
-__host__ __device__ inline int small_diag_waves(int d) { return (d + kDiagRows - 1) / kDiagRows; }
 
 __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __restrict__ B, int d, double zeta,
                                                             PivCholState st, int64_t* __restrict__ rank_out) {
   __shared__ __align__(16) double lvec[kLvec];
-  __shared__ Cand cand[kSmallD / kDiagRows];
+  __shared__ PivotMsg msg;
 
   const int lane = threadIdx.x & 63;
   // wave-uniform values kept scalar (the compiler cannot infer it)
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nrect = small_rects(d);
-  const bool square = wave < nrect;  // uniform
-  const int ndiag = small_diag_waves(d);
+  const bool square = wave < nrect;  // uniform; the last wave is the diagonal one
   int a = 0, b = 0;
   if (square) small_rect(wave, d, a, b);
   a = __builtin_amdgcn_readfirstlane(a);
@@ -257,9 +256,6 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
   const int gr = lane >> 3, gc = lane & 7;
   const int ri0 = kBandR * a + 8 * gr;
   const int cj0 = kBandC * b + 8 * gc;
-  const int q = wave - nrect;           // diagonal wave index
-  const int i0 = kDiagRows * q + lane;  // its two diagonal rows
-  const int i1 = i0 + 64;
 
   v16d s0, s1, s2, s3;
   {
@@ -283,54 +279,16 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
   }
   for (int t = threadIdx.x; t < kLvec; t += blockDim.x) lvec[t] = 0.0;
 
-  // diagonal waves: d_i in registers; leave the wave's candidate
-  double dg0 = -INFINITY, dg1 = -INFINITY;
-  auto publish_candidate = [&]() {
-    const double m = wave_max_f64(fmax(dg0, dg1));
-    const unsigned long long h0 = __ballot(dg0 == m && dg0 != -INFINITY);
-    const unsigned long long h1 = __ballot(dg1 == m && dg1 != -INFINITY);
-    if (lane == 0) {
-      Cand cd;
-      cd.v = m;
-      cd.idx = h0 ? kDiagRows * q + __builtin_ctzll(h0)
-                  : (h1 ? kDiagRows * q + 64 + __builtin_ctzll(h1) : 0x7fffffff);
-      cand[q] = cd;
-    }
-  };
-  if (!square) {
-    if (i0 < d) dg0 = B[(int64_t)i0 * d + i0];
-    if (i1 < d) dg1 = B[(int64_t)i1 * d + i1];
-    publish_candidate();
-  }
-  __syncthreads();
+  for (int t = threadIdx.x; t < kLvec; t += blockDim.x) lvec[t] = 0.0;
 
-  double r00 = 0.0;
-  int J = 0;
-  for (; J < d; ++J) {
-    // the best candidate (larger value, ties to the lower index): all reads
-    // issued together
-    Cand cs[kSmallD / kDiagRows];
-#pragma unroll
-    for (int t = 0; t < kSmallD / kDiagRows; ++t) cs[t] = cand[t < ndiag ? t : 0];
-    Cand best = cs[0];
-#pragma unroll
-    for (int t = 1; t < kSmallD / kDiagRows; ++t)
-      if (t < ndiag && (cs[t].v > best.v || (cs[t].v == best.v && cs[t].idx < best.idx))) best = cs[t];
-    // uniform by construction: kept in scalar registers
-    const double pv = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(best.v)),
-                                       __builtin_amdgcn_readfirstlane(__double2loint(best.v)));
-    const int p = __builtin_amdgcn_readfirstlane(best.idx);
-    // 1/sqrt(pv): hardware estimate + two Newton steps (~1 ulp); sqrt = pv/sqrt
-    double y = __builtin_amdgcn_rsq(pv);
-    y = y * fma(-0.5 * pv * y, y, 1.5);
-    y = y * fma(-0.5 * pv * y, y, 1.5);
-    y = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(y)),
-                         __builtin_amdgcn_readfirstlane(__double2loint(y)));
-    const double inv = pv > 0.0 ? y : 0.0;
-    const double rpp = pv > 0.0 ? pv * y : 0.0;
-    if (J == 0) r00 = rpp;
-    if (!(pv > 0.0) || !(rpp > zeta * r00)) break;  // uniform
-    if (square) {
+  if (square) {
+    __syncthreads();  // the first pivot is posted
+    for (int J = 0; J < d; ++J) {
+      const int p = __builtin_amdgcn_readfirstlane(msg.p);
+      const int ok = __builtin_amdgcn_readfirstlane(msg.ok);
+      const double inv = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(msg.inv)),
+                                          __builtin_amdgcn_readfirstlane(__double2loint(msg.inv)));
+      if (!ok) break;
       const int bp = p / kBandC;
       const int pl = p - kBandC * bp;  // p's position inside its band
       if (b == bp) {
@@ -365,9 +323,7 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
           for (int c = 0; c < 8; c += 2) dst[c / 2] = make_double2(w[c] * inv, w[c + 1] * inv);
         }
       }
-    }
-    lds_barrier();
-    if (square) {
+      lds_barrier();
       // S -= l l^T on the lane's 8 x 8 block: 8 column values and 8 row
       // values of l, 64 FMAs (each result pinned so that the compiler keeps
       // the FMAs where they are)
@@ -400,23 +356,72 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
       LEV_ROWS4(4) LEV_UPD16(s2, 0) LEV_UPD16(s3, 2)
 #undef LEV_ROWS4
 #undef LEV_UPD16
-    } else {
-      const double l0 = i0 < d ? lvec[i0] : 0.0;
-      const double l1 = i1 < d ? lvec[i1] : 0.0;
-      dg0 = (i0 == p) ? -INFINITY : fma(-l0, l0, dg0);
-      dg1 = (i1 == p) ? -INFINITY : fma(-l1, l1, dg1);
-      if (i0 < d) st.Rrows[(int64_t)J * d + i0] = l0;
-      if (i1 < d) st.Rrows[(int64_t)J * d + i1] = l1;
-      publish_candidate();
+      if (threadIdx.x == 0) st.piv[J] = p;
+      lds_barrier();
     }
-    if (threadIdx.x == 0) st.piv[J] = p;
-    lds_barrier();
-  }
-  if (threadIdx.x == 0) {
-    *st.r00 = r00;
-    st.flags[0] = 1;
-    st.flags[1] = J;
-    *rank_out = J;
+  } else {
+    // the diagonal wave: d_i for rows lane + 64 t; the serial part of each
+    // pivot, so first in issue
+    __builtin_amdgcn_s_setprio(3);
+    double dg[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i = lane + 64 * t;
+      dg[t] = i < d ? B[(int64_t)i * d + i] : -INFINITY;
+    }
+    double r00 = 0.0;
+    // posts the pivot of step J: the largest d_i, ties to the lower index,
+    // with 1/sqrt(d_p) (hardware estimate + two Newton steps, ~1 ulp); returns
+    // whether the factorization continues
+    auto post = [&](int J) -> bool {
+      const double m = wave_max_f64(fmax(fmax(dg[0], dg[1]), fmax(dg[2], dg[3])));
+      int p = 0x7fffffff;
+#pragma unroll
+      for (int t = 3; t >= 0; --t) {
+        const unsigned long long h = __ballot(dg[t] == m && dg[t] != -INFINITY);
+        if (h) p = 64 * t + __builtin_ctzll(h);
+      }
+      p = __builtin_amdgcn_readfirstlane(p);
+      const double pv = m;
+      double y = __builtin_amdgcn_rsq(pv);
+      y = y * fma(-0.5 * pv * y, y, 1.5);
+      y = y * fma(-0.5 * pv * y, y, 1.5);
+      const double inv = pv > 0.0 ? y : 0.0;
+      const double rpp = pv > 0.0 ? pv * y : 0.0;
+      if (J == 0) r00 = rpp;
+      const bool ok = pv > 0.0 && rpp > zeta * r00;
+      if (lane == 0) {
+        PivotMsg pm;
+        pm.inv = inv;
+        pm.p = p;
+        pm.ok = ok ? 1 : 0;
+        msg = pm;
+      }
+      return ok;
+    };
+    bool ok = post(0);
+    __syncthreads();
+    int J = 0;
+    for (; J < d && ok; ++J) {
+      const int p = __builtin_amdgcn_readfirstlane(msg.p);
+      lds_barrier();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = lane + 64 * t;
+        const double l = i < d ? lvec[i] : 0.0;
+        dg[t] = (i == p || i >= d) ? -INFINITY : fma(-l, l, dg[t]);
+        if (i < d) st.Rrows[(int64_t)J * d + i] = l;
+      }
+      ok = post(J + 1);
+      lds_barrier();
+    }
+    __builtin_amdgcn_s_setprio(0);
+    if (lane == 0) {
+      *st.r00 = r00;
+      st.flags[0] = 1;
+      st.flags[1] = J;
+      *rank_out = J;
+    }
   }
 }
 
@@ -466,7 +471,7 @@ hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState&
   (void)gemm_partial;
   if (d <= 0 || d > kMaxD) return hipErrorInvalidValue;
   if (d <= kSmallD) {
-    const int waves = small_rects((int)d) + small_diag_waves((int)d);
+    const int waves = small_rects((int)d) + 1;
     pivchol_small_kernel<<<1, 64 * waves, 0, s>>>(B, (int)d, zeta, st, rank_out);
     return hipGetLastError();
   }
