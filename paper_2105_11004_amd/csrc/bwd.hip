@@ -248,8 +248,8 @@ __global__ __launch_bounds__(kThreads) void bwd_grad_kernel(const T* __restrict_
     for (int q = threadIdx.x; q < g.TM; q += kThreads) {
       const int64_t i = r0 + q;
       if (i < n) {
-        const uint64_t x = (hp.a * (uint64_t)i + hp.c) % hp.P;
-        hrow[q] = (int32_t)(x % (uint64_t)hp.r_cs);
+        const uint64_t x = hash_x(hp, (uint64_t)i);
+        hrow[q] = (int32_t)((uint32_t)x % (uint32_t)hp.r_cs);  // x < P < 2^32
         srow[q] = sign_negative(hp, (uint64_t)i) ? -1 : 1;
       } else {
         hrow[q] = 0;

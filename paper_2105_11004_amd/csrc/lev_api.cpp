@@ -255,14 +255,16 @@ RankBufs carve_rank(Carver& c, int64_t m, int64_t d) {
 lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::SeedDraws& dr,
                           const SketchBufs& b, double* SA, double* At, hipStream_t s) {
   const int64_t d = A->d, m = p->m, r_cs = p->r_cs;
-  LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, 1.0 / std::sqrt((double)m), b.Gm, s));
+  // G_m is drawn by pass 1's workgroups (compute under its memory traffic)
+  const lev::GaussDraw gm{dr.key_m, m * r_cs, 1.0 / std::sqrt((double)m), b.Gm};
   LEV_HIP(mark_phase(1, s));
   if (A->n > 0 && A->format == LEV_CSR) {
     LEV_HIP(lev::launch_countsketch_csr(A->dtype, A->values, A->row_ptr, A->col_idx, A->n, d, A->nnz, dr.hash,
-                                        SA, s));
+                                        SA, gm, s));
   } else if (A->n > 0) {
-    LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, s));
+    LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, gm, s));
   } else {
+    LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, gm.scale, b.Gm, s));
     LEV_HIP(lev::launch_fill_zero(SA, sizeof(double) * (size_t)(r_cs * d), s));
   }
   LEV_HIP(mark_phase(2, s));
@@ -367,6 +369,7 @@ SeedDraws derive_draws(uint64_t seed, int64_t n, int64_t r_cs) {
   h.c = w[1] % h.P;
   h.ainv = modinv(h.a, h.P);
   h.delta = (h.ainv * ((uint64_t)r_cs % h.P)) % h.P;
+  h.pbar = ~0ull / h.P;
   h.c0 = w[2] % kP61;
   h.c1 = w[3] % kP61;
   h.c2 = w[4] % kP61;

@@ -37,16 +37,33 @@ __device__ __forceinline__ bool sign_negative(const HashParams& hp, uint64_t i) 
   return (g & 1ull) != 0;
 }
 
+// x mod P for any 64-bit x (P < 2^32), by Barrett reduction with
+// pbar = floor((2^64 - 1) / P): the quotient estimate umulhi(x, pbar) is at
+// most two below floor(x / P), so two conditional subtractions finish it
+// (a 64-bit division is a long software sequence on the GPU).
+__device__ __forceinline__ uint64_t mod_p(const HashParams& hp, uint64_t x) {
+  uint64_t r = x - __umul64hi(x, hp.pbar) * hp.P;
+  r = r >= hp.P ? r - hp.P : r;
+  return r >= hp.P ? r - hp.P : r;
+}
+
+// Bucket-hash argument of row i: (a i + c) mod P (a, i, c < P < 2^32, so
+// a i + c < 2^64).
+__device__ __forceinline__ uint64_t hash_x(const HashParams& hp, uint64_t i) {
+  return mod_p(hp, hp.a * i + hp.c);
+}
+
 // Row id at position t of bucket b's progression: (i0 + t*delta) mod P.
 // P < 2^32 and t, delta < 2^32, so t*delta fits in 64 bits.
 __device__ __forceinline__ uint64_t bucket_row(const HashParams& hp, uint64_t i0, uint64_t t) {
-  return (i0 + (t * hp.delta) % hp.P) % hp.P;
+  const uint64_t r = i0 + mod_p(hp, t * hp.delta);  // < 2 P
+  return r >= hp.P ? r - hp.P : r;
 }
 
 __device__ __forceinline__ uint64_t bucket_start(const HashParams& hp, int64_t b) {
   const uint64_t x = (uint64_t)b;  // b < P here
-  const uint64_t diff = (x + hp.P - hp.c) % hp.P;
-  return (hp.ainv * diff) % hp.P;
+  const uint64_t diff = mod_p(hp, x + hp.P - hp.c);
+  return mod_p(hp, hp.ainv * diff);
 }
 
 __device__ __forceinline__ int64_t bucket_len(const HashParams& hp, int64_t b) {

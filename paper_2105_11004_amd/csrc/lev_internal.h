@@ -17,6 +17,7 @@ namespace lev {
 // Sign: s(i) = +1 if (c3 i^3 + c2 i^2 + c1 i + c0) mod (2^61 - 1) is even.
 struct HashParams {
   uint64_t P, a, c, ainv, delta;
+  uint64_t pbar;  // floor((2^64 - 1) / P): Barrett reduction mod P (P < 2^32)
   uint64_t c0, c1, c2, c3;
   int64_t n, r_cs;
 };
@@ -41,15 +42,28 @@ hipError_t launch_hash_rows(const HashParams& hp, int64_t* h_out, int8_t* s_out,
 // bucket_off[r_cs+1], bucket_rows[n] in pass-1 order (debug/inspection).
 hipError_t launch_bucket_lists(const HashParams& hp, int64_t* off, int32_t* rows, hipStream_t s);
 
-// Pass 1, dense: SA (r_cs x d, FP64, ld = d) = S A.
+// A Gaussian matrix drawn by pass 1 on the side (the draws of
+// launch_gaussian, element e = pair e / 2 of the Philox stream, times
+// scale): the r_cs bucket workgroups each take an equal share of the pairs,
+// so the FP64 transcendentals run while the CUs stream A.  out == nullptr:
+// none.
+struct GaussDraw {
+  PhiloxKey key;
+  int64_t total;  // elements
+  double scale;
+  double* out;
+};
+
+// Pass 1, dense: SA (r_cs x d, FP64, ld = d) = S A, plus the draw g.
 // dtype: 0 = f64, 1 = f32, 2 = bf16.
 hipError_t launch_countsketch_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
-                                    const HashParams& hp, double* SA, hipStream_t s);
-// Pass 1, CSR (row_ptr int64[n+1], col_idx int32[nnz], vals[nnz]).  Row
-// extents are clamped to [0, nnz] and to d entries, column ids >= d skipped.
+                                    const HashParams& hp, double* SA, const GaussDraw& g, hipStream_t s);
+// Pass 1, CSR (row_ptr int64[n+1], col_idx int32[nnz], vals[nnz]), plus the
+// draw g.  Row extents are clamped to [0, nnz] and to d entries, column ids
+// >= d skipped.
 hipError_t launch_countsketch_csr(int dtype, const void* vals, const int64_t* row_ptr,
                                   const int32_t* col_idx, int64_t n, int64_t d, int64_t nnz,
-                                  const HashParams& hp, double* SA, hipStream_t s);
+                                  const HashParams& hp, double* SA, const GaussDraw& g, hipStream_t s);
 
 // rows x cols FP64 Gaussian matrix, Philox4x32-10 + Box-Muller, times scale.
 hipError_t launch_gaussian(PhiloxKey key, int64_t rows, int64_t cols, double scale, double* out,

@@ -29,8 +29,8 @@ constexpr uint32_t kInvalid = 0xFFFFFFFFu;  // sentinel (row ids < 2^31 - 1)
 __global__ void hash_rows_kernel(HashParams hp, int64_t* h_out, int8_t* s_out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= hp.n) return;
-  const uint64_t x = ((uint64_t)hp.a * (uint64_t)i + hp.c) % hp.P;
-  h_out[i] = (int64_t)(x % (uint64_t)hp.r_cs);
+  const uint64_t x = hash_x(hp, (uint64_t)i);
+  h_out[i] = (int64_t)((uint32_t)x % (uint32_t)hp.r_cs);  // x < P < 2^32
   s_out[i] = sign_negative(hp, (uint64_t)i) ? (int8_t)-1 : (int8_t)1;
 }
 
@@ -104,6 +104,21 @@ __device__ __forceinline__ void to_double<__hip_bfloat16>(const uint4& raw, doub
   }
 }
 
+// Workgroup (blockIdx.x of gridDim.x) share of the side draw: pairs
+// [part * per, (part + 1) * per), one Box-Muller pair per thread and round.
+__device__ __forceinline__ void side_draw(const GaussDraw& g) {
+  if (g.out == nullptr || blockIdx.y != 0) return;
+  const int64_t pairs = (g.total + 1) / 2;
+  const int64_t per = (pairs + gridDim.x - 1) / gridDim.x;
+  const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min<int64_t>(q0 + per, pairs);
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    double z0, z1;
+    box_muller_pair((uint64_t)q, g.key, &z0, &z1);
+    g.out[2 * q] = z0 * g.scale;
+    if (2 * q + 1 < g.total) g.out[2 * q + 1] = z1 * g.scale;
+  }
+}
+
 // One workgroup = one bucket x one column chunk of 64 * NV * E columns.
 // Lane l of every wave covers 16-byte vectors v*64 + l (v < NV) of the
 // chunk, so each wave reads NV contiguous KB-sized segments of a row.
@@ -111,7 +126,7 @@ __device__ __forceinline__ void to_double<__hip_bfloat16>(const uint4& raw, doub
 template <typename T, int NV, int U>
 __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __restrict__ A, int64_t d,
                                                                      int64_t ld, HashParams hp,
-                                                                     double* __restrict__ SA) {
+                                                                     double* __restrict__ SA, GaussDraw g) {
   constexpr int E = Vec16<T>::E;
   constexpr int kCols = 64 * NV * E;
   __shared__ uint32_t entries[kChunk];
@@ -134,6 +149,7 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
 
   const int64_t T_b = bucket_len(hp, b);
   const uint64_t i0 = T_b > 0 ? bucket_start(hp, b) : 0;
+  side_draw(g);
 
   for (int64_t t0 = 0; t0 < T_b; t0 += kChunk) {
     const int cnt = (int)min<int64_t>(kChunk, T_b - t0);
@@ -191,21 +207,21 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
 
 template <typename T>
 hipError_t launch_dense_typed(const void* A, int64_t n, int64_t d, int64_t ld, const HashParams& hp,
-                              double* SA, hipStream_t s) {
+                              double* SA, const GaussDraw& g, hipStream_t s) {
   (void)n;
   constexpr int E = Vec16<T>::E;
   const T* a = static_cast<const T*>(A);
   const int64_t per_vec_row = 64 * E;
   if (d <= per_vec_row) {
     dim3 grid((unsigned)hp.r_cs, 1);
-    countsketch_dense_kernel<T, 1, 8><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA);
+    countsketch_dense_kernel<T, 1, 8><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   } else if (d <= 2 * per_vec_row) {
     dim3 grid((unsigned)hp.r_cs, 1);
-    countsketch_dense_kernel<T, 2, 4><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA);
+    countsketch_dense_kernel<T, 2, 4><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   } else {
     const int64_t cols = 4 * per_vec_row;
     dim3 grid((unsigned)hp.r_cs, (unsigned)((d + cols - 1) / cols));
-    countsketch_dense_kernel<T, 4, 2><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA);
+    countsketch_dense_kernel<T, 4, 2><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   }
   return hipGetLastError();
 }
@@ -240,7 +256,7 @@ __global__ __launch_bounds__(kThreads) void countsketch_csr_kernel(const T* __re
                                                                    const int64_t* __restrict__ row_ptr,
                                                                    const int32_t* __restrict__ col_idx,
                                                                    int64_t d, int64_t nnz, HashParams hp,
-                                                                   double* __restrict__ SA) {
+                                                                   double* __restrict__ SA, GaussDraw g) {
   extern __shared__ double acc[];  // [kWaves][d]
   __shared__ uint32_t entries[kChunk];
   const int64_t b = blockIdx.x;
@@ -248,6 +264,7 @@ __global__ __launch_bounds__(kThreads) void countsketch_csr_kernel(const T* __re
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* my = acc + (int64_t)wave * d;
   for (int64_t c = threadIdx.x; c < kWaves * d; c += kThreads) acc[c] = 0.0;
+  side_draw(g);
 
   const int64_t T_b = bucket_len(hp, b);
   const uint64_t i0 = T_b > 0 ? bucket_start(hp, b) : 0;
@@ -343,10 +360,10 @@ __global__ __launch_bounds__(kThreads) void countsketch_csr_kernel(const T* __re
 
 template <typename T>
 hipError_t launch_csr_typed(const void* vals, const int64_t* row_ptr, const int32_t* col_idx, int64_t d,
-                            int64_t nnz, const HashParams& hp, double* SA, hipStream_t s) {
+                            int64_t nnz, const HashParams& hp, double* SA, const GaussDraw& g, hipStream_t s) {
   const size_t lds = (size_t)kWaves * (size_t)d * sizeof(double);
   countsketch_csr_kernel<T><<<(unsigned)hp.r_cs, kThreads, lds, s>>>(static_cast<const T*>(vals), row_ptr,
-                                                                      col_idx, d, nnz, hp, SA);
+                                                                      col_idx, d, nnz, hp, SA, g);
   return hipGetLastError();
 }
 
@@ -369,23 +386,23 @@ hipError_t launch_bucket_lists(const HashParams& hp, int64_t* off, int32_t* rows
 }
 
 hipError_t launch_countsketch_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
-                                    const HashParams& hp, double* SA, hipStream_t s) {
+                                    const HashParams& hp, double* SA, const GaussDraw& g, hipStream_t s) {
   switch (dtype) {
-    case 0: return launch_dense_typed<double>(A, n, d, ld, hp, SA, s);
-    case 1: return launch_dense_typed<float>(A, n, d, ld, hp, SA, s);
-    case 2: return launch_dense_typed<__hip_bfloat16>(A, n, d, ld, hp, SA, s);
+    case 0: return launch_dense_typed<double>(A, n, d, ld, hp, SA, g, s);
+    case 1: return launch_dense_typed<float>(A, n, d, ld, hp, SA, g, s);
+    case 2: return launch_dense_typed<__hip_bfloat16>(A, n, d, ld, hp, SA, g, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_countsketch_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
                                   int64_t n, int64_t d, int64_t nnz, const HashParams& hp, double* SA,
-                                  hipStream_t s) {
+                                  const GaussDraw& g, hipStream_t s) {
   (void)n;
   switch (dtype) {
-    case 0: return launch_csr_typed<double>(vals, row_ptr, col_idx, d, nnz, hp, SA, s);
-    case 1: return launch_csr_typed<float>(vals, row_ptr, col_idx, d, nnz, hp, SA, s);
-    case 2: return launch_csr_typed<__hip_bfloat16>(vals, row_ptr, col_idx, d, nnz, hp, SA, s);
+    case 0: return launch_csr_typed<double>(vals, row_ptr, col_idx, d, nnz, hp, SA, g, s);
+    case 1: return launch_csr_typed<float>(vals, row_ptr, col_idx, d, nnz, hp, SA, g, s);
+    case 2: return launch_csr_typed<__hip_bfloat16>(vals, row_ptr, col_idx, d, nnz, hp, SA, g, s);
     default: return hipErrorInvalidValue;
   }
 }
