@@ -122,7 +122,8 @@ __device__ __forceinline__ void side_draw(const GaussDraw& g) {
 // One workgroup = one bucket x one column chunk of 64 * NV * E columns.
 // Lane l of every wave covers 16-byte vectors v*64 + l (v < NV) of the
 // chunk, so each wave reads NV contiguous KB-sized segments of a row.
-// Wave w takes rows t = w, w + 4, ... of the staged row list, U at a time.
+// Wave w takes rows t = w, w + 4, ... of the staged row list, U at a time,
+// with the next U rows in flight while the current ones are added.
 template <typename T, int NV, int U>
 __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __restrict__ A, int64_t d,
                                                                      int64_t ld, HashParams hp,
@@ -161,13 +162,14 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
       entries[q] = e;
     }
     __syncthreads();
-    for (int q0 = wave; q0 < cnt; q0 += kWaves * U) {
-      uint4 raw[U][NV];
-      double sgn[U];
+    // The entries are the same for every lane: read as scalars, so the row
+    // base is an SGPR pair and the sign a scalar operand.  Two batches of U
+    // rows alternate, the next one in flight while the current one is added.
+    auto load_batch = [&](int q0, uint4 (&raw)[U][NV], double (&sgn)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u * kWaves;
-        const uint32_t ent = q < cnt ? entries[q] : kInvalid;
+        const uint32_t ent = __builtin_amdgcn_readfirstlane(q < cnt ? entries[q] : kInvalid);
         const bool ok = ent != kInvalid;
         sgn[u] = ok ? ((ent & 0x80000000u) ? -1.0 : 1.0) : 0.0;
         const int64_t row = ok ? (int64_t)(ent & 0x7FFFFFFFu) : 0;
@@ -176,6 +178,8 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
         for (int v = 0; v < NV; ++v)
           raw[u][v] = (ok && vec_ok[v]) ? rp[v * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
       }
+    };
+    auto add_batch = [&](const uint4 (&raw)[U][NV], const double (&sgn)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
 #pragma unroll
@@ -186,6 +190,19 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
           for (int e = 0; e < E; ++e) acc[v][e] = fma(sgn[u], x[e], acc[v][e]);
         }
       }
+    };
+    uint4 ra[U][NV], rb[U][NV];
+    double sa[U], sb[U];
+    int q0 = wave;
+    if (q0 < cnt) load_batch(q0, ra, sa);
+    for (; q0 < cnt; q0 += 2 * kWaves * U) {
+      const int q1 = q0 + kWaves * U;
+      if (q1 < cnt) load_batch(q1, rb, sb);
+      add_batch(ra, sa);
+      if (q1 >= cnt) break;
+      const int q2 = q1 + kWaves * U;
+      if (q2 < cnt) load_batch(q2, ra, sa);
+      add_batch(rb, sb);
     }
   }
 
@@ -214,14 +231,14 @@ hipError_t launch_dense_typed(const void* A, int64_t n, int64_t d, int64_t ld, c
   const int64_t per_vec_row = 64 * E;
   if (d <= per_vec_row) {
     dim3 grid((unsigned)hp.r_cs, 1);
-    countsketch_dense_kernel<T, 1, 8><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
+    countsketch_dense_kernel<T, 1, 4><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   } else if (d <= 2 * per_vec_row) {
     dim3 grid((unsigned)hp.r_cs, 1);
-    countsketch_dense_kernel<T, 2, 4><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
+    countsketch_dense_kernel<T, 2, 2><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   } else {
     const int64_t cols = 4 * per_vec_row;
     dim3 grid((unsigned)hp.r_cs, (unsigned)((d + cols - 1) / cols));
-    countsketch_dense_kernel<T, 4, 2><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
+    countsketch_dense_kernel<T, 4, 1><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   }
   return hipGetLastError();
 }
