@@ -27,6 +27,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lev_internal.h"
 
@@ -166,6 +167,32 @@ __device__ __forceinline__ void split3(const F8& f, v8bf& h, v8bf& m, v8bf& l) {
   m = __builtin_convertvector(r1, v8bf);
   const v8f r2 = r1 - __builtin_convertvector(m, v8f);
   l = __builtin_convertvector(r2, v8bf);
+}
+
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+// The same split with one packed conversion per pair of values; the BF16
+// parts are widened back to FP32 by shifting them into the high half, which
+// is exact, so the parts equal those of split3 bit for bit.
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
+}
+__device__ __forceinline__ void split3_pk(const F8& f, v8bf& h, v8bf& m, v8bf& l) {
+  const uint32_t w[8] = {f.lo.x, f.lo.y, f.lo.z, f.lo.w, f.hi.x, f.hi.y, f.hi.z, f.hi.w};
+  uint32_t hp[4], mp[4], lp[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float x0 = __uint_as_float(w[2 * j]), x1 = __uint_as_float(w[2 * j + 1]);
+    hp[j] = pk_bf16(x0, x1);
+    const float r0 = x0 - __uint_as_float(hp[j] << 16), r1 = x1 - __uint_as_float(hp[j] & 0xFFFF0000u);
+    mp[j] = pk_bf16(r0, r1);
+    const float s0 = r0 - __uint_as_float(mp[j] << 16), s1 = r1 - __uint_as_float(mp[j] & 0xFFFF0000u);
+    lp[j] = pk_bf16(s0, s1);
+  }
+  h = __builtin_bit_cast(v8bf, make_uint4(hp[0], hp[1], hp[2], hp[3]));
+  m = __builtin_bit_cast(v8bf, make_uint4(mp[0], mp[1], mp[2], mp[3]));
+  l = __builtin_bit_cast(v8bf, make_uint4(lp[0], lp[1], lp[2], lp[3]));
 }
 
 __device__ __forceinline__ v4f mfma_bf16(const v8bf& a, const v8bf& b, v4f c) {
@@ -339,6 +366,165 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
 
 constexpr size_t kMaxLdsZ = 144 * 1024;
 
+// BF16x3 over FP32 rows with Z staged in LDS (the dense FP32 workload's
+// pass).  Two shapes of workgroup: 768 threads when two copies of Z fit in a
+// CU's LDS (24 waves per CU, two chunks in flight per wave: more waves with
+// fewer registers each keep more of HBM's latency covered than fewer waves
+// with deeper batches), else 1024 threads and one workgroup per CU.
+//  * Z is staged with every load of a thread in flight before its first LDS
+//    store (a load-store loop would pay one L2 round trip per vector).
+//  * Tiles whose 16 rows all exist, when d is a multiple of 32, take a path
+//    with no per-element checks: one base address per lane, the chunk
+//    offsets folded into the load instructions.  The last partial tile and
+//    ragged d take the masked path: each load reads an address that holds
+//    valid data (its own, else the row start) and invalid parts are zeroed.
+//  * Per chunk the six products accumulate from zero in FP32 and are added
+//    to the FP64 accumulators, as in rownorm_dense_kernel.
+template <int WG>
+struct X3Shape;
+template <>
+struct X3Shape<768> {
+  static constexpr int kMinWaves = 6, kBatch = 2, kMaxZVecs = 80 * 1024 / 16;
+};
+template <>
+struct X3Shape<1024> {
+  static constexpr int kMinWaves = 4, kBatch = 4, kMaxZVecs = (int)(kMaxLdsZ / 16);
+};
+
+template <int CB, int WG>
+__global__ __launch_bounds__(WG, X3Shape<WG>::kMinWaves) void rownorm_x3_kernel(
+    const float* __restrict__ A, int64_t n, int64_t d, int64_t ld, int64_t nt, const uint4* __restrict__ Zg,
+    int64_t zvecs, int64_t part_vecs, void* __restrict__ theta_out) {
+  constexpr int kB = X3Shape<WG>::kBatch;
+  constexpr int kZPer = (X3Shape<WG>::kMaxZVecs + WG - 1) / WG;
+  constexpr int kWaves = WG / 64;
+  float* theta = static_cast<float*>(theta_out);
+  extern __shared__ uint4 zs[];
+  {
+    // indexes past the end load and store the last vector again (same value)
+    uint4 zt[kZPer];
+#pragma unroll
+    for (int j = 0; j < kZPer; ++j) {
+      const int64_t i = threadIdx.x + (int64_t)j * WG;
+      zt[j] = Zg[i < zvecs ? i : zvecs - 1];
+    }
+#pragma unroll
+    for (int j = 0; j < kZPer; ++j) {
+      const int64_t i = threadIdx.x + (int64_t)j * WG;
+      zs[i < zvecs ? i : zvecs - 1] = zt[j];
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int64_t ntiles = (n + 15) / 16;
+  const bool whole = (d % 32) == 0;
+  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+    const int64_t row = tile * 16 + (lane & 15);
+    const bool ok = row < n;
+    const float* rp = A + (ok ? row : 0) * ld;
+    double acc64[CB][4];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[cb][v] = 0.0;
+    auto chunks = [&](auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
+      const float* lp = rp + 8 * g;
+      for (int64_t t0 = 0; t0 < nt; t0 += kB) {
+        F8 a[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int64_t t = t0 + u;
+          if constexpr (FULL) {
+            const float* p = lp + (t < nt ? t : 0) * 32;
+            a[u].lo = *reinterpret_cast<const uint4*>(p);
+            a[u].hi = *reinterpret_cast<const uint4*>(p + 4);
+          } else {
+            const int64_t col = t * 32 + 8 * g;
+            const bool vlo = ok && t < nt && col < d;
+            const bool vhi = vlo && col + 4 < d;
+            a[u].lo = *reinterpret_cast<const uint4*>(rp + (vlo ? col : 0));
+            a[u].hi = *reinterpret_cast<const uint4*>(rp + (vhi ? col + 4 : 0));
+          }
+        }
+        if constexpr (!FULL) {
+#pragma unroll
+          for (int u = 0; u < kB; ++u) {
+            const int64_t t = t0 + u;
+            const int64_t col = t * 32 + 8 * g;
+            uint32_t w[8] = {a[u].lo.x, a[u].lo.y, a[u].lo.z, a[u].lo.w, a[u].hi.x, a[u].hi.y, a[u].hi.z, a[u].hi.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (!ok || t >= nt || col + e >= d) w[e] = 0u;
+            a[u].lo = make_uint4(w[0], w[1], w[2], w[3]);
+            a[u].hi = make_uint4(w[4], w[5], w[6], w[7]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int64_t t = t0 + u;
+          if (t < nt) {
+            v8bf ah, am, al;
+            split3_pk(a[u], ah, am, al);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+              const int zi = ((int)t * CB + cb) * 64 + lane;
+              const v8bf zh = as_bf(zs[zi]), zm = as_bf(zs[zi + part_vecs]), zl = as_bf(zs[zi + 2 * part_vecs]);
+              v4f c = v4f{};
+              c = mfma_bf16(al, zh, c);  // smallest terms first
+              c = mfma_bf16(am, zm, c);
+              c = mfma_bf16(ah, zl, c);
+              c = mfma_bf16(am, zh, c);
+              c = mfma_bf16(ah, zm, c);
+              c = mfma_bf16(ah, zh, c);
+#pragma unroll
+              for (int v = 0; v < 4; ++v) acc64[cb][v] += (double)c[v];
+            }
+          }
+        }
+      }
+    };
+    if (whole && tile * 16 + 16 <= n) chunks(std::true_type{});
+    else chunks(std::false_type{});
+    double sq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sq[v] = fma(acc64[cb][v], acc64[cb][v], sq[v]);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sq[v] = sum16(sq[v]);
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = tile * 16 + 4 * g + v;
+        if (r < n) theta[r] = (float)sq[v];
+      }
+    }
+  }
+}
+
+template <int CB, int WG>
+hipError_t launch_x3(const float* a, int64_t n, int64_t d, int64_t ld, int64_t nt, const uint4* z, int64_t zvecs,
+                     int64_t part_vecs, size_t zbytes, int num_cu, void* theta, hipStream_t s) {
+  auto kern = rownorm_x3_kernel<CB, WG>;
+  hipError_t e = hipSuccess;
+  if (zbytes > 64 * 1024) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)zbytes);
+    if (e != hipSuccess) return e;
+  }
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WG, zbytes);
+  if (e != hipSuccess) return e;
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t want = (ntiles + WG / 64 - 1) / (WG / 64);
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * std::max(per_cu, 1)));
+  kern<<<(unsigned)blocks, WG, zbytes, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta);
+  return hipGetLastError();
+}
+
 template <int VAR, typename TA, int CB>
 hipError_t launch_cb(const void* A, int64_t n, int64_t d, int64_t ld, int64_t nt, const void* Zpack,
                      size_t zbytes, void* theta, hipStream_t s) {
@@ -355,6 +541,16 @@ hipError_t launch_cb(const void* A, int64_t n, int64_t d, int64_t ld, int64_t nt
   if (e != hipSuccess) return e;
   // a persistent grid of exactly the resident workgroups: every wave strides
   // over the 16-row tiles, so no tail of half-empty rounds
+  if constexpr (VAR == 4) {
+    if (zbytes <= kMaxLdsZ) {
+      // (four column tiles need more than the 768-thread shape's 80 registers)
+      if constexpr (CB < 4) {
+        if (zbytes <= (size_t)X3Shape<768>::kMaxZVecs * 16)
+          return launch_x3<CB, 768>(a, n, d, ld, nt, z, zvecs, part_vecs, zbytes, num_cu, theta, s);
+      }
+      return launch_x3<CB, 1024>(a, n, d, ld, nt, z, zvecs, part_vecs, zbytes, num_cu, theta, s);
+    }
+  }
   if (zbytes <= kMaxLdsZ) {
     auto kern = rownorm_dense_kernel<VAR, TA, CB, true>;
     if (zbytes > 64 * 1024) {
