@@ -166,6 +166,7 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
 // hardware estimate plus two Newton steps.  No global memory is read inside
 // the loop.
 constexpr int kSmallD = 256;
+constexpr int kSpinLimit = 1 << 22;  // bound on the pivot wait (never reached: see the wait)
 constexpr int kBandR = 64, kBandC = 64;
 constexpr int kLvec = 256;  // >= 64 * ceil(256 / 64)
 
@@ -230,7 +231,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // The pivot of the next step, posted by the diagonal wave.
-struct PivotMsg {
+struct __align__(16) PivotMsg {
   double inv;  // 1 / sqrt(S_pp)
   int p;
   int ok;  // 0: the factorization stops here
@@ -238,8 +239,11 @@ struct PivotMsg {
 
 __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __restrict__ B, int d, double zeta,
                                                             PivCholState st, int64_t* __restrict__ rank_out) {
-  __shared__ __align__(16) double lvec[kLvec];
-  __shared__ PivotMsg msg;
+  // step J uses lvec[J & 1] and msg[J & 1]; `posted` counts the pivots the
+  // diagonal wave has posted (msg[J & 1] holds pivot J once posted > J)
+  __shared__ __align__(16) double lvec[2][kLvec];
+  __shared__ PivotMsg msg[2];
+  __shared__ int posted;
 
   const int lane = threadIdx.x & 63;
   // wave-uniform values kept scalar (the compiler cannot infer it)
@@ -277,48 +281,70 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
     LEV_LOAD16(s0, 0) LEV_LOAD16(s1, 2) LEV_LOAD16(s2, 4) LEV_LOAD16(s3, 6)
 #undef LEV_LOAD16
   }
-  for (int t = threadIdx.x; t < kLvec; t += blockDim.x) lvec[t] = 0.0;
-
-  for (int t = threadIdx.x; t < kLvec; t += blockDim.x) lvec[t] = 0.0;
+  for (int t = threadIdx.x; t < 2 * kLvec; t += blockDim.x) lvec[t / kLvec][t % kLvec] = 0.0;
 
   if (square) {
     __syncthreads();  // the first pivot is posted
     for (int J = 0; J < d; ++J) {
-      const int p = __builtin_amdgcn_readfirstlane(msg.p);
-      const int ok = __builtin_amdgcn_readfirstlane(msg.ok);
-      const double inv = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(msg.inv)),
-                                          __builtin_amdgcn_readfirstlane(__double2loint(msg.inv)));
+      // pivot J: posted by the diagonal wave once every wave has passed the
+      // barrier of step J - 1, which this wave has, so the wait ends
+      // The message is read right behind the counter, in one round trip:
+      // LDS serves a wave's accesses in order, and the diagonal wave's
+      // message store completes before its counter store, so a counter that
+      // shows pivot J comes with message J.
+      uint64_t m0, m1;
+      for (int spin = 0;; ++spin) {
+        const int seen = __hip_atomic_load(&posted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        uint64_t* mp = reinterpret_cast<uint64_t*>(&msg[J & 1]);
+        m0 = __hip_atomic_load(mp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        m1 = __hip_atomic_load(mp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (seen > J || spin >= kSpinLimit) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+      const int p = __builtin_amdgcn_readfirstlane((int)(uint32_t)m1);
+      const int ok = __builtin_amdgcn_readfirstlane((int)(uint32_t)(m1 >> 32));
+      const double inv = __hiloint2double(__builtin_amdgcn_readfirstlane((int)(uint32_t)(m0 >> 32)),
+                                          __builtin_amdgcn_readfirstlane((int)(uint32_t)m0));
       if (!ok) break;
+      double* lv = lvec[J & 1];
       const int bp = p / kBandC;
       const int pl = p - kBandC * bp;  // p's position inside its band
       if (b == bp) {
         // column p of the squares (a, b_p), a >= b_p: rows of bands >= b_p;
-        // the 8 lanes of column group pl / 8 each hold 8 rows of it, picked
-        // with uniform-index register extracts
+        // the 8 lanes of column group pl / 8 each hold 8 rows of it (entry
+        // (r, c) of the lane's block is element (r % 2) * 8 + c of vector
+        // r / 2), picked by a uniform switch on c
         if (gc == (pl >> 3)) {
-          const int e = __builtin_amdgcn_readfirstlane(pl & 7);
-          const double v0 = s0[e], v1 = s0[8 + e], v2 = s1[e], v3 = s1[8 + e];
-          const double v4 = s2[e], v5 = s2[8 + e], v6 = s3[e], v7 = s3[8 + e];
-          double2* dst = reinterpret_cast<double2*>(&lvec[ri0]);
-          dst[0] = make_double2(v0 * inv, v1 * inv);
-          dst[1] = make_double2(v2 * inv, v3 * inv);
-          dst[2] = make_double2(v4 * inv, v5 * inv);
-          dst[3] = make_double2(v6 * inv, v7 * inv);
+          double v[8];
+          switch (__builtin_amdgcn_readfirstlane(pl & 7)) {
+#define LEV_COL(C)                                                                                  \
+  case C:                                                                                           \
+    v[0] = s0[C], v[1] = s0[8 + C], v[2] = s1[C], v[3] = s1[8 + C];                                 \
+    v[4] = s2[C], v[5] = s2[8 + C], v[6] = s3[C], v[7] = s3[8 + C];                                 \
+    break;
+            LEV_COL(0) LEV_COL(1) LEV_COL(2) LEV_COL(3) LEV_COL(4) LEV_COL(5) LEV_COL(6) default: LEV_COL(7)
+#undef LEV_COL
+          }
+          double2* dst = reinterpret_cast<double2*>(&lv[ri0]);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) dst[q] = make_double2(v[2 * q] * inv, v[2 * q + 1] * inv);
         }
       } else if (a == bp) {
         // row p of the squares (b_p, b), b < b_p: columns of bands < b_p,
-        // by symmetry the entries of column p there
+        // by symmetry the entries of column p there; row r = pl % 8 of the
+        // lane's block is elements (r % 2) * 8 .. + 7 of vector r / 2
         if (gr == (pl >> 3)) {
-          const int rr = pl & 7;
-          const int e = __builtin_amdgcn_readfirstlane((rr & 1) * 8);
-          const int vs = __builtin_amdgcn_readfirstlane(rr >> 1);
           double w[8];
-#pragma unroll
-          for (int c = 0; c < 8; ++c) {
-            const double u0 = s0[e + c], u1 = s1[e + c], u2 = s2[e + c], u3 = s3[e + c];
-            w[c] = vs == 0 ? u0 : (vs == 1 ? u1 : (vs == 2 ? u2 : u3));
+          switch (__builtin_amdgcn_readfirstlane(pl & 7)) {
+#define LEV_ROW(R, V)                                                                               \
+  case R:                                                                                           \
+    _Pragma("unroll") for (int c = 0; c < 8; ++c) w[c] = V[((R) & 1) * 8 + c];                      \
+    break;
+            LEV_ROW(0, s0) LEV_ROW(1, s0) LEV_ROW(2, s1) LEV_ROW(3, s1) LEV_ROW(4, s2) LEV_ROW(5, s2)
+            LEV_ROW(6, s3) default: LEV_ROW(7, s3)
+#undef LEV_ROW
           }
-          double2* dst = reinterpret_cast<double2*>(&lvec[cj0]);
+          double2* dst = reinterpret_cast<double2*>(&lv[cj0]);
 #pragma unroll
           for (int c = 0; c < 8; c += 2) dst[c / 2] = make_double2(w[c] * inv, w[c + 1] * inv);
         }
@@ -329,7 +355,7 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
       // the FMAs where they are)
       double lc[8], lr[4];
       {
-        const double2* src = reinterpret_cast<const double2*>(&lvec[cj0]);
+        const double2* src = reinterpret_cast<const double2*>(&lv[cj0]);
 #pragma unroll
         for (int c = 0; c < 8; c += 2) {
           const double2 t = src[c / 2];
@@ -337,7 +363,7 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
           lc[c + 1] = t.y;
         }
       }
-      const double2* srr = reinterpret_cast<const double2*>(&lvec[ri0]);
+      const double2* srr = reinterpret_cast<const double2*>(&lv[ri0]);
 #define LEV_ROWS4(R0)                                                      \
   {                                                                        \
     const double2 t0 = srr[(R0) / 2], t1 = srr[(R0) / 2 + 1];              \
@@ -357,7 +383,6 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
 #undef LEV_ROWS4
 #undef LEV_UPD16
       if (threadIdx.x == 0) st.piv[J] = p;
-      lds_barrier();
     }
   } else {
     // the diagonal wave: d_i for rows lane + 64 t; the serial part of each
@@ -370,6 +395,7 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
       dg[t] = i < d ? B[(int64_t)i * d + i] : -INFINITY;
     }
     double r00 = 0.0;
+    int cur_p = 0;
     // posts the pivot of step J: the largest d_i, ties to the lower index,
     // with 1/sqrt(d_p) (hardware estimate + two Newton steps, ~1 ulp); returns
     // whether the factorization continues
@@ -395,25 +421,35 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
         pm.inv = inv;
         pm.p = p;
         pm.ok = ok ? 1 : 0;
-        msg = pm;
+        msg[J & 1] = pm;
+        __hip_atomic_store(&posted, J + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
+      cur_p = p;
       return ok;
     };
     bool ok = post(0);
     __syncthreads();
     int J = 0;
     for (; J < d && ok; ++J) {
-      const int p = __builtin_amdgcn_readfirstlane(msg.p);
+      const int p = cur_p;
       lds_barrier();
+      // all four reads in flight at once (lvec holds kLvec >= 4 * 64 entries,
+      // zero past d), the next pivot posted before the stores of R's row
+      const double* lv = lvec[J & 1];
+      double l[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) l[t] = lv[lane + 64 * t];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int i = lane + 64 * t;
-        const double l = i < d ? lvec[i] : 0.0;
-        dg[t] = (i == p || i >= d) ? -INFINITY : fma(-l, l, dg[t]);
-        if (i < d) st.Rrows[(int64_t)J * d + i] = l;
+        dg[t] = (i == p || i >= d) ? -INFINITY : fma(-l[t], l[t], dg[t]);
       }
       ok = post(J + 1);
-      lds_barrier();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int i = lane + 64 * t;
+        if (i < d) st.Rrows[(int64_t)J * d + i] = l[t];
+      }
     }
     __builtin_amdgcn_s_setprio(0);
     if (lane == 0) {
