@@ -165,9 +165,11 @@ __global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, const dou
 int dgemm_choose_splits(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   int splits = 1;
-  // Aim for >= 512 workgroups (2 per CU) while each split keeps >= 128 of K
-  // (four K steps, so the prefetch of the next step has work to hide behind).
-  while (tiles * splits < 512 && K / (splits * 2) >= 128 && splits < 64) splits *= 2;
+  // Aim for >= 512 workgroups (2 per CU) while each split keeps >= 64 of K
+  // (two K steps, so the prefetch of the second has the first to hide
+  // behind): a short-K product like the 256 x 256 Gram of a 512-row sketch
+  // then spreads over 128 workgroups instead of 32.
+  while (tiles * splits < 512 && K / (splits * 2) >= 64 && splits < 64) splits *= 2;
   return splits;
 }
 

@@ -252,19 +252,22 @@ RankBufs carve_rank(Carver& c, int64_t m, int64_t d) {
   return b;
 }
 
+// Gk (d x k, may be null): the JL Gaussian, drawn alongside G_m.
 lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::SeedDraws& dr,
-                          const SketchBufs& b, double* SA, double* At, hipStream_t s) {
-  const int64_t d = A->d, m = p->m, r_cs = p->r_cs;
-  // G_m is drawn by pass 1's workgroups (compute under its memory traffic)
-  const lev::GaussDraw gm{dr.key_m, m * r_cs, 1.0 / std::sqrt((double)m), b.Gm};
+                          const SketchBufs& b, double* SA, double* At, double* Gk, hipStream_t s) {
+  const int64_t d = A->d, m = p->m, r_cs = p->r_cs, k = p->k;
+  // G_m and G_k are drawn by pass 1's workgroups (compute under its memory traffic)
+  const lev::GaussDraw g{{{dr.key_m, m * r_cs, 1.0 / std::sqrt((double)m), b.Gm},
+                          {dr.key_k, d * k, 1.0 / std::sqrt((double)k), Gk}}};
   LEV_HIP(mark_phase(1, s));
   if (A->n > 0 && A->format == LEV_CSR) {
     LEV_HIP(lev::launch_countsketch_csr(A->dtype, A->values, A->row_ptr, A->col_idx, A->n, d, A->nnz, dr.hash,
-                                        SA, gm, s));
+                                        SA, g, s));
   } else if (A->n > 0) {
-    LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, gm, s));
+    LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, g, s));
   } else {
-    LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, gm.scale, b.Gm, s));
+    LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, g.m[0].scale, b.Gm, s));
+    if (Gk != nullptr) LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, g.m[1].scale, Gk, s));
     LEV_HIP(lev::launch_fill_zero(SA, sizeof(double) * (size_t)(r_cs * d), s));
   }
   LEV_HIP(mark_phase(2, s));
@@ -461,7 +464,7 @@ lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out, 
   SketchBufs b = carve_sketch(c, A->n, A->d, p->m, p->r_cs, true);
   const lev::SeedDraws dr = lev::derive_draws(p->seed, A->n, p->r_cs);
   double* SA = SA_out != nullptr ? SA_out : b.SA;
-  return enqueue_sketch(A, p, dr, b, SA, At_out, stream);
+  return enqueue_sketch(A, p, dr, b, SA, At_out, nullptr, stream);
 }
 
 lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta, int32_t* perm_out,
@@ -502,8 +505,7 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
 
   const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
   LEV_HIP(mark_phase(0, stream));
-  LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, 1.0 / std::sqrt((double)k), Gk, stream));
-  LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, stream));
+  LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, Gk, stream));
   LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, stream));
   LEV_HIP(mark_phase(4, stream));
   LEV_HIP(lev::launch_form_z(variant, d, k, sv.R, rank, sv.perm, Gk, sv.Z64, Zpack, stream));

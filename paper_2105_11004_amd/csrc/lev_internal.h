@@ -42,16 +42,19 @@ hipError_t launch_hash_rows(const HashParams& hp, int64_t* h_out, int8_t* s_out,
 // bucket_off[r_cs+1], bucket_rows[n] in pass-1 order (debug/inspection).
 hipError_t launch_bucket_lists(const HashParams& hp, int64_t* off, int32_t* rows, hipStream_t s);
 
-// A Gaussian matrix drawn by pass 1 on the side (the draws of
-// launch_gaussian, element e = pair e / 2 of the Philox stream, times
-// scale): the r_cs bucket workgroups each take an equal share of the pairs,
-// so the FP64 transcendentals run while the CUs stream A.  out == nullptr:
-// none.
-struct GaussDraw {
+// Up to two Gaussian matrices drawn by pass 1 on the side (each the draws
+// of launch_gaussian: element e = pair e / 2 of its Philox stream, times its
+// scale): the bucket workgroups each take an equal share of the pairs of
+// both, so the FP64 transcendentals run while the CUs stream A.  A matrix
+// with out == nullptr is not drawn.
+struct GaussMatrix {
   PhiloxKey key;
   int64_t total;  // elements
   double scale;
   double* out;
+};
+struct GaussDraw {
+  GaussMatrix m[2];
 };
 
 // Pass 1, dense: SA (r_cs x d, FP64, ld = d) = S A, plus the draw g.

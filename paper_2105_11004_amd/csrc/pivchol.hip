@@ -462,42 +462,44 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
 }
 
 // perm: pivots, then the unselected columns ascending.  R_out: pivoted,
-// upper triangular, rows >= r zero.  One workgroup of kMaxD threads for the
-// permutation, then the R gather.
-__global__ __launch_bounds__(kMaxD) void pivchol_perm_kernel(int64_t d, PivCholState st,
-                                                             const int64_t* __restrict__ rank,
-                                                             int32_t* __restrict__ perm_out) {
+// upper triangular, rows >= r zero.  One launch: every workgroup rebuilds
+// the permutation in LDS (a ballot count of the unselected columns per wave,
+// then a sum over the waves before it), workgroup 0 writes it out, and each
+// workgroup gathers kFinalRows rows of R.
+constexpr int kFinalRows = 4;
+
+__global__ __launch_bounds__(kMaxD) void pivchol_finalize_kernel(int64_t d, PivCholState st,
+                                                                 const int64_t* __restrict__ rank,
+                                                                 int32_t* __restrict__ perm_out,
+                                                                 double* __restrict__ R_out) {
   __shared__ int chosen[kMaxD];
-  __shared__ int scan[kMaxD];
+  __shared__ int wave_cnt[kMaxD / 64];
+  __shared__ int perm_s[kMaxD];
   const int c = threadIdx.x;
-  const int64_t r = *rank;
-  if (c < d) chosen[c] = 0;
+  const int lane = c & 63, w = c >> 6;
+  const int64_t r = *rank;  // 0 <= r <= d
+  chosen[c] = 0;
   __syncthreads();
   if (c < r) chosen[st.piv[c]] = 1;
   __syncthreads();
-  const int free_c = (c < d && !chosen[c]) ? 1 : 0;
-  scan[c] = free_c;
+  const bool free_c = c < d && chosen[c] == 0;
+  const unsigned long long bal = __ballot(free_c);
+  if (lane == 0) wave_cnt[w] = __popcll(bal);
   __syncthreads();
-  // inclusive Hillis-Steele scan over kMaxD entries
-  for (int off = 1; off < kMaxD; off <<= 1) {
-    const int add = (c >= off) ? scan[c - off] : 0;
-    __syncthreads();
-    scan[c] += add;
-    __syncthreads();
-  }
-  if (c < r) perm_out[c] = st.piv[c];
-  if (free_c) perm_out[r + scan[c] - 1] = c;
-}
-
-__global__ void pivchol_gather_r_kernel(int64_t d, PivCholState st, const int64_t* __restrict__ rank,
-                                        const int32_t* __restrict__ perm, double* __restrict__ R_out) {
-  const int64_t j = blockIdx.x;  // output row
-  const int64_t r = *rank;
-  for (int64_t t = threadIdx.x; t < d; t += blockDim.x) {
-    double v = 0.0;
-    if (j < r && t >= j) v = st.Rrows[j * d + perm[t]];
-    R_out[j * d + t] = v;
-  }
+  int before = __popcll(bal & ((1ull << lane) - 1ull));
+  for (int q = 0; q < w; ++q) before += wave_cnt[q];
+  if (c < r) perm_s[c] = st.piv[c];
+  if (free_c) perm_s[r + before] = c;
+  __syncthreads();
+  if (blockIdx.x == 0 && c < d) perm_out[c] = perm_s[c];
+  const int64_t j0 = (int64_t)blockIdx.x * kFinalRows;
+  const int64_t j1 = j0 + kFinalRows < d ? j0 + kFinalRows : d;
+  for (int64_t j = j0; j < j1; ++j)
+    for (int64_t t = c; t < d; t += kMaxD) {
+      double v = 0.0;
+      if (j < r && t >= j) v = st.Rrows[j * d + perm_s[t]];
+      R_out[j * d + t] = v;
+    }
 }
 
 }  // namespace
@@ -527,8 +529,9 @@ hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState&
 
 hipError_t launch_pivchol_finalize(int64_t d, const PivCholState& st, const int64_t* rank,
                                    int32_t* perm_out, double* R_out, hipStream_t s) {
-  pivchol_perm_kernel<<<1, kMaxD, 0, s>>>(d, st, rank, perm_out);
-  pivchol_gather_r_kernel<<<(unsigned)d, 256, 0, s>>>(d, st, rank, perm_out, R_out);
+  if (d <= 0 || d > kMaxD) return hipErrorInvalidValue;
+  pivchol_finalize_kernel<<<(unsigned)((d + kFinalRows - 1) / kFinalRows), kMaxD, 0, s>>>(d, st, rank, perm_out,
+                                                                                          R_out);
   return hipGetLastError();
 }
 

@@ -104,18 +104,25 @@ __device__ __forceinline__ void to_double<__hip_bfloat16>(const uint4& raw, doub
   }
 }
 
-// Workgroup (blockIdx.x of gridDim.x) share of the side draw: pairs
-// [part * per, (part + 1) * per), one Box-Muller pair per thread and round.
+// Workgroup (blockIdx.x of gridDim.x) share of the side draw: the pairs of
+// the two matrices taken as one sequence, [part * per, (part + 1) * per) of
+// it, one Box-Muller pair per thread and round.
 __device__ __forceinline__ void side_draw(const GaussDraw& g) {
-  if (g.out == nullptr || blockIdx.y != 0) return;
-  const int64_t pairs = (g.total + 1) / 2;
+  if (blockIdx.y != 0) return;
+  const int64_t pairs0 = g.m[0].out != nullptr ? (g.m[0].total + 1) / 2 : 0;
+  const int64_t pairs1 = g.m[1].out != nullptr ? (g.m[1].total + 1) / 2 : 0;
+  const int64_t pairs = pairs0 + pairs1;
+  if (pairs == 0) return;
   const int64_t per = (pairs + gridDim.x - 1) / gridDim.x;
   const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min<int64_t>(q0 + per, pairs);
-  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+  for (int64_t qq = q0 + threadIdx.x; qq < q1; qq += blockDim.x) {
+    const bool second = qq >= pairs0;
+    const GaussMatrix& gm = second ? g.m[1] : g.m[0];
+    const int64_t q = second ? qq - pairs0 : qq;
     double z0, z1;
-    box_muller_pair((uint64_t)q, g.key, &z0, &z1);
-    g.out[2 * q] = z0 * g.scale;
-    if (2 * q + 1 < g.total) g.out[2 * q + 1] = z1 * g.scale;
+    box_muller_pair((uint64_t)q, gm.key, &z0, &z1);
+    gm.out[2 * q] = z0 * gm.scale;
+    if (2 * q + 1 < gm.total) gm.out[2 * q + 1] = z1 * gm.scale;
   }
 }
 
