@@ -103,7 +103,7 @@ __device__ __forceinline__ void box_muller_pair(uint64_t counter, PhiloxKey key,
   const double u2 = ((double)b + 0.5) * 0x1.0p-53;
   const double radius = sqrt(-2.0 * log(u1));
   double sn, cs;
-  sincos(2.0 * 3.14159265358979323846 * u2, &sn, &cs);
+  sincospi(2.0 * u2, &sn, &cs);  // sin, cos of 2 pi u2; 2 u2 is exact, so no reduction by pi is needed
   *z_even = radius * cs;
   *z_odd = radius * sn;
 }
