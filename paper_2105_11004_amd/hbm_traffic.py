@@ -31,7 +31,9 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 COPY_BYTES = 1 << 30
 KERNELS = {
-    "pass2_rownorm": ("rownorm_dense_kernel", PKG / "csrc" / "rownorm.hip"),
+    # the benchmark's FP32 pass runs the BF16x3 kernel (rownorm_x3_kernel);
+    # the other dense forms run rownorm_dense_kernel
+    "pass2_rownorm": ("rownorm_x3_kernel", PKG / "csrc" / "rownorm.hip"),
     "pass1_countsketch": ("countsketch_dense_kernel", PKG / "csrc" / "sketch.hip"),
 }
 
