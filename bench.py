@@ -132,6 +132,33 @@ def traffic_for(kernel: str):
     return ent.get("bytes_per_launch")
 
 
+def _median_ms(fn, stream, reps=5) -> float:
+    fn()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return float(np.median(times))
+
+
+def copy_ceiling(A, stream) -> dict:
+    """Measured ceilings on A's storage: a device-to-device copy (bytes read +
+    bytes written) and a read-only reduction (torch's sum over its words)."""
+    src = (A.values if _is_csr(A) else A).reshape(-1).view(torch.uint8)
+    nbytes = src.numel()
+    dst = torch.empty_like(src)
+    copy_ms = _median_ms(lambda: dst.copy_(src), stream)
+    del dst
+    # the reduction reads the bytes as FP32 words (their values do not matter here)
+    words = src[: nbytes // 4 * 4].view(torch.float32)
+    read_ms = min(_median_ms(lambda: torch.sum(words), stream), _median_ms(lambda: torch.amax(words), stream))
+    return {"torch_copy_gbs": 2 * nbytes / (copy_ms * 1e-3) / 1e9, "torch_read_gbs": nbytes / (read_ms * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,9 +217,15 @@ def main():
     ms = total_ms / args.steps
 
     phases = {}
+    spread = {}
     for i, name in enumerate(api.PHASE_NAMES):
         vals = [ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(args.steps)]
         phases[name] = float(np.mean(vals))
+        spread[name] = {"median": float(np.median(vals)), "min": float(np.min(vals)), "max": float(np.max(vals))}
+    step_vals = [ev[s][0].elapsed_time(ev[s][len(api.PHASE_NAMES)]) for s in range(args.steps)]
+    spread["step"] = {"median": float(np.median(step_vals)), "min": float(np.min(step_vals)),
+                      "max": float(np.max(step_vals))}
+    copy_gbs = copy_ceiling(A, stream)
     n = A.n if _is_csr(A) else A.shape[0]
     vals = A.values if _is_csr(A) else A
     bpl = bytes_per_launch(A, cfg)
@@ -217,8 +250,13 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom), "kernel": dom},
         "phases_ms": phases,
+        "phases_ms_spread": spread,
         "pass1_hbm_gbs": pass1_gbs,
         "pass1_frac": pass1_gbs / HBM_PEAK_GBS,
+        # measured ceilings beside the spec-sheet peak, on the same GPU: a
+        # device-to-device copy of A's bytes (read + write) and a torch
+        # reduction that reads them once
+        "measured_ceilings": copy_gbs,
     }
     if backward:
         bms = float(np.mean([e[0].elapsed_time(e[1]) for e in bwd_ev]))
