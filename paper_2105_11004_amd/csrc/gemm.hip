@@ -58,20 +58,40 @@ __device__ __forceinline__ void load_stage(Stage& st, int tid, int64_t m0, int64
   }
 }
 
-__device__ __forceinline__ void store_stage(const Stage& st, int tid, bool a_kfast, bool b_jfast,
-                                            double (*As)[BM + 1], double (*Bs)[BN + 1]) {
+// LDS layouts of one K step of an operand (64 rows x BK), chosen so that
+// both the staging stores (consecutive threads walk the operand's contiguous
+// index) and the MFMA operand reads (16 consecutive rows or columns per
+// 16-lane group, one k per group) are free of bank conflicts:
+//  * operand contiguous in k (KF): [i][k] with a row stride of BK + 2
+//    doubles (68 banks = 4 mod 64: the four k groups of an MFMA read land on
+//    disjoint bank pairs);
+//  * operand contiguous in i: [k][i ^ 16 (k odd)] with a row stride of 64
+//    doubles (the swizzle moves the odd-k groups to the other 32 banks).
+constexpr int kLdsOp = BM * (BK + 2);  // doubles per operand buffer (the larger layout)
+
+template <bool KF>
+__device__ __forceinline__ int lds_idx(int k, int i) {
+  if constexpr (KF) return i * (BK + 2) + k;
+  else return k * BM + (i ^ ((k & 1) << 4));
+}
+
+template <bool AK, bool BJ>
+__device__ __forceinline__ void store_stage(const Stage& st, int tid, double* __restrict__ As,
+                                            double* __restrict__ Bs) {
 #pragma unroll
   for (int q = 0; q < kPerThread; ++q) {
     const int e = tid + kThreads * q;
-    const int kk = a_kfast ? e % BK : e / BM;
-    const int ii = a_kfast ? e / BK : e % BM;
-    As[kk][ii] = st.a[q];
-    const int kb = b_jfast ? e / BN : e % BK;
-    const int jj = b_jfast ? e % BN : e / BK;
-    Bs[kb][jj] = st.b[q];
+    const int kk = AK ? e % BK : e / BM;
+    const int ii = AK ? e / BK : e % BM;
+    As[lds_idx<AK>(kk, ii)] = st.a[q];
+    const int kb = BJ ? e / BN : e % BK;
+    const int jj = BJ ? e % BN : e / BK;
+    Bs[lds_idx<!BJ>(kb, jj)] = st.b[q];
   }
 }
 
+// AK: A is contiguous in k (sak == 1); BJ: B is contiguous in j (sbj == 1).
+template <bool AK, bool BJ>
 __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                          const double* __restrict__ A, int64_t sai,
                                                          int64_t sak, const double* __restrict__ B,
@@ -80,8 +100,8 @@ __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, i
                                                          int64_t kchunk, double* __restrict__ partial,
                                                          const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip != 0) return;
-  __shared__ double As[2][BK][BM + 1];
-  __shared__ double Bs[2][BK][BN + 1];
+  __shared__ double As[2][kLdsOp];
+  __shared__ double Bs[2][kLdsOp];
 
   const int64_t m0 = (int64_t)blockIdx.x * BM;
   const int64_t n0 = (int64_t)blockIdx.y * BN;
@@ -90,8 +110,6 @@ __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, i
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const bool a_kfast = (sak == 1);
-  const bool b_jfast = (sbj == 1);
 
   v4d acc[2][2];
 #pragma unroll
@@ -103,27 +121,36 @@ __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, i
   int buf = 0;
   if (kb < ke) {
     load_stage(st, tid, m0, n0, kb, ke, M, N, A, sai, sak, B, sbk, sbj);
-    store_stage(st, tid, a_kfast, b_jfast, As[0], Bs[0]);
+    store_stage<AK, BJ>(st, tid, As[0], Bs[0]);
   }
   __syncthreads();
   for (int64_t k0 = kb; k0 < ke; k0 += BK) {
     const bool more = k0 + BK < ke;  // uniform
     if (more) load_stage(st, tid, m0, n0, k0 + BK, ke, M, N, A, sai, sak, B, sbk, sbj);
+    // the operands of group g + 1 are read before the MFMAs of group g are
+    // issued, so the LDS latency hides behind them
+    double a[2][2], b[2][2];
+    auto read_group = [&](int k4, int slot) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[slot][i] = As[buf][lds_idx<AK>(k4 + (lane >> 4), wm + 16 * i + (lane & 15))];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[slot][j] = Bs[buf][lds_idx<!BJ>(k4 + (lane >> 4), wn + 16 * j + (lane & 15))];
+    };
+    read_group(0, 0);
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
-      double a[2], b[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[buf][k4 + (lane >> 4)][wm + 16 * i + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[buf][k4 + (lane >> 4)][wn + 16 * j + (lane & 15)];
+      const int cur = (k4 / 4) & 1;
+      if (k4 + 4 < BK) read_group(k4 + 4, cur ^ 1);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[cur][i], b[cur][j], acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     // the other buffer was last read before the previous barrier
-    if (more) store_stage(st, tid, a_kfast, b_jfast, As[buf ^ 1], Bs[buf ^ 1]);
+    if (more) store_stage<AK, BJ>(st, tid, As[buf ^ 1], Bs[buf ^ 1]);
     __syncthreads();
     buf ^= 1;
   }
@@ -187,8 +214,11 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const dou
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   if (kchunk == 0) kchunk = BK;
   dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN), (unsigned)splits);
-  dgemm_kernel<<<grid, kThreads, 0, s>>>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc, splits,
-                                    kchunk, partial, skip);
+  const bool ak = (sak == 1), bj = (sbj == 1);
+  auto kern = ak ? (bj ? dgemm_kernel<true, true> : dgemm_kernel<true, false>)
+                 : (bj ? dgemm_kernel<false, true> : dgemm_kernel<false, false>);
+  kern<<<grid, kThreads, 0, s>>>(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc, splits, kchunk, partial,
+                                 skip);
   if (splits > 1) {
     const int64_t total = M * N;
     splitk_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, partial, alpha,
