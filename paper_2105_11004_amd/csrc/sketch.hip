@@ -104,16 +104,23 @@ __device__ __forceinline__ void to_double<__hip_bfloat16>(const uint4& raw, doub
   }
 }
 
-// Workgroup (blockIdx.x of gridDim.x) share of the side draw: the pairs of
-// the two matrices taken as one sequence, [part * per, (part + 1) * per) of
-// it, one Box-Muller pair per thread and round.
+// Workgroup (blockIdx.x) share of the side draw: the pairs of the two
+// matrices taken as one sequence, split over the first kDrawGroups
+// workgroups (more when that would leave a thread over 16 pairs), one
+// Box-Muller pair per thread and round.  Drawing in the workgroups that
+// start first puts the matrices' stores ahead of most of the read stream
+// (measured: 6-8 us less than spreading them over every workgroup).
+constexpr int64_t kDrawGroups = 256;
 __device__ __forceinline__ void side_draw(const GaussDraw& g) {
   if (blockIdx.y != 0) return;
   const int64_t pairs0 = g.m[0].out != nullptr ? (g.m[0].total + 1) / 2 : 0;
   const int64_t pairs1 = g.m[1].out != nullptr ? (g.m[1].total + 1) / 2 : 0;
   const int64_t pairs = pairs0 + pairs1;
   if (pairs == 0) return;
-  const int64_t per = (pairs + gridDim.x - 1) / gridDim.x;
+  const int64_t want = max<int64_t>(kDrawGroups, (pairs + 16 * kThreads - 1) / (16 * kThreads));
+  const int64_t groups = min<int64_t>((int64_t)gridDim.x, want);
+  if ((int64_t)blockIdx.x >= groups) return;
+  const int64_t per = (pairs + groups - 1) / groups;
   const int64_t q0 = (int64_t)blockIdx.x * per, q1 = min<int64_t>(q0 + per, pairs);
   for (int64_t qq = q0 + threadIdx.x; qq < q1; qq += blockDim.x) {
     const bool second = qq >= pairs0;
