@@ -399,6 +399,7 @@ __global__ __launch_bounds__(WG, X3Shape<WG>::kMinWaves) void rownorm_x3_kernel(
   constexpr int kZPer = (X3Shape<WG>::kMaxZVecs + WG - 1) / WG;
   constexpr int kWaves = WG / 64;
   float* theta = static_cast<float*>(theta_out);
+  const bool theta_vec = (reinterpret_cast<uintptr_t>(theta) & 15) == 0;
   extern __shared__ uint4 zs[];
   {
     // indexes past the end load and store the last vector again (same value)
@@ -496,10 +497,15 @@ __global__ __launch_bounds__(WG, X3Shape<WG>::kMinWaves) void rownorm_x3_kernel(
 #pragma unroll
     for (int v = 0; v < 4; ++v) sq[v] = sum16(sq[v]);
     if ((lane & 15) == 0) {
+      // rows 4 g .. 4 g + 3 of the tile: one 16-byte store when they all
+      // exist and theta is 16-byte aligned
+      const int64_t r0 = tile * 16 + 4 * g;
+      if (theta_vec && r0 + 4 <= n) {
+        *reinterpret_cast<float4*>(theta + r0) = make_float4((float)sq[0], (float)sq[1], (float)sq[2], (float)sq[3]);
+      } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = tile * 16 + 4 * g + v;
-        if (r < n) theta[r] = (float)sq[v];
+        for (int v = 0; v < 4; ++v)
+          if (r0 + v < n) theta[r0 + v] = (float)sq[v];
       }
     }
   }

@@ -244,6 +244,22 @@ def test_padded_rows_and_odd_width(gpu):
     assert _rel(theta.astype(np.float64), o.theta).max() < 1e-4
 
 
+def test_unaligned_theta_output(gpu):
+    """theta_out at a 4-byte offset (not 16-byte aligned) and n not a
+    multiple of 16: the same bits as an aligned output."""
+    _log("unaligned theta")
+    n, d = 20011, 256
+    A = W.low_rank_coherent(n, d, 64, 6).to(gpu)
+    plan = api.EstimatePlan(A, 3, 1024, 512, 48, 1e-5)
+    ref = plan.run().clone()
+    buf = torch.full((n + 1,), float("nan"), dtype=torch.float32, device=gpu)
+    plan.theta = buf[1:]
+    out = plan.run()
+    torch.cuda.synchronize()
+    assert out.data_ptr() % 16 != 0
+    assert torch.equal(out, ref)
+
+
 def test_estimate_is_deterministic(gpu):
     A = W.low_rank_coherent(50000, 128, 64, 4).to(gpu)
     t1 = api.lev_estimate(A, 9, 2048, 256, 32, 1e-5)
