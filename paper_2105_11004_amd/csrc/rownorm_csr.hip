@@ -144,20 +144,31 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
       }
     };
     flush_rows();
+    // the column ids and values of the next 64 nonzeros are loaded while the
+    // current 64 are multiplied (one global round trip per chunk is no
+    // longer on the wave's critical path)
+    auto load_chunk = [&](int64_t cs, int32_t& c, T& v) {
+      const int64_t p = cs + lane;
+      const int64_t q = p < N1 ? p : (N1 > 0 ? N1 - 1 : 0);  // in bounds whenever nnz > 0
+      c = p < N1 ? col_idx[q] : -1;
+      v = p < N1 ? vals[q] : T{};
+    };
+    int32_t nc = -1;
+    T nv{};
+    if (N0 < N1) load_chunk(N0, nc, nv);
     for (int64_t c0 = N0; c0 < N1; c0 += 64) {
-      const int64_t p = c0 + lane;
+      const int32_t c = nc;
+      const T cv = nv;
+      if (c0 + 64 < N1) load_chunk(c0 + 64, nc, nv);
       StageEntry<ZT> e;
       e.off = 0;
       e.val = 0;
-      if (p < N1) {
-        const int32_t c = col_idx[p];
-        if ((uint32_t)c < (uint32_t)d) {
-          e.off = c * kZStride;
-          if constexpr (sizeof(ZT) == 8) {
-            e.val = (ZT)vals[p];
-          } else {
-            e.val = to_f32<T>(vals[p]);
-          }
+      if ((uint32_t)c < (uint32_t)d) {
+        e.off = c * kZStride;
+        if constexpr (sizeof(ZT) == 8) {
+          e.val = (ZT)cv;
+        } else {
+          e.val = to_f32<T>(cv);
         }
       }
       my[lane] = e;
