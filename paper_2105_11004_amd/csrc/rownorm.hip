@@ -421,7 +421,10 @@ __global__ __launch_bounds__(WG, X3Shape<WG>::kMinWaves) void rownorm_x3_kernel(
   const int g = lane >> 4;
   const int64_t ntiles = (n + 15) / 16;
   const bool whole = (d % 32) == 0;
-  for (int64_t tile = (int64_t)blockIdx.x * kWaves + wave; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
+  // the workgroup index runs fastest over the tiles, so when the tile count
+  // is not a multiple of the resident waves the last round's tiles are spread
+  // over every workgroup (and CU) instead of filling the first few
+  for (int64_t tile = (int64_t)wave * gridDim.x + blockIdx.x; tile < ntiles; tile += (int64_t)gridDim.x * kWaves) {
     const int64_t row = tile * 16 + (lane & 15);
     const bool ok = row < n;
     const float* rp = A + (ok ? row : 0) * ld;
