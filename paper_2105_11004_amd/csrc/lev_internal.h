@@ -100,9 +100,11 @@ hipError_t launch_pivchol_finalize(int64_t d, const PivCholState& st, const int6
                                    int32_t* perm_out, double* R_out, hipStream_t s);
 
 // Z = R11^{-1} G_k[0:r, 0:k] in FP64 (R pivoted d x d, ld = d), r read from
-// the device.  Z64 is d x k (rows >= r zeroed).
-hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, const double* Gk,
-                         double* Z64, hipStream_t s);
+// the device.  Z64 is d x k (rows >= r zeroed).  For d > 256 the solve runs
+// over diagonal blocks of 256 and G's rows above the last block are
+// overwritten (they carry the updated right-hand side).
+hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, double* G, double* Z64,
+                         hipStream_t s);
 
 // Prepares the operand of pass 2: Z_full (d x k, rows indexed by original
 // column, zero off K) converted to the pass-2 compute type and laid out for
@@ -114,10 +116,10 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
 hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
                          const double* Z64, void* Zpack, hipStream_t s);
 size_t pack_z_bytes(int variant, int64_t d, int64_t k);
-// trsm + pack in one launch where it fits (r <= 256, k <= 64), else the two
-// launches above.  Zpack as for launch_pack_z.
+// trsm + pack in one launch where it fits (d <= 256, k <= 64), else the
+// launches above (Gk overwritten as there).  Zpack as for launch_pack_z.
 hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, const int64_t* rank,
-                         const int32_t* perm, const double* Gk, double* Z64, void* Zpack, hipStream_t s);
+                         const int32_t* perm, double* Gk, double* Z64, void* Zpack, hipStream_t s);
 size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k);
 
 // Pass 2, dense: theta[i] = || A[i, :] Z_full ||^2.

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lev_internal.h"
@@ -14,38 +15,8 @@
 namespace lev {
 namespace {
 
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-  return x;
-}
-
-// One 64-thread workgroup per right-hand side c < k.  The dot product of
-// row j of R with the solved tail is split over the 64 lanes; the next row
-// is prefetched while the current one is reduced.
-__global__ __launch_bounds__(64) void trsm_z_kernel(int64_t d, int64_t k, const double* __restrict__ R,
-                                                    const int64_t* __restrict__ rank,
-                                                    const double* __restrict__ Gk,
-                                                    double* __restrict__ Z64) {
-  extern __shared__ double zs[];  // d entries
-  const int64_t c = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int64_t r = *rank;
-  for (int64_t j = r + lane; j < d; j += 64) Z64[j * k + c] = 0.0;
-  for (int64_t j = r - 1; j >= 0; --j) {
-    double part = 0.0;
-    for (int64_t t = j + 1 + lane; t < r; t += 64) part = fma(R[j * d + t], zs[t], part);
-    const double tot = wave_sum(part);
-    const double zj = (Gk[j * k + c] - tot) / R[j * d + j];
-    if (lane == 0) {
-      zs[j] = zj;
-      Z64[j * k + c] = zj;
-    }
-    __syncthreads();
-  }
-}
-
-// r <= 256: one workgroup of 16 waves solves R11 Z = G for a group of 64
+// A diagonal block of at most 256 pivot positions (all of R11 when
+// r <= 256): one workgroup of 16 waves solves R11 Z = G for a group of 64
 // right-hand sides (columns c0 .. c0 + 63) by blocked back substitution with
 // inverted diagonal blocks, all products on 16 x 16 x 4 FP64 MFMAs.  Wave w
 // owns row block w (rows 16 w .. 16 w + 15):
@@ -324,17 +295,24 @@ __device__ __forceinline__ void store_operand(const double* zall, const int32_t*
   }
 }
 
-// R11^{-1} G for k <= 64 columns per workgroup (grid.y groups of 64; every
-// group has 4 column blocks, the last one possibly partly past k).
-__global__ __launch_bounds__(1024) void trsm_blocked_kernel(int64_t d, int64_t k, const double* __restrict__ R,
+// The diagonal block of pivot positions j0 .. j0 + 255 (fewer at the end of
+// d) of R11 Z = G, for k <= 64 columns per workgroup (grid.y groups of 64;
+// every group has 4 column blocks, the last one possibly partly past k).  G
+// holds the right-hand side of these rows with the contributions of the
+// blocks below already subtracted; the rank is read here, so a block wholly
+// past it writes zero rows of Z.
+__global__ __launch_bounds__(1024) void trsm_blocked_kernel(int64_t d, int64_t k, int64_t j0,
+                                                            const double* __restrict__ R,
                                                             const int64_t* __restrict__ rank,
-                                                            const double* __restrict__ Gk,
+                                                            const double* __restrict__ G,
                                                             double* __restrict__ Z64) {
   __shared__ double lds[kSolveLdsDoubles];
   __shared__ int32_t ready[16];
-  const int c0 = 64 * (int)blockIdx.y, r = (int)*rank;
-  blocked_solve<4>(lds, ready, (int)d, (int)k, c0, R, r, Gk);
-  store_z64<4>(lds, (int)d, (int)k, c0, r, Z64);
+  const int c0 = 64 * (int)blockIdx.y;
+  const int rows = (int)std::min<int64_t>(kTrsmR, d - j0);
+  const int r = (int)std::min<int64_t>(rows, std::max<int64_t>(0, *rank - j0));
+  blocked_solve<4>(lds, ready, (int)d, (int)k, c0, R + j0 * d + j0, r, G + j0 * k);
+  store_z64<4>(lds, rows, (int)k, c0, r, Z64 + j0 * k);
 }
 
 // Value of packed element idx (see the layouts above); inv maps a column id
@@ -437,12 +415,24 @@ __global__ __launch_bounds__(1024) void form_z_kernel(int64_t d, int64_t k, cons
 
 }  // namespace
 
-hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, const double* Gk,
-                         double* Z64, hipStream_t s) {
-  if (d <= kTrsmR) {
-    trsm_blocked_kernel<<<dim3(1, (unsigned)((k + 63) / 64)), 1024, 0, s>>>(d, k, R, rank, Gk, Z64);
-  } else {
-    trsm_z_kernel<<<(unsigned)k, 64, (size_t)d * sizeof(double), s>>>(d, k, R, rank, Gk, Z64);
+hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, double* G, double* Z64,
+                         hipStream_t s) {
+  if (d <= 0 || k <= 0) return hipSuccess;
+  // Blocked back substitution over diagonal blocks of 256 pivot positions,
+  // last block first: solve block q, then subtract its contribution
+  // R[0:j0, j0:j0+256] Z_q from the right-hand side of every row above it.
+  // The block bounds do not depend on the rank (it stays on the device): Z
+  // rows past the rank are exact zeros, so an update from a block past the
+  // rank changes nothing in the rows that are solved.
+  const dim3 grid(1, (unsigned)((k + 63) / 64));
+  for (int64_t j0 = ((d - 1) / kTrsmR) * kTrsmR; j0 >= 0; j0 -= kTrsmR) {
+    trsm_blocked_kernel<<<grid, 1024, 0, s>>>(d, k, j0, R, rank, G, Z64);
+    if (j0 > 0) {
+      const int64_t kb = std::min<int64_t>(kTrsmR, d - j0);
+      hipError_t e = launch_dgemm(j0, k, kb, -1.0, R + j0, d, 1, Z64 + j0 * k, k, 1, 1.0, G, k, 1, nullptr,
+                                  nullptr, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipGetLastError();
 }
@@ -510,7 +500,7 @@ hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm,
 }
 
 hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, const int64_t* rank,
-                         const int32_t* perm, const double* Gk, double* Z64, void* Zpack, hipStream_t s) {
+                         const int32_t* perm, double* Gk, double* Z64, void* Zpack, hipStream_t s) {
   if (variant < 0 || variant > 6) return hipErrorInvalidValue;
   if (d > kTrsmR || k > 64) {
     hipError_t e = launch_trsm_z(d, k, R, rank, Gk, Z64, s);

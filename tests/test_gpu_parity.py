@@ -175,6 +175,30 @@ def test_estimate_fp32_low_rank_coherent(gpu, n, precision):
     assert rel.max() < 1e-4
 
 
+@pytest.mark.parametrize("n,d,rank,k", [(2500, 600, 600, 64), (2500, 600, 300, 40), (2500, 513, 200, 64),
+                                         (3000, 1024, 1024, 48)])
+def test_estimate_fp64_wide_blocked_solve(gpu, n, d, rank, k):
+    """d > 256: Z = R11^{-1} G_k is solved over diagonal blocks of 256 pivot
+    positions with the rank on the device; ranks inside the first and second
+    block leave later blocks past the rank (zero rows of Z).  zeta = 1e-6:
+    the pivoted Cholesky of the Gram resolves ranks only well above sqrt(u)."""
+    _log("wide solve", n, d, rank, k)
+    rng = np.random.default_rng(d + rank)
+    A = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, d))
+    r_cs, m, zeta, seed = 2048, d + 64, 1e-6, 2010
+    ld = d + (d & 1)  # rows padded to 16 bytes
+    buf = torch.full((n, ld), float("nan"), dtype=torch.float64, device=gpu)
+    buf[:, :d] = torch.from_numpy(A).to(gpu)
+    theta, state = api.lev_estimate(buf[:, :d], seed, r_cs, m, k, zeta, return_state=True)
+    o = _oracle_theta(A, seed, r_cs, m, k, zeta)
+    r = int(state.rank.item())
+    assert r == o.rank == rank
+    np.testing.assert_array_equal(state.perm.cpu().numpy()[:r], o.perm[:r])
+    rel = _rel(theta.cpu().numpy(), o.theta)
+    _log("wide solve max rel", rel.max())
+    assert rel.max() < 1e-9
+
+
 @pytest.mark.parametrize("precision,bar_max,bar_p99", [("fp32", 1e-4, 1e-5), ("bf16x2", 2e-4, 2e-5),
                                                       ("bf16", 5e-2, 2e-2)])
 def test_estimate_bf16_storage(gpu, precision, bar_max, bar_p99):
