@@ -104,6 +104,33 @@ __device__ __forceinline__ void to_double<__hip_bfloat16>(const uint4& raw, doub
   }
 }
 
+// Negates the elements of a 16-byte vector of T when neg is all ones (0:
+// unchanged) by flipping their sign bits: exact, so adding the flipped
+// value rounds exactly as adding s * x with s = -1 would.
+template <typename T>
+__device__ __forceinline__ void negate_if(uint4& raw, uint32_t neg);
+template <>
+__device__ __forceinline__ void negate_if<double>(uint4& raw, uint32_t neg) {
+  raw.y ^= neg & 0x80000000u;
+  raw.w ^= neg & 0x80000000u;
+}
+template <>
+__device__ __forceinline__ void negate_if<float>(uint4& raw, uint32_t neg) {
+  const uint32_t m = neg & 0x80000000u;
+  raw.x ^= m;
+  raw.y ^= m;
+  raw.z ^= m;
+  raw.w ^= m;
+}
+template <>
+__device__ __forceinline__ void negate_if<__hip_bfloat16>(uint4& raw, uint32_t neg) {
+  const uint32_t m = neg & 0x80008000u;
+  raw.x ^= m;
+  raw.y ^= m;
+  raw.z ^= m;
+  raw.w ^= m;
+}
+
 // Workgroup (blockIdx.x) share of the side draw: the pairs of the two
 // matrices taken as one sequence, split over the first kDrawGroups
 // workgroups (more when that would leave a thread over 16 pairs), one
@@ -179,15 +206,17 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
     }
     __syncthreads();
     // The entries are the same for every lane: read as scalars, so the row
-    // base is an SGPR pair and the sign a scalar operand.  Two batches of U
-    // rows alternate, the next one in flight while the current one is added.
-    auto load_batch = [&](int q0, uint4 (&raw)[U][NV], double (&sgn)[U]) {
+    // base is an SGPR pair and the sign a scalar mask that flips the sign
+    // bits of the loaded row (rows past n load zeros and keep them).  Two
+    // batches of U rows alternate, the next one in flight while the current
+    // one is added.
+    auto load_batch = [&](int q0, uint4 (&raw)[U][NV], uint32_t (&neg)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int q = q0 + u * kWaves;
         const uint32_t ent = __builtin_amdgcn_readfirstlane(q < cnt ? entries[q] : kInvalid);
         const bool ok = ent != kInvalid;
-        sgn[u] = ok ? ((ent & 0x80000000u) ? -1.0 : 1.0) : 0.0;
+        neg[u] = (ok && (ent & 0x80000000u)) ? 0xFFFFFFFFu : 0u;
         const int64_t row = ok ? (int64_t)(ent & 0x7FFFFFFFu) : 0;
         const uint4* rp = reinterpret_cast<const uint4*>(A + row * ld + col0);
 #pragma unroll
@@ -195,20 +224,21 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
           raw[u][v] = (ok && vec_ok[v]) ? rp[v * 64 + lane] : make_uint4(0u, 0u, 0u, 0u);
       }
     };
-    auto add_batch = [&](const uint4 (&raw)[U][NV], const double (&sgn)[U]) {
+    auto add_batch = [&](uint4 (&raw)[U][NV], const uint32_t (&neg)[U]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+          negate_if<T>(raw[u][v], neg[u]);
           double x[E];
           to_double<T>(raw[u][v], x);
 #pragma unroll
-          for (int e = 0; e < E; ++e) acc[v][e] = fma(sgn[u], x[e], acc[v][e]);
+          for (int e = 0; e < E; ++e) acc[v][e] += x[e];
         }
       }
     };
     uint4 ra[U][NV], rb[U][NV];
-    double sa[U], sb[U];
+    uint32_t sa[U], sb[U];
     int q0 = wave;
     if (q0 < cnt) load_batch(q0, ra, sa);
     for (; q0 < cnt; q0 += 2 * kWaves * U) {
