@@ -206,8 +206,9 @@ lev_status lev_debug_gaussian(uint64_t seed, int which, int64_t rows, int64_t co
 /* Phase timing.  Registers `count` caller-created HIP events (count must be
  * LEV_PHASES, or 0 / NULL to stop) for the calling thread; each following
  * lev_estimate call on that thread records them on its stream at the phase
- * boundaries: [0] start, [1] after the Gaussian draws, [2] after pass 1
- * (S A), [3] after A~ = G (S A), [4] after the rank-revealing factorisation,
+ * boundaries: [0] start, [1] before pass 1 (nothing runs in between: the
+ * Gaussian draws run inside pass 1), [2] after pass 1 (S A and the draws),
+ * [3] after A~ = G (S A), [4] after the rank-revealing factorisation,
  * [5] after Z is formed, [6] after pass 2 (theta~).  The events stay owned
  * by the caller. */
 #define LEV_PHASES 7

@@ -33,7 +33,9 @@ EXPORTED = ["lev_workspace_size", "lev_rank_workspace_size", "lev_state_size", "
             "lev_debug_buckets", "lev_debug_gaussian", "lev_set_phase_events", "lev_status_string",
             "lev_last_error"]
 LEV_PHASES = 7
-PHASE_NAMES = ["gaussian_draws", "pass1_countsketch", "gaussian_transform", "rank_revealing_qr",
+# phase 0 holds no kernels (the Gaussian draws run inside pass 1): its time is
+# the cost of two back-to-back events
+PHASE_NAMES = ["entry", "pass1_countsketch", "gaussian_transform", "rank_revealing_qr",
                "form_z", "pass2_rownorm"]
 
 
