@@ -87,6 +87,23 @@ struct StageEntry {
   ZT val;
 };
 
+// G consecutive steps t .. t + G - 1 of the staged list: the G entry reads,
+// then the G Z-row reads, then the products (alternating accumulators).
+template <int G, typename ZT>
+__device__ __forceinline__ void steps(const StageEntry<ZT>* my, const ZT* Z, int t, int lane, ZT& y, ZT& y2) {
+  StageEntry<ZT> e[G];
+  ZT z[G];
+#pragma unroll
+  for (int u = 0; u < G; ++u) e[u] = my[t + u];
+#pragma unroll
+  for (int u = 0; u < G; ++u) z[u] = Z[e[u].off + lane];
+#pragma unroll
+  for (int u = 0; u < G; u += 2) {
+    y = fma(e[u].val, z[u], y);
+    y2 = fma(e[u + 1].val, z[u + 1], y2);
+  }
+}
+
 // T: storage type of A's values; ZT: type of Z_full and of the arithmetic
 // (float for FP32/BF16 values, double for FP64 values).  ZLDS: Z_full staged
 // in LDS (else read from global memory, for d * 64 * sizeof(ZT) beyond LDS).
@@ -178,21 +195,21 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
         const int stop = (int)(min(rend, cend) - c0);
         int t = (int)(pos - c0);
         // eight steps at a time: all sixteen LDS reads are issued before the
-        // first product, so their latencies overlap
-        for (; t + 8 <= stop; t += 8) {
-          StageEntry<ZT> e8[8];
-          ZT z8[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) e8[u] = my[t + u];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) z8[u] = Z[e8[u].off + lane];
-#pragma unroll
-          for (int u = 0; u < 8; u += 2) {
-            y = fma(e8[u].val, z8[u], y);
-            y2 = fma(e8[u + 1].val, z8[u + 1], y2);
-          }
+        // first product, so their latencies overlap; a segment's last steps
+        // go in groups of 4, 2 and 1 (at most three dependent LDS round
+        // trips instead of seven, and no step padded: with Z_full filling
+        // LDS the pass runs four waves per SIMD and is bound by LDS issue
+        // as much as by latency)
+        for (; t + 8 <= stop; t += 8) steps<8>(my, Z, t, lane, y, y2);
+        if (t + 4 <= stop) {
+          steps<4>(my, Z, t, lane, y, y2);
+          t += 4;
         }
-        for (; t < stop; ++t) {
+        if (t + 2 <= stop) {
+          steps<2>(my, Z, t, lane, y, y2);
+          t += 2;
+        }
+        if (t < stop) {
           const StageEntry<ZT> e1 = my[t];
           y = fma(e1.val, Z[e1.off + lane], y);
         }
