@@ -32,26 +32,29 @@ namespace {
 constexpr int NB = 32;
 constexpr int kMaxD = 1024;
 
-struct ArgMax {
-  double v;
-  int i;
-};
+typedef double v16d __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ ArgMax better(ArgMax a, ArgMax b) {
-  // larger value wins; ties to the lower column index
-  if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
-  return a;
+// One DPP step of a wave max over doubles (identity -inf).
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_max_step(double v) {
+  const int olo = 0, ohi = (int)0xFFF00000;  // -inf
+  const int slo = __builtin_amdgcn_update_dpp(olo, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int shi = __builtin_amdgcn_update_dpp(ohi, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return fmax(v, __hiloint2double(shi, slo));
 }
 
-__device__ __forceinline__ ArgMax wave_argmax(ArgMax x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    ArgMax o;
-    o.v = __shfl_xor(x.v, off);
-    o.i = __shfl_xor(x.i, off);
-    x = better(x, o);
-  }
-  return x;
+// Max over the 64 lanes (row shifts within 16-lane rows, then row broadcasts;
+// lane 63 ends with the total), returned to every lane.
+__device__ __forceinline__ double wave_max_f64(double v) {
+  v = dpp_max_step<0x111, 0xF>(v);  // row_shr:1
+  v = dpp_max_step<0x112, 0xF>(v);  // row_shr:2
+  v = dpp_max_step<0x114, 0xF>(v);  // row_shr:4
+  v = dpp_max_step<0x118, 0xF>(v);  // row_shr:8
+  v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15
+  v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // flags[0] = done, flags[1] = pivots computed so far.
@@ -87,17 +90,26 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
   for (int j = 0; j < NB; ++j) {
     if (active && J >= d) active = false;
     if (!active) continue;
-    ArgMax mine{alive ? dg : -INFINITY, alive ? c : 0x7fffffff};
-    mine = wave_argmax(mine);
+    // the wave's largest alive diagonal (DPP max; NaN never wins) and the
+    // lowest lane holding it (ties go to the lower column)
+    const double mv = alive ? dg : -INFINITY;
+    const double wmax = wave_max_f64(mv);
+    const uint64_t hit = __ballot(mv == wmax);
     if (lane == 0) {
-      wv[j & 1][wave] = mine.v;
-      wi[j & 1][wave] = mine.i;
+      wv[j & 1][wave] = hit != 0 ? wmax : -INFINITY;
+      wi[j & 1][wave] = hit != 0 ? wave * 64 + (__ffsll((unsigned long long)hit) - 1) : 0x7fffffff;
     }
     __syncthreads();
-    ArgMax best{-INFINITY, 0x7fffffff};
-    for (int w = 0; w < nwaves; ++w) best = better(best, ArgMax{wv[j & 1][w], wi[j & 1][w]});
-    const double pv = best.v;
-    const int p = best.i;
+    // the workgroup's pivot, found by every wave: lane w takes wave w's
+    // candidate; the largest value wins, ties to the lowest wave (whose
+    // columns are the lower ones)
+    const double cv = lane < nwaves ? wv[j & 1][lane] : -INFINITY;
+    const int ci = lane < nwaves ? wi[j & 1][lane] : 0x7fffffff;
+    const double bmax = wave_max_f64(cv);
+    const uint64_t bhit = __ballot(cv == bmax);
+    const int bw = bhit != 0 ? (__ffsll((unsigned long long)bhit) - 1) : 0;
+    const double pv = bhit != 0 ? bmax : -INFINITY;
+    const int p = __builtin_amdgcn_readlane(ci, bw);
     if (J == 0) r00 = pv > 0.0 ? sqrt(pv) : 0.0;
     if (!(pv > 0.0) || !(sqrt(pv) > zeta * r00)) {
       stop = true;
@@ -195,31 +207,6 @@ __device__ inline void small_rect(int w, int d, int& a_out, int& b_out) {
   }
   a_out = 0;
   b_out = 0;
-}
-
-typedef double v16d __attribute__((ext_vector_type(16)));
-
-// One DPP step of a wave max over doubles (identity -inf).
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_max_step(double v) {
-  const int olo = 0, ohi = (int)0xFFF00000;  // -inf
-  const int slo = __builtin_amdgcn_update_dpp(olo, __double2loint(v), CTRL, ROWMASK, 0xF, false);
-  const int shi = __builtin_amdgcn_update_dpp(ohi, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
-  return fmax(v, __hiloint2double(shi, slo));
-}
-
-// Max over the 64 lanes (row shifts within 16-lane rows, then row broadcasts;
-// lane 63 ends with the total), returned to every lane.
-__device__ __forceinline__ double wave_max_f64(double v) {
-  v = dpp_max_step<0x111, 0xF>(v);  // row_shr:1
-  v = dpp_max_step<0x112, 0xF>(v);  // row_shr:2
-  v = dpp_max_step<0x114, 0xF>(v);  // row_shr:4
-  v = dpp_max_step<0x118, 0xF>(v);  // row_shr:8
-  v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15
-  v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  return __hiloint2double(hi, lo);
 }
 
 // Workgroup barrier that orders LDS traffic only.  __syncthreads() also
