@@ -284,6 +284,132 @@ __global__ __launch_bounds__(kThreads) void bwd_grad_kernel(const T* __restrict_
   }
 }
 
+// Abar for FP32 A with d a multiple of 16 (d <= 256) and k <= 64, without
+// staging A: each wave owns 16-row tiles and keeps everything of a tile in
+// registers.  Lane l (i = l % 16, g = l / 16) loads the 16-byte pieces
+// A[row i][16 j + 4 g .. + 3] of its row (j < d / 16).
+//  1. Y^T = Z_full^T A_tile^T on 16x16x4 FP32 MFMAs, the contraction index
+//     of step (j, e) being column 16 j + 4 g + e: the A operand is
+//     Z_full[16 j + 4 g + e][16 nb + i] (LDS), the B operand element e of
+//     the lane's piece j.  Accumulator element v of lane l is then
+//     Y[row i][16 nb + 4 g + v], which is scaled by 2 w_i.
+//  2. G_tile = Y Z_full^T with the contraction index of step (nb, v) taken
+//     as 16 nb + 4 g + v: the A operand is exactly accumulator element v of
+//     step 1 (Y never leaves the registers), the B operand Z_full[16 db + i]
+//     [16 nb + 4 g + v] (LDS).  Element v of the result is G[row 4 g + v]
+//     [16 db + i], to which s_r H_full[h(r)][16 db + i] is added before the
+//     store.
+// Z_full sits in LDS with a row stride of 68 floats (the reads of step 1
+// are free of bank conflicts).  NJ = d / 16 rounded up to a multiple of 4:
+// pieces past d / 16 load the row's first piece again and are not used.
+constexpr int kGradWaves = 8;
+constexpr int kZsStride = 68;
+
+template <int KB, int NJ>
+__global__ __launch_bounds__(64 * kGradWaves, 4) void bwd_grad_f32_kernel(
+    const float* __restrict__ A, int64_t n, int64_t d, int64_t ld, const float* __restrict__ w,
+    const float* __restrict__ Zg, const float* __restrict__ Hf, HashParams hp, float* __restrict__ G,
+    int64_t ldg) {
+  extern __shared__ float zs[];
+  const int di = (int)d;
+  for (int q = threadIdx.x; q < di * 16 * KB; q += 64 * kGradWaves) {
+    const int r = q / (16 * KB), c = q % (16 * KB);
+    zs[r * kZsStride + c] = Zg[(int64_t)r * kZCols + c];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, i16 = lane & 15;
+  const int nj = di / 16;
+  const int64_t ntiles = (n + 15) / 16;
+  for (int64_t tile = (int64_t)wave * gridDim.x + blockIdx.x; tile < ntiles;
+       tile += (int64_t)gridDim.x * kGradWaves) {
+    const int64_t row = tile * 16 + i16;
+    const bool ok = row < n;
+    const float* rp = A + (ok ? row : 0) * ld + 4 * g;
+    float4 a[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) a[j] = *reinterpret_cast<const float4*>(rp + 16 * (j < nj ? j : 0));
+    const float ws = ok ? 2.0f * w[row] : 0.0f;
+    // the rows this lane stores in step 2: 4 g + v
+    int hr[4];
+    bool neg[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = tile * 16 + 4 * g + v;
+      const uint64_t x = hash_x(hp, (uint64_t)(r < n ? r : 0));
+      hr[v] = (int)((uint32_t)x % (uint32_t)hp.r_cs);  // x < P < 2^32
+      neg[v] = sign_negative(hp, (uint64_t)(r < n ? r : 0));
+    }
+    v4f yt[KB];
+#pragma unroll
+    for (int nb = 0; nb < KB; ++nb) yt[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (j < nj) {
+        const float* zr = zs + (16 * j + 4 * g) * kZsStride + i16;
+        const float av[4] = {a[j].x, a[j].y, a[j].z, a[j].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int nb = 0; nb < KB; ++nb)
+            yt[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(zr[e * kZsStride + 16 * nb], av[e], yt[nb], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < KB; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) yt[nb][v] *= ws;
+    for (int db = 0; db < nj; ++db) {
+      const int col = 16 * db + i16;
+      float hv[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) hv[v] = Hf[(int64_t)hr[v] * d + col];
+      const float* zb = zs + col * kZsStride + 4 * g;
+      v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int nb = 0; nb < KB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(yt[nb][v], zb[16 * nb + v], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = tile * 16 + 4 * g + v;
+        if (r < n) G[r * ldg + col] = acc[v] + (neg[v] ? -hv[v] : hv[v]);
+      }
+    }
+  }
+}
+
+template <int KB, int NJ>
+hipError_t launch_grad_f32(const float* a, int64_t n, int64_t d, int64_t ld, const float* w, const float* z,
+                           const float* h, const HashParams& hp, float* out, int64_t ldg, hipStream_t s) {
+  auto kern = bwd_grad_f32_kernel<KB, NJ>;
+  const size_t lds = (size_t)d * kZsStride * sizeof(float);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int dev = 0, num_cu = 0, per_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * kGradWaves, lds)) != hipSuccess)
+    return e;
+  const int64_t ntiles = (n + 15) / 16;
+  const int64_t want = (ntiles + kGradWaves - 1) / kGradWaves;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * std::max(per_cu, 1)));
+  kern<<<(unsigned)blocks, 64 * kGradWaves, lds, s>>>(a, n, d, ld, w, z, h, hp, out, ldg);
+  return hipGetLastError();
+}
+
+template <int KB>
+hipError_t launch_grad_f32_kb(const float* a, int64_t n, int64_t d, int64_t ld, const float* w, const float* z,
+                              const float* h, const HashParams& hp, float* out, int64_t ldg, hipStream_t s) {
+  switch ((d / 16 + 3) / 4) {
+    case 1: return launch_grad_f32<KB, 4>(a, n, d, ld, w, z, h, hp, out, ldg, s);
+    case 2: return launch_grad_f32<KB, 8>(a, n, d, ld, w, z, h, hp, out, ldg, s);
+    case 3: return launch_grad_f32<KB, 12>(a, n, d, ld, w, z, h, hp, out, ldg, s);
+    default: return launch_grad_f32<KB, 16>(a, n, d, ld, w, z, h, hp, out, ldg, s);
+  }
+}
+
 // Workgroups of the C pass: one per compute unit of an MI355X (each holds
 // ~130 KB of LDS, so one fits per CU).  A constant, so that the partial-sum
 // order, hence the bits of C, do not depend on the device queried.
@@ -330,6 +456,22 @@ hipError_t gram_typed(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k
 template <typename T>
 hipError_t grad_typed(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k, const void* w, const void* Zfull,
                       const void* Hfull, const HashParams& hp, void* G, int64_t ldg, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    // rows are 16-byte aligned (the interface requires it), so the pieces are
+    if (d % 16 == 0 && d <= 256 && k <= 64) {
+      const float* a = static_cast<const float*>(A);
+      const float* wv = static_cast<const float*>(w);
+      const float* z = static_cast<const float*>(Zfull);
+      const float* h = static_cast<const float*>(Hfull);
+      float* out = static_cast<float*>(G);
+      switch ((k + 15) / 16) {
+        case 1: return launch_grad_f32_kb<1>(a, n, d, ld, wv, z, h, hp, out, ldg, s);
+        case 2: return launch_grad_f32_kb<2>(a, n, d, ld, wv, z, h, hp, out, ldg, s);
+        case 3: return launch_grad_f32_kb<3>(a, n, d, ld, wv, z, h, hp, out, ldg, s);
+        default: return launch_grad_f32_kb<4>(a, n, d, ld, wv, z, h, hp, out, ldg, s);
+      }
+    }
+  }
   const TileGeom g = tile_geom<T>(d, k);
   const bool zlds = lds_bytes<T>(g, true) <= 144 * 1024;
   const size_t lds = lds_bytes<T>(g, zlds);

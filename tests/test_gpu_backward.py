@@ -38,6 +38,7 @@ def _compare(gpu_grad, ref_grad, bar):
 @pytest.mark.parametrize("dtype,n,d,k,r_cs,m,bar", [
     (torch.float64, 4096 + 5, 64, 32, 1024, 256, 1e-9),
     (torch.float32, 8192 + 3, 48, 16, 512, 96, 1e-5),
+    (torch.float32, 5000 + 7, 80, 64, 1024, 160, 1e-5),
     (torch.float64, 1000, 20, 7, 100, 40, 1e-9),
 ])
 def test_backward_matches_reference_gradient(gpu, dtype, n, d, k, r_cs, m, bar):
