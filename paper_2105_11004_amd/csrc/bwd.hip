@@ -410,6 +410,157 @@ hipError_t launch_grad_f32_kb(const float* a, int64_t n, int64_t d, int64_t ld, 
   }
 }
 
+// C = A^T (w o Y) for FP32 A under the same conditions.  Wave w of a
+// workgroup of 2 KB waves owns column block nb = w % KB of C (d x 16, in its
+// registers for the whole pass) and tile stream w / KB.  Per 16-row tile:
+//  1. column block nb of Y^T as in bwd_grad_f32_kernel (Z_full's block nb
+//     only), scaled by w_i;
+//  2. through a per-wave LDS block, so that lane l holds Yw[row 4 s + g]
+//     [16 nb + i] (s < 4);
+//  3. C^T[block nb] += Yw^T A_tile on 16x16x4 FP32 MFMAs contracting over
+//     the tile's rows (step s takes row 4 s + g).  The B operand needs A
+//     with the row in the lane group, so the tile is read a second time in
+//     that layout, 16 bytes per lane: lane l loads A[row 4 s + g][64 q +
+//     4 i .. + 3], and column block (q, e) of C^T is the set of columns
+//     64 q + 4 jj + e (jj < 16), un-permuted when C is written out.
+// The KB waves of a stream read the same tile at about the same time, so A
+// comes from HBM once and from L2 otherwise; a tile's second reads are
+// issued before its step 1.  At the end the two streams add their C into
+// LDS in stream order and the workgroup writes one partial (the layout and
+// reduction of bwd_gram_kernel).
+constexpr int kYtStride = 80;  // floats per row of the per-wave Y block (16 mod 64 words)
+
+template <int KB, int NJ>
+__global__ __launch_bounds__(128 * KB, 2) void bwd_gram_f32_kernel(const float* __restrict__ A, int64_t n, int64_t d,
+                                                                   int64_t ld, const float* __restrict__ w,
+                                                                   const float* __restrict__ Zg,
+                                                                   float* __restrict__ partials) {
+  constexpr int NQ = NJ / 4;  // 64-column groups
+  constexpr int kT = 128 * KB;
+  extern __shared__ float smem_f[];
+  float* zs = smem_f;                            // d x kZsStride (then C)
+  float* ybuf = smem_f + (size_t)d * kZsStride;  // 2 KB x 16 x kYtStride
+  const int di = (int)d;
+  for (int q = threadIdx.x; q < di * 16 * KB; q += kT) {
+    const int r = q / (16 * KB), c = q % (16 * KB);
+    zs[r * kZsStride + c] = Zg[(int64_t)r * kZCols + c];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nb = wave % KB, stream = wave / KB;
+  const int g = lane >> 4, i16 = lane & 15;
+  const int nj = di / 16;
+  float* yb = ybuf + wave * 16 * kYtStride;
+  v4f cacc[NQ][4];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) cacc[q][e] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t ntiles = (n + 15) / 16;
+  for (int64_t tile = (int64_t)stream * gridDim.x + blockIdx.x; tile < ntiles; tile += (int64_t)gridDim.x * 2) {
+    // the tile, rows in the lane group (columns 64 q + 4 i16 .. + 3; pieces
+    // past d read column 0 and are dropped)
+    float4 rl[4][NQ];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int64_t r = tile * 16 + 4 * s4 + g;
+      const float* rp = A + (r < n ? r : 0) * ld;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c = 64 * q + 4 * i16;
+        rl[s4][q] = *reinterpret_cast<const float4*>(rp + (c < di ? c : 0));
+      }
+    }
+    // the tile, row i16 in the lanes: pieces 16 j + 4 g .. + 3
+    const int64_t row = tile * 16 + i16;
+    const float* rp = A + (row < n ? row : 0) * ld + 4 * g;
+    float4 a[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) a[j] = *reinterpret_cast<const float4*>(rp + 16 * (j < nj ? j : 0));
+    const float ws = row < n ? w[row] : 0.0f;
+    v4f yt = v4f{0.f, 0.f, 0.f, 0.f};
+    const float* zc = zs + 4 * g * kZsStride + 16 * nb + i16;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (j < nj) {
+        const float av[4] = {a[j].x, a[j].y, a[j].z, a[j].w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          yt = __builtin_amdgcn_mfma_f32_16x16x4f32(zc[(16 * j + e) * kZsStride], av[e], yt, 0, 0, 0);
+      }
+    }
+    // Yw[row i16][16 nb + 4 g + v] -> LDS, back as Yw[row 4 s + g][16 nb + i16]
+    // (the wave's own block: LDS serves a wave's accesses in order)
+    *reinterpret_cast<float4*>(yb + i16 * kYtStride + 4 * g) =
+        make_float4(yt[0] * ws, yt[1] * ws, yt[2] * ws, yt[3] * ws);
+    float yop[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) yop[s4] = yb[(4 * s4 + g) * kYtStride + i16];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q * 4 < nj) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const float rv[4] = {rl[s4][q].x, rl[s4][q].y, rl[s4][q].z, rl[s4][q].w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            cacc[q][e] = __builtin_amdgcn_mfma_f32_16x16x4f32(yop[s4], rv[e], cacc[q][e], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // C[64 q + 4 i16 + e][16 nb + 4 g + v] = cacc[q][e][v]; streams add in order
+  __syncthreads();  // every wave is done with zs
+  float* red = zs;  // d x 64
+  for (int st = 0; st < 2; ++st) {
+    if (stream == st) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 64 * q + 4 * i16 + e;
+          if (c < di) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              float* dst = red + c * kZCols + 16 * nb + 4 * g + v;
+              *dst = st == 0 ? cacc[q][e][v] : *dst + cacc[q][e][v];
+            }
+          }
+        }
+    }
+    __syncthreads();
+  }
+  float* out = partials + (int64_t)blockIdx.x * d * kZCols;
+  for (int q = threadIdx.x; q < di * 16 * KB; q += kT) {
+    const int r = q / (16 * KB), c = q % (16 * KB);
+    out[(int64_t)r * kZCols + c] = red[r * kZCols + c];
+  }
+}
+
+template <int KB, int NJ>
+hipError_t launch_gram_f32(const float* a, int64_t n, int64_t d, int64_t ld, const float* w, const float* z,
+                           float* partials, int groups, hipStream_t s) {
+  auto kern = bwd_gram_f32_kernel<KB, NJ>;
+  const size_t lds = ((size_t)d * kZsStride + 2 * KB * 16 * kYtStride) * sizeof(float);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  kern<<<(unsigned)groups, 128 * KB, lds, s>>>(a, n, d, ld, w, z, partials);
+  return hipGetLastError();
+}
+
+template <int KB>
+hipError_t launch_gram_f32_kb(const float* a, int64_t n, int64_t d, int64_t ld, const float* w, const float* z,
+                              float* partials, int groups, hipStream_t s) {
+  switch ((d / 16 + 3) / 4) {
+    case 1: return launch_gram_f32<KB, 4>(a, n, d, ld, w, z, partials, groups, s);
+    case 2: return launch_gram_f32<KB, 8>(a, n, d, ld, w, z, partials, groups, s);
+    case 3: return launch_gram_f32<KB, 12>(a, n, d, ld, w, z, partials, groups, s);
+    default: return launch_gram_f32<KB, 16>(a, n, d, ld, w, z, partials, groups, s);
+  }
+}
+
 // Workgroups of the C pass: one per compute unit of an MI355X (each holds
 // ~130 KB of LDS, so one fits per CU).  A constant, so that the partial-sum
 // order, hence the bits of C, do not depend on the device queried.
@@ -426,6 +577,26 @@ hipError_t launch_with_lds(K kern, dim3 grid, size_t lds, hipStream_t s) {
 template <typename T>
 hipError_t gram_typed(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k, const void* w, const void* Zfull,
                       void* partials, int groups, double* C64, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (d % 16 == 0 && d <= 256 && k <= 64) {
+      const float* a = static_cast<const float*>(A);
+      const float* wv = static_cast<const float*>(w);
+      const float* z = static_cast<const float*>(Zfull);
+      float* p = static_cast<float*>(partials);
+      hipError_t e;
+      switch ((k + 15) / 16) {
+        case 1: e = launch_gram_f32_kb<1>(a, n, d, ld, wv, z, p, groups, s); break;
+        case 2: e = launch_gram_f32_kb<2>(a, n, d, ld, wv, z, p, groups, s); break;
+        case 3: e = launch_gram_f32_kb<3>(a, n, d, ld, wv, z, p, groups, s); break;
+        default: e = launch_gram_f32_kb<4>(a, n, d, ld, wv, z, p, groups, s); break;
+      }
+      if (e != hipSuccess) return e;
+      const int64_t total = d * k;
+      bwd_reduce_kernel<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(static_cast<const T*>(partials), groups,
+                                                                            d, k, C64);
+      return hipGetLastError();
+    }
+  }
   const TileGeom g = tile_geom<T>(d, k);
   const bool zlds = lds_bytes<T>(g, true) <= 144 * 1024;
   const size_t lds = lds_bytes<T>(g, zlds);
