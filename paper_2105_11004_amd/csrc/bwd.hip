@@ -218,8 +218,19 @@ __global__ void bwd_reduce_kernel(const T* __restrict__ partials, int groups, in
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d * k) return;
   const int64_t i = idx / k, c = idx % k;
+  const T* p = partials + i * kZCols + c;
+  const int64_t step = d * kZCols;
   double s = 0.0;
-  for (int q = 0; q < groups; ++q) s += (double)partials[((int64_t)q * d + i) * kZCols + c];
+  // sixteen loads in flight at a time; the sum stays in group order
+  int q = 0;
+  for (; q + 16 <= groups; q += 16) {
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = p[(int64_t)(q + u) * step];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += (double)v[u];
+  }
+  for (; q < groups; ++q) s += (double)p[(int64_t)q * step];
   C64[idx] = s;
 }
 
