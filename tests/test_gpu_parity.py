@@ -232,6 +232,34 @@ def test_estimate_full_size_sampled(gpu):
     assert np.all(theta >= 0) and np.all(np.isfinite(theta))
 
 
+@pytest.mark.timeout(600)
+def test_estimate_bf16_full_size_sampled(gpu):
+    """The BF16 workload at full size (2^22 x 1024 stored BF16, lognormal row
+    scales: 4.3e9 elements, beyond 32-bit offsets) in the benchmark's launch
+    configuration (native BF16 pass 2), checked on sampled rows against the
+    oracle run on the whole matrix (about 15 s on the GPU host, most of it
+    the oracle's draw of the 2048 x 16384 Gaussian)."""
+    cfg = W.CONFIGS["dense_bf16_4Mx1024"]
+    n, d = cfg["n"], cfg["d"]
+    _log("bf16 full size: generating")
+    A = W.row_scaled_bf16(n, d, W.data_seed(4), device=gpu)
+    plan = api.EstimatePlan(A, W.sketch_seed(4), cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+    theta = plan.run().cpu().numpy().astype(np.float64)
+    assert np.all(theta >= 0) and np.all(np.isfinite(theta))
+    A_host = A.float().cpu().numpy()  # exact: every BF16 value is an FP32 value
+    del A, plan
+    torch.cuda.empty_cache()
+    rows = np.sort(np.random.default_rng(4).choice(n, 2000, replace=False))
+    _log("bf16 full size: oracle")
+    o = _oracle_theta(A_host, W.sketch_seed(4), cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows)
+    assert o.rank == d
+    rel = _rel(theta[rows], o.theta_rows)
+    _log("bf16 full size max rel", rel.max(), "p99", np.quantile(rel, 0.99))
+    # Z rounded to BF16 (relative 2^-9) moves each y_c by about 2^-9 and theta
+    # by about 2^-8 ~ 4e-3; the max allows for cancellation within a row
+    assert rel.max() < 1e-2 and np.quantile(rel, 0.99) < 4e-3
+
+
 # ------------------------------------------------------------------ edge cases
 def test_zero_matrix_and_zero_rows(gpu):
     A = torch.zeros(1000, 32, dtype=torch.float32, device=gpu)
