@@ -370,21 +370,45 @@ __global__ __launch_bounds__(64 * kGradWaves, 4) void bwd_grad_f32_kernel(
     for (int nb = 0; nb < KB; ++nb)
 #pragma unroll
       for (int v = 0; v < 4; ++v) yt[nb][v] *= ws;
-    for (int db = 0; db < nj; ++db) {
-      const int col = 16 * db + i16;
-      float hv[4];
+    // column blocks two at a time (two independent MFMA chains); the H
+    // values of the next pair are loaded while a pair is multiplied (an L2
+    // round trip per block would otherwise stall the wave 16 times a tile)
+    auto load_h = [&](int db, float (&h)[4]) {
+      const int cc = 16 * (db < nj ? db : 0) + i16;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) hv[v] = Hf[(int64_t)hr[v] * d + col];
-      const float* zb = zs + col * kZsStride + 4 * g;
-      v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+      for (int v = 0; v < 4; ++v) h[v] = Hf[(int64_t)hr[v] * d + cc];
+    };
+    float hn0[4], hn1[4];
+    load_h(0, hn0);
+    load_h(1, hn1);
+    for (int db = 0; db < nj; db += 2) {
+      float h0[4], h1[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        h0[v] = hn0[v];
+        h1[v] = hn1[v];
+      }
+      load_h(db + 2, hn0);
+      load_h(db + 3, hn1);
+      const bool two = db + 1 < nj;  // uniform
+      const int col0 = 16 * db + i16, col1 = col0 + 16;
+      const float* zb0 = zs + col0 * kZsStride + 4 * g;
+      const float* zb1 = zs + (two ? col1 : col0) * kZsStride + 4 * g;
+      v4f a0 = v4f{0.f, 0.f, 0.f, 0.f}, a1 = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int nb = 0; nb < KB; ++nb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(yt[nb][v], zb[16 * nb + v], acc, 0, 0, 0);
+        for (int v = 0; v < 4; ++v) {
+          a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(yt[nb][v], zb0[16 * nb + v], a0, 0, 0, 0);
+          a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(yt[nb][v], zb1[16 * nb + v], a1, 0, 0, 0);
+        }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t r = tile * 16 + 4 * g + v;
-        if (r < n) G[r * ldg + col] = acc[v] + (neg[v] ? -hv[v] : hv[v]);
+        if (r < n) {
+          G[r * ldg + col0] = a0[v] + (neg[v] ? -h0[v] : h0[v]);
+          if (two) G[r * ldg + col1] = a1[v] + (neg[v] ? -h1[v] : h1[v]);
+        }
       }
     }
   }
