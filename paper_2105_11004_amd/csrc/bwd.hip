@@ -446,8 +446,9 @@ hipError_t launch_grad_f32_kb(const float* a, int64_t n, int64_t d, int64_t ld, 
 }
 
 // C = A^T (w o Y) for FP32 A under the same conditions.  Wave w of a
-// workgroup of 2 KB waves owns column block nb = w % KB of C (d x 16, in its
-// registers for the whole pass) and tile stream w / KB.  Per 16-row tile:
+// workgroup of KB * S waves owns column block nb = w % KB of C (d x 16, in
+// its registers for the whole pass) and tile stream w / KB; S is chosen so
+// that the waves spread evenly over the four SIMDs.  Per 16-row tile:
 //  1. column block nb of Y^T as in bwd_grad_f32_kernel (Z_full's block nb
 //     only), scaled by w_i;
 //  2. through a per-wave LDS block, so that lane l holds Yw[row 4 s + g]
@@ -459,22 +460,26 @@ hipError_t launch_grad_f32_kb(const float* a, int64_t n, int64_t d, int64_t ld, 
 //     4 i .. + 3], and column block (q, e) of C^T is the set of columns
 //     64 q + 4 jj + e (jj < 16), un-permuted when C is written out.
 // The KB waves of a stream read the same tile at about the same time, so A
-// comes from HBM once and from L2 otherwise; a tile's second reads are
-// issued before its step 1.  At the end the two streams add their C into
-// LDS in stream order and the workgroup writes one partial (the layout and
-// reduction of bwd_gram_kernel).
+// comes from HBM once and from L2 otherwise; the second reads are issued
+// after step 1, when the pieces are dead (fewer registers, more waves).  At
+// the end the streams add their C into LDS in stream order and the
+// workgroup writes one partial (the layout and reduction of
+// bwd_gram_kernel).
 constexpr int kYtStride = 80;  // floats per row of the per-wave Y block (16 mod 64 words)
 
+template <int KB>
+constexpr int gram_streams() { return KB == 3 ? 4 : (KB == 1 ? 4 : 2); }
+
 template <int KB, int NJ>
-__global__ __launch_bounds__(128 * KB, 2) void bwd_gram_f32_kernel(const float* __restrict__ A, int64_t n, int64_t d,
-                                                                   int64_t ld, const float* __restrict__ w,
-                                                                   const float* __restrict__ Zg,
-                                                                   float* __restrict__ partials) {
+__global__ __launch_bounds__(64 * KB * gram_streams<KB>(), KB * gram_streams<KB>() / 4) void bwd_gram_f32_kernel(
+    const float* __restrict__ A, int64_t n, int64_t d, int64_t ld, const float* __restrict__ w,
+    const float* __restrict__ Zg, float* __restrict__ partials) {
+  constexpr int S = gram_streams<KB>();
   constexpr int NQ = NJ / 4;  // 64-column groups
-  constexpr int kT = 128 * KB;
+  constexpr int kT = 64 * KB * S;
   extern __shared__ float smem_f[];
   float* zs = smem_f;                            // d x kZsStride (then C)
-  float* ybuf = smem_f + (size_t)d * kZsStride;  // 2 KB x 16 x kYtStride
+  float* ybuf = smem_f + (size_t)d * kZsStride;  // KB S x 16 x kYtStride
   const int di = (int)d;
   for (int q = threadIdx.x; q < di * 16 * KB; q += kT) {
     const int r = q / (16 * KB), c = q % (16 * KB);
@@ -493,21 +498,8 @@ __global__ __launch_bounds__(128 * KB, 2) void bwd_gram_f32_kernel(const float* 
     for (int e = 0; e < 4; ++e) cacc[q][e] = v4f{0.f, 0.f, 0.f, 0.f};
 
   const int64_t ntiles = (n + 15) / 16;
-  for (int64_t tile = (int64_t)stream * gridDim.x + blockIdx.x; tile < ntiles; tile += (int64_t)gridDim.x * 2) {
-    // the tile, rows in the lane group (columns 64 q + 4 i16 .. + 3; pieces
-    // past d read column 0 and are dropped)
-    float4 rl[4][NQ];
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int64_t r = tile * 16 + 4 * s4 + g;
-      const float* rp = A + (r < n ? r : 0) * ld;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int c = 64 * q + 4 * i16;
-        rl[s4][q] = *reinterpret_cast<const float4*>(rp + (c < di ? c : 0));
-      }
-    }
-    // the tile, row i16 in the lanes: pieces 16 j + 4 g .. + 3
+  for (int64_t tile = (int64_t)stream * gridDim.x + blockIdx.x; tile < ntiles; tile += (int64_t)gridDim.x * S) {
+    // the tile's pieces, row i16 in the lanes: 16 j + 4 g .. + 3
     const int64_t row = tile * 16 + i16;
     const float* rp = A + (row < n ? row : 0) * ld + 4 * g;
     float4 a[NJ];
@@ -523,6 +515,19 @@ __global__ __launch_bounds__(128 * KB, 2) void bwd_gram_f32_kernel(const float* 
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           yt = __builtin_amdgcn_mfma_f32_16x16x4f32(zc[(16 * j + e) * kZsStride], av[e], yt, 0, 0, 0);
+      }
+    }
+    // the tile again, rows in the lane group (columns 64 q + 4 i16 .. + 3;
+    // pieces past d read column 0 and are dropped)
+    float4 rl[4][NQ];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int64_t r = tile * 16 + 4 * s4 + g;
+      const float* rq = A + (r < n ? r : 0) * ld;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c = 64 * q + 4 * i16;
+        rl[s4][q] = *reinterpret_cast<const float4*>(rq + (c < di ? c : 0));
       }
     }
     // Yw[row i16][16 nb + 4 g + v] -> LDS, back as Yw[row 4 s + g][16 nb + i16]
@@ -548,7 +553,7 @@ __global__ __launch_bounds__(128 * KB, 2) void bwd_gram_f32_kernel(const float* 
   // C[64 q + 4 i16 + e][16 nb + 4 g + v] = cacc[q][e][v]; streams add in order
   __syncthreads();  // every wave is done with zs
   float* red = zs;  // d x 64
-  for (int st = 0; st < 2; ++st) {
+  for (int st = 0; st < S; ++st) {
     if (stream == st) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
@@ -577,11 +582,12 @@ template <int KB, int NJ>
 hipError_t launch_gram_f32(const float* a, int64_t n, int64_t d, int64_t ld, const float* w, const float* z,
                            float* partials, int groups, hipStream_t s) {
   auto kern = bwd_gram_f32_kernel<KB, NJ>;
-  const size_t lds = ((size_t)d * kZsStride + 2 * KB * 16 * kYtStride) * sizeof(float);
+  constexpr int kWavesWg = KB * gram_streams<KB>();
+  const size_t lds = ((size_t)d * kZsStride + (size_t)kWavesWg * 16 * kYtStride) * sizeof(float);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  kern<<<(unsigned)groups, 128 * KB, lds, s>>>(a, n, d, ld, w, z, partials);
+  kern<<<(unsigned)groups, 64 * kWavesWg, lds, s>>>(a, n, d, ld, w, z, partials);
   return hipGetLastError();
 }
 
