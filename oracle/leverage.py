@@ -245,6 +245,41 @@ def ls_hrn_approx(A, seed: int, r_cs: int, m: int, k_jl: int, zeta: float, rows=
     return Estimate(None, row_norms_sq(AK_rows, Z), rr.perm, k, R11, Z, At, SA, rr.R, Gk)
 
 
+@dataclass
+class ExactEstimate:
+    theta: np.ndarray | None
+    theta_rows: np.ndarray | None
+    perm: np.ndarray           # full QRCP permutation of the sketch
+    rank: int
+
+
+def ls_hrn_exact(A, seed: int, r_cs: int, m: int, zeta: float, rows=None) -> ExactEstimate:
+    """Algorithm 7 (LS-HRN-exact): the columns K and the rank k from
+    Algorithm 4 on the sketch (as in ls_hrn_approx), then B = A_K^T A_K, its
+    eigendecomposition B = V Sigma^2 V^T (the SVD of a symmetric positive
+    definite B), and theta~_i = ||e_i^T A_K V Sigma^{-1}||^2: the exact
+    leverage scores of A_K.  ``rows`` restricts the last step to a subset."""
+    n, d = A.shape
+    rnd = conv.derive(seed, n, r_cs)
+    K, _, k, _, _, rr = count_gauss_srrqr(rnd, A, m, zeta)
+    if k == 0:
+        return ExactEstimate(np.zeros(n) if rows is None else None,
+                             np.zeros(len(rows)) if rows is not None else None, rr.perm, 0)
+    AK = A[:, K]
+    if sp.issparse(AK):
+        AK = AK.tocsr().astype(np.float64)
+        B = (AK.T @ AK).toarray()
+    else:
+        AK = np.asarray(AK, dtype=np.float64)
+        B = AK.T @ AK
+    w, V = np.linalg.eigh(B)
+    W = V / np.sqrt(w)  # V Sigma^{-1}
+    th = row_norms_sq(AK, W, rows=rows)
+    if rows is None:
+        return ExactEstimate(th, None, rr.perm, k)
+    return ExactEstimate(None, th, rr.perm, k)
+
+
 def theta_prime(A, K: np.ndarray, R11: np.ndarray, rows=None) -> np.ndarray:
     """The estimate without the JL step: ||e_i^T A_{:,K} R~^{-1}||^2."""
     X = sla.solve_triangular(R11, np.eye(R11.shape[0]), lower=False)

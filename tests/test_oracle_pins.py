@@ -381,3 +381,30 @@ def test_pins_catch_a_transposed_sketch(monkeypatch):
     orig = C.buckets
     monkeypatch.setattr(C, "buckets", lambda r: (orig(r) + 1) % r.r_cs)  # off-by-one bucket
     assert not np.array_equal(L.countsketch_apply(rnd, A), S @ A)
+
+
+# ------------------------------------------------------------------ Algorithm 7
+def test_ls_hrn_exact_equals_exact_scores_when_the_rank_is_found():
+    """Algorithm 7 returns the leverage scores of A_K.  When K holds rank(A)
+    independent columns, range(A_K) = range(A), so they must equal the
+    scores of A itself from the thin SVD (an independent route), for full
+    rank and for an exactly rank-deficient A; on a tiny input also the hat
+    diagonal of A_K written out."""
+    rng = np.random.default_rng(71)
+    A = rng.standard_normal((600, 24)) * rng.uniform(0.3, 3.0, 24)
+    e = L.ls_hrn_exact(A, 5, 256, 48, 1e-10)
+    ref, rho = L.exact_theta_svd(A, 1e-12)
+    assert e.rank == rho == 24
+    np.testing.assert_allclose(e.theta, ref, rtol=1e-10, atol=1e-13)
+    B = rng.standard_normal((500, 7)) @ rng.standard_normal((7, 20))
+    e = L.ls_hrn_exact(B, 6, 256, 40, 1e-8)
+    ref, rho = L.exact_theta_svd(B, 1e-10)
+    assert e.rank == rho == 7
+    np.testing.assert_allclose(e.theta, ref, rtol=1e-8, atol=1e-12)
+    assert abs(e.theta.sum() - 7) < 1e-9 and np.all(e.theta >= -1e-15) and np.all(e.theta <= 1 + 1e-12)
+    C = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 9))
+    e = L.ls_hrn_exact(C, 7, 64, 18, 1e-8)
+    K = e.perm[:e.rank]
+    np.testing.assert_allclose(e.theta, L.hat_diagonal_bruteforce(C[:, K], 1e-12), rtol=1e-9, atol=1e-12)
+    rows = np.array([0, 5, 39])
+    np.testing.assert_allclose(L.ls_hrn_exact(C, 7, 64, 18, 1e-8, rows=rows).theta_rows, e.theta[rows])
