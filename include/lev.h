@@ -100,13 +100,20 @@ typedef struct {
  *  zeta  -- rank tolerance: the revealed rank is r = #{ j : R_jj > zeta R_00 }
  *           on the column-pivoted factor of the sketch (the cutoff rule of
  *           Section 7).  0 <= zeta < 1.
- *  az_precision -- LEV_AZ_* above. */
+ *  az_precision -- LEV_AZ_* above.
+ *  exact -- 0: Algorithm 10 (LS-HRN-approx, the JL estimate with k
+ *           columns).  1: Algorithm 7 (LS-HRN-exact): the same columns K
+ *           and rank from the sketch, then the exact leverage scores of A_K
+ *           from B = A_K^T A_K (one more pass over A); k is ignored.  Dense
+ *           FP32/FP64 A with d <= 64 only (LEV_ERR_NOT_SUPPORTED /
+ *           LEV_ERR_DTYPE / LEV_ERR_SHAPE otherwise); lev_estimate's
+ *           state_out must be NULL (no backward). */
 typedef struct {
   uint64_t seed;
   int64_t r_cs, m, k;
   double zeta;
   int32_t az_precision;
-  int32_t reserved;
+  int32_t exact;
 } lev_params;
 
 /* Workspace bytes needed by lev_sketch (which = LEV_WS_SKETCH),

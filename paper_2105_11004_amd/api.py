@@ -47,7 +47,7 @@ class LevMatrix(ctypes.Structure):
 
 class LevParams(ctypes.Structure):
     _fields_ = [("seed", c_uint64), ("r_cs", c_int64), ("m", c_int64), ("k", c_int64),
-                ("zeta", c_double), ("az_precision", c_int32), ("reserved", c_int32)]
+                ("zeta", c_double), ("az_precision", c_int32), ("exact", c_int32)]
 
 
 class LevError(RuntimeError):
@@ -180,10 +180,11 @@ def _matrix(A) -> LevMatrix:
     return LevMatrix(DENSE, _DTYPES[A.dtype], A.shape[0], A.shape[1], ld, 0, A.data_ptr(), None, None)
 
 
-def _params(seed, r_cs, m, k, zeta, precision) -> LevParams:
+def _params(seed, r_cs, m, k, zeta, precision, exact=False) -> LevParams:
     if precision not in AZ:
         raise ValueError(f"precision must be one of {list(AZ)}")
-    return LevParams(int(seed) & ((1 << 64) - 1), int(r_cs), int(m), int(k), float(zeta), AZ[precision], 0)
+    return LevParams(int(seed) & ((1 << 64) - 1), int(r_cs), int(m), int(k), float(zeta), AZ[precision],
+                     1 if exact else 0)
 
 
 def _workspace(nbytes: int, device) -> tuple[torch.Tensor, c_void_p]:
@@ -295,13 +296,16 @@ def lev_rank_estimate(At: torch.Tensor, zeta: float):
 
 
 def lev_estimate(A, seed: int, r_cs: int, m: int, k: int, zeta: float,
-                 precision: str = "native", return_state: bool = False):
+                 precision: str = "native", return_state: bool = False, exact: bool = False):
     """Algorithm 10 (LS-HRN-approx): theta~ (FP64 for FP64 A, else FP32).
-    A is a dense device tensor or a CSR matrix (see lev_sketch)."""
+    A is a dense device tensor or a CSR matrix (see lev_sketch).  exact=True
+    runs Algorithm 7 (LS-HRN-exact) instead: the exact leverage scores of the
+    columns K the sketch selects (dense FP32/FP64, d <= 64; k is ignored,
+    no state)."""
     lib = load_library()
     A = _as_csr(A)  # held until the call returns: it owns converted index arrays
     dev, (n, d), dt = _device(A), _shape(A), _dtype(A)
-    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
+    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, exact)
     nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_ESTIMATE)
     if nbytes == 0:
         _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))

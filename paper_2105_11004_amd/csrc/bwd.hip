@@ -136,7 +136,7 @@ __device__ void tile_y(const T* As, const T* Zs, const T* __restrict__ Zg, int64
     for (int v = 0; v < 4; ++v) {
       const int row = 16 * mb + M::row(lane, v);
       const int64_t i = r0 + row;
-      const T wi = i < n ? w[i] : (T)0;
+      const T wi = i < n ? (w != nullptr ? w[i] : (T)1) : (T)0;  // w = null: all ones
       Ys[row * g.sy + 16 * nb + (lane & 15)] = acc[v] * wi * scale;
     }
   }
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(64 * KB * gram_streams<KB>(), KB * gram_streams<KB>
     float4 a[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) a[j] = *reinterpret_cast<const float4*>(rp + 16 * (j < nj ? j : 0));
-    const float ws = row < n ? w[row] : 0.0f;
+    const float ws = row < n ? (w != nullptr ? w[row] : 1.0f) : 0.0f;  // w = null: all ones
     v4f yt = v4f{0.f, 0.f, 0.f, 0.f};
     const float* zc = zs + 4 * g * kZsStride + 16 * nb + i16;
 #pragma unroll
@@ -707,6 +707,32 @@ hipError_t grad_typed(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k
   return hipGetLastError();
 }
 
+// ---- LS-HRN-exact (Algorithm 7) helpers -----------------------------------------
+// Z_full = I as the operand of the C pass (d x 64 of T): with w = 1 the pass
+// then computes C = A^T A.
+template <typename T>
+__global__ void identity_rows_kernel(int64_t d, T* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * kZCols) return;
+  out[idx] = (idx / kZCols == idx % kZCols) ? (T)1 : (T)0;
+}
+
+// B_K[i][j] = C[perm[i]][perm[j]] for i, j < r, else 0 (d x d).
+__global__ void gather_bk_kernel(int64_t d, const int32_t* __restrict__ perm, const int64_t* __restrict__ rank,
+                                 const double* __restrict__ C, double* __restrict__ B) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * d) return;
+  const int64_t i = idx / d, j = idx % d, r = *rank;
+  B[idx] = (i < r && j < r) ? C[(int64_t)perm[i] * d + perm[j]] : 0.0;
+}
+
+// permc[j] = perm[perm2[j]]: column ids of A in the order of the Cholesky of B_K.
+__global__ void compose_perm_kernel(int64_t d, const int32_t* __restrict__ perm, const int32_t* __restrict__ perm2,
+                                    int32_t* __restrict__ permc) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < d) permc[j] = perm[perm2[j]];
+}
+
 // ---- small FP64 helpers of the core --------------------------------------------
 // Zbar[j][c] = j < r ? 2 C64[perm[j]][c] : 0.
 __global__ void gather_zbar_kernel(int64_t d, int64_t k, const int32_t* __restrict__ perm,
@@ -783,6 +809,24 @@ hipError_t launch_bwd_grad(int dtype, const void* A, int64_t n, int64_t d, int64
   if (dtype == 0) return grad_typed<double>(A, n, d, ld, k, w, Zfull, Hfull, hp, G, ldg, s);
   if (dtype == 1) return grad_typed<float>(A, n, d, ld, k, w, Zfull, Hfull, hp, G, ldg, s);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_identity_rows(int dtype, int64_t d, void* out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((d * kZCols + 255) / 256);
+  if (dtype == 0) identity_rows_kernel<double><<<blocks, 256, 0, s>>>(d, static_cast<double*>(out));
+  else identity_rows_kernel<float><<<blocks, 256, 0, s>>>(d, static_cast<float*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_bk(int64_t d, const int32_t* perm, const int64_t* rank, const double* C, double* B,
+                            hipStream_t s) {
+  gather_bk_kernel<<<(unsigned)((d * d + 255) / 256), 256, 0, s>>>(d, perm, rank, C, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose_perm(int64_t d, const int32_t* perm, const int32_t* perm2, int32_t* permc, hipStream_t s) {
+  compose_perm_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(d, perm, perm2, permc);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather_zbar(int64_t d, int64_t k, const int32_t* perm, const int64_t* rank, const double* C64,

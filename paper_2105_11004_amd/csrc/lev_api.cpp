@@ -174,6 +174,12 @@ lev_status check_params(const lev_matrix* A, const lev_params* p) {
   if (!(p->zeta >= 0.0 && p->zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
   if (az_variant(A->format, A->dtype, p->az_precision) < 0)
     return fail(LEV_ERR_ARG, "az_precision %d not valid for dtype %d", p->az_precision, A->dtype);
+  if (p->exact != 0 && p->exact != 1) return fail(LEV_ERR_ARG, "exact must be 0 or 1");
+  if (p->exact) {
+    if (A->format != LEV_DENSE_ROWMAJOR) return fail(LEV_ERR_NOT_SUPPORTED, "exact scores take dense A only");
+    if (A->dtype != LEV_F32 && A->dtype != LEV_F64) return fail(LEV_ERR_DTYPE, "exact scores take FP32 or FP64 A");
+    if (A->d > 64) return fail(LEV_ERR_SHAPE, "exact scores need d <= 64 (d = %lld)", (long long)A->d);
+  }
   return LEV_OK;
 }
 
@@ -338,6 +344,39 @@ BwdBufs carve_bwd(Carver& c, const lev_matrix* A, const lev_params* p) {
   return b;
 }
 
+// LS-HRN-exact (Algorithm 7): the C pass's buffers for B = A^T A, and a
+// second pivoted Cholesky (of B_K) with its outputs.
+struct ExactBufs {
+  void* ZI;
+  void* partials;
+  int groups;
+  double* C64;
+  RankBufs rb2;
+  int32_t* perm2;
+  double* R2;
+  int64_t* rank2;
+  int32_t* permc;
+  double* I;
+};
+
+ExactBufs carve_exact(Carver& c, const lev_matrix* A, const lev_params* p) {
+  const int64_t n = A->n, d = A->d, m = p->m;
+  const int dt = A->dtype == LEV_F64 ? 0 : 1;
+  const size_t es = lev::bwd_elem_size(dt);
+  ExactBufs b;
+  b.groups = lev::bwd_groups(dt, n, d, d);
+  b.ZI = c.take<char>((size_t)d * 64 * es);
+  b.partials = c.take<char>((size_t)b.groups * (size_t)d * 64 * es);
+  b.C64 = c.take<double>((size_t)(d * d));
+  b.rb2 = carve_rank(c, m, d);
+  b.perm2 = c.take<int32_t>((size_t)d);
+  b.R2 = c.take<double>((size_t)(d * d));
+  b.rank2 = c.take<int64_t>(1);
+  b.permc = c.take<int32_t>((size_t)d);
+  b.I = c.take<double>((size_t)(d * d));
+  return b;
+}
+
 lev_status check_backward_input(const lev_matrix* A) {
   if (A->format != LEV_DENSE_ROWMAJOR)
     return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass takes dense A only");
@@ -436,6 +475,14 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
     carve_sketch(c, A->n, d, m, r_cs, true);
     return c.used;
   }
+  if (which == LEV_WS_ESTIMATE && p->exact) {
+    carve_sketch(c, A->n, d, m, r_cs, true);
+    carve_rank(c, m, d);
+    c.take<char>(state_bytes(d, m, d));
+    carve_exact(c, A, p);
+    c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, d));
+    return c.used;
+  }
   if (which == LEV_WS_ESTIMATE) {
     carve_sketch(c, A->n, d, m, r_cs, true);
     carve_rank(c, m, d);
@@ -482,6 +529,54 @@ lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta
   return enqueue_rank(At, m, d, zeta, b, perm_out, R_out, rank_out, stream);
 }
 
+// Algorithm 7 (LS-HRN-exact) on dense FP32/FP64 A with d <= 64: the columns K
+// and the rank from Algorithm 4 on the sketch (as for Algorithm 10), then
+// B = A^T A in one pass over A (the backward's C pass with w = 1 and
+// Z_full = I), B_K = B[K, K], its pivoted Cholesky (A_K P2)^T (A_K P2) =
+// R_B^T R_B, Z = R_B^{-1} and theta~_i = ||e_i^T A_K P2 R_B^{-1}||^2 in pass
+// 2.  A_K P2 R_B^{-1} and Algorithm 7's A_K V Sigma^{-1} are both orthonormal
+// bases of range(A_K), so the row norms are the same.  The Cholesky runs with
+// zeta = 0: B_K's rows and columns past the rank are exact zeros, where it
+// stops.
+lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant, void* theta_out, void* ws,
+                          hipStream_t stream) {
+  const int64_t n = A->n, d = A->d, m = p->m, r_cs = p->r_cs;
+  const int dt = A->dtype == LEV_F64 ? 0 : 1;
+  hipStream_t s = stream;
+  Carver c(ws);
+  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
+  RankBufs rb = carve_rank(c, m, d);
+  void* state_ws = c.take<char>(state_bytes(d, m, d));
+  ExactBufs eb = carve_exact(c, A, p);
+  void* Zpack = c.take<char>(lev::pack_z_bytes(variant, d, d));
+  StateView sv = carve_state(state_ws, d, m, d);
+  int64_t* rank = sv.header + 4;
+  const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
+  LEV_HIP(mark_phase(0, s));
+  LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, nullptr, s));
+  LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, s));
+  LEV_HIP(mark_phase(4, s));
+  LEV_HIP(lev::launch_identity_rows(dt, d, eb.ZI, s));
+  if (n > 0) {
+    LEV_HIP(lev::launch_bwd_gram(dt, A->values, n, d, A->ld, d, nullptr, eb.ZI, eb.partials, eb.groups, eb.C64, s));
+  } else {
+    LEV_HIP(lev::launch_fill_zero(eb.C64, sizeof(double) * (size_t)(d * d), s));
+  }
+  LEV_HIP(lev::launch_gather_bk(d, sv.perm, rank, eb.C64, eb.rb2.B, s));
+  if (d > 256) LEV_HIP(lev::launch_fill_zero(eb.rb2.pc.flags, 64 * sizeof(int32_t), s));
+  LEV_HIP(lev::launch_pivchol(eb.rb2.B, d, 0.0, eb.rb2.pc, eb.rank2, eb.rb2.partial, s));
+  LEV_HIP(lev::launch_pivchol_finalize(d, eb.rb2.pc, eb.rank2, eb.perm2, eb.R2, s));
+  LEV_HIP(lev::launch_compose_perm(d, sv.perm, eb.perm2, eb.permc, s));
+  LEV_HIP(lev::launch_identity(d, eb.I, s));
+  LEV_HIP(lev::launch_form_z(variant, d, d, eb.R2, eb.rank2, eb.permc, eb.I, sv.Z64, Zpack, s));
+  LEV_HIP(mark_phase(5, s));
+  if (n > 0) {
+    LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, d, Zpack, eb.rank2, theta_out, s));
+  }
+  LEV_HIP(mark_phase(6, s));
+  return LEV_OK;
+}
+
 lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_out, void* state_out, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
   LEV_TRY(check_matrix(A));
@@ -494,6 +589,10 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
 
   const int64_t n = A->n, d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
   const int variant = az_variant(A->format, A->dtype, p->az_precision);
+  if (p->exact) {
+    if (state_out != nullptr) return fail(LEV_ERR_NOT_SUPPORTED, "exact scores have no backward state");
+    return estimate_exact(A, p, variant, theta_out, ws, stream);
+  }
   Carver c(ws);
   SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
   RankBufs rb = carve_rank(c, m, d);

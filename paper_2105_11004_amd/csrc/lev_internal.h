@@ -163,4 +163,12 @@ hipError_t launch_store_i64x4(int64_t* dst, int64_t a, int64_t b, int64_t c, int
 // Zero-fill helper (a kernel, so it is safe under graph capture).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
+// LS-HRN-exact (Algorithm 7): Z_full = I (d x 64 of the pass type; dtype 0
+// FP64, 1 FP32) for the C pass, B_K = C[K, K] (zeros past the rank), and
+// permc[j] = perm[perm2[j]].  The C pass treats w == nullptr as all ones.
+hipError_t launch_identity_rows(int dtype, int64_t d, void* out, hipStream_t s);
+hipError_t launch_gather_bk(int64_t d, const int32_t* perm, const int64_t* rank, const double* C, double* B,
+                            hipStream_t s);
+hipError_t launch_compose_perm(int64_t d, const int32_t* perm, const int32_t* perm2, int32_t* permc, hipStream_t s);
+
 }  // namespace lev

@@ -56,9 +56,10 @@ def _mat(api, **kw):
 
 
 def _par(api, **kw):
-    base = dict(seed=1, r_cs=64, m=32, k=8, zeta=1e-5, az=0)
+    base = dict(seed=1, r_cs=64, m=32, k=8, zeta=1e-5, az=0, exact=0)
     base.update(kw)
-    return api.LevParams(base["seed"], base["r_cs"], base["m"], base["k"], base["zeta"], base["az"], 0)
+    return api.LevParams(base["seed"], base["r_cs"], base["m"], base["k"], base["zeta"], base["az"],
+                         base["exact"])
 
 
 @pytest.mark.parametrize("mat_kw,par_kw,expected", [
@@ -82,6 +83,10 @@ def _par(api, **kw):
     ({"format": 1, "row_ptr": 8192, "nnz": 10}, {}, -1),            # nnz > 0 without col_idx
     ({"format": 1, "row_ptr": 8192, "dtype": 0}, {"az": 1}, -1),    # FP64 CSR runs in FP64 only
     ({"format": 1, "row_ptr": 8192, "nnz": 5, "col_idx": 16384}, {"az": 2}, -1),  # no BF16 products on CSR
+    ({}, {"exact": 2}, -1),
+    ({"d": 80, "ld": 80}, {"exact": 1, "m": 96}, -2),                               # exact scores: d <= 64
+    ({"dtype": 2, "ld": 16}, {"exact": 1}, -3),                                     # exact scores: FP32/FP64
+    ({"format": 1, "row_ptr": 8192, "nnz": 5, "col_idx": 16384}, {"exact": 1}, -7),  # exact scores: dense
 ])
 def test_estimate_rejects_bad_arguments(lib, mat_kw, par_kw, expected):
     from paper_2105_11004_amd import api

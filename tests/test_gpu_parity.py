@@ -260,6 +260,35 @@ def test_estimate_bf16_full_size_sampled(gpu):
     assert rel.max() < 1e-2 and np.quantile(rel, 0.99) < 4e-3
 
 
+@pytest.mark.parametrize("dtype,n,d,rank,bar", [
+    (torch.float64, 4096, 64, 64, 1e-10),     # the FP64 workload's shape
+    (torch.float64, 3000 + 7, 40, 17, 1e-9),  # exactly rank-deficient: 17 columns kept
+    (torch.float32, 20000 + 5, 64, 64, 1e-4),
+    (torch.float32, 5000 + 3, 48, 48, 1e-4),
+])
+def test_estimate_exact_scores(gpu, dtype, n, d, rank, bar):
+    """Algorithm 7 (LS-HRN-exact, exact=True): the exact leverage scores of
+    the columns K the sketch selects, from B = A_K^T A_K, against the
+    oracle's Algorithm 7 (which the oracle pins tie to the thin SVD of A).
+    FP32 runs on full-rank A only: the Gram squares the conditioning of A_K."""
+    _log("exact", dtype, n, d, rank)
+    rng = np.random.default_rng(n + d + rank)
+    if rank < d:
+        A = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, d))
+    else:
+        A = rng.standard_normal((n, d)) * rng.uniform(0.5, 2.0, d)
+    At = torch.from_numpy(A).to(dtype)
+    r_cs, m, seed = 1024, d + 64, 3003
+    zeta = 1e-10 if dtype == torch.float64 else 1e-5
+    theta = api.lev_estimate(At.to(gpu), seed, r_cs, m, 8, zeta, exact=True).cpu().numpy().astype(np.float64)
+    o = L.ls_hrn_exact(At.to(torch.float64).numpy(), seed, r_cs, m, zeta)
+    assert o.rank == rank
+    rel = _rel(theta, o.theta)
+    _log("exact max rel", rel.max(), "sum", theta.sum())
+    assert rel.max() < bar
+    assert abs(theta.sum() - rank) < 1e-6 * rank if dtype == torch.float64 else abs(theta.sum() - rank) < 1e-3 * rank
+
+
 # ------------------------------------------------------------------ edge cases
 def test_zero_matrix_and_zero_rows(gpu):
     A = torch.zeros(1000, 32, dtype=torch.float32, device=gpu)
