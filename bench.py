@@ -44,7 +44,9 @@ def _src_hash(path: Path) -> str:
 def make_workload(name: str, device):
     cfg = dict(W.CONFIGS[name])
     idx = list(W.CONFIGS).index(name) + 1
-    if name.startswith("dense_f32"):
+    if name.endswith("_exact"):
+        A = W.dense_gaussian(cfg["n"], cfg["d"], W.data_seed(idx), dtype=torch.float32, device=device)
+    elif name.startswith("dense_f32"):
         heavy = 0.0 if name.endswith("_bwd") else 0.01  # the backward workload has no heavy rows
         A = W.low_rank_coherent(cfg["n"], cfg["d"], cfg["rank"], W.data_seed(idx), heavy_frac=heavy, device=device)
     elif name.startswith("dense_f64"):
@@ -82,12 +84,18 @@ def bytes_per_launch(A, cfg) -> dict:
     }
 
 
-def cpu_baseline(A, cfg, seed, target_s: float = 10.0):
+def cpu_baseline(A, cfg, seed, target_s: float = 10.0, exact: bool = False):
     """Times the oracle's estimator on the first n_s rows of the workload
     (same d, sketch sizes and seed), growing n_s until about a quarter of
     target_s; when that covers the whole workload, the whole workload is
     timed repeatedly until about target_s and the mean is reported."""
     from oracle import leverage as L
+
+    def oracle(Ah):
+        if exact:
+            return L.ls_hrn_exact(Ah, seed, cfg["r_cs"], cfg["m"], cfg["zeta"])
+        return L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
@@ -105,7 +113,7 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0):
     while True:
         Ah = host(ns)
         t0 = time.perf_counter()
-        L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+        oracle(Ah)
         dt = time.perf_counter() - t0
         if dt > target_s / 4 or ns >= n:
             break
@@ -113,13 +121,14 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0):
     reps, total = 1, dt
     while ns >= n and total < target_s:
         t0 = time.perf_counter()
-        L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+        oracle(Ah)
         total += time.perf_counter() - t0
         reps += 1
     dt = total / reps
     what = f"first {ns} rows of the workload" if ns < n else f"the whole workload ({n} rows), mean of {reps} runs"
     return {"value": ns / dt, "unit": "rows/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{what}, full estimator (sketch, QRCP, Z, row norms), FP64 NumPy/SciPy, {dt:.2f} s per run"}
+            "sample": f"{what}, full estimator ({'sketch, QRCP, Gram of A_K, eigh, row norms' if exact else 'sketch, QRCP, Z, row norms'}), "
+                      f"FP64 NumPy/SciPy, {dt:.2f} s per run"}
 
 
 def traffic_for(kernel: str):
@@ -167,6 +176,8 @@ def main():
     ap.add_argument("--workload", default="dense_f32_1Mx256_rank128")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="native")
+    ap.add_argument("--exact", action="store_true",
+                    help="time Algorithm 7 (LS-HRN-exact: dense FP32/FP64, d <= 64) instead of Algorithm 10")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -178,7 +189,8 @@ def main():
     api.load_library()
     print(f"# generating workload {args.workload}", file=sys.stderr, flush=True)
     A, cfg, seed = make_workload(args.workload, dev)
-    plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=args.precision)
+    plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=args.precision,
+                            exact=args.exact)
     backward = args.workload.endswith("_bwd")
     if backward:
         bwd = api.BackwardPlan(plan, torch.rand(A.shape[0], device=dev, dtype=A.dtype,
@@ -255,7 +267,8 @@ def main():
         "dtype": {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[str(vals.dtype).split(".")[1]],
         "data": "synthetic (seeded, generated on the GPU)",
         "config": {"workload": args.workload, "n": n, "d": cfg["d"], "r_cs": cfg["r_cs"], "m": cfg["m"],
-                   "k": cfg["k"], "zeta": cfg["zeta"], "precision": args.precision},
+                   "k": cfg["k"], "zeta": cfg["zeta"], "precision": args.precision,
+                   "algorithm": "LS-HRN-exact (Algorithm 7)" if args.exact else "LS-HRN-approx (Algorithm 10)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom), "kernel": dom},
         "phases_ms": phases,
@@ -273,7 +286,7 @@ def main():
         out["backward_hbm_gbs"] = 3 * a_bytes(A) / (bms * 1e-3) / 1e9  # two reads of A, one write of the gradient
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(A, cfg, seed)
+        out["cpu_baseline"] = cpu_baseline(A, cfg, seed, exact=args.exact)
     print(json.dumps(out), flush=True)
 
 

@@ -324,10 +324,10 @@ class EstimatePlan:
     """Pre-allocated workspace and outputs for repeated lev_estimate calls on
     same-shaped inputs (what the benchmark times)."""
 
-    def __init__(self, A, seed, r_cs, m, k, zeta, precision="native"):
+    def __init__(self, A, seed, r_cs, m, k, zeta, precision="native", exact=False):
         self.lib = load_library()
         A = _as_csr(A)  # kept in self.A: the pointers below refer to its arrays
-        self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
+        self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, exact)
         self.nbytes = self.lib.lev_workspace_size(ctypes.byref(self.mat), ctypes.byref(self.par), WS_ESTIMATE)
         if self.nbytes == 0:
             _check(self.lib.lev_estimate(ctypes.byref(self.mat), ctypes.byref(self.par), None, None, None, 0,

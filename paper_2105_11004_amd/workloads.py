@@ -162,6 +162,9 @@ CONFIGS = {
     "csr_f32_8Mx512": dict(n=1 << 23, d=512, zero_cols=64, dtype="f32", r_cs=8192, m=1024, k=64, zeta=1e-5),
     "dense_bf16_4Mx1024": dict(n=1 << 22, d=1024, dtype="bf16", r_cs=16384, m=2048, k=64, zeta=1e-3),
     "dense_f32_1Mx256_rank192_bwd": dict(n=1 << 20, d=256, rank=192, dtype="f32", r_cs=4096, m=512, k=48, zeta=1e-5),
+    # LS-HRN-exact (Algorithm 7) at scale: a well-conditioned FP32 Gaussian
+    # (the FP32 Gram squares the conditioning of A_K); k is unused there
+    "dense_f32_1Mx64_exact": dict(n=1 << 20, d=64, dtype="f32", r_cs=4096, m=128, k=32, zeta=1e-5),
 }
 
 

@@ -289,6 +289,25 @@ def test_estimate_exact_scores(gpu, dtype, n, d, rank, bar):
     assert abs(theta.sum() - rank) < 1e-6 * rank if dtype == torch.float64 else abs(theta.sum() - rank) < 1e-3 * rank
 
 
+def test_estimate_exact_full_size_sampled(gpu):
+    """Algorithm 7 at the size its benchmark line runs (2^20 x 64 FP32
+    Gaussian) in the benchmark's launch configuration, on sampled rows
+    against the oracle run on the whole matrix."""
+    cfg = W.CONFIGS["dense_f32_1Mx64_exact"]
+    idx = list(W.CONFIGS).index("dense_f32_1Mx64_exact") + 1
+    n, d = cfg["n"], cfg["d"]
+    A = W.dense_gaussian(n, d, W.data_seed(idx), dtype=torch.float32, device=gpu)
+    plan = api.EstimatePlan(A, W.sketch_seed(idx), cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], exact=True)
+    theta = plan.run().cpu().numpy().astype(np.float64)
+    rows = np.sort(np.random.default_rng(6).choice(n, 3000, replace=False))
+    o = L.ls_hrn_exact(A.cpu().numpy().astype(np.float64), W.sketch_seed(idx), cfg["r_cs"], cfg["m"], cfg["zeta"],
+                       rows=rows)
+    assert o.rank == d
+    rel = _rel(theta[rows], o.theta_rows)
+    _log("exact full size max rel", rel.max(), "sum", theta.sum())
+    assert rel.max() < 1e-4 and abs(theta.sum() - d) < 1e-3 * d
+
+
 # ------------------------------------------------------------------ edge cases
 def test_zero_matrix_and_zero_rows(gpu):
     A = torch.zeros(1000, 32, dtype=torch.float32, device=gpu)
