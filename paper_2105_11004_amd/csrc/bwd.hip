@@ -467,14 +467,16 @@ hipError_t launch_grad_f32_kb(const float* a, int64_t n, int64_t d, int64_t ld, 
 // bwd_gram_kernel).
 constexpr int kYtStride = 80;  // floats per row of the per-wave Y block (16 mod 64 words)
 
-template <int KB>
-constexpr int gram_streams() { return KB == 3 ? 4 : (KB == 1 ? 4 : 2); }
+// Tile streams per workgroup: waves spread evenly over the four SIMDs within
+// the registers C needs; at d <= 64 (NJ = 4) the waves are small and 16 fit.
+template <int KB, int NJ>
+constexpr int gram_streams() { return NJ <= 4 ? 16 / KB : (KB == 3 ? 4 : (KB == 1 ? 4 : 2)); }
 
 template <int KB, int NJ>
-__global__ __launch_bounds__(64 * KB * gram_streams<KB>(), KB * gram_streams<KB>() / 4) void bwd_gram_f32_kernel(
+__global__ __launch_bounds__((64 * KB * gram_streams<KB, NJ>()), (KB * gram_streams<KB, NJ>() / 4)) void bwd_gram_f32_kernel(
     const float* __restrict__ A, int64_t n, int64_t d, int64_t ld, const float* __restrict__ w,
     const float* __restrict__ Zg, float* __restrict__ partials) {
-  constexpr int S = gram_streams<KB>();
+  constexpr int S = gram_streams<KB, NJ>();
   constexpr int NQ = NJ / 4;  // 64-column groups
   constexpr int kT = 64 * KB * S;
   extern __shared__ float smem_f[];
@@ -582,7 +584,7 @@ template <int KB, int NJ>
 hipError_t launch_gram_f32(const float* a, int64_t n, int64_t d, int64_t ld, const float* w, const float* z,
                            float* partials, int groups, hipStream_t s) {
   auto kern = bwd_gram_f32_kernel<KB, NJ>;
-  constexpr int kWavesWg = KB * gram_streams<KB>();
+  constexpr int kWavesWg = KB * gram_streams<KB, NJ>();
   const size_t lds = ((size_t)d * kZsStride + (size_t)kWavesWg * 16 * kYtStride) * sizeof(float);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
