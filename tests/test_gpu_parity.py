@@ -319,6 +319,16 @@ def test_zero_matrix_and_zero_rows(gpu):
     assert theta[0] == 0 and theta[999] == 0 and theta[1999] == 0
 
 
+def test_empty_matrix(gpu):
+    """n = 0 (no rows): rank 0 and an empty theta~, for the JL estimate and
+    for the exact scores."""
+    A = torch.zeros(0, 16, dtype=torch.float32, device=gpu)
+    theta, st = api.lev_estimate(A, 1, 64, 32, 8, 1e-5, return_state=True)
+    assert theta.shape == (0,) and int(st.rank.item()) == 0
+    theta = api.lev_estimate(A, 1, 64, 32, 8, 1e-5, exact=True)
+    assert theta.shape == (0,)
+
+
 @pytest.mark.parametrize("n,d,k,r_cs,m", [(1, 4, 1, 1, 4), (15, 8, 17, 3, 8), (33, 64, 64, 7, 64),
                                           (5000, 36, 5, 1, 40), (300, 12, 16, 5000, 12)])
 def test_small_and_degenerate_shapes(gpu, n, d, k, r_cs, m):
