@@ -180,7 +180,7 @@ def main():
                     help="time Algorithm 7 (LS-HRN-exact: dense FP32/FP64, d <= 64) instead of Algorithm 10")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
                                    "(the multi-GPU row-sharded design is described, not built)"}))
         sys.exit(2)
     if not torch.cuda.is_available():

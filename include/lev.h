@@ -50,7 +50,7 @@ enum {
   LEV_ERR_FORMAT = -4,        /* malformed CSR (checked only where stated) */
   LEV_ERR_WORKSPACE = -5,     /* ws too small or misaligned */
   LEV_ERR_HIP = -6,           /* a HIP runtime call failed at launch */
-  LEV_ERR_NOT_SUPPORTED = -7  /* valid request this build does not handle */
+  LEV_ERR_NOT_SUPPORTED = -7  /* valid request the library does not handle */
 };
 
 enum { LEV_DENSE_ROWMAJOR = 0, LEV_CSR = 1 };
