@@ -163,7 +163,13 @@ lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta
  *  theta_out -- n entries: FP64 when A is F64, else FP32.
  *  state_out -- optional (NULL to skip): lev_state_size(d, m, k) bytes that
  *               lev_estimate_backward needs (perm, rank, R, Z, A~); 256-byte
- *               aligned.
+ *               aligned.  Its header is int64[8]: [0] a magic value, [1] d,
+ *               [2] m, [3] k, [4] the rank r, [5] the device error word (low
+ *               32 bits; 0 on success).  The kernels' waits on each other
+ *               end by construction but are bounded; a wait that ran out sets
+ *               bit 1 (pivoting) or bit 2 (triangular solve) of the error
+ *               word, and the call's results are then meaningless.  The word
+ *               is cleared at the start of every call.
  * Dense (F64/F32/BF16) and CSR (F64/F32/BF16 values) input.
  * r = 0 (e.g. A = 0) gives theta~ = 0.  Zero rows give theta~_i = 0. */
 lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_out,
@@ -180,7 +186,9 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
  *               CSR gives LEV_ERR_NOT_SUPPORTED, BF16 LEV_ERR_DTYPE).
  *  p         -- the same parameters.
  *  state     -- the blob lev_estimate wrote for this A and p (256-byte
- *               aligned); it is read, not modified.  A blob from another A
+ *               aligned); it is read, and only its error word (header slot
+ *               5) may be written: a bounded wait of the triangular solve
+ *               that ran out sets bit 2 there.  A blob from another A
  *               or other parameters gives a meaningless gradient (its header
  *               is not checked on the host, which would need a sync).
  *  w         -- n weights of A's type.
@@ -192,6 +200,14 @@ lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const
                                  hipStream_t stream);
 
 /* ---- inspection helpers (used by the tests) -------------------------------- */
+
+/* Host-only: the CountSketch hash and sign coefficients a seed expands to
+ * (Section 3.4, CountSketch: a pairwise independent bucket hash and 4-wise
+ * independent signs).  out (HOST, 7 entries) receives P (the smallest prime
+ * >= max(n, 2)), a and c of h(i) = ((a i + c) mod P) mod r_cs, and c0..c3 of
+ * the sign polynomial (c3 i^3 + c2 i^2 + c1 i + c0) mod (2^61 - 1).  No
+ * device work; callable without a GPU. */
+lev_status lev_hash_params(uint64_t seed, int64_t n, int64_t r_cs, uint64_t* out);
 
 /* h(i) and s(i) of the CountSketch for every row i < n (int64 h_out[n],
  * int8 s_out[n], device). */

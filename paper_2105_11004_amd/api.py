@@ -30,8 +30,8 @@ WS_SKETCH, WS_ESTIMATE, WS_BACKWARD = 0, 2, 3
 # Every symbol the header declares (checked by the CPU tests).
 EXPORTED = ["lev_workspace_size", "lev_rank_workspace_size", "lev_state_size", "lev_sketch",
             "lev_rank_estimate", "lev_estimate", "lev_estimate_backward", "lev_debug_hash",
-            "lev_debug_buckets", "lev_debug_gaussian", "lev_set_phase_events", "lev_status_string",
-            "lev_last_error"]
+            "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params", "lev_set_phase_events",
+            "lev_status_string", "lev_last_error"]
 LEV_PHASES = 7
 # phase 0 holds no kernels (the Gaussian draws run inside pass 1): its time is
 # the cost of two back-to-back events
@@ -85,6 +85,7 @@ def load_library(path: Path | None = None):
     lib.lev_debug_hash.argtypes = [c_uint64, c_int64, c_int64, vp, vp, vp]
     lib.lev_debug_buckets.argtypes = [c_uint64, c_int64, c_int64, vp, vp, vp]
     lib.lev_debug_gaussian.argtypes = [c_uint64, c_int, c_int64, c_int64, vp, vp]
+    lib.lev_hash_params.argtypes = [c_uint64, c_int64, c_int64, POINTER(c_uint64)]
     lib.lev_set_phase_events.argtypes = [vp, c_int]
     lib.lev_set_phase_events.restype = c_int
     lib.lev_status_string.argtypes = [c_int]
@@ -92,7 +93,7 @@ def load_library(path: Path | None = None):
     lib.lev_last_error.argtypes = []
     lib.lev_last_error.restype = ctypes.c_char_p
     for name in ("lev_sketch", "lev_rank_estimate", "lev_estimate", "lev_estimate_backward",
-                 "lev_debug_hash", "lev_debug_buckets", "lev_debug_gaussian"):
+                 "lev_debug_hash", "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -221,6 +222,12 @@ class State:
     def rank(self) -> torch.Tensor:
         off = self.layout(self.d, self.m, self.k)["header"]
         return self.blob[off + 32:off + 40].view(torch.int64)
+
+    @property
+    def error(self) -> torch.Tensor:
+        """The device error word (0: every bounded wait ended normally)."""
+        off = self.layout(self.d, self.m, self.k)["header"]
+        return self.blob[off + 40:off + 44].view(torch.int32)
 
     @property
     def perm(self) -> torch.Tensor:
@@ -405,6 +412,15 @@ def lev_debug_buckets(seed: int, n: int, r_cs: int, device="cuda"):
     _check(lib.lev_debug_buckets(int(seed) & ((1 << 64) - 1), n, r_cs, _ptr(off), _ptr(rows),
                                  _stream(torch.device(device))))
     return off, rows[:n]
+
+
+def lev_hash_params(seed: int, n: int, r_cs: int) -> dict:
+    """The hash and sign coefficients liblev derives from a seed (host
+    only, no GPU needed): P, a, c, c0..c3."""
+    lib = load_library()
+    out = (c_uint64 * 7)()
+    _check(lib.lev_hash_params(int(seed) & ((1 << 64) - 1), int(n), int(r_cs), out))
+    return dict(zip(("P", "a", "c", "c0", "c1", "c2", "c3"), [int(v) for v in out]))
 
 
 def lev_debug_gaussian(seed: int, which: int, rows: int, cols: int, device="cuda"):

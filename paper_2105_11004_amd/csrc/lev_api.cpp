@@ -193,7 +193,7 @@ lev_status check_ws(const void* ws, size_t have, size_t need) {
 
 // ---- state blob ---------------------------------------------------------------
 struct StateView {
-  int64_t* header;  // [0] magic, [1] d, [2] m, [3] k, [4] rank
+  int64_t* header;  // [0] magic, [1] d, [2] m, [3] k, [4] rank, [5] error word (low 32 bits)
   int32_t* perm;
   double* R;
   double* Z64;
@@ -221,6 +221,10 @@ StateView carve_state(void* base, int64_t d, int64_t m, int64_t k) {
   v.At = c.take<double>((size_t)(m * d));
   return v;
 }
+
+// The device error word of a state blob (bits lev::kErrPivotWait,
+// lev::kErrSolveWait).
+int32_t* state_err(const StateView& v) { return reinterpret_cast<int32_t*>(v.header + 5); }
 
 // ---- workspace plans -------------------------------------------------------------
 struct SketchBufs {
@@ -255,6 +259,7 @@ RankBufs carve_rank(Carver& c, int64_t m, int64_t d) {
   b.pc.piv = c.take<int32_t>((size_t)d);
   b.pc.flags = c.take<int32_t>(64);
   b.pc.r00 = c.take<double>(1);
+  b.pc.err = nullptr;
   return b;
 }
 
@@ -551,8 +556,12 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   void* Zpack = c.take<char>(lev::pack_z_bytes(variant, d, d));
   StateView sv = carve_state(state_ws, d, m, d);
   int64_t* rank = sv.header + 4;
+  int32_t* err = state_err(sv);
+  rb.pc.err = err;
+  eb.rb2.pc.err = err;
   const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
   LEV_HIP(mark_phase(0, s));
+  LEV_HIP(lev::launch_fill_zero(sv.header + 5, sizeof(int64_t), s));
   LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, nullptr, s));
   LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, s));
   LEV_HIP(mark_phase(4, s));
@@ -568,7 +577,7 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   LEV_HIP(lev::launch_pivchol_finalize(d, eb.rb2.pc, eb.rank2, eb.perm2, eb.R2, s));
   LEV_HIP(lev::launch_compose_perm(d, sv.perm, eb.perm2, eb.permc, s));
   LEV_HIP(lev::launch_identity(d, eb.I, s));
-  LEV_HIP(lev::launch_form_z(variant, d, d, eb.R2, eb.rank2, eb.permc, eb.I, sv.Z64, Zpack, s));
+  LEV_HIP(lev::launch_form_z(variant, d, d, eb.R2, eb.rank2, eb.permc, eb.I, sv.Z64, Zpack, err, s));
   LEV_HIP(mark_phase(5, s));
   if (n > 0) {
     LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, d, Zpack, eb.rank2, theta_out, s));
@@ -601,13 +610,16 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   void* Zpack = c.take<char>(lev::pack_z_bytes(variant, d, k));
   StateView sv = carve_state(state_out != nullptr ? state_out : state_ws, d, m, k);
   int64_t* rank = sv.header + 4;
+  int32_t* err = state_err(sv);
+  rb.pc.err = err;
 
   const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
   LEV_HIP(mark_phase(0, stream));
+  LEV_HIP(lev::launch_fill_zero(sv.header + 5, sizeof(int64_t), stream));
   LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, Gk, stream));
   LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, stream));
   LEV_HIP(mark_phase(4, stream));
-  LEV_HIP(lev::launch_form_z(variant, d, k, sv.R, rank, sv.perm, Gk, sv.Z64, Zpack, stream));
+  LEV_HIP(lev::launch_form_z(variant, d, k, sv.R, rank, sv.perm, Gk, sv.Z64, Zpack, err, stream));
   LEV_HIP(mark_phase(5, stream));
   if (n > 0 && A->format == LEV_CSR) {
     LEV_HIP(lev::launch_rownorm_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, Zpack, theta_out,
@@ -659,7 +671,7 @@ lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const
   LEV_HIP(lev::launch_gather_zbar(d, k, sv.perm, rank, b.C64, b.Zbar, s));
   LEV_TRY(gemm(d, d, k, b.Zbar, k, 1, sv.Z64, 1, k, T1, b.gemm_partial, s));          // Zbar Z^T
   LEV_HIP(lev::launch_identity(d, I, s));
-  LEV_HIP(lev::launch_trsm_z(d, d, sv.R, rank, I, Rinv, s));                           // R11^{-1}
+  LEV_HIP(lev::launch_trsm_z(d, d, sv.R, rank, I, Rinv, state_err(sv), s));           // R11^{-1}
   LEV_TRY(gemm(d, d, d, Rinv, 1, d, T1, d, 1, X, b.gemm_partial, s));                 // R11^{-T} T1
   LEV_HIP(lev::launch_neg_triu(d, X, s));                                              // Rbar
   double* M1 = I;
@@ -685,6 +697,16 @@ lev_status lev_debug_hash(uint64_t seed, int64_t n, int64_t r_cs, int64_t* h_out
   if (n > 0 && (h_out == nullptr || s_out == nullptr)) return fail(LEV_ERR_ARG, "null output");
   const lev::SeedDraws dr = lev::derive_draws(seed, n, r_cs);
   LEV_HIP(lev::launch_hash_rows(dr.hash, h_out, s_out, stream));
+  return LEV_OK;
+}
+
+lev_status lev_hash_params(uint64_t seed, int64_t n, int64_t r_cs, uint64_t* out) {
+  if (n < 0 || n > kMaxRows || r_cs < 1 || r_cs > kMaxRows) return fail(LEV_ERR_SHAPE, "bad n or r_cs");
+  if (out == nullptr) return fail(LEV_ERR_ARG, "out is null");
+  const lev::SeedDraws dr = lev::derive_draws(seed, n, r_cs);
+  const lev::HashParams& h = dr.hash;
+  const uint64_t v[7] = {h.P, h.a, h.c, h.c0, h.c1, h.c2, h.c3};
+  for (int i = 0; i < 7; ++i) out[i] = v[i];
   return LEV_OK;
 }
 

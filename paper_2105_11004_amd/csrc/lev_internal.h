@@ -91,7 +91,15 @@ struct PivCholState {
   int32_t* piv;        // d: pivot at position J
   int32_t* flags;      // [0] = done, [1] = pivots so far, [2..] scratch
   double* r00;         // 1
+  int32_t* err;        // optional (may be null): bit kErrPivotWait is set when a bounded wait ran out
 };
+
+// Bits of the device error word (state header, slot 5).  A bounded wait
+// inside a kernel that runs out sets its bit and ends that kernel's work
+// early, so the results of the call are then meaningless; the word is
+// cleared at the start of every estimate.
+constexpr int32_t kErrPivotWait = 1;
+constexpr int32_t kErrSolveWait = 2;
 hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState& st, int64_t* rank_out,
                           double* gemm_partial, hipStream_t s);
 // Writes perm (int32[d], unpivoted columns ascending after the rank) and
@@ -103,8 +111,9 @@ hipError_t launch_pivchol_finalize(int64_t d, const PivCholState& st, const int6
 // the device.  Z64 is d x k (rows >= r zeroed).  For d > 256 the solve runs
 // over diagonal blocks of 256 and G's rows above the last block are
 // overwritten (they carry the updated right-hand side).
+// err (may be null): bit kErrSolveWait is set if a bounded wait runs out.
 hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, double* G, double* Z64,
-                         hipStream_t s);
+                         int32_t* err, hipStream_t s);
 
 // Prepares the operand of pass 2: Z_full (d x k, rows indexed by original
 // column, zero off K) converted to the pass-2 compute type and laid out for
@@ -119,7 +128,8 @@ size_t pack_z_bytes(int variant, int64_t d, int64_t k);
 // trsm + pack in one launch where it fits (d <= 256, k <= 64), else the
 // launches above (Gk overwritten as there).  Zpack as for launch_pack_z.
 hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, const int64_t* rank,
-                         const int32_t* perm, double* Gk, double* Z64, void* Zpack, hipStream_t s);
+                         const int32_t* perm, double* Gk, double* Z64, void* Zpack, int32_t* err,
+                         hipStream_t s);
 size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k);
 
 // Pass 2, dense: theta[i] = || A[i, :] Z_full ||^2.

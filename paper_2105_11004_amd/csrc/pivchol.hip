@@ -178,7 +178,10 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
 // hardware estimate plus two Newton steps.  No global memory is read inside
 // the loop.
 constexpr int kSmallD = 256;
-constexpr int kSpinLimit = 1 << 22;  // bound on the pivot wait (never reached: see the wait)
+// Bound on the pivot wait.  The wait ends by construction (see the loop);
+// if the bound is ever reached the wave sets kErrPivotWait in st.err and
+// stops, so the call's results are flagged instead of silently wrong.
+constexpr int kSpinLimit = 1 << 22;
 constexpr int kBandR = 64, kBandC = 64;
 constexpr int kLvec = 256;  // >= 64 * ceil(256 / 64)
 
@@ -274,19 +277,28 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
     __syncthreads();  // the first pivot is posted
     for (int J = 0; J < d; ++J) {
       // pivot J: posted by the diagonal wave once every wave has passed the
-      // barrier of step J - 1, which this wave has, so the wait ends
-      // The message is read right behind the counter, in one round trip:
-      // LDS serves a wave's accesses in order, and the diagonal wave's
-      // message store completes before its counter store, so a counter that
-      // shows pivot J comes with message J.
-      uint64_t m0, m1;
+      // barrier of step J - 1, which this wave has, so the wait ends.
+      // The counter is read with acquire semantics and the diagonal wave
+      // stores it with release semantics after the message, so a counter
+      // that shows pivot J makes message J visible to the loads behind it.
+      uint64_t m0 = 0, m1 = 0;
+      bool timed_out = false;
       for (int spin = 0;; ++spin) {
-        const int seen = __hip_atomic_load(&posted, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int seen = __hip_atomic_load(&posted, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
         uint64_t* mp = reinterpret_cast<uint64_t*>(&msg[J & 1]);
         m0 = __hip_atomic_load(mp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         m1 = __hip_atomic_load(mp + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (seen > J || spin >= kSpinLimit) break;
+        if (seen > J) break;
+        if (spin >= kSpinLimit) {
+          timed_out = true;
+          break;
+        }
         __builtin_amdgcn_s_sleep(1);
+      }
+      if (timed_out) {
+        if (lane == 0 && st.err != nullptr)
+          __hip_atomic_fetch_or(st.err, kErrPivotWait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;  // this wave leaves the factorization; the call is flagged
       }
       const int p = __builtin_amdgcn_readfirstlane((int)(uint32_t)m1);
       const int ok = __builtin_amdgcn_readfirstlane((int)(uint32_t)(m1 >> 32));

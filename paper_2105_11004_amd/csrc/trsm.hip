@@ -40,7 +40,12 @@ constexpr int kTrsmR = 256;
 constexpr int kDiagDoubles = (kTrsmR / 16) * 16 * 16;
 constexpr int kZallDoubles = (kTrsmR / 16) * 4 * 4 * 64;  // every Z_b, KB <= 4
 constexpr int kSolveLdsDoubles = kZallDoubles;            // 128 KB; the diagonal blocks first
-constexpr int kSpinLimit = 1 << 22;  // bound on a flag wait (never reached: blocks only wait on later ones)
+// Bound on a flag wait.  The waits end by construction (a block only waits
+// on later ones, whose owners never wait on it); if the bound is ever
+// reached the wave sets kErrSolveWait in the error word, stops updating and
+// publishes what it has, so no other wave waits on it and the call is
+// flagged instead of silently wrong.
+constexpr int kSpinLimit = 1 << 22;
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 // Pass-2 operand layouts (see rownorm.hip).  For chunk t of the contraction
@@ -82,7 +87,7 @@ __device__ __forceinline__ int zall_index(int j, int c) {
 template <int KB>
 __device__ __forceinline__ void blocked_solve(double* lds, int32_t* ready, int d, int k, int c0,
                                               const double* __restrict__ R, int r,
-                                              const double* __restrict__ G) {
+                                              const double* __restrict__ G, int32_t* err) {
   double* rdg = lds;   // prologue: [16][256], diagonal block b, then T_b; then the wave's scratch
   double* zall = lds;  // [16][4][KB][64]: Z_b in the B-operand order
   const int lane = threadIdx.x & 63;
@@ -205,10 +210,20 @@ __device__ __forceinline__ void blocked_solve(double* lds, int32_t* ready, int d
       for (int q = 0; q < 4; ++q) ma[q] = -rb[(lane & 15) * 16 + 4 * (lane >> 4) + q];
       // the next owner's last wait is the serial chain
       if (b == w + 1) __builtin_amdgcn_s_setprio(3);
-      for (int spin = 0; __hip_atomic_load(ready + b, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0 &&
-                         spin < kSpinLimit;
-           ++spin)
+      bool timed_out = false;
+      for (int spin = 0; __hip_atomic_load(ready + b, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == 0;
+           ++spin) {
+        if (spin >= kSpinLimit) {
+          timed_out = true;
+          break;
+        }
         __builtin_amdgcn_s_sleep(1);
+      }
+      if (timed_out) {
+        if (lane == 0 && err != nullptr)
+          __hip_atomic_fetch_or(err, kErrSolveWait, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
       const double* zb = zall + b * (4 * KB * 64) + (lane >> 4) * KB * 64 + (lane & 15);
 #pragma unroll
       for (int q = 0; q < 4; ++q)
@@ -305,13 +320,13 @@ __global__ __launch_bounds__(1024) void trsm_blocked_kernel(int64_t d, int64_t k
                                                             const double* __restrict__ R,
                                                             const int64_t* __restrict__ rank,
                                                             const double* __restrict__ G,
-                                                            double* __restrict__ Z64) {
+                                                            double* __restrict__ Z64, int32_t* err) {
   __shared__ double lds[kSolveLdsDoubles];
   __shared__ int32_t ready[16];
   const int c0 = 64 * (int)blockIdx.y;
   const int rows = (int)std::min<int64_t>(kTrsmR, d - j0);
   const int r = (int)std::min<int64_t>(rows, std::max<int64_t>(0, *rank - j0));
-  blocked_solve<4>(lds, ready, (int)d, (int)k, c0, R + j0 * d + j0, r, G + j0 * k);
+  blocked_solve<4>(lds, ready, (int)d, (int)k, c0, R + j0 * d + j0, r, G + j0 * k, err);
   store_z64<4>(lds, rows, (int)k, c0, r, Z64 + j0 * k);
 }
 
@@ -400,14 +415,15 @@ __global__ __launch_bounds__(1024) void form_z_kernel(int64_t d, int64_t k, cons
                                                       const int64_t* __restrict__ rank,
                                                       const int32_t* __restrict__ perm,
                                                       const double* __restrict__ Gk, double* __restrict__ Z64,
-                                                      void* __restrict__ Zpack, int64_t nt, int64_t cbn) {
+                                                      void* __restrict__ Zpack, int64_t nt, int64_t cbn,
+                                                      int32_t* err) {
   __shared__ double lds[kSolveLdsDoubles];
   __shared__ int32_t ready[16];
   __shared__ int32_t inv[kTrsmR];
   using F = PackForm<VARIANT>;
   const int r = (int)*rank, di = (int)d;
   for (int j = threadIdx.x; j < di; j += 1024) inv[perm[j]] = j < r ? j : -1;
-  blocked_solve<KB>(lds, ready, di, (int)k, 0, R, r, Gk);  // ends with a barrier: inv is visible
+  blocked_solve<KB>(lds, ready, di, (int)k, 0, R, r, Gk, err);  // ends with a barrier: inv is visible
   store_z64<KB>(lds, di, (int)k, 0, r, Z64);
   const int total = F::kRowMajor ? di * 64 : (int)(nt * cbn * 64 * F::EL);
   store_operand<VARIANT, KB>(lds, inv, di, total, Zpack);
@@ -416,7 +432,7 @@ __global__ __launch_bounds__(1024) void form_z_kernel(int64_t d, int64_t k, cons
 }  // namespace
 
 hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, double* G, double* Z64,
-                         hipStream_t s) {
+                         int32_t* err, hipStream_t s) {
   if (d <= 0 || k <= 0) return hipSuccess;
   // Blocked back substitution over diagonal blocks of 256 pivot positions,
   // last block first: solve block q, then subtract its contribution
@@ -426,7 +442,7 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
   // rank changes nothing in the rows that are solved.
   const dim3 grid(1, (unsigned)((k + 63) / 64));
   for (int64_t j0 = ((d - 1) / kTrsmR) * kTrsmR; j0 >= 0; j0 -= kTrsmR) {
-    trsm_blocked_kernel<<<grid, 1024, 0, s>>>(d, k, j0, R, rank, G, Z64);
+    trsm_blocked_kernel<<<grid, 1024, 0, s>>>(d, k, j0, R, rank, G, Z64, err);
     if (j0 > 0) {
       const int64_t kb = std::min<int64_t>(kTrsmR, d - j0);
       hipError_t e = launch_dgemm(j0, k, kb, -1.0, R + j0, d, 1, Z64 + j0 * k, k, 1, 1.0, G, k, 1, nullptr,
@@ -500,10 +516,11 @@ hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm,
 }
 
 hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, const int64_t* rank,
-                         const int32_t* perm, double* Gk, double* Z64, void* Zpack, hipStream_t s) {
+                         const int32_t* perm, double* Gk, double* Z64, void* Zpack, int32_t* err,
+                         hipStream_t s) {
   if (variant < 0 || variant > 6) return hipErrorInvalidValue;
   if (d > kTrsmR || k > 64) {
-    hipError_t e = launch_trsm_z(d, k, R, rank, Gk, Z64, s);
+    hipError_t e = launch_trsm_z(d, k, R, rank, Gk, Z64, err, s);
     if (e != hipSuccess) return e;
     return launch_pack_z(variant, d, k, perm, rank, Z64, Zpack, s);
   }
@@ -513,10 +530,10 @@ hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, con
 #define LEV_FZ(V)                                                                                      \
   case V:                                                                                              \
     switch (cbn) {                                                                                     \
-      case 1: form_z_kernel<V, 1><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn); break; \
-      case 2: form_z_kernel<V, 2><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn); break; \
-      case 3: form_z_kernel<V, 3><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn); break; \
-      default: form_z_kernel<V, 4><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn); break; \
+      case 1: form_z_kernel<V, 1><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn, err); break; \
+      case 2: form_z_kernel<V, 2><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn, err); break; \
+      case 3: form_z_kernel<V, 3><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn, err); break; \
+      default: form_z_kernel<V, 4><<<1, 1024, 0, s>>>(d, k, R, rank, perm, Gk, Z64, Zpack, nt, cbn, err); break; \
     }                                                                                                  \
     break;
   switch (variant) {

@@ -149,3 +149,19 @@ def test_other_calls_validate(lib):
     assert lib.lev_debug_hash(1, -5, 8, vp(8), vp(8), None) == -2
     assert lib.lev_debug_gaussian(1, 2, 4, 4, vp(8), None) == -1
     assert lib.lev_debug_buckets(1, 10, 0, vp(8), vp(8), None) == -2
+
+
+def test_hash_params_match_known_primes_and_oracle(lib):
+    """liblev's host-side seed expansion (its own next-prime search and
+    SplitMix64 words) gives the primes fixed by number theory and the same
+    hash and sign coefficients as the oracle."""
+    from oracle import conventions as C
+    from paper_2105_11004_amd import api
+    from test_oracle_pins import PRIME_KATS
+    for n, p in PRIME_KATS:
+        assert api.lev_hash_params(1, n, 8)["P"] == p
+    for seed, n, r in [(3, 5000, 97), (2 ** 64 - 3, 100003, 4096), (0, 17, 1), (2002, (1 << 20) + 7, 4096)]:
+        hp = api.lev_hash_params(seed, n, r)
+        rnd = C.derive(seed, n, r)
+        assert (hp["P"], hp["a"], hp["c"]) == (rnd.P, rnd.a, rnd.c)
+        assert (hp["c0"], hp["c1"], hp["c2"], hp["c3"]) == tuple(rnd.sign_coef)

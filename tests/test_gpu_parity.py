@@ -153,6 +153,7 @@ def test_estimate_fp64_dense_gaussian(gpu):
     A = W.dense_gaussian(n, d, 1001, dtype=torch.float64)
     theta, state = api.lev_estimate(A.to(gpu), seed, r_cs, m, k, zeta, return_state=True)
     o = _oracle_theta(A.numpy(), seed, r_cs, m, k, zeta)
+    assert int(state.error.item()) == 0
     assert int(state.rank.item()) == o.rank == d
     np.testing.assert_array_equal(state.perm.cpu().numpy()[:d], o.perm[:d])
     rel = _rel(theta.cpu().numpy(), o.theta)
@@ -167,6 +168,7 @@ def test_estimate_fp32_low_rank_coherent(gpu, n, precision):
     A = W.low_rank_coherent(n, d, rank, 1002)
     theta, state = api.lev_estimate(A.to(gpu), seed, r_cs, m, k, zeta, precision=precision, return_state=True)
     o = _oracle_theta(A.numpy().astype(np.float64), seed, r_cs, m, k, zeta)
+    assert int(state.error.item()) == 0
     r = int(state.rank.item())
     assert r == o.rank == rank
     np.testing.assert_array_equal(state.perm.cpu().numpy()[:r], o.perm[:r])
@@ -191,6 +193,7 @@ def test_estimate_fp64_wide_blocked_solve(gpu, n, d, rank, k):
     buf[:, :d] = torch.from_numpy(A).to(gpu)
     theta, state = api.lev_estimate(buf[:, :d], seed, r_cs, m, k, zeta, return_state=True)
     o = _oracle_theta(A, seed, r_cs, m, k, zeta)
+    assert int(state.error.item()) == 0  # no bounded wait of pivoting or solve ran out
     r = int(state.rank.item())
     assert r == o.rank == rank
     np.testing.assert_array_equal(state.perm.cpu().numpy()[:r], o.perm[:r])

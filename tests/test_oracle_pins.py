@@ -63,6 +63,20 @@ def test_gaussian_scaling_and_determinism():
 
 
 # ---------------------------------------------------------------- hashing
+# Smallest prime >= n for values fixed by number theory: 4099 and 65537
+# (the Fermat prime F4), and the first primes above 2^20, 2^22 and 2^23
+# (2^20 + 7, 2^22 + 15, 2^23 + 9; tables of primes just above powers of two).
+# The last case starts between 2^23 and the next prime.
+PRIME_KATS = [(4096, 4099), (65536, 65537), (1 << 20, 1048583), (1 << 22, 4194319), (1 << 23, 8388617),
+              ((1 << 23) + 5, 8388617), (2, 2), (0, 2), (1, 2), (3, 3), (4, 5), (100, 101)]
+
+
+def test_prime_modulus_known_answers():
+    for n, p in PRIME_KATS:
+        assert C.next_prime(max(n, 2)) == p
+        assert C.derive(1, n, 8).P == p
+
+
 def test_prime_modulus():
     for n in [0, 1, 2, 3, 4, 100, 4096, 65536, 1 << 20, (1 << 23) + 5]:
         rnd = C.derive(1, n, 8)
