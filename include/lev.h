@@ -175,6 +175,25 @@ lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta
 lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_out,
                         void* state_out, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* lev_estimate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and the same kernels, with the workspace taken from a
+ * static device array of lev_noalloc_max_bytes() bytes (64 MiB) inside the
+ * library instead of a caller buffer, and no state output.  The call itself
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine);
+ * the array is part of the library's device code and each GPU the call runs
+ * on holds its own copy from the first call on that GPU until the process
+ * ends.  The current device must be the device of A, theta_out and stream.
+ *  Returns LEV_ERR_WORKSPACE, before touching the device, when
+ *  lev_workspace_size(A, p, LEV_WS_ESTIMATE) exceeds the array (e.g. the
+ *  Gaussian G_m of an m x r_cs sketch above about 5e6 elements).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (on different streams, or from different host threads with different
+ * streams) race and give wrong results; calls on one stream are ordered and
+ * safe.  Each call clears what it needs cleared. */
+size_t lev_noalloc_max_bytes(void);
+lev_status lev_estimate_noalloc(const lev_matrix* A, const lev_params* p, void* theta_out, hipStream_t stream);
+
 /* Adjoint of f(A) = sum_i w_i theta~_i with the sketch (S, G_m, G_k), the
  * pivots K and the rank r held fixed (the paper differentiates nothing; this
  * is the reverse of Algorithms 3, 4 and 8 step by step):

@@ -31,7 +31,7 @@ WS_SKETCH, WS_ESTIMATE, WS_BACKWARD = 0, 2, 3
 EXPORTED = ["lev_workspace_size", "lev_rank_workspace_size", "lev_state_size", "lev_sketch",
             "lev_rank_estimate", "lev_estimate", "lev_estimate_backward", "lev_debug_hash",
             "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params", "lev_set_phase_events",
-            "lev_status_string", "lev_last_error"]
+            "lev_status_string", "lev_last_error", "lev_noalloc_max_bytes", "lev_estimate_noalloc"]
 LEV_PHASES = 7
 # phase 0 holds no kernels (the Gaussian draws run inside pass 1): its time is
 # the cost of two back-to-back events
@@ -86,6 +86,9 @@ def load_library(path: Path | None = None):
     lib.lev_debug_buckets.argtypes = [c_uint64, c_int64, c_int64, vp, vp, vp]
     lib.lev_debug_gaussian.argtypes = [c_uint64, c_int, c_int64, c_int64, vp, vp]
     lib.lev_hash_params.argtypes = [c_uint64, c_int64, c_int64, POINTER(c_uint64)]
+    lib.lev_noalloc_max_bytes.argtypes = []
+    lib.lev_noalloc_max_bytes.restype = c_size_t
+    lib.lev_estimate_noalloc.argtypes = [POINTER(LevMatrix), POINTER(LevParams), vp, vp]
     lib.lev_set_phase_events.argtypes = [vp, c_int]
     lib.lev_set_phase_events.restype = c_int
     lib.lev_status_string.argtypes = [c_int]
@@ -93,7 +96,8 @@ def load_library(path: Path | None = None):
     lib.lev_last_error.argtypes = []
     lib.lev_last_error.restype = ctypes.c_char_p
     for name in ("lev_sketch", "lev_rank_estimate", "lev_estimate", "lev_estimate_backward",
-                 "lev_debug_hash", "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params"):
+                 "lev_debug_hash", "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params",
+                 "lev_estimate_noalloc"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -325,6 +329,21 @@ def lev_estimate(A, seed: int, r_cs: int, m: int, k: int, zeta: float,
     _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), _ptr(theta),
                             _ptr(state.blob) if state is not None else None, ws, nbytes, _stream(dev)))
     return (theta, state) if return_state else theta
+
+
+def lev_estimate_noalloc(A, seed: int, r_cs: int, m: int, k: int, zeta: float, precision: str = "native",
+                         theta: torch.Tensor | None = None):
+    """lev_estimate through the entry point that allocates no device memory
+    (its workspace is the library's static scratch array).  theta may be a
+    preallocated output; it is allocated here only when it is None."""
+    lib = load_library()
+    A = _as_csr(A)
+    dev, (n, _), dt = _device(A), _shape(A), _dtype(A)
+    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision)
+    if theta is None:
+        theta = torch.empty(n, dtype=torch.float64 if dt == torch.float64 else torch.float32, device=dev)
+    _check(lib.lev_estimate_noalloc(ctypes.byref(mat), ctypes.byref(par), _ptr(theta), _stream(dev)))
+    return theta
 
 
 class EstimatePlan:

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "lev_internal.h"
@@ -17,6 +18,17 @@
 namespace {
 
 thread_local std::string g_last_error;
+
+// Workspace of lev_estimate_noalloc: one copy per GPU, held from the first
+// call on that GPU until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol); it uses the device address that hipGetSymbolAddress returns for
+// the current device, cached per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
 thread_local hipEvent_t g_phase_events[LEV_PHASES];
 thread_local bool g_phase_on = false;
 
@@ -689,6 +701,37 @@ lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const
   // Abar = 2 diag(w) A Z_full Z_full^T + S^T H_full
   LEV_HIP(lev::launch_bwd_grad(dt, A->values, n, d, A->ld, k, w, b.Zpack, b.Hf, dr.hash, gradA_out, A->ld, s));
   return LEV_OK;
+}
+
+size_t lev_noalloc_max_bytes(void) { return kScratchBytes; }
+
+lev_status lev_estimate_noalloc(const lev_matrix* A, const lev_params* p, void* theta_out, hipStream_t stream) {
+  // every check that needs no device comes first: a request beyond the
+  // scratch array is refused before the device is touched
+  LEV_TRY(check_matrix(A));
+  LEV_TRY(check_params(A, p));
+  const size_t need = lev_workspace_size(A, p, LEV_WS_ESTIMATE);
+  if (need > kScratchBytes)
+    return fail(LEV_ERR_WORKSPACE,
+                "lev_estimate_noalloc: this problem needs %zu bytes of workspace, more than the %zu-byte "
+                "static scratch; use lev_estimate with a caller-provided workspace",
+                need, kScratchBytes);
+  int dev = 0;
+  LEV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LEV_ERR_NOT_SUPPORTED, "device index %d out of range", dev);
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+      void* ptr = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || ptr == nullptr)
+        return fail(LEV_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+      g_scratch_ptr[dev] = ptr;
+    }
+    ws = g_scratch_ptr[dev];
+  }
+  return lev_estimate(A, p, theta_out, nullptr, ws, kScratchBytes, stream);
 }
 
 lev_status lev_debug_hash(uint64_t seed, int64_t n, int64_t r_cs, int64_t* h_out, int8_t* s_out,
