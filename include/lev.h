@@ -99,7 +99,10 @@ typedef struct {
  *  k     -- columns of the JL Gaussian Pi_2 (Algorithm 8's r_2).  1..64.
  *  zeta  -- rank tolerance: the revealed rank is r = #{ j : R_jj > zeta R_00 }
  *           on the column-pivoted factor of the sketch (the cutoff rule of
- *           Section 7).  0 <= zeta < 1.
+ *           Section 7).  Supported: 1e-10 <= zeta < 1 (1e-10 is the FP64
+ *           cutoff of the paper's experiments); smaller values give
+ *           LEV_ERR_NOT_SUPPORTED, values outside [0, 1) LEV_ERR_ARG.
+ *           (lev_sketch ignores zeta.)
  *  az_precision -- LEV_AZ_* above.
  *  exact -- 0: Algorithm 10 (LS-HRN-approx, the JL estimate with k
  *           columns).  1: Algorithm 7 (LS-HRN-exact): the same columns K
@@ -148,9 +151,18 @@ lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out,
  *              upper-triangular factor (R_out[j][t] for t >= j, zeros left of
  *              the diagonal); rows j >= r are zero.
  *  rank_out -- device int64 scalar r.
- * The factor is obtained as the pivoted Cholesky factor of A~^T A~ (equal to
- * the QRCP factor with positive diagonal in exact arithmetic); see the
- * design notes for its accuracy range.  Requires d <= 1024 and d <= m. */
+ * Computed without Householder reflections, from the Gram matrix and
+ * Cholesky QR: for zeta >= 1e-5 the pivoted Cholesky of A~^T A~ alone (its
+ * factor is the QRCP factor with positive diagonal; in floating point it
+ * decides residual norms down to about sqrt(u) R_00 ~ 1.5e-8 R_00 and its
+ * R carries relative error about u kappa(R11)^2).  For 1e-10 <= zeta < 1e-5
+ * a refinement: the Gram pivoting down to 1e-5 R_00, those columns
+ * orthonormalised by Cholesky QR twice and projected out of the others
+ * twice, pivoting again on the Gram of that explicit residual (cutoff
+ * zeta R_00), Cholesky QR twice of the new columns, and R's rows as Q^T A~;
+ * rank, pivots (off near-ties) and R (to rounding, relative error about
+ * u kappa(R11)) are those of Householder QRCP on A~.  zeta < 1e-10 gives
+ * LEV_ERR_NOT_SUPPORTED.  Requires d <= 1024 and d <= m. */
 lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta,
                              int32_t* perm_out, double* R_out, int64_t* rank_out,
                              void* ws, size_t ws_bytes, hipStream_t stream);

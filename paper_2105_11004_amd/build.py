@@ -24,8 +24,8 @@ BUILD_DIR = PKG / "_build"
 LIB = PKG / "liblev.so"
 ARCH = "gfx950"
 
-SOURCES = ["sketch.hip", "gauss.hip", "gemm.hip", "pivchol.hip", "trsm.hip", "rownorm.hip", "rownorm_csr.hip",
-           "bwd.hip", "lev_api.cpp"]
+SOURCES = ["sketch.hip", "gauss.hip", "gemm.hip", "pivchol.hip", "rrqr.hip", "trsm.hip", "rownorm.hip",
+           "rownorm_csr.hip", "bwd.hip", "lev_api.cpp"]
 
 COMMON_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

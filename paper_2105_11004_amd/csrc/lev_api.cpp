@@ -100,6 +100,13 @@ uint64_t modinv(uint64_t a, uint64_t p) {
 }
 
 constexpr uint64_t kP61 = (1ull << 61) - 1;
+// Rank cutoffs.  The Gram pivoting alone decides ranks reliably only while
+// R_jj / R_00 stays far above sqrt(u) ~ 1.5e-8 (the Gram is rounded at
+// u R_00^2): it is used alone for zeta >= kZetaGram.  Below that the refined
+// path (rrqr.hip) resolves cutoffs down to kZetaMin, the FP64 cutoff of the
+// paper's experiments; smaller cutoffs are refused.
+constexpr double kZetaGram = 1e-5;
+constexpr double kZetaMin = 1e-10;
 constexpr int64_t kMaxRows = (1ll << 31) - 2;  // row ids + sign bit in 32 bits
 constexpr int64_t kMaxD = 1024;
 constexpr int64_t kMaxK = 64;
@@ -177,13 +184,16 @@ lev_status check_matrix(const lev_matrix* A) {
   return LEV_OK;
 }
 
-lev_status check_params(const lev_matrix* A, const lev_params* p) {
+// uses_zeta: false for lev_sketch, which takes no rank decision.
+lev_status check_params(const lev_matrix* A, const lev_params* p, bool uses_zeta = true) {
   if (p == nullptr) return fail(LEV_ERR_ARG, "params is null");
   if (p->r_cs < 1 || p->r_cs > kMaxRows) return fail(LEV_ERR_ARG, "r_cs = %lld out of range", (long long)p->r_cs);
   if (p->m < A->d) return fail(LEV_ERR_SHAPE, "m = %lld < d = %lld", (long long)p->m, (long long)A->d);
   if (p->m > (1ll << 24)) return fail(LEV_ERR_SHAPE, "m too large");
   if (p->k < 1 || p->k > kMaxK) return fail(LEV_ERR_ARG, "k = %lld outside [1, 64]", (long long)p->k);
   if (!(p->zeta >= 0.0 && p->zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
+  if (uses_zeta && p->zeta < kZetaMin)
+    return fail(LEV_ERR_NOT_SUPPORTED, "zeta = %g is below the smallest supported rank cutoff %g", p->zeta, kZetaMin);
   if (az_variant(A->format, A->dtype, p->az_precision) < 0)
     return fail(LEV_ERR_ARG, "az_precision %d not valid for dtype %d", p->az_precision, A->dtype);
   if (p->exact != 0 && p->exact != 1) return fail(LEV_ERR_ARG, "exact must be 0 or 1");
@@ -275,6 +285,50 @@ RankBufs carve_rank(Carver& c, int64_t m, int64_t d) {
   return b;
 }
 
+// Buffers of the refined rank-revealing path (zeta < kZetaGram).
+struct RefineBufs {
+  double *X1, *X2, *Qa, *Q;                        // m x d
+  double *I, *Rinv, *Bq, *W1, *W2, *Rtop, *Rbot;  // d x d
+  double *R1, *Rf, *R2;                            // d x d
+  int32_t *perm1, *permf, *perm2;                  // d
+  int64_t *r1, *rf, *r2;                           // device scalars
+  lev::PivCholState stf, st2;
+  double* partial;
+};
+
+lev::PivCholState carve_pivchol_state(Carver& c, int64_t d) {
+  lev::PivCholState st;
+  st.diag = c.take<double>((size_t)d);
+  st.Rrows = c.take<double>((size_t)(d * d));
+  st.piv = c.take<int32_t>((size_t)d);
+  st.flags = c.take<int32_t>(64);
+  st.r00 = c.take<double>(1);
+  st.err = nullptr;
+  return st;
+}
+
+RefineBufs carve_refine(Carver& c, int64_t m, int64_t d) {
+  RefineBufs b;
+  double** md[] = {&b.X1, &b.X2, &b.Qa, &b.Q};
+  for (double** p : md) *p = c.take<double>((size_t)(m * d));
+  double** dd[] = {&b.I, &b.Rinv, &b.Bq, &b.W1, &b.W2, &b.Rtop, &b.Rbot, &b.R1, &b.Rf, &b.R2};
+  for (double** p : dd) *p = c.take<double>((size_t)(d * d));
+  b.perm1 = c.take<int32_t>((size_t)d);
+  b.permf = c.take<int32_t>((size_t)d);
+  b.perm2 = c.take<int32_t>((size_t)d);
+  b.r1 = c.take<int64_t>(1);
+  b.rf = c.take<int64_t>(1);
+  b.r2 = c.take<int64_t>(1);
+  b.stf = carve_pivchol_state(c, d);
+  b.st2 = carve_pivchol_state(c, d);
+  size_t mx = 0;
+  const int64_t shapes[2][3] = {{m, d, d}, {d, d, m}};
+  for (const auto& sh : shapes)
+    mx = std::max(mx, lev::dgemm_partial_elems(sh[0], sh[1], lev::dgemm_choose_splits(sh[0], sh[1], sh[2])));
+  b.partial = c.take<double>(mx);
+  return b;
+}
+
 // Gk (d x k, may be null): the JL Gaussian, drawn alongside G_m.
 lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::SeedDraws& dr,
                           const SketchBufs& b, double* SA, double* At, double* Gk, hipStream_t s) {
@@ -302,16 +356,83 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
   return LEV_OK;
 }
 
+// C = op(A) op(B) (beta = 0) or C += alpha op(A) op(B) (beta = 1) with the
+// split the shape calls for; strides as in launch_dgemm.
+lev_status gemm_ab(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sai, int64_t sak,
+                   const double* B, int64_t sbk, int64_t sbj, double beta, double* C, double* partial,
+                   hipStream_t s) {
+  const int sp = lev::dgemm_choose_splits(M, N, K);
+  return hip_check(lev::launch_dgemm(M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, N, sp, partial, nullptr, s),
+                   "dgemm");
+}
+
+// Pivoted Cholesky of B (d x d, overwritten) into st, then perm / R / rank.
+lev_status pivchol_into(double* B, int64_t d, double zeta, const lev::PivCholState& st, int64_t* rank,
+                        int32_t* perm, double* R, double* partial, hipStream_t s, int fixed = 0,
+                        const double* ref_r00 = nullptr) {
+  // the panel path (d > 256) tracks progress in flags; the single-workgroup
+  // path does not read them
+  if (d > 256) LEV_HIP(lev::launch_fill_zero(st.flags, 64 * sizeof(int32_t), s));
+  LEV_HIP(lev::launch_pivchol(B, d, zeta, st, rank, partial, s, fixed, ref_r00));
+  LEV_HIP(lev::launch_pivchol_finalize(d, st, rank, perm, R, s));
+  return LEV_OK;
+}
+
+// Q (m x d) = an orthonormal basis of the first r columns of X (the other
+// columns of X and Q zero) by Cholesky QR twice, starting from the Cholesky
+// factor Rc of X^T X that the pivoting already produced (rows < r): Qa =
+// X Rc^{-1}, then Qa^T Qa = Rf^T Rf (plain Cholesky, fixed order) and Q =
+// Qa Rf^{-1}.  One pass leaves Qa^T Qa - I at about u kappa^2; the second
+// brings it to rounding.
+lev_status cholqr2(int64_t m, int64_t d, const double* X, const double* Rc, const int64_t* r, RefineBufs& b,
+                   double* Q, int32_t* err, hipStream_t s) {
+  LEV_HIP(lev::launch_identity(d, b.I, s));
+  LEV_HIP(lev::launch_trsm_z(d, d, Rc, r, b.I, b.Rinv, err, s));  // Rc11^{-1}, zero past r
+  LEV_TRY(gemm_ab(m, d, d, 1.0, X, d, 1, b.Rinv, d, 1, 0.0, b.Qa, b.partial, s));
+  LEV_TRY(gemm_ab(d, d, m, 1.0, b.Qa, 1, d, b.Qa, d, 1, 0.0, b.Bq, b.partial, s));
+  LEV_TRY(pivchol_into(b.Bq, d, 0.0, b.stf, b.rf, b.permf, b.Rf, b.partial, s, /*fixed=*/1));
+  LEV_HIP(lev::launch_identity(d, b.I, s));
+  LEV_HIP(lev::launch_trsm_z(d, d, b.Rf, b.rf, b.I, b.Rinv, err, s));
+  LEV_TRY(gemm_ab(m, d, d, 1.0, b.Qa, d, 1, b.Rinv, d, 1, 0.0, Q, b.partial, s));
+  return LEV_OK;
+}
+
+// Algorithm 4, steps 2-3: perm, R (sign-normalised, positive diagonal) and
+// the cutoff rank of the column-pivoted QR of A~.  For zeta >= kZetaGram the
+// pivoted Cholesky of the Gram decides alone; below it (rf != null) the
+// refined path of rrqr.hip: round 1 to kZetaGram, Cholesky QR twice of those
+// columns, the rest projected off them twice, round 2 on the residual's Gram
+// with the cutoff zeta * R_00 of round 1, Cholesky QR twice of the round-2
+// columns, R's rows as Q^T X.
 lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, const RankBufs& b,
-                        int32_t* perm, double* R, int64_t* rank, hipStream_t s) {
+                        int32_t* perm, double* R, int64_t* rank, hipStream_t s, RefineBufs* rf = nullptr) {
   // Gram B = A~^T A~ (d x d)
   const int splits = lev::dgemm_choose_splits(d, d, m);
   LEV_HIP(lev::launch_dgemm(d, d, m, 1.0, At, 1, d, At, d, 1, 0.0, b.B, d, splits, b.partial, nullptr, s));
-  // the panel path (d > 256) tracks progress in flags; the single-workgroup
-  // path does not read them
-  if (d > 256) LEV_HIP(lev::launch_fill_zero(b.pc.flags, 64 * sizeof(int32_t), s));
-  LEV_HIP(lev::launch_pivchol(b.B, d, zeta, b.pc, rank, b.partial, s));
-  LEV_HIP(lev::launch_pivchol_finalize(d, b.pc, rank, perm, R, s));
+  if (zeta >= kZetaGram || rf == nullptr) return pivchol_into(b.B, d, zeta, b.pc, rank, perm, R, b.partial, s);
+
+  RefineBufs& f = *rf;
+  int32_t* err = b.pc.err;
+  f.stf.err = err;
+  f.st2.err = err;
+  // round 1: the columns the Gram resolves
+  LEV_TRY(pivchol_into(b.B, d, kZetaGram, b.pc, f.r1, f.perm1, f.R1, b.partial, s));
+  LEV_HIP(lev::launch_gather_split(m, d, f.perm1, f.r1, At, f.X1, f.X2, s));
+  LEV_TRY(cholqr2(m, d, f.X1, f.R1, f.r1, f, f.Q, err, s));
+  // the rest projected off range(Q1) twice; R's rows 0..r1-1 = Q1^T X
+  LEV_TRY(gemm_ab(d, d, m, 1.0, f.Q, 1, d, f.X2, d, 1, 0.0, f.W1, f.partial, s));
+  LEV_TRY(gemm_ab(m, d, d, -1.0, f.Q, d, 1, f.W1, d, 1, 1.0, f.X2, f.partial, s));
+  LEV_TRY(gemm_ab(d, d, m, 1.0, f.Q, 1, d, f.X2, d, 1, 0.0, f.W2, f.partial, s));
+  LEV_TRY(gemm_ab(m, d, d, -1.0, f.Q, d, 1, f.W2, d, 1, 1.0, f.X2, f.partial, s));
+  LEV_TRY(gemm_ab(d, d, m, 1.0, f.Q, 1, d, f.X1, d, 1, 0.0, f.Rtop, f.partial, s));
+  LEV_HIP(lev::launch_add2(d * d, f.Rtop, f.W1, f.W2, s));
+  // round 2: pivoting on the residual's Gram, cutoff zeta * R_00 of round 1
+  LEV_TRY(gemm_ab(d, d, m, 1.0, f.X2, 1, d, f.X2, d, 1, 0.0, f.Bq, f.partial, s));
+  LEV_TRY(pivchol_into(f.Bq, d, zeta, f.st2, f.r2, f.perm2, f.R2, b.partial, s, 0, b.pc.r00));
+  LEV_HIP(lev::launch_gather_split(m, d, f.perm2, f.r2, f.X2, f.X1, nullptr, s));  // X1 <- the round-2 columns
+  LEV_TRY(cholqr2(m, d, f.X1, f.R2, f.r2, f, f.Q, err, s));
+  LEV_TRY(gemm_ab(d, d, m, 1.0, f.Q, 1, d, f.X2, d, 1, 0.0, f.Rbot, f.partial, s));
+  LEV_HIP(lev::launch_rrqr_assemble(d, f.perm1, f.r1, f.perm2, f.r2, f.Rtop, f.Rbot, perm, R, rank, s));
   return LEV_OK;
 }
 
@@ -481,11 +602,12 @@ size_t lev_rank_workspace_size(int64_t m, int64_t d) {
   if (d < 1 || d > kMaxD || m < d) return 0;
   Carver c(nullptr);
   carve_rank(c, m, d);
+  carve_refine(c, m, d);  // any zeta: the size does not depend on it
   return c.used;
 }
 
 size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
-  if (check_matrix(A) != LEV_OK || check_params(A, p) != LEV_OK) return 0;
+  if (check_matrix(A) != LEV_OK || check_params(A, p, which != LEV_WS_SKETCH) != LEV_OK) return 0;
   const int64_t d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
   Carver c(nullptr);
   if (which == LEV_WS_SKETCH) {
@@ -495,6 +617,7 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
   if (which == LEV_WS_ESTIMATE && p->exact) {
     carve_sketch(c, A->n, d, m, r_cs, true);
     carve_rank(c, m, d);
+    if (p->zeta < kZetaGram) carve_refine(c, m, d);
     c.take<char>(state_bytes(d, m, d));
     carve_exact(c, A, p);
     c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, d));
@@ -503,6 +626,7 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
   if (which == LEV_WS_ESTIMATE) {
     carve_sketch(c, A->n, d, m, r_cs, true);
     carve_rank(c, m, d);
+    if (p->zeta < kZetaGram) carve_refine(c, m, d);
     c.take<char>(state_bytes(d, m, k));
     c.take<double>((size_t)(d * k));  // G_k
     c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, k));
@@ -519,7 +643,7 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
 lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out, double* SA_out, void* ws,
                       size_t ws_bytes, hipStream_t stream) {
   LEV_TRY(check_matrix(A));
-  LEV_TRY(check_params(A, p));
+  LEV_TRY(check_params(A, p, /*uses_zeta=*/false));
   if (At_out == nullptr) return fail(LEV_ERR_ARG, "At_out is null");
   Carver sizing(nullptr);
   carve_sketch(sizing, A->n, A->d, p->m, p->r_cs, true);
@@ -539,11 +663,14 @@ lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta
   if (d < 1 || d > kMaxD) return fail(LEV_ERR_SHAPE, "d = %lld outside [1, 1024]", (long long)d);
   if (m < d) return fail(LEV_ERR_SHAPE, "m = %lld < d = %lld", (long long)m, (long long)d);
   if (!(zeta >= 0.0 && zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
+  if (zeta < kZetaMin)
+    return fail(LEV_ERR_NOT_SUPPORTED, "zeta = %g is below the smallest supported rank cutoff %g", zeta, kZetaMin);
   const size_t need = lev_rank_workspace_size(m, d);
   LEV_TRY(check_ws(ws, ws_bytes, need));
   Carver c(ws);
   RankBufs b = carve_rank(c, m, d);
-  return enqueue_rank(At, m, d, zeta, b, perm_out, R_out, rank_out, stream);
+  RefineBufs rf = carve_refine(c, m, d);
+  return enqueue_rank(At, m, d, zeta, b, perm_out, R_out, rank_out, stream, &rf);
 }
 
 // Algorithm 7 (LS-HRN-exact) on dense FP32/FP64 A with d <= 64: the columns K
@@ -563,6 +690,9 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   Carver c(ws);
   SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
   RankBufs rb = carve_rank(c, m, d);
+  RefineBufs rf;
+  const bool refine = p->zeta < kZetaGram;
+  if (refine) rf = carve_refine(c, m, d);
   void* state_ws = c.take<char>(state_bytes(d, m, d));
   ExactBufs eb = carve_exact(c, A, p);
   void* Zpack = c.take<char>(lev::pack_z_bytes(variant, d, d));
@@ -575,7 +705,7 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   LEV_HIP(mark_phase(0, s));
   LEV_HIP(lev::launch_fill_zero(sv.header + 5, sizeof(int64_t), s));
   LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, nullptr, s));
-  LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, s));
+  LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, s, refine ? &rf : nullptr));
   LEV_HIP(mark_phase(4, s));
   LEV_HIP(lev::launch_identity_rows(dt, d, eb.ZI, s));
   if (n > 0) {
@@ -617,6 +747,9 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   Carver c(ws);
   SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
   RankBufs rb = carve_rank(c, m, d);
+  RefineBufs rf;
+  const bool refine = p->zeta < kZetaGram;
+  if (refine) rf = carve_refine(c, m, d);
   void* state_ws = c.take<char>(state_bytes(d, m, k));
   double* Gk = c.take<double>((size_t)(d * k));
   void* Zpack = c.take<char>(lev::pack_z_bytes(variant, d, k));
@@ -629,7 +762,7 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   LEV_HIP(mark_phase(0, stream));
   LEV_HIP(lev::launch_fill_zero(sv.header + 5, sizeof(int64_t), stream));
   LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, Gk, stream));
-  LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, stream));
+  LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, stream, refine ? &rf : nullptr));
   LEV_HIP(mark_phase(4, stream));
   LEV_HIP(lev::launch_form_z(variant, d, k, sv.R, rank, sv.perm, Gk, sv.Z64, Zpack, err, stream));
   LEV_HIP(mark_phase(5, stream));

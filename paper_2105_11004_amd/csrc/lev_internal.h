@@ -100,8 +100,12 @@ struct PivCholState {
 // cleared at the start of every estimate.
 constexpr int32_t kErrPivotWait = 1;
 constexpr int32_t kErrSolveWait = 2;
+// fixed != 0: no pivoting (step J takes column J), i.e. the plain Cholesky
+// of B, stopping at the first non-positive diagonal.  ref_r00 (device, may
+// be null): the R_00 the cutoff zeta * R_00 refers to, instead of the first
+// pivot's own.
 hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState& st, int64_t* rank_out,
-                          double* gemm_partial, hipStream_t s);
+                          double* gemm_partial, hipStream_t s, int fixed = 0, const double* ref_r00 = nullptr);
 // Writes perm (int32[d], unpivoted columns ascending after the rank) and
 // R_out (d x d, pivoted order, zero below the diagonal and below the rank).
 hipError_t launch_pivchol_finalize(int64_t d, const PivCholState& st, const int64_t* rank,
@@ -166,6 +170,21 @@ hipError_t launch_gather_cols(int64_t m, int64_t d, const int32_t* perm, const i
                               double* AtK, hipStream_t s);
 hipError_t launch_scatter_h(int dtype, int64_t rows, int64_t d, const int32_t* perm, const int64_t* rank,
                             const double* H, void* Hf, hipStream_t s);
+
+// ---- refined rank-revealing factorisation (rrqr.hip) --------------------------
+// X1 = A~[:, perm[0..r)] with the other columns zero, X2 = the rest (may be
+// null), both m x d in perm order.
+hipError_t launch_gather_split(int64_t m, int64_t d, const int32_t* perm, const int64_t* rank, const double* At,
+                               double* X1, double* X2, hipStream_t s);
+// dst += a + b
+hipError_t launch_add2(int64_t n, double* dst, const double* a, const double* b, hipStream_t s);
+// Final perm, R and rank from round 1 (perm1, r1, rows Rtop) and round 2
+// (perm2 as positions of perm1, r2, rows Rbot); see rrqr.hip.
+hipError_t launch_rrqr_assemble(int64_t d, const int32_t* perm1, const int64_t* rank1, const int32_t* perm2,
+                                const int64_t* rank2, const double* Rtop, const double* Rbot, int32_t* perm_out,
+                                double* R_out, int64_t* rank_out, hipStream_t s);
+// *flag = (*rank == d)
+hipError_t launch_full_rank_flag(int64_t d, const int64_t* rank, int32_t* flag, hipStream_t s);
 
 // dst[0..3] = (a, b, c, e) from a kernel (capture-safe small header write).
 hipError_t launch_store_i64x4(int64_t* dst, int64_t a, int64_t b, int64_t c, int64_t e, hipStream_t s);

@@ -61,7 +61,8 @@ __device__ __forceinline__ double wave_max_f64(double v) {
 __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __restrict__ S, int64_t d,
                                                               double zeta, int64_t J0,
                                                               PivCholState st,
-                                                              int64_t* __restrict__ rank_out) {
+                                                              int64_t* __restrict__ rank_out, int fixed,
+                                                              const double* __restrict__ ref_r00) {
   __shared__ double bc[NB];
   __shared__ double wv[2][kMaxD / 64];
   __shared__ int wi[2][kMaxD / 64];
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
   if (c < d) dg = (J0 == 0) ? S[(int64_t)c * d + c] : st.diag[c];
   else dg = -INFINITY;
   bool alive = (c < d) && (dg != -INFINITY);
-  double r00 = (J0 == 0) ? 0.0 : *st.r00;
+  double r00 = ref_r00 != nullptr ? *ref_r00 : ((J0 == 0) ? 0.0 : *st.r00);
 
   double rp[NB];
 #pragma unroll
@@ -92,7 +93,8 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
     if (!active) continue;
     // the wave's largest alive diagonal (DPP max; NaN never wins) and the
     // lowest lane holding it (ties go to the lower column)
-    const double mv = alive ? dg : -INFINITY;
+    // (fixed order: the only candidate of step J is column J)
+    const double mv = (alive && (!fixed || c == J)) ? dg : -INFINITY;
     const double wmax = wave_max_f64(mv);
     const uint64_t hit = __ballot(mv == wmax);
     if (lane == 0) {
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
     const int bw = bhit != 0 ? (__ffsll((unsigned long long)bhit) - 1) : 0;
     const double pv = bhit != 0 ? bmax : -INFINITY;
     const int p = __builtin_amdgcn_readlane(ci, bw);
-    if (J == 0) r00 = pv > 0.0 ? sqrt(pv) : 0.0;
+    if (J == 0 && ref_r00 == nullptr) r00 = pv > 0.0 ? sqrt(pv) : 0.0;
     if (!(pv > 0.0) || !(sqrt(pv) > zeta * r00)) {
       stop = true;
       active = false;
@@ -228,7 +230,8 @@ struct __align__(16) PivotMsg {
 };
 
 __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __restrict__ B, int d, double zeta,
-                                                            PivCholState st, int64_t* __restrict__ rank_out) {
+                                                            PivCholState st, int64_t* __restrict__ rank_out,
+                                                            int fixed, const double* __restrict__ ref_r00) {
   // step J uses lvec[J & 1] and msg[J & 1]; `posted` counts the pivots the
   // diagonal wave has posted (msg[J & 1] holds pivot J once posted > J)
   __shared__ __align__(16) double lvec[2][kLvec];
@@ -393,17 +396,20 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
       const int i = lane + 64 * t;
       dg[t] = i < d ? B[(int64_t)i * d + i] : -INFINITY;
     }
-    double r00 = 0.0;
+    double r00 = ref_r00 != nullptr ? *ref_r00 : 0.0;
     int cur_p = 0;
-    // posts the pivot of step J: the largest d_i, ties to the lower index,
-    // with 1/sqrt(d_p) (hardware estimate + two Newton steps, ~1 ulp); returns
-    // whether the factorization continues
+    // posts the pivot of step J: the largest d_i, ties to the lower index
+    // (fixed order: d_J), with 1/sqrt(d_p) (hardware estimate + two Newton
+    // steps, ~1 ulp); returns whether the factorization continues
     auto post = [&](int J) -> bool {
-      const double m = wave_max_f64(fmax(fmax(dg[0], dg[1]), fmax(dg[2], dg[3])));
+      double cand[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) cand[t] = (!fixed || lane + 64 * t == J) ? dg[t] : -INFINITY;
+      const double m = wave_max_f64(fmax(fmax(cand[0], cand[1]), fmax(cand[2], cand[3])));
       int p = 0x7fffffff;
 #pragma unroll
       for (int t = 3; t >= 0; --t) {
-        const unsigned long long h = __ballot(dg[t] == m && dg[t] != -INFINITY);
+        const unsigned long long h = __ballot(cand[t] == m && cand[t] != -INFINITY);
         if (h) p = 64 * t + __builtin_ctzll(h);
       }
       p = __builtin_amdgcn_readfirstlane(p);
@@ -413,7 +419,7 @@ __global__ __launch_bounds__(768) void pivchol_small_kernel(const double* __rest
       y = y * fma(-0.5 * pv * y, y, 1.5);
       const double inv = pv > 0.0 ? y : 0.0;
       const double rpp = pv > 0.0 ? pv * y : 0.0;
-      if (J == 0) r00 = rpp;
+      if (J == 0 && ref_r00 == nullptr) r00 = rpp;
       const bool ok = pv > 0.0 && rpp > zeta * r00;
       if (lane == 0) {
         PivotMsg pm;
@@ -504,17 +510,17 @@ __global__ __launch_bounds__(kMaxD) void pivchol_finalize_kernel(int64_t d, PivC
 }  // namespace
 
 hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState& st, int64_t* rank_out,
-                          double* gemm_partial, hipStream_t s) {
+                          double* gemm_partial, hipStream_t s, int fixed, const double* ref_r00) {
   (void)gemm_partial;
   if (d <= 0 || d > kMaxD) return hipErrorInvalidValue;
   if (d <= kSmallD) {
     const int waves = small_rects((int)d) + 1;
-    pivchol_small_kernel<<<1, 64 * waves, 0, s>>>(B, (int)d, zeta, st, rank_out);
+    pivchol_small_kernel<<<1, 64 * waves, 0, s>>>(B, (int)d, zeta, st, rank_out, fixed, ref_r00);
     return hipGetLastError();
   }
   const int threads = (int)(((d + 63) / 64) * 64);
   for (int64_t J0 = 0; J0 < d; J0 += NB) {
-    pivchol_panel_kernel<<<1, threads, 0, s>>>(B, d, zeta, J0, st, rank_out);
+    pivchol_panel_kernel<<<1, threads, 0, s>>>(B, d, zeta, J0, st, rank_out, fixed, ref_r00);
     if (J0 + NB < d) {
       // S <- S - R_panel^T R_panel over the panel's NB rows (skipped once done)
       const double* Rp = st.Rrows + J0 * d;

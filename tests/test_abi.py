@@ -76,6 +76,8 @@ def _par(api, **kw):
     ({}, {"k": 65}, -1),
     ({}, {"r_cs": 0}, -1),
     ({}, {"zeta": 1.5}, -1),
+    ({}, {"zeta": 1e-11}, -7),                   # below the smallest supported rank cutoff
+    ({}, {"zeta": 0.0}, -7),
     ({}, {"az": 2}, -1),                         # BF16 products need BF16 storage
     ({"dtype": 0, "ld": 16}, {"az": 1}, -1),     # FP64 input only in FP64
     ({"format": 1}, {}, -1),                     # CSR without row_ptr
@@ -146,6 +148,7 @@ def test_other_calls_validate(lib):
     vp = ctypes.c_void_p
     assert lib.lev_rank_estimate(None, 32, 16, 1e-5, vp(8), vp(8), vp(8), vp(1 << 20), 1 << 30, None) == -1
     assert lib.lev_rank_estimate(vp(8), 8, 16, 1e-5, vp(8), vp(8), vp(8), vp(1 << 20), 1 << 30, None) == -2
+    assert lib.lev_rank_estimate(vp(8), 32, 16, 1e-12, vp(8), vp(8), vp(8), vp(1 << 20), 1 << 30, None) == -7
     assert lib.lev_debug_hash(1, -5, 8, vp(8), vp(8), None) == -2
     assert lib.lev_debug_gaussian(1, 2, 4, 4, vp(8), None) == -1
     assert lib.lev_debug_buckets(1, 10, 0, vp(8), vp(8), None) == -2

@@ -137,6 +137,46 @@ def test_rank_estimate_rank_deficient_and_zero(gpu):
     Z[:, 5] = rng.standard_normal(64)
     _rank_check(gpu, Z, 1e-6, expect_rank=1)
     _rank_check(gpu, np.zeros((16, 8)), 1e-6, expect_rank=0)
+    # the same at the paper's FP64 cutoff (the refined path): exact rank
+    # deficiency, one live column, nothing
+    E = rng.standard_normal((300, 40)) @ rng.standard_normal((40, 100))
+    _rank_check(gpu, E, 1e-10, expect_rank=40)
+    _rank_check(gpu, Z, 1e-10, expect_rank=1)
+    _rank_check(gpu, np.zeros((16, 8)), 1e-10, expect_rank=0)
+
+
+def _fixed_tail(d, tail, seed):
+    sig = np.concatenate([np.linspace(1, 0.1, d - 16), np.repeat(tail[0], 8), np.repeat(tail[1], 8)])
+    return W.fixed_spectrum(4000, sig, seed).numpy()
+
+
+@pytest.mark.parametrize("case", ["tail 1e-6/1e-7", "tail 1e-7/1e-9", "tail 1e-9/1e-11", "logspace 1..1e-12",
+                                  "rank 300 of 600", "rank 17 of 40", "rank 200 of 513"])
+def test_rank_estimate_at_the_paper_cutoff(gpu, case):
+    """Section 7's cutoff |R_kk| < c |R_11| with its FP64 value c = 1e-10, on
+    sketches whose spectra put columns between sqrt(u) and c (where the
+    Gram alone cannot decide) or exactly rank deficient: the rank, the
+    pivots and R must be DGEQP3's on the same sketch (the oracle's)."""
+    _log("paper cutoff", case)
+    rng = np.random.default_rng(600)
+    if case.startswith("tail"):
+        t = [float(x) for x in case.split()[1].split("/")]
+        A = _fixed_tail(64, t, 77)
+        At, _ = L.count_gauss_sketch(C.derive(5, 4000, 1024), A, 256)
+        expect = None
+    elif case.startswith("logspace"):
+        A = W.fixed_spectrum(4000, np.logspace(0, -12, 64), 78).numpy()
+        At, _ = L.count_gauss_sketch(C.derive(6, 4000, 1024), A, 256)
+        expect = None
+    else:
+        rank, d = (int(x) for x in case.split()[1::2])
+        n = 3007 if d == 40 else 2500
+        rng = np.random.default_rng(d + rank + (n if d == 40 else 0))
+        A = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, d))
+        At, _ = L.count_gauss_sketch(C.derive(2010, n, 2048 if d > 40 else 1024), A, d + 64)
+        expect = rank
+    r = _rank_check(gpu, At, 1e-10, expect_rank=expect)
+    _log("paper cutoff rank", r)
 
 
 # ------------------------------------------------------------------ the estimator
@@ -182,12 +222,13 @@ def test_estimate_fp32_low_rank_coherent(gpu, n, precision):
 def test_estimate_fp64_wide_blocked_solve(gpu, n, d, rank, k):
     """d > 256: Z = R11^{-1} G_k is solved over diagonal blocks of 256 pivot
     positions with the rank on the device; ranks inside the first and second
-    block leave later blocks past the rank (zero rows of Z).  zeta = 1e-6:
-    the pivoted Cholesky of the Gram resolves ranks only well above sqrt(u)."""
+    block leave later blocks past the rank (zero rows of Z).  zeta = 1e-10,
+    the paper's FP64 cutoff: exactly rank-deficient A is decided by the
+    refined path (round 2 on the explicit residual)."""
     _log("wide solve", n, d, rank, k)
     rng = np.random.default_rng(d + rank)
     A = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, d))
-    r_cs, m, zeta, seed = 2048, d + 64, 1e-6, 2010
+    r_cs, m, zeta, seed = 2048, d + 64, 1e-10, 2010
     ld = d + (d & 1)  # rows padded to 16 bytes
     buf = torch.full((n, ld), float("nan"), dtype=torch.float64, device=gpu)
     buf[:, :d] = torch.from_numpy(A).to(gpu)
@@ -286,6 +327,11 @@ def test_estimate_exact_scores(gpu, dtype, n, d, rank, bar):
     theta = api.lev_estimate(At.to(gpu), seed, r_cs, m, 8, zeta, exact=True).cpu().numpy().astype(np.float64)
     o = L.ls_hrn_exact(At.to(torch.float64).numpy(), seed, r_cs, m, zeta)
     assert o.rank == rank
+    # the GPU's own rank and columns on the same sketch (the exact mode keeps
+    # no state; Algorithm 10 with the same seed sketches and pivots the same)
+    _, st = api.lev_estimate(At.to(gpu), seed, r_cs, m, 8, zeta, return_state=True)
+    assert int(st.rank.item()) == rank and int(st.error.item()) == 0
+    np.testing.assert_array_equal(st.perm.cpu().numpy()[:rank], o.perm[:rank])
     rel = _rel(theta, o.theta)
     _log("exact max rel", rel.max(), "sum", theta.sum())
     assert rel.max() < bar
@@ -309,6 +355,26 @@ def test_estimate_exact_full_size_sampled(gpu):
     rel = _rel(theta[rows], o.theta_rows)
     _log("exact full size max rel", rel.max(), "sum", theta.sum())
     assert rel.max() < 1e-4 and abs(theta.sum() - d) < 1e-3 * d
+
+
+@pytest.mark.parametrize("tail", [(1e-6, 1e-7), (1e-9, 1e-11)])
+def test_estimate_fp64_paper_cutoff_fixed_spectrum(gpu, tail):
+    """The whole estimator at zeta = 1e-10 on the fixed-spectrum recipe of
+    Section 7 with a tail between sqrt(u) and below the cutoff: rank and
+    pivots equal the oracle's (DGEQP3), theta~ within the conditioning of
+    R11 (both factors are backward stable: |dtheta|/theta ~ u kappa(R11))."""
+    A = _fixed_tail(64, tail, 79)
+    r_cs, m, k, seed = 1024, 256, 32, 2021
+    theta, st = api.lev_estimate(torch.from_numpy(A).to(gpu), seed, r_cs, m, k, 1e-10, return_state=True)
+    o = _oracle_theta(A, seed, r_cs, m, k, 1e-10)
+    r = int(st.rank.item())
+    assert int(st.error.item()) == 0
+    assert r == o.rank == (64 if tail[0] > 1e-10 and tail[1] > 1e-10 else 56)
+    np.testing.assert_array_equal(st.perm.cpu().numpy()[:r], o.perm[:r])
+    kappa = np.linalg.cond(o.R11)
+    rel = _rel(theta.cpu().numpy(), o.theta)
+    _log("paper cutoff estimate", tail, "rank", r, "kappa", kappa, "max rel", rel.max())
+    assert rel.max() < max(1e-9, 1e-13 * kappa)
 
 
 # ------------------------------------------------------------------ edge cases
