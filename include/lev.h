@@ -62,12 +62,15 @@ enum { LEV_F64 = 0, LEV_F32 = 1, LEV_BF16 = 2 };
  *  FP32:   FP32 MFMA (16x16x4), any storage type but F64.
  *  BF16:   BF16 MFMA with Z rounded to BF16 (BF16 input only).
  *  BF16X2: BF16 MFMA, Z split into a BF16 high and low part (BF16 input only).
- *  BF16X3: FP32 input only.  A and Z are each split exactly into three BF16
+ *  BF16X3: FP32 input: A and Z are each split exactly into three BF16
  *          parts (24 significant bits, like FP32) and the six products above
  *          2^-24 relative run on the BF16 matrix cores: FP32-level accuracy at
- *          a fraction of the FP32 matrix-core time.
- * MFMA accumulators are FP32 (FP64 for F64 input) and are flushed into FP64
- * after every contraction chunk of 8-32 columns.
+ *          a fraction of the FP32 matrix-core time.  BF16 input: A is exact
+ *          in BF16, so only Z is split into three parts (three products):
+ *          the FP32-level form of the BF16-stored estimator.
+ * MFMA accumulators are FP32 (FP64 for F64 input) and are added into FP64
+ * accumulators after every contraction chunk of 8-32 columns (BF16 input:
+ * every 4 chunks of 32, i.e. runs of 128 products).
  * CSR A (no dense tile for the matrix cores): NATIVE or FP32 -> FP32 vector
  * FMAs (FP64 for F64 values, NATIVE only). */
 enum { LEV_AZ_NATIVE = 0, LEV_AZ_FP32 = 1, LEV_AZ_BF16 = 2, LEV_AZ_BF16X2 = 3, LEV_AZ_BF16X3 = 4 };

@@ -154,6 +154,7 @@ int az_variant(int format, int dtype, int az) {
       case LEV_AZ_FP32: return 1;
       case LEV_AZ_BF16: return 2;
       case LEV_AZ_BF16X2: return 3;
+      case LEV_AZ_BF16X3: return 4;  // Z in three BF16 parts (A is exact in BF16)
       default: return -1;
     }
   }

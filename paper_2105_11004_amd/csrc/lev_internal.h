@@ -141,6 +141,10 @@ size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k);
 hipError_t launch_rownorm_dense(int variant, int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
                                 int64_t k, const void* Zpack, const int64_t* rank, void* theta,
                                 hipStream_t s);
+// Pass 2 for BF16 storage (rownorm_bf16.hip): Z_full packed as variant 2
+// (parts = 1), 3 (parts = 2) or 4 (parts = 3); theta FP32.
+hipError_t launch_rownorm_bf16(int parts, const void* A, int64_t n, int64_t d, int64_t ld, int64_t k,
+                               const void* Zpack, void* theta, hipStream_t s);
 // Pass 2, CSR: theta[i] = || A[i, :] Z_full ||^2 with Z_full packed by
 // launch_pack_z as variant 5 (FP32, for F32/BF16 values) or 6 (FP64, for
 // F64 values): d rows of 64 elements (columns >= k zero).  theta is FP64 for

@@ -15,8 +15,8 @@
 // are summed per lane and across the 16 lanes of a row with shuffles.
 //
 // Variants (LEV_AZ_*): FP64 (16x16x4f64, EL 2), FP32 (16x16x4f32, EL 4; A
-// may be stored as FP32 or BF16), BF16 (16x16x32bf16, EL 8, Z in BF16),
-// BF16 hi/lo (two BF16 products, Z = Z_hi + Z_lo) and BF16x3 for FP32 A:
+// may be stored as FP32 or BF16) and BF16x3 for FP32 A (BF16 storage with Z
+// in one, two or three BF16 parts runs in rownorm_bf16.hip):
 // A and Z are each split exactly into three BF16 parts (hi + mid + lo, 24
 // significant bits, like FP32) and the six products above 2^-24 relative
 // (hh, hm, mh, hl, mm, lh) run on the BF16 matrix cores, which on gfx950
@@ -87,36 +87,6 @@ struct Frag<1, __hip_bfloat16> {
       o.w = 0u;
     }
     return o;
-  }
-};
-
-// BF16 storage: eight bf16, 16-byte load.
-__device__ __forceinline__ uint4 load_bf16x8(const __hip_bfloat16* row, int64_t col, int64_t d, bool ok) {
-  if (!ok || col >= d) return make_uint4(0u, 0u, 0u, 0u);
-  uint4 v = *reinterpret_cast<const uint4*>(row + col);
-  if (col + 7 >= d) {
-    uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int e = 0; e < 8; ++e)
-      if (col + e >= d) w[e >> 1] &= (e & 1) ? 0x0000FFFFu : 0xFFFF0000u;
-    v = make_uint4(w[0], w[1], w[2], w[3]);
-  }
-  return v;
-}
-template <>
-struct Frag<2, __hip_bfloat16> {
-  static constexpr int EL = 8, CW = 32, NZ = 1;
-  using T = uint4;
-  __device__ static T load(const __hip_bfloat16* row, int64_t col, int64_t d, bool ok) {
-    return load_bf16x8(row, col, d, ok);
-  }
-};
-template <>
-struct Frag<3, __hip_bfloat16> {
-  static constexpr int EL = 8, CW = 32, NZ = 2;
-  using T = uint4;
-  __device__ static T load(const __hip_bfloat16* row, int64_t col, int64_t d, bool ok) {
-    return load_bf16x8(row, col, d, ok);
   }
 };
 
@@ -218,15 +188,6 @@ __device__ __forceinline__ void mma<1, uint4>(v4f& acc, const uint4& a, const ui
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(z[0].y), acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(z[0].z), acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(z[0].w), acc, 0, 0, 0);
-}
-template <>
-__device__ __forceinline__ void mma<2, uint4>(v4f& acc, const uint4& a, const uint4* z) {
-  acc = mfma_bf16(as_bf(a), as_bf(z[0]), acc);
-}
-template <>
-__device__ __forceinline__ void mma<3, uint4>(v4f& acc, const uint4& a, const uint4* z) {
-  acc = mfma_bf16(as_bf(a), as_bf(z[0]), acc);
-  acc = mfma_bf16(as_bf(a), as_bf(z[1]), acc);
 }
 
 template <typename T>
@@ -606,8 +567,10 @@ hipError_t launch_rownorm_dense(int variant, int dtype, const void* A, int64_t n
   if (variant == 0 && dtype == 0) return launch_var<0, double>(A, n, d, ld, k, Zpack, theta, s);
   if (variant == 1 && dtype == 1) return launch_var<1, float>(A, n, d, ld, k, Zpack, theta, s);
   if (variant == 1 && dtype == 2) return launch_var<1, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, s);
-  if (variant == 2 && dtype == 2) return launch_var<2, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, s);
-  if (variant == 3 && dtype == 2) return launch_var<3, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, s);
+  // BF16 storage: the streaming kernel of rownorm_bf16.hip, Z in 1, 2 or 3 parts
+  if (variant == 2 && dtype == 2) return launch_rownorm_bf16(1, A, n, d, ld, k, Zpack, theta, s);
+  if (variant == 3 && dtype == 2) return launch_rownorm_bf16(2, A, n, d, ld, k, Zpack, theta, s);
+  if (variant == 4 && dtype == 2) return launch_rownorm_bf16(3, A, n, d, ld, k, Zpack, theta, s);
   if (variant == 4 && dtype == 1) return launch_var<4, float>(A, n, d, ld, k, Zpack, theta, s);
   return hipErrorInvalidValue;
 }
