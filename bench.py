@@ -1,22 +1,41 @@
 """Benchmark of the rSLS estimator (LS-HRN-approx) on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                    [--precision auto|native|fp32|bf16|bf16x2|bf16x3]
+                    [--no-accuracy] [--no-cpu-baseline] [--exact]
 
 One step = one lev_estimate call over the whole workload resident in HBM:
-Gaussian draws, pass 1 (CountSketch S A), the Gaussian transform, the
+the Gaussian draws and pass 1 (CountSketch S A), the Gaussian transform, the
 rank-revealing factorisation, Z = R11^{-1} G_k and pass 2 (theta~); for the
-backward workload (name ending in _bwd) also the adjoint of w^T theta~.  Prints
-one JSON line with rows/s, the per-phase times, the roofline of the
-dominant kernel (HBM-bound pass 2) measured live with HIP events, and the
+backward workload (name ending in _bwd) also the adjoint of w^T theta~.
+Prints one JSON line with rows/s, the per-phase times and rooflines (the
+headline `roofline` is the slowest phase's, measured live with the HIP
+events liblev records on its own stream), the accuracy of theta~ on sampled
+rows (against the oracle's FP64 estimator with the same sketch, and against
+the exact scores; for BF16 storage every BF16 form side by side), and the
 CPU oracle timed on a bounded sample of the same workload.
+
+HBM traffic of the passes (rocprofv3 counters, one process per counter):
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o fetch -- python3 bench.py --traffic-run [--workload NAME]
+    rocprofv3 --pmc WRITE_SIZE -d OUT/write -o write -- python3 bench.py --traffic-run [--workload NAME]
+    python3 bench.py --traffic-summarize OUT/fetch OUT/write [--workload NAME]
+
+A traffic run first copies a 1 GiB device buffer (a plain copy kernel that
+reads and writes exactly 1 GiB: the calibration of each counter), then runs
+lev_estimate twice; the summary scales each pass's counter by the copy's
+factor and stores bytes per launch in profiles/hbm_traffic.json, tied to the
+SHA-256 of the kernel's source so that a later change to the kernel makes
+the entry stale (reported as null).
 """
 
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -31,10 +50,14 @@ sys.path.insert(0, str(ROOT))
 from paper_2105_11004_amd import api  # noqa: E402
 from paper_2105_11004_amd import workloads as W  # noqa: E402
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+CSRC = ROOT / "paper_2105_11004_amd" / "csrc"
 TRAFFIC_FILE = ROOT / "profiles" / "hbm_traffic.json"
-KERNEL_SOURCES = {"pass2_rownorm": ROOT / "paper_2105_11004_amd" / "csrc" / "rownorm.hip",
-                  "pass1_countsketch": ROOT / "paper_2105_11004_amd" / "csrc" / "sketch.hip"}
+COPY_BYTES = 1 << 30
+DEFAULT_WORKLOAD = "dense_bf16_4Mx1024"
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def _src_hash(path: Path) -> str:
@@ -64,6 +87,22 @@ def _is_csr(A) -> bool:
     return not isinstance(A, torch.Tensor)
 
 
+def _n(A) -> int:
+    return A.n if _is_csr(A) else A.shape[0]
+
+
+def _values(A):
+    return A.values if _is_csr(A) else A
+
+
+def resolve_precision(A, precision: str) -> str:
+    """'auto': the FP32-level form for BF16 storage (Z in three BF16 parts),
+    the native form otherwise."""
+    if precision != "auto":
+        return precision
+    return "bf16x3" if (not _is_csr(A) and A.dtype == torch.bfloat16) else "native"
+
+
 def a_bytes(A) -> int:
     """Bytes of A as stored (dense: n*d elements; CSR: row_ptr, col_idx, values)."""
     if _is_csr(A):
@@ -71,17 +110,66 @@ def a_bytes(A) -> int:
     return A.shape[0] * A.shape[1] * A.element_size()
 
 
-def bytes_per_launch(A, cfg) -> dict:
-    vals = A.values if _is_csr(A) else A
-    n = A.n if _is_csr(A) else A.shape[0]
-    d = cfg["d"]
-    theta_es = 8 if vals.dtype == torch.float64 else 4
+# kernels that carry each pass (for the traffic counters and the profiles)
+def pass_kernels_for(csr: bool, dtype: torch.dtype, precision: str) -> dict:
+    if csr:
+        return {"pass1_countsketch": ("countsketch_csr_kernel", CSRC / "sketch.hip"),
+                "pass2_rownorm": ("rownorm_csr_kernel", CSRC / "rownorm_csr.hip")}
+    if precision == "fp32" or dtype == torch.float64:
+        p2 = ("rownorm_dense_kernel", CSRC / "rownorm.hip")
+    elif dtype == torch.bfloat16:
+        p2 = ("rownorm_bf16s_kernel", CSRC / "rownorm_bf16.hip")
+    else:
+        p2 = ("rownorm_x3_kernel", CSRC / "rownorm.hip")
+    return {"pass1_countsketch": ("countsketch_dense_kernel", CSRC / "sketch.hip"), "pass2_rownorm": p2}
+
+
+def pass_kernels(A, precision: str) -> dict:
+    return pass_kernels_for(_is_csr(A), _values(A).dtype, precision)
+
+
+def phase_work(A, cfg) -> dict:
+    """Algorithmic work of each phase of one estimate: bytes for the passes
+    over A (HBM-bound), FP64 flops for the n-independent phases (their
+    dominant kernels are FP64 MFMA GEMMs and the pivoting that drives them)."""
+    n, d, m, r_cs, k = _n(A), cfg["d"], cfg["m"], cfg["r_cs"], cfg["k"]
+    theta_es = 8 if _values(A).dtype == torch.float64 else 4
+    r = min(d, cfg.get("rank", d))
     return {
-        # pass 2 reads A once and writes theta~ (Z is ~KB, read from cache)
-        "pass2_rownorm": a_bytes(A) + n * theta_es,
-        # pass 1 reads A once and writes S A (FP64)
-        "pass1_countsketch": a_bytes(A) + cfg["r_cs"] * d * 8,
+        # pass 1 reads A once and writes S A (FP64) plus the two Gaussian
+        # matrices it draws on the side (G_m m x r_cs, G_k d x k, FP64)
+        "pass1_countsketch": ("hbm", a_bytes(A) + 8 * (r_cs * d + m * r_cs + d * k)),
+        # A~ = G_m (S A): 2 m r_cs d flops
+        "gaussian_transform": ("mfma_fp64", 2.0 * m * r_cs * d),
+        # Gram 2 m d^2 + pivoted Cholesky d^3 / 3 (to the rank r: r d^2 - ...)
+        "rank_revealing_qr": ("mfma_fp64", 2.0 * m * d * d + d ** 3 / 3.0),
+        # Z = R11^{-1} G_k: r^2 k flops
+        "form_z": ("mfma_fp64", float(r) * r * k),
+        # pass 2 reads A once and writes theta~
+        "pass2_rownorm": ("hbm", a_bytes(A) + n * theta_es),
     }
+
+
+def rooflines(A, cfg, phases_ms: dict, traffic: dict) -> dict:
+    out = {}
+    for name, (bound, work) in phase_work(A, cfg).items():
+        t = phases_ms[name] * 1e-3
+        if bound == "hbm":
+            ach = work / t / 1e9
+            out[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get(name), "algorithmic_bytes": work}
+        else:
+            ach = work / t / 1e12
+            out[name] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": ach / FP64_PEAK_TFLOPS, "traffic": None, "algorithmic_flops": work,
+                         "dtype": "f64"}
+    return out
+
+
+# ---------------------------------------------------------------------------- CPU oracle
+def _host_rows(A, lo: int, hi: int) -> np.ndarray:
+    """Rows lo..hi-1 of dense A as FP64 numpy (exact for BF16/FP32)."""
+    return A[lo:hi].to(torch.float64).cpu().numpy()
 
 
 def cpu_baseline(A, cfg, seed, target_s: float = 10.0, exact: bool = False):
@@ -101,14 +189,12 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0, exact: bool = False):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    n = A.n if _is_csr(A) else A.shape[0]
+    n = _n(A)
     ns = min(n, 1 << 15)
     S = A.to_scipy() if _is_csr(A) else None
 
     def host(rows):
-        if S is not None:
-            return S[:rows]
-        return A[:rows].to(torch.float64).cpu().numpy() if A.dtype == torch.bfloat16 else A[:rows].cpu().numpy()
+        return S[:rows] if S is not None else _host_rows(A, 0, rows)
 
     while True:
         Ah = host(ns)
@@ -131,41 +217,209 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0, exact: bool = False):
                       f"FP64 NumPy/SciPy, {dt:.2f} s per run"}
 
 
-def traffic_for(kernel: str):
+def _stats(ratio: np.ndarray) -> dict:
+    return {"median": float(np.median(ratio)), "q01": float(np.quantile(ratio, 0.01)),
+            "q99": float(np.quantile(ratio, 0.99)),
+            "frac_within_0.5": float(np.mean(np.abs(ratio - 1.0) <= 0.5))}
+
+
+def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000) -> dict:
+    """theta~ of each form (name -> full theta~ on the device) on sampled
+    rows against (i) the oracle's FP64 estimator with the same sketch and
+    (ii) the exact scores (Algorithm 5's Gram route over the whole matrix,
+    streamed in row blocks, cutoff zeta); raw and sum-normalised
+    (theta~ * r / sum theta~, which uses sum theta = rank)."""
+    from oracle import leverage as L
+
+    n = _n(A)
+    rows = np.sort(np.random.default_rng(12345).choice(n, min(n_rows, n), replace=False))
+    t0 = time.perf_counter()
+    if _is_csr(A):
+        Ah = A.to_scipy()
+        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows)
+        blk = 1 << 20
+        chunks = lambda: ((lo, Ah[lo:lo + blk].toarray()) for lo in range(0, n, blk))  # noqa: E731
+    else:
+        Ah = A.float().cpu().numpy() if A.dtype == torch.bfloat16 else A.cpu().numpy()
+        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows)
+        blk = 1 << 16
+        chunks = lambda: ((lo, Ah[lo:lo + blk]) for lo in range(0, n, blk))  # noqa: E731
+    t_same = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    exact, rho = L.theta_gram_rows(chunks, rows, max(cfg["zeta"], 1e-6))
+    t_exact = time.perf_counter() - t0
+    del Ah
+    out = {"rows_sampled": int(rows.size), "oracle_rank": int(o.rank), "exact_rank": int(rho),
+           "oracle_s": {"same_sketch": t_same, "exact_gram": t_exact}, "forms": {}}
+    for name, theta in forms.items():
+        th = theta.to(torch.float64)
+        total = float(th.sum().item())
+        got = th.cpu().numpy()[rows]
+        rel = np.abs(got - o.theta_rows) / np.maximum(np.abs(o.theta_rows), 1e-300)
+        live = exact > 1e-300
+        ratio = got[live] / exact[live]
+        norm = ratio * (o.rank / total) if total > 0 else ratio
+        out["forms"][name] = {
+            "vs_oracle_same_sketch": {"max_rel": float(rel.max()), "p99_rel": float(np.quantile(rel, 0.99))},
+            "vs_exact_theta": {"raw": _stats(ratio), "normalised": _stats(norm)},
+            "sum_theta": total, "rank": int(o.rank),
+        }
+    return out
+
+
+# ---------------------------------------------------------------------------- traffic
+def traffic_for(workload: str, A, precision: str) -> dict:
+    """Counter bytes per launch of each pass for this workload, or None when
+    the counters predate the kernel's current source."""
+    out = {}
     if not TRAFFIC_FILE.exists():
-        return None
-    data = json.loads(TRAFFIC_FILE.read_text())
-    ent = data.get(kernel)
-    if not ent or ent.get("source_sha") != _src_hash(KERNEL_SOURCES[kernel]):
-        return None  # counters predate the current kernel
-    return ent.get("bytes_per_launch")
+        return out
+    data = json.loads(TRAFFIC_FILE.read_text()).get(workload, {})
+    for key, (kernel, src) in pass_kernels(A, precision).items():
+        ent = data.get(key)
+        ok = ent and ent.get("kernel") == kernel and ent.get("source_sha") == _src_hash(src) \
+            and ent.get("precision") == precision
+        out[key] = ent.get("bytes_per_launch") if ok else None
+    return out
 
 
-def _median_ms(fn, stream, reps=5) -> float:
-    fn()
-    times = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        fn()
-        e1.record(stream)
-        e1.synchronize()
-        times.append(e0.elapsed_time(e1))
-    return float(np.median(times))
-
-
-def copy_ceiling(A, stream) -> dict:
-    """Measured ceilings on A's storage: a device-to-device copy (bytes read +
-    bytes written) and a read-only reduction (torch's sum over its words)."""
-    src = (A.values if _is_csr(A) else A).reshape(-1).view(torch.uint8)
-    nbytes = src.numel()
+def traffic_run(workload: str, precision: str):
+    dev = torch.device("cuda:0")
+    api.load_library()
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
-    copy_ms = _median_ms(lambda: dst.copy_(src), stream)
-    del dst
-    # the reduction reads the bytes as FP32 words (their values do not matter here)
-    words = src[: nbytes // 4 * 4].view(torch.float32)
-    read_ms = min(_median_ms(lambda: torch.sum(words), stream), _median_ms(lambda: torch.amax(words), stream))
-    return {"torch_copy_gbs": 2 * nbytes / (copy_ms * 1e-3) / 1e9, "torch_read_gbs": nbytes / (read_ms * 1e-3) / 1e9}
+    torch.cuda.synchronize()
+    dst.copy_(src)  # the calibration copy: COPY_BYTES read, COPY_BYTES written
+    torch.cuda.synchronize()
+    del src, dst
+    A, cfg, seed = make_workload(workload, dev)
+    plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"],
+                            precision=resolve_precision(A, precision))
+    for _ in range(2):
+        plan.run()
+    torch.cuda.synchronize()
+    print("traffic run done", flush=True)
+
+
+def _counter_rows(d: str):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    with open(files[0], newline="") as f:
+        return list(csv.DictReader(f)), files[0]
+
+
+def _per_dispatch(rows, counter: str):
+    """[(kernel name, KiB)] in dispatch order (values summed over the
+    counter's instances within a dispatch)."""
+    acc: dict = {}
+    order = []
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        if key not in acc:
+            acc[key] = [r.get("Kernel_Name", ""), 0.0]
+            order.append(key)
+        acc[key][1] += float(r["Counter_Value"])
+    return [tuple(acc[k]) for k in order]
+
+
+def traffic_summarize(fetch_dir: str, write_dir: str, workload: str, precision: str):
+    cfg = W.CONFIGS[workload]
+    fetch_rows, fetch_file = _counter_rows(fetch_dir)
+    write_rows, write_file = _counter_rows(write_dir)
+    fetch = _per_dispatch(fetch_rows, "FETCH_SIZE")
+    write = _per_dispatch(write_rows, "WRITE_SIZE")
+
+    def copy_kib(disp):
+        cands = [v for name, v in disp if "copy" in name.lower()]
+        if not cands:
+            raise SystemExit("calibration copy kernel not found in the counter output")
+        return max(cands)  # the 1 GiB copy is the largest copy dispatch
+
+    f_read = COPY_BYTES / (copy_kib(fetch) * 1024.0)
+    f_write = COPY_BYTES / (copy_kib(write) * 1024.0)
+    dtype = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[cfg["dtype"]]
+    csr = workload.startswith("csr")
+    if precision == "auto":
+        precision = "bf16x3" if (dtype == torch.bfloat16 and not csr) else "native"
+    kern = pass_kernels_for(csr, dtype, precision)
+    n, d = cfg["n"], cfg["d"]
+    es = torch.empty(0, dtype=dtype).element_size()
+    theta_es = 8 if dtype == torch.float64 else 4
+    algorithmic = {} if csr else {
+        "pass2_rownorm": n * d * es + n * theta_es,
+        "pass1_countsketch": n * d * es + 8 * (cfg["r_cs"] * d + cfg["m"] * cfg["r_cs"] + d * cfg["k"])}
+    entry = {"copy_bytes": COPY_BYTES, "factor_read": f_read, "factor_write": f_write}
+    lines = [f"# HBM traffic per launch, workload {workload}, precision {precision} "
+             f"(rocprofv3 FETCH_SIZE / WRITE_SIZE, KiB per dispatch)",
+             f"# fetch counters: {fetch_file}", f"# write counters: {write_file}",
+             f"# calibration: 1 GiB device copy counted {copy_kib(fetch):.0f} KiB fetched, "
+             f"{copy_kib(write):.0f} KiB written -> factors read {f_read:.4f}, write {f_write:.4f}"]
+    for key, (pattern, src) in kern.items():
+        fk = [v for name, v in fetch if pattern in name]
+        wk = [v for name, v in write if pattern in name]
+        if not fk or not wk:
+            continue
+        fb = fk[-1] * 1024.0 * f_read
+        wb = wk[-1] * 1024.0 * f_write
+        entry[key] = {"kernel": pattern, "precision": precision, "source_sha": _src_hash(src),
+                      "bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                      "algorithmic_bytes": algorithmic.get(key), "launches_seen": len(fk)}
+        alg = algorithmic.get(key)
+        ratio = f" (ratio {(fb + wb) / alg:.3f})" if alg else ""
+        lines.append(f"{key} ({pattern}): fetch {fb / 1e9:.4f} GB + write {wb / 1e9:.4f} GB = "
+                     f"{(fb + wb) / 1e9:.4f} GB per launch; algorithmic "
+                     f"{(alg or 0) / 1e9:.4f} GB{ratio}; kernel source sha {entry[key]['source_sha']}")
+    data = json.loads(TRAFFIC_FILE.read_text()) if TRAFFIC_FILE.exists() else {}
+    data = {k: v for k, v in data.items() if isinstance(v, dict) and k in W.CONFIGS}
+    data[workload] = entry
+    TRAFFIC_FILE.parent.mkdir(exist_ok=True)
+    TRAFFIC_FILE.write_text(json.dumps(data, indent=1) + "\n")
+    print("\n".join(lines))
+
+
+# ---------------------------------------------------------------------------- the benchmark
+def time_steps(plan, bwd, steps: int, stream) -> float:
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        plan.run()
+        if bwd is not None:
+            bwd.run()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def phase_times(plan, bwd, steps: int, stream):
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(api.LEV_PHASES)] for _ in range(steps)]
+    for row in ev:
+        for e in row:
+            e.record(stream)
+    torch.cuda.synchronize()
+    bwd_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    for s in range(steps):
+        api.lev_set_phase_events(ev[s])
+        plan.run()
+        if bwd is not None:
+            bwd_ev[s][0].record(stream)
+            bwd.run()
+            bwd_ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    api.lev_set_phase_events(None)
+    phases, spread = {}, {}
+    for i, name in enumerate(api.PHASE_NAMES):
+        vals = [ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(steps)]
+        phases[name] = float(np.mean(vals))
+        spread[name] = {"median": float(np.median(vals)), "min": float(np.min(vals)), "max": float(np.max(vals))}
+    step_vals = [ev[s][0].elapsed_time(ev[s][len(api.PHASE_NAMES)]) for s in range(steps)]
+    spread["step"] = {"median": float(np.median(step_vals)), "min": float(np.min(step_vals)),
+                      "max": float(np.max(step_vals))}
+    bms = float(np.mean([e[0].elapsed_time(e[1]) for e in bwd_ev])) if bwd is not None else None
+    return phases, spread, bms
 
 
 def main():
@@ -173,86 +427,58 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="dense_f32_1Mx256_rank128")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--precision", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", default="native")
+    ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--exact", action="store_true",
-                    help="time Algorithm 7 (LS-HRN-exact: dense FP32/FP64, d <= 64) instead of Algorithm 10")
+                    help="time Algorithm 7 (LS-HRN-exact) instead of Algorithm 10")
+    ap.add_argument("--traffic-run", action="store_true", help="the process a counter run profiles")
+    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.traffic_summarize:
+        traffic_summarize(*args.traffic_summarize, args.workload, args.precision)
+        return
     if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU row-sharded design is described, not built)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(the row-sharded multi-GPU design is described, not built)"}))
         sys.exit(2)
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.traffic_run:
+        traffic_run(args.workload, args.precision)
+        return
     dev = torch.device("cuda:0")
     api.load_library()
     print(f"# generating workload {args.workload}", file=sys.stderr, flush=True)
     A, cfg, seed = make_workload(args.workload, dev)
-    plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=args.precision,
+    precision = resolve_precision(A, args.precision)
+    plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=precision,
                             exact=args.exact)
-    backward = args.workload.endswith("_bwd")
-    if backward:
+    bwd = None
+    if args.workload.endswith("_bwd"):
         bwd = api.BackwardPlan(plan, torch.rand(A.shape[0], device=dev, dtype=A.dtype,
                                                 generator=torch.Generator(device=dev).manual_seed(5)))
     for _ in range(args.warmup):
         plan.run()
-        if backward:
+        if bwd is not None:
             bwd.run()
     torch.cuda.synchronize()
     print("# warmup done", file=sys.stderr, flush=True)
-
-    # per-step phase events (created by one record each, then handed to liblev)
     stream = torch.cuda.current_stream(dev)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(api.LEV_PHASES)] for _ in range(args.steps)]
-    for row in ev:
-        for e in row:
-            e.record(stream)
-    torch.cuda.synchronize()
 
-    # the headline: K steps with no instrumentation inside them
-    t_start = torch.cuda.Event(enable_timing=True)
-    t_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start.record(stream)
-    for s in range(args.steps):
-        plan.run()
-        if backward:
-            bwd.run()
-    t_end.record(stream)
-    torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    ms = total_ms / args.steps
-
-    # the breakdown: K more steps with liblev's phase events (recording them
-    # adds a little time of its own between the kernels)
-    bwd_ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
-    for s in range(args.steps):
-        api.lev_set_phase_events(ev[s])
-        plan.run()
-        if backward:
-            bwd_ev[s][0].record(stream)
-            bwd.run()
-            bwd_ev[s][1].record(stream)
-    torch.cuda.synchronize()
-    api.lev_set_phase_events(None)
-
-    phases = {}
-    spread = {}
-    for i, name in enumerate(api.PHASE_NAMES):
-        vals = [ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(args.steps)]
-        phases[name] = float(np.mean(vals))
-        spread[name] = {"median": float(np.median(vals)), "min": float(np.min(vals)), "max": float(np.max(vals))}
-    step_vals = [ev[s][0].elapsed_time(ev[s][len(api.PHASE_NAMES)]) for s in range(args.steps)]
-    spread["step"] = {"median": float(np.median(step_vals)), "min": float(np.min(step_vals)),
-                      "max": float(np.max(step_vals))}
-    copy_gbs = copy_ceiling(A, stream)
-    n = A.n if _is_csr(A) else A.shape[0]
-    vals = A.values if _is_csr(A) else A
-    bpl = bytes_per_launch(A, cfg)
-    dom = "pass2_rownorm"
-    achieved = bpl[dom] / (phases[dom] * 1e-3) / 1e9
-    pass1_gbs = bpl["pass1_countsketch"] / (phases["pass1_countsketch"] * 1e-3) / 1e9
+    # the headline: K steps with no instrumentation inside them; then the
+    # breakdown from K more steps with liblev's phase events
+    ms = time_steps(plan, bwd, args.steps, stream)
+    phases, spread, bms = phase_times(plan, bwd, args.steps, stream)
+    n = _n(A)
+    traffic = traffic_for(args.workload, A, precision)
+    roofs = rooflines(A, cfg, phases, traffic)
+    slowest = max(roofs, key=lambda k: phases[k])
+    kern = pass_kernels(A, precision)
+    headline = dict(roofs[slowest])
+    headline["phase"] = slowest
+    headline["kernel"] = kern[slowest][0] if slowest in kern else None
     out = {
         "metric": "rows/sec and HBM GB/s for rSLS estimate at eps=0.5 (fraction of HBM roofline)",
         "value": n / (ms * 1e-3),
@@ -264,26 +490,41 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[str(vals.dtype).split(".")[1]],
+        "dtype": {"float32": "f32", "float64": "f64", "bfloat16": "bf16"}[str(_values(A).dtype).split(".")[1]],
         "data": "synthetic (seeded, generated on the GPU)",
         "config": {"workload": args.workload, "n": n, "d": cfg["d"], "r_cs": cfg["r_cs"], "m": cfg["m"],
-                   "k": cfg["k"], "zeta": cfg["zeta"], "precision": args.precision,
+                   "k": cfg["k"], "zeta": cfg["zeta"], "precision": precision,
                    "algorithm": "LS-HRN-exact (Algorithm 7)" if args.exact else "LS-HRN-approx (Algorithm 10)"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom), "kernel": dom},
+        "roofline": headline,
+        "rooflines": roofs,
         "phases_ms": phases,
         "phases_ms_spread": spread,
-        "pass1_hbm_gbs": pass1_gbs,
-        "pass1_frac": pass1_gbs / HBM_PEAK_GBS,
-        # measured ceilings beside the spec-sheet peak, on the same GPU: a
-        # device-to-device copy of A's bytes (read + write) and a torch
-        # reduction that reads them once
-        "measured_ceilings": copy_gbs,
+        "passes_hbm_frac": {"pass1": roofs["pass1_countsketch"]["frac"], "pass2": roofs["pass2_rownorm"]["frac"],
+                            "both": (roofs["pass1_countsketch"]["algorithmic_bytes"]
+                                     + roofs["pass2_rownorm"]["algorithmic_bytes"])
+                            / ((phases["pass1_countsketch"] + phases["pass2_rownorm"]) * 1e-3) / 1e9
+                            / HBM_PEAK_GBS},
     }
-    if backward:
-        bms = float(np.mean([e[0].elapsed_time(e[1]) for e in bwd_ev]))
+    if bwd is not None:
         out["backward_ms"] = bms
         out["backward_hbm_gbs"] = 3 * a_bytes(A) / (bms * 1e-3) / 1e9  # two reads of A, one write of the gradient
+    forms = {precision: plan.theta.clone()}
+    if not args.exact and not _is_csr(A) and A.dtype == torch.bfloat16:
+        # the other BF16 forms on the same GPU: time and theta~
+        out["bf16_forms"] = {precision: {"ms_per_step": ms, "pass2_ms": phases["pass2_rownorm"]}}
+        for other in ("bf16", "bf16x2", "bf16x3"):
+            if other == precision:
+                continue
+            p2 = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=other)
+            p2.run()
+            t = time_steps(p2, None, max(3, args.steps // 4), stream)
+            ph, _, _ = phase_times(p2, None, max(3, args.steps // 4), stream)
+            out["bf16_forms"][other] = {"ms_per_step": t, "pass2_ms": ph["pass2_rownorm"]}
+            forms[other] = p2.theta.clone()
+            del p2
+    if not args.no_accuracy and not args.exact:
+        print("# accuracy on sampled rows (oracle: same sketch, and exact scores)", file=sys.stderr, flush=True)
+        out["accuracy"] = accuracy_report(A, cfg, seed, forms)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(A, cfg, seed, exact=args.exact)

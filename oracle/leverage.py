@@ -106,6 +106,36 @@ def theta_gram(A, tol: float) -> tuple[np.ndarray, int]:
     return np.sum(Y * Y, axis=1), k
 
 
+def theta_gram_rows(chunks, rows, tol: float) -> tuple[np.ndarray, int]:
+    """Algorithm 5 for a matrix too large to hold at once: ``chunks`` is a
+    callable returning an iterable of (row offset, FP64 block of consecutive
+    rows) covering A in order (it is called twice).  Pass 1 accumulates
+    B = A^T A block by block; B = V S^2 V^T keeps the rank-k part
+    (S_jj > tol * S_11); pass 2 returns theta_i = ||e_i^T A V_k S_k^{-1}||^2
+    for the sorted row indices ``rows`` only.  Returns (theta[rows], k)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    B = None
+    for _, blk in chunks():
+        blk = np.asarray(blk, dtype=np.float64)
+        B = blk.T @ blk if B is None else B + blk.T @ blk
+    w, V = np.linalg.eigh(B)
+    order = np.argsort(w)[::-1]
+    w, V = w[order], V[:, order]
+    sig = np.sqrt(np.clip(w, 0.0, None))
+    out = np.zeros(rows.size)
+    if sig.size == 0 or sig[0] == 0.0:
+        return out, 0
+    k = int(np.sum(sig > tol * sig[0]))
+    W = V[:, :k] / sig[:k]
+    for lo, blk in chunks():
+        hi = lo + blk.shape[0]
+        sel = (rows >= lo) & (rows < hi)
+        if np.any(sel):
+            Y = np.asarray(blk, dtype=np.float64)[rows[sel] - lo] @ W
+            out[sel] = np.sum(Y * Y, axis=1)
+    return out, k
+
+
 # ==========================================================================
 # Algorithm 3: CountGaussSketch
 # ==========================================================================

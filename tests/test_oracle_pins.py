@@ -422,3 +422,29 @@ def test_ls_hrn_exact_equals_exact_scores_when_the_rank_is_found():
     np.testing.assert_allclose(e.theta, L.hat_diagonal_bruteforce(C[:, K], 1e-12), rtol=1e-9, atol=1e-12)
     rows = np.array([0, 5, 39])
     np.testing.assert_allclose(L.ls_hrn_exact(C, 7, 64, 18, 1e-8, rows=rows).theta_rows, e.theta[rows])
+
+
+def test_gram_rows_streaming_equals_svd_scores():
+    """The streamed Gram route (Algorithm 5 over row blocks, sampled rows)
+    gives the thin-SVD scores of Section 1 on full-rank, rank-deficient and
+    row-scaled inputs, whatever the block size.  (Cutoff 1e-6: the Gram
+    squares the singular values, so it resolves them only down to about
+    sqrt(u) sigma_1.)"""
+    rng = np.random.default_rng(31)
+    cases = [rng.standard_normal((3000, 40)),
+             rng.standard_normal((2500, 12)) @ rng.standard_normal((12, 30)),
+             rng.standard_normal((2000, 24)) * np.exp(rng.standard_normal((2000, 1)))]
+    for A in cases:
+        ref, rho = L.exact_theta_svd(A, 1e-6)
+        rows = np.sort(rng.choice(A.shape[0], 200, replace=False))
+        for blk in (97, 1000, A.shape[0]):
+            def chunks(A=A, blk=blk):
+                for lo in range(0, A.shape[0], blk):
+                    yield lo, A[lo:lo + blk]
+            th, k = L.theta_gram_rows(chunks, rows, 1e-6)
+            assert k == rho
+            np.testing.assert_allclose(th, ref[rows], rtol=1e-9, atol=1e-13)
+    # the sum over all rows is the rank (Section 1: trace of the projector)
+    A = cases[1]
+    th, k = L.theta_gram_rows(lambda: iter([(0, A)]), np.arange(A.shape[0]), 1e-6)
+    assert k == 12 and abs(th.sum() - 12) < 1e-9
