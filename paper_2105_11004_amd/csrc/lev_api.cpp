@@ -251,16 +251,39 @@ int32_t* state_err(const StateView& v) { return reinterpret_cast<int32_t*>(v.hea
 
 // ---- workspace plans -------------------------------------------------------------
 struct SketchBufs {
-  double* Gm;
+  double* Gm;        // FP64 G_m (m x r_cs), or null when x3
   double* SA;
   double* partial;
+  bool x3 = false;   // the transform in FP32-level arithmetic (xgemm.hip)
+  uint32_t* Gp;      // x3: G_m as three BF16 parts
+  void* SAp;         // x3: (S A)^T as three BF16 parts
 };
 
 int gm_splits(int64_t m, int64_t d, int64_t r_cs) { return lev::dgemm_choose_splits(m, d, r_cs); }
 
-SketchBufs carve_sketch(Carver& c, int64_t n, int64_t d, int64_t m, int64_t r_cs, bool need_sa) {
+// The Gaussian transform runs in FP32-level arithmetic on the BF16 matrix
+// cores (six products of three-part splits) for BF16-stored dense A, whose
+// entries carry 8 significant bits: its relative error ~2^-24 is far below
+// them, and the FP64 product would take longer than either pass over A.
+// Every other input keeps the FP64 transform.
+bool use_x3_transform(const lev_matrix* A, int64_t r_cs) {
+  return A->format == LEV_DENSE_ROWMAJOR && A->dtype == LEV_BF16 && r_cs % 8 == 0;
+}
+
+SketchBufs carve_sketch(Carver& c, int64_t n, int64_t d, int64_t m, int64_t r_cs, bool need_sa, bool x3) {
   (void)n;
   SketchBufs b;
+  b.x3 = x3;
+  if (x3) {
+    b.Gm = nullptr;
+    b.Gp = c.take<uint32_t>(3 * lev::split3_elems(m, r_cs) / 2);
+    b.SAp = c.take<uint32_t>(3 * lev::split3_elems(d, r_cs) / 2);
+    b.SA = c.take<double>((size_t)(r_cs * d));
+    b.partial = c.take<double>(lev::xgemm_partial_elems(m, d, lev::xgemm_choose_splits(m, d, r_cs)));
+    return b;
+  }
+  b.Gp = nullptr;
+  b.SAp = nullptr;
   b.Gm = c.take<double>((size_t)(m * r_cs));
   b.SA = need_sa ? c.take<double>((size_t)(r_cs * d)) : nullptr;
   b.partial = c.take<double>(lev::dgemm_partial_elems(m, d, gm_splits(m, d, r_cs)));
@@ -335,8 +358,9 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
                           const SketchBufs& b, double* SA, double* At, double* Gk, hipStream_t s) {
   const int64_t d = A->d, m = p->m, r_cs = p->r_cs, k = p->k;
   // G_m and G_k are drawn by pass 1's workgroups (compute under its memory traffic)
-  const lev::GaussDraw g{{{dr.key_m, m * r_cs, 1.0 / std::sqrt((double)m), b.Gm},
-                          {dr.key_k, d * k, 1.0 / std::sqrt((double)k), Gk}}};
+  lev::GaussDraw g{{{dr.key_m, m * r_cs, 1.0 / std::sqrt((double)m), b.Gm},
+                    {dr.key_k, d * k, 1.0 / std::sqrt((double)k), Gk}}};
+  if (b.x3) g.m[0].parts3 = b.Gp;  // G_m drawn straight into its three parts
   LEV_HIP(mark_phase(1, s));
   if (A->n > 0 && A->format == LEV_CSR) {
     LEV_HIP(lev::launch_countsketch_csr(A->dtype, A->values, A->row_ptr, A->col_idx, A->n, d, A->nnz, dr.hash,
@@ -344,15 +368,22 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
   } else if (A->n > 0) {
     LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, g, s));
   } else {
-    LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, g.m[0].scale, b.Gm, s));
+    if (!b.x3) LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, g.m[0].scale, b.Gm, s));
     if (Gk != nullptr) LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, g.m[1].scale, Gk, s));
     LEV_HIP(lev::launch_fill_zero(SA, sizeof(double) * (size_t)(r_cs * d), s));
   }
   LEV_HIP(mark_phase(2, s));
   // A~ = G_m (S A): (m x r_cs) (r_cs x d)
-  const int splits = gm_splits(m, d, r_cs);
-  LEV_HIP(lev::launch_dgemm(m, d, r_cs, 1.0, b.Gm, r_cs, 1, SA, d, 1, 0.0, At, d, splits, b.partial,
-                            nullptr, s));
+  if (b.x3 && A->n > 0) {
+    LEV_HIP(lev::launch_split_t3(r_cs, d, SA, b.SAp, s));
+    LEV_HIP(lev::launch_xgemm(m, d, r_cs, b.Gp, b.SAp, At, d, lev::xgemm_choose_splits(m, d, r_cs), b.partial, s));
+  } else if (b.x3) {
+    LEV_HIP(lev::launch_fill_zero(At, sizeof(double) * (size_t)(m * d), s));
+  } else {
+    const int splits = gm_splits(m, d, r_cs);
+    LEV_HIP(lev::launch_dgemm(m, d, r_cs, 1.0, b.Gm, r_cs, 1, SA, d, 1, 0.0, At, d, splits, b.partial,
+                              nullptr, s));
+  }
   LEV_HIP(mark_phase(3, s));
   return LEV_OK;
 }
@@ -612,11 +643,11 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
   const int64_t d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
   Carver c(nullptr);
   if (which == LEV_WS_SKETCH) {
-    carve_sketch(c, A->n, d, m, r_cs, true);
+    carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
     return c.used;
   }
   if (which == LEV_WS_ESTIMATE && p->exact) {
-    carve_sketch(c, A->n, d, m, r_cs, true);
+    carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
     carve_rank(c, m, d);
     if (p->zeta < kZetaGram) carve_refine(c, m, d);
     c.take<char>(state_bytes(d, m, d));
@@ -625,7 +656,7 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
     return c.used;
   }
   if (which == LEV_WS_ESTIMATE) {
-    carve_sketch(c, A->n, d, m, r_cs, true);
+    carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
     carve_rank(c, m, d);
     if (p->zeta < kZetaGram) carve_refine(c, m, d);
     c.take<char>(state_bytes(d, m, k));
@@ -647,10 +678,10 @@ lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out, 
   LEV_TRY(check_params(A, p, /*uses_zeta=*/false));
   if (At_out == nullptr) return fail(LEV_ERR_ARG, "At_out is null");
   Carver sizing(nullptr);
-  carve_sketch(sizing, A->n, A->d, p->m, p->r_cs, true);
+  carve_sketch(sizing, A->n, A->d, p->m, p->r_cs, true, use_x3_transform(A, p->r_cs));
   LEV_TRY(check_ws(ws, ws_bytes, sizing.used));
   Carver c(ws);
-  SketchBufs b = carve_sketch(c, A->n, A->d, p->m, p->r_cs, true);
+  SketchBufs b = carve_sketch(c, A->n, A->d, p->m, p->r_cs, true, use_x3_transform(A, p->r_cs));
   const lev::SeedDraws dr = lev::derive_draws(p->seed, A->n, p->r_cs);
   double* SA = SA_out != nullptr ? SA_out : b.SA;
   return enqueue_sketch(A, p, dr, b, SA, At_out, nullptr, stream);
@@ -689,7 +720,7 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   const int dt = A->dtype == LEV_F64 ? 0 : 1;
   hipStream_t s = stream;
   Carver c(ws);
-  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
+  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true, use_x3_transform(A, r_cs));
   RankBufs rb = carve_rank(c, m, d);
   RefineBufs rf;
   const bool refine = p->zeta < kZetaGram;
@@ -746,7 +777,7 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
     return estimate_exact(A, p, variant, theta_out, ws, stream);
   }
   Carver c(ws);
-  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true);
+  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true, use_x3_transform(A, r_cs));
   RankBufs rb = carve_rank(c, m, d);
   RefineBufs rf;
   const bool refine = p->zeta < kZetaGram;

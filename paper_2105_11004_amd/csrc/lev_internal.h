@@ -52,6 +52,10 @@ struct GaussMatrix {
   int64_t total;  // elements
   double scale;
   double* out;
+  // instead of out (FP64): the values rounded to FP32 and split exactly
+  // into three BF16 parts, part p of element e at BF16 index
+  // p * 2 * ceil(total / 2) + e (the operand of launch_xgemm)
+  uint32_t* parts3 = nullptr;
 };
 struct GaussDraw {
   GaussMatrix m[2];
@@ -189,6 +193,21 @@ hipError_t launch_rrqr_assemble(int64_t d, const int32_t* perm1, const int64_t* 
                                 double* R_out, int64_t* rank_out, hipStream_t s);
 // *flag = (*rank == d)
 hipError_t launch_full_rank_flag(int64_t d, const int64_t* rank, int32_t* flag, hipStream_t s);
+
+// ---- the Gaussian transform in FP32-level arithmetic (xgemm.hip) -------------
+// out (3 parts of N x K BF16, rows contiguous in k) = the three-part split
+// of SA^T (SA K x N FP64 row-major); K even.
+hipError_t launch_split_t3(int64_t K, int64_t N, const double* SA, void* out, hipStream_t s);
+// C (M x N FP64, row stride ldc) = A B^T from three-part operands: Ap 3
+// parts of M x K, Bp 3 parts of N x K (BF16, rows of K elements, K a
+// multiple of 8), the six products above 2^-24 on BF16 MFMAs, FP32 within a
+// 32-wide K step, FP64 beyond; partial: splits x M x N FP64 when splits > 1.
+hipError_t launch_xgemm(int64_t M, int64_t N, int64_t K, const void* Ap, const void* Bp, double* C, int64_t ldc,
+                        int splits, double* partial, hipStream_t s);
+int xgemm_choose_splits(int64_t M, int64_t N, int64_t K);
+size_t xgemm_partial_elems(int64_t M, int64_t N, int splits);
+// BF16 elements of one part of a three-part split of rows x K (K rounded up to even)
+size_t split3_elems(int64_t rows, int64_t K);
 
 // dst[0..3] = (a, b, c, e) from a kernel (capture-safe small header write).
 hipError_t launch_store_i64x4(int64_t* dst, int64_t a, int64_t b, int64_t c, int64_t e, hipStream_t s);

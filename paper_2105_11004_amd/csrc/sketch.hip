@@ -138,10 +138,28 @@ __device__ __forceinline__ void negate_if<__hip_bfloat16>(uint4& raw, uint32_t n
 // start first puts the matrices' stores ahead of most of the read stream
 // (measured: 6-8 us less than spreading them over every workgroup).
 constexpr int64_t kDrawGroups = 256;
+typedef __bf16 v2bf_t __attribute__((ext_vector_type(2)));
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+
+// x = h + m + l exactly in FP32 for two values; BF16 parts packed in pairs
+// (element 0 in the low half).
+__device__ __forceinline__ void split3_pair(float x0, float x1, uint32_t& h, uint32_t& m, uint32_t& l) {
+  auto pk = [](float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f_t){a, b}, v2bf_t));
+  };
+  h = pk(x0, x1);
+  const float r0 = x0 - __uint_as_float(h << 16), r1 = x1 - __uint_as_float(h & 0xFFFF0000u);
+  m = pk(r0, r1);
+  const float s0 = r0 - __uint_as_float(m << 16), s1 = r1 - __uint_as_float(m & 0xFFFF0000u);
+  l = pk(s0, s1);
+}
+
 __device__ __forceinline__ void side_draw(const GaussDraw& g) {
   if (blockIdx.y != 0) return;
-  const int64_t pairs0 = g.m[0].out != nullptr ? (g.m[0].total + 1) / 2 : 0;
-  const int64_t pairs1 = g.m[1].out != nullptr ? (g.m[1].total + 1) / 2 : 0;
+  const bool on0 = g.m[0].out != nullptr || g.m[0].parts3 != nullptr;
+  const bool on1 = g.m[1].out != nullptr || g.m[1].parts3 != nullptr;
+  const int64_t pairs0 = on0 ? (g.m[0].total + 1) / 2 : 0;
+  const int64_t pairs1 = on1 ? (g.m[1].total + 1) / 2 : 0;
   const int64_t pairs = pairs0 + pairs1;
   if (pairs == 0) return;
   const int64_t want = max<int64_t>(kDrawGroups, (pairs + 16 * kThreads - 1) / (16 * kThreads));
@@ -157,8 +175,20 @@ __device__ __forceinline__ void side_draw(const GaussDraw& g) {
     box_muller_pair((uint64_t)q, gm.key, &z0, &z1);
     // streaming stores: the matrix is read back only by the next kernel, and
     // non-temporal writes disturb pass 1's read stream less (measured ~3 us)
-    __builtin_nontemporal_store(z0 * gm.scale, gm.out + 2 * q);
-    if (2 * q + 1 < gm.total) __builtin_nontemporal_store(z1 * gm.scale, gm.out + 2 * q + 1);
+    if (gm.parts3 != nullptr) {
+      // FP32 value split exactly into three BF16 parts (pairs packed)
+      const float x0 = (float)(z0 * gm.scale);
+      const float x1 = 2 * q + 1 < gm.total ? (float)(z1 * gm.scale) : 0.0f;
+      uint32_t h, m, l;
+      split3_pair(x0, x1, h, m, l);
+      const int64_t np = (gm.total + 1) / 2;
+      __builtin_nontemporal_store(h, gm.parts3 + q);
+      __builtin_nontemporal_store(m, gm.parts3 + np + q);
+      __builtin_nontemporal_store(l, gm.parts3 + 2 * np + q);
+    } else {
+      __builtin_nontemporal_store(z0 * gm.scale, gm.out + 2 * q);
+      if (2 * q + 1 < gm.total) __builtin_nontemporal_store(z1 * gm.scale, gm.out + 2 * q + 1);
+    }
   }
 }
 

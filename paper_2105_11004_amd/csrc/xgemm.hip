@@ -1,0 +1,294 @@
+// The Gaussian transform A~ = G (S A) of Algorithm 3 in FP32-level
+// arithmetic on the BF16 matrix cores, for BF16-stored A.
+//
+// Both operands are split exactly into three BF16 parts (hi + mid + lo,
+// 24 significant bits, like FP32): G while pass 1 draws it (the side draw
+// writes the parts instead of FP64 values), S A by split_t3_kernel below,
+// which also transposes it so that both operands are contiguous in the
+// contraction index.  The six part products above 2^-24 relative (hh, hm,
+// mh, hl, mm, lh) run on 16x16x32 BF16 MFMAs; each 32-wide K step of them is
+// summed in FP32 and added into FP64 accumulators, so FP32 rounding only
+// ever sums 192 products of one K step.  A~ then carries relative error
+// ~2^-24 against the FP64 product (the FP64 transform takes the GEMM at the
+// FP64 matrix rate, ~25x slower than this on gfx950).
+//
+// Tiling: 128 x 128 output tile per workgroup of 8 waves (each wave 64 rows
+// x 32 columns = 4 x 2 MFMA blocks), K in steps of 32 through
+// double-buffered LDS (3 parts x 128 rows x 32 k per operand, rows padded
+// to 80 bytes so that the 16 rows an MFMA operand read touches fall on
+// distinct banks), the next step's global loads in registers while the
+// current step's MFMAs run, optional split-K with partials reduced in a
+// fixed order.  Workgroups that share an A tile are placed on the same XCD
+// (blockIdx % 8) so that its re-reads hit that die's L2.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "lev_internal.h"
+
+namespace lev {
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+constexpr int TM = 128, TN = 128, TK = 32;
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kRowHalfs = 40;  // LDS row stride in BF16 elements (80 bytes)
+constexpr int kPieces = 2 * 3 * TM * (TK / 8);       // 16-byte pieces per K step (A and B)
+constexpr int kPer = kPieces / kThreads;             // 6 per thread
+constexpr int kOpHalfs = 3 * TM * kRowHalfs;         // BF16 elements per operand buffer
+
+__device__ __forceinline__ v8bf as_bf(const uint4& u) { return __builtin_bit_cast(v8bf, u); }
+
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
+}
+
+// x = h + m + l exactly in FP32 for two values, parts packed in pairs.
+__device__ __forceinline__ void split3_pair(float x0, float x1, uint32_t& h, uint32_t& m, uint32_t& l) {
+  h = pk_bf16(x0, x1);
+  const float r0 = x0 - __uint_as_float(h << 16), r1 = x1 - __uint_as_float(h & 0xFFFF0000u);
+  m = pk_bf16(r0, r1);
+  const float s0 = r0 - __uint_as_float(m << 16), s1 = r1 - __uint_as_float(m & 0xFFFF0000u);
+  l = pk_bf16(s0, s1);
+}
+
+// out part p (N x K, BF16, row-major: contiguous in k) = split(SA^T), SA
+// K x N FP64 row-major.  A 64 x 64 tile goes through LDS (as FP32: the
+// split starts from the FP32 value) so that both the reads (along j) and
+// the writes (pairs of k along k) are coalesced.
+constexpr int kT = 64;
+__global__ __launch_bounds__(256) void split_t3_kernel(int64_t K, int64_t N, const double* __restrict__ SA,
+                                                       uint32_t* __restrict__ out) {
+  __shared__ float tile[kT][kT + 1];
+  const int64_t Kp = (K + 1) / 2;
+  const int64_t k0 = (int64_t)blockIdx.x * kT, j0 = (int64_t)blockIdx.y * kT;
+  const int t = threadIdx.x;
+  // read: thread t covers column j0 + t % 64 of rows k0 + t / 64 + 4 r
+#pragma unroll 4
+  for (int r = 0; r < kT / 4; ++r) {
+    const int kk = t / kT + 4 * r, jj = t % kT;
+    const int64_t k = k0 + kk, j = j0 + jj;
+    tile[kk][jj] = (k < K && j < N) ? (float)SA[k * N + j] : 0.0f;
+  }
+  __syncthreads();
+  // write: thread t covers pair kp0 + t % 32 of columns j0 + t / 32 + 8 r
+#pragma unroll 4
+  for (int r = 0; r < kT / 8; ++r) {
+    const int pp = t % (kT / 2), jj = t / (kT / 2) + 8 * r;
+    const int64_t kp = k0 / 2 + pp, j = j0 + jj;
+    if (kp < Kp && j < N) {
+      uint32_t h, m, l;
+      split3_pair(tile[2 * pp][jj], tile[2 * pp + 1][jj], h, m, l);
+      const int64_t o = j * Kp + kp;
+      out[o] = h;
+      out[Kp * N + o] = m;
+      out[2 * Kp * N + o] = l;
+    }
+  }
+}
+
+// C or partial[z] (M x N FP64) = sum over the products of A part p (M x K)
+// times B part q (N x K), K range of split z.  Ap, Bp: 3 parts one after
+// the other, each `pstride` BF16 elements, rows of ldk elements.
+__global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N, int64_t K, int64_t ldk,
+                                                            const __hip_bfloat16* __restrict__ Ap, int64_t apstride,
+                                                            const __hip_bfloat16* __restrict__ Bp, int64_t bpstride,
+                                                            double* __restrict__ C, int64_t ldc, int splits,
+                                                            int64_t kchunk, double* __restrict__ partial) {
+  __shared__ __align__(16) __hip_bfloat16 As[2][kOpHalfs];
+  __shared__ __align__(16) __hip_bfloat16 Bs[2][kOpHalfs];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // XCD-aware placement: the 8 column tiles of one (row tile, split) pair
+  // run on one XCD (blockIdx % 8), so its A tile is re-read from that L2
+  const int64_t mt = (M + TM - 1) / TM, ntl = (N + TN - 1) / TN;
+  const int64_t nwg = (int64_t)gridDim.x;
+  int64_t id = blockIdx.x;
+  int64_t pair, nt_i;
+  if (ntl == 8 && nwg % 64 == 0) {  // (row tile, split) pairs a multiple of 8
+    const int64_t xcd = id % 8, j = id / 8;
+    pair = (nwg / 64) * xcd + j / 8;  // (row tile, split) pairs of this XCD
+    nt_i = j % 8;
+  } else {
+    pair = id / ntl;
+    nt_i = id % ntl;
+  }
+  const int64_t z = pair % splits, mt_i = pair / splits;
+  if (mt_i >= mt) return;
+  const int64_t m0 = mt_i * TM, n0 = nt_i * TN;
+  const int64_t kb = z * kchunk;
+  const int64_t ke = std::min<int64_t>(K, kb + kchunk);
+  const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
+
+  // staging: piece e = tid + kThreads * q; operand e / (kPieces / 2), part,
+  // row and 16-byte k piece within the step
+  uint4 stg[kPer];
+  auto load_step = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + kThreads * q;
+      const int op = e / (kPieces / 2), ee = e % (kPieces / 2);
+      const int part = ee / (TM * 4), row = (ee % (TM * 4)) / 4, pc = ee % 4;
+      const int64_t gk = k0 + 8 * pc;
+      const __hip_bfloat16* base = op == 0 ? Ap + part * apstride : Bp + part * bpstride;
+      const int64_t gr = (op == 0 ? m0 : n0) + row;
+      const int64_t lim = op == 0 ? M : N;
+      // rows past the matrix and k pieces past the range read a valid
+      // address and are zeroed (K is a multiple of 8 in every use)
+      const bool ok = gr < lim && gk < ke;
+      const uint4 v = *reinterpret_cast<const uint4*>(base + (ok ? gr : 0) * ldk + (ok ? gk : 0));
+      stg[q] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_step = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + kThreads * q;
+      const int op = e / (kPieces / 2), ee = e % (kPieces / 2);
+      const int part = ee / (TM * 4), row = (ee % (TM * 4)) / 4, pc = ee % 4;
+      __hip_bfloat16* dst = (op == 0 ? As[buf] : Bs[buf]) + (part * TM + row) * kRowHalfs + 8 * pc;
+      *reinterpret_cast<uint4*>(dst) = stg[q];
+    }
+  };
+
+  v4f acc[4][2];
+  double acc64[4][2][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
+    }
+
+  int buf = 0;
+  if (kb < ke) {
+    load_step(kb);
+    store_step(0);
+  }
+  __syncthreads();
+  for (int64_t k0 = kb; k0 < ke; k0 += TK) {
+    const bool more = k0 + TK < ke;  // uniform
+    if (more) load_step(k0 + TK);
+    // B fragments of the wave's two column blocks (all parts), then per row
+    // block the A fragments and the six products, smallest first
+    uint4 bq[2][3];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        bq[j][p] = *reinterpret_cast<const uint4*>(Bs[buf] + (p * TM + wn + 16 * j + (lane & 15)) * kRowHalfs +
+                                                   8 * (lane >> 4));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint4 ap[3];
+#pragma unroll
+      for (int p = 0; p < 3; ++p)
+        ap[p] = *reinterpret_cast<const uint4*>(As[buf] + (p * TM + wm + 16 * i + (lane & 15)) * kRowHalfs +
+                                                8 * (lane >> 4));
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        v4f c = acc[i][j];
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[2]), as_bf(bq[j][0]), c, 0, 0, 0);  // l h
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][1]), c, 0, 0, 0);  // m m
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][2]), c, 0, 0, 0);  // h l
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][0]), c, 0, 0, 0);  // m h
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][1]), c, 0, 0, 0);  // h m
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][0]), c, 0, 0, 0);  // h h
+        acc[i][j] = c;
+      }
+    }
+    // the step's FP32 sums into FP64
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
+        acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+      }
+    // the other buffer was last read before the previous barrier
+    if (more) store_step(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  // accumulator element v of lane l: row 4 (l / 16) + v, column l % 16 of
+  // its 16 x 16 block
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = m0 + wm + 16 * i + 4 * (lane >> 4) + v;
+        const int64_t gj = n0 + wn + 16 * j + (lane & 15);
+        if (gi < M && gj < N) {
+          if (splits == 1) C[gi * ldc + gj] = acc64[i][j][v];
+          else partial[(z * M + gi) * N + gj] = acc64[i][j][v];
+        }
+      }
+}
+
+__global__ void xgemm_reduce_kernel(int64_t M, int64_t N, int splits, const double* __restrict__ partial,
+                                    double* __restrict__ C, int64_t ldc) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * M * N + idx];
+  C[(idx / N) * ldc + idx % N] = s;
+}
+
+}  // namespace
+
+int xgemm_choose_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  int splits = 1;
+  // about one workgroup per CU (one fits: its LDS is 120 KB), each split
+  // keeping at least 16 K steps
+  while (tiles * splits < 256 && K / (splits * 2) >= 16 * TK && splits < 64) splits *= 2;
+  return splits;
+}
+
+size_t xgemm_partial_elems(int64_t M, int64_t N, int splits) {
+  return splits > 1 ? (size_t)splits * (size_t)M * (size_t)N : 0;
+}
+
+size_t split3_elems(int64_t rows, int64_t K) { return (size_t)rows * (size_t)((K + 1) / 2) * 2; }
+
+hipError_t launch_split_t3(int64_t K, int64_t N, const double* SA, void* out, hipStream_t s) {
+  if (K <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((K + kT - 1) / kT), (unsigned)((N + kT - 1) / kT));
+  split_t3_kernel<<<grid, 256, 0, s>>>(K, N, SA, static_cast<uint32_t*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_xgemm(int64_t M, int64_t N, int64_t K, const void* Ap, const void* Bp, double* C, int64_t ldc,
+                        int splits, double* partial, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (K % 8 != 0) return hipErrorInvalidValue;  // 16-byte pieces of k
+  if (splits < 1) splits = 1;
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + TK - 1) / TK * TK;
+  const int64_t ldk = K;  // rows of the parts are exactly K elements (K even)
+  const int64_t apstride = M * ldk, bpstride = N * ldk;
+  const int64_t pairs = ((M + TM - 1) / TM) * splits;
+  const int64_t ntl = (N + TN - 1) / TN;
+  xgemm_kernel<<<(unsigned)(pairs * ntl), kThreads, 0, s>>>(
+      M, N, K, ldk, static_cast<const __hip_bfloat16*>(Ap), apstride, static_cast<const __hip_bfloat16*>(Bp),
+      bpstride, C, ldc, splits, kchunk, partial);
+  if (splits > 1) {
+    const int64_t total = M * N;
+    xgemm_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, partial, C, ldc);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lev

@@ -84,15 +84,51 @@ def test_sketch_integer_matrix_bit_exact(gpu, dtype, n, d):
     np.testing.assert_array_equal(SA.cpu().numpy(), SA_o)   # integer sums are exact in FP64
     G = C.gaussian_transform(rnd, m)
     At_o = G @ SA_o
-    bound = 1e-13 * (np.abs(G) @ np.abs(SA_o)) + 1e-300
-    assert np.all(np.abs(At.cpu().numpy() - At_o) <= bound)
+    if dtype == torch.bfloat16:
+        # the FP32-level transform of BF16-stored A: both operands rounded to
+        # FP32 and split exactly into three BF16 parts (2^-24 each, the
+        # dropped part products below 2^-24 too), sums in FP32 within 32-wide
+        # K steps of six products (worst case gamma_192 u_32 ~ 1.2e-5 of the
+        # absolute sum), FP64 beyond
+        rel = 1.2e-5 + 4 * 2.0 ** -24
+    else:
+        rel = 1e-13  # FP64 GEMM
+    bound = rel * (np.abs(G) @ np.abs(SA_o)) + 1e-300
+    err = np.abs(At.cpu().numpy() - At_o)
+    _log("sketch transform max err / bound", (err / bound).max())
+    assert np.all(err <= bound)
+
+
+@pytest.mark.parametrize("m,r_cs,d", [(2048, 16384, 1024), (256, 8200, 100), (40, 72, 33)])
+def test_transform_fp32_level_bf16(gpu, m, r_cs, d):
+    """The FP32-level Gaussian transform (BF16-stored A) on Gaussian data at
+    the BF16 workload's sketch shape and at ragged shapes (tiles not full,
+    one split): relative error about 2^-24 of |G| |S A| on average, and
+    never above the worst-case bound of the FP32 sums within a K step."""
+    n = max(4 * r_cs, 2 * d)
+    A = W.row_scaled_bf16(n, d, m + d)
+    ld = (d + 7) // 8 * 8  # rows padded to 16 bytes
+    buf = torch.zeros(n, ld, dtype=torch.bfloat16, device=gpu)
+    buf[:, :d] = A.to(gpu)
+    At, SA = api.lev_sketch(buf[:, :d], 41, r_cs, m, return_sa=True)
+    rnd = C.derive(41, n, r_cs)
+    SA_o = L.countsketch_apply(rnd, A.to(torch.float64).numpy())
+    # S A itself is the FP64 sum of pass 1 (checked bit for bit elsewhere)
+    np.testing.assert_allclose(SA.cpu().numpy(), SA_o, rtol=1e-12, atol=1e-12)
+    G = C.gaussian_transform(rnd, m)
+    At_o = G @ SA.cpu().numpy()  # the transform alone, on the GPU's own S A
+    scale = np.abs(G) @ np.abs(SA.cpu().numpy()) + 1e-300
+    r = np.abs(At.cpu().numpy() - At_o) / scale
+    _log("x3 transform", m, r_cs, d, "max", r.max(), "mean", r.mean())
+    assert r.max() <= 1.2e-5 + 4 * 2.0 ** -24 and r.mean() < 1e-7
 
 
 def test_sketch_is_deterministic(gpu):
-    A = W.dense_gaussian(30000, 128, 5, dtype=torch.float32).to(gpu)
-    a1 = api.lev_sketch(A, 3, 1024, 256)
-    a2 = api.lev_sketch(A, 3, 1024, 256)
-    assert torch.equal(a1, a2)
+    for dt, d in ((torch.float32, 128), (torch.bfloat16, 256)):
+        A = W.dense_gaussian(30000, d, 5, dtype=dt).to(gpu)
+        a1 = api.lev_sketch(A, 3, 1024, 256)
+        a2 = api.lev_sketch(A, 3, 1024, 256)
+        assert torch.equal(a1, a2)
 
 
 # ------------------------------------------------------------------ rank-revealing QR
