@@ -57,6 +57,14 @@ __device__ __forceinline__ double wave_max_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
+// waits for every outstanding global store to be acknowledged; inside the
+// pivot loop the waves exchange data through LDS alone, and the R rows they
+// store to global memory are not read back before the kernel ends.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // flags[0] = done, flags[1] = pivots computed so far.
 __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __restrict__ S, int64_t d,
                                                               double zeta, int64_t J0,
@@ -101,7 +109,10 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
       wv[j & 1][wave] = hit != 0 ? wmax : -INFINITY;
       wi[j & 1][wave] = hit != 0 ? wave * 64 + (__ffsll((unsigned long long)hit) - 1) : 0x7fffffff;
     }
-    __syncthreads();
+    // (LDS-only barriers: the R rows this kernel stores are read by later
+    // launches only, and waiting for their acknowledgement at every pivot
+    // step would put a global-store round trip into each step)
+    lds_barrier();
     // the workgroup's pivot, found by every wave: lane w takes wave w's
     // candidate; the largest value wins, ties to the lowest wave (whose
     // columns are the lower ones)
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
 #pragma unroll
       for (int t = 0; t < j; ++t) bc[t] = rp[t];
     }
-    __syncthreads();
+    lds_barrier();
     double val = 0.0;
     if (c == p) {
       val = rjj;
@@ -214,13 +225,6 @@ __device__ inline void small_rect(int w, int d, int& a_out, int& b_out) {
   b_out = 0;
 }
 
-// Workgroup barrier that orders LDS traffic only.  __syncthreads() also
-// waits for every outstanding global store to be acknowledged; inside the
-// pivot loop the waves exchange data through LDS alone, and the R rows they
-// store to global memory are not read back before the kernel ends.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
 
 // The pivot of the next step, posted by the diagonal wave.
 struct __align__(16) PivotMsg {
