@@ -99,7 +99,9 @@ typedef struct {
  *  r_cs  -- rows of the CountSketch S (Algorithm 3's r).  >= 1.
  *  m     -- rows of the Gaussian transform G (Algorithm 3's m = ceil(gamma d)).
  *           d <= m required.
- *  k     -- columns of the JL Gaussian Pi_2 (Algorithm 8's r_2).  1..64.
+ *  k     -- columns of the JL Gaussian Pi_2 (Algorithm 8's r_2).  1..4096
+ *           (the backward pass takes k <= 64).  Ignored unless mode is
+ *           LEV_MODE_JL.  Pass 2 makes one pass over A per 64 columns.
  *  zeta  -- rank tolerance: the revealed rank is r = #{ j : R_jj > zeta R_00 }
  *           on the column-pivoted factor of the sketch (the cutoff rule of
  *           Section 7).  Supported: 1e-10 <= zeta < 1 (1e-10 is the FP64
@@ -107,20 +109,30 @@ typedef struct {
  *           LEV_ERR_NOT_SUPPORTED, values outside [0, 1) LEV_ERR_ARG.
  *           (lev_sketch ignores zeta.)
  *  az_precision -- LEV_AZ_* above.
- *  exact -- 0: Algorithm 10 (LS-HRN-approx, the JL estimate with k
- *           columns).  1: Algorithm 7 (LS-HRN-exact): the same columns K
- *           and rank from the sketch, then the exact leverage scores of A_K
- *           from B = A_K^T A_K (one more pass over A); k is ignored.  Dense
- *           FP32/FP64 A with d <= 64 only (LEV_ERR_NOT_SUPPORTED /
- *           LEV_ERR_DTYPE / LEV_ERR_SHAPE otherwise); lev_estimate's
- *           state_out must be NULL (no backward). */
+ *  mode  -- what lev_estimate returns (LEV_MODE_* below); lev_estimate's
+ *           state_out must be NULL unless mode is LEV_MODE_JL. */
 typedef struct {
   uint64_t seed;
   int64_t r_cs, m, k;
   double zeta;
   int32_t az_precision;
-  int32_t exact;
+  int32_t mode;
 } lev_params;
+
+/* LEV_MODE_JL: Algorithm 10 (LS-HRN-approx): theta~_i = ||e_i^T A_K
+ *   R11^{-1} Pi_2||^2 with the k-column JL Gaussian Pi_2.
+ * LEV_MODE_NOJL: the same estimator without the JL step (Pi_2 = I, i.e.
+ *   Algorithm 8 with r_2 = r): theta'_i = ||e_i^T A_K R11^{-1}||^2, the
+ *   estimate the JL step approximates; pass 2 runs over ceil(r / 64) column
+ *   tiles.
+ * LEV_MODE_EXACT: Algorithm 7 (LS-HRN-exact): the same columns K and rank r
+ *   from the sketch, then the exact leverage scores of A_K from B = A_K^T
+ *   A_K (Algorithm 5's Gram route): one more pass over A for B (dense: FP64
+ *   matrix cores, 2 n d^2 flops; CSR: sum_i nnz_i^2 products), the pivoted
+ *   Cholesky B_K P2 = R_B^T R_B, and theta~_i = ||e_i^T A_K P2 R_B^{-1}||^2
+ *   over ceil(r / 64) column tiles.  The CSR Gram adds its FP64 products
+ *   with LDS atomics, so its last bits can differ between runs. */
+enum { LEV_MODE_JL = 0, LEV_MODE_EXACT = 1, LEV_MODE_NOJL = 2 };
 
 /* Workspace bytes needed by lev_sketch (which = LEV_WS_SKETCH),
  * lev_estimate (LEV_WS_ESTIMATE) or lev_estimate_backward (LEV_WS_BACKWARD)

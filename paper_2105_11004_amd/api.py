@@ -47,7 +47,7 @@ class LevMatrix(ctypes.Structure):
 
 class LevParams(ctypes.Structure):
     _fields_ = [("seed", c_uint64), ("r_cs", c_int64), ("m", c_int64), ("k", c_int64),
-                ("zeta", c_double), ("az_precision", c_int32), ("exact", c_int32)]
+                ("zeta", c_double), ("az_precision", c_int32), ("mode", c_int32)]
 
 
 class LevError(RuntimeError):
@@ -185,11 +185,22 @@ def _matrix(A) -> LevMatrix:
     return LevMatrix(DENSE, _DTYPES[A.dtype], A.shape[0], A.shape[1], ld, 0, A.data_ptr(), None, None)
 
 
-def _params(seed, r_cs, m, k, zeta, precision, exact=False) -> LevParams:
+# lev_params.mode: the JL estimate (Algorithm 10), the exact scores of A_K
+# (Algorithm 7) or the estimate without the JL step (Pi_2 = I).
+MODES = {"jl": 0, "exact": 1, "nojl": 2}
+
+
+def _params(seed, r_cs, m, k, zeta, precision, mode="jl") -> LevParams:
     if precision not in AZ:
         raise ValueError(f"precision must be one of {list(AZ)}")
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {list(MODES)}")
     return LevParams(int(seed) & ((1 << 64) - 1), int(r_cs), int(m), int(k), float(zeta), AZ[precision],
-                     1 if exact else 0)
+                     MODES[mode])
+
+
+def _mode(mode: str, exact: bool) -> str:
+    return "exact" if exact else mode
 
 
 def _workspace(nbytes: int, device) -> tuple[torch.Tensor, c_void_p]:
@@ -307,16 +318,18 @@ def lev_rank_estimate(At: torch.Tensor, zeta: float):
 
 
 def lev_estimate(A, seed: int, r_cs: int, m: int, k: int, zeta: float,
-                 precision: str = "native", return_state: bool = False, exact: bool = False):
+                 precision: str = "native", return_state: bool = False, exact: bool = False,
+                 mode: str = "jl"):
     """Algorithm 10 (LS-HRN-approx): theta~ (FP64 for FP64 A, else FP32).
-    A is a dense device tensor or a CSR matrix (see lev_sketch).  exact=True
-    runs Algorithm 7 (LS-HRN-exact) instead: the exact leverage scores of the
-    columns K the sketch selects (dense FP32/FP64, d <= 64; k is ignored,
-    no state)."""
+    A is a dense device tensor or a CSR matrix (see lev_sketch).
+    mode="exact" (or exact=True) runs Algorithm 7 (LS-HRN-exact) instead:
+    the exact leverage scores of the columns K the sketch selects;
+    mode="nojl" the estimate without the JL step, ||e_i^T A_K R11^{-1}||^2.
+    Both ignore k and have no state."""
     lib = load_library()
     A = _as_csr(A)  # held until the call returns: it owns converted index arrays
     dev, (n, d), dt = _device(A), _shape(A), _dtype(A)
-    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, exact)
+    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, _mode(mode, exact))
     nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_ESTIMATE)
     if nbytes == 0:
         _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))
@@ -350,10 +363,10 @@ class EstimatePlan:
     """Pre-allocated workspace and outputs for repeated lev_estimate calls on
     same-shaped inputs (what the benchmark times)."""
 
-    def __init__(self, A, seed, r_cs, m, k, zeta, precision="native", exact=False):
+    def __init__(self, A, seed, r_cs, m, k, zeta, precision="native", exact=False, mode="jl"):
         self.lib = load_library()
         A = _as_csr(A)  # kept in self.A: the pointers below refer to its arrays
-        self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, exact)
+        self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, _mode(mode, exact))
         self.nbytes = self.lib.lev_workspace_size(ctypes.byref(self.mat), ctypes.byref(self.par), WS_ESTIMATE)
         if self.nbytes == 0:
             _check(self.lib.lev_estimate(ctypes.byref(self.mat), ctypes.byref(self.par), None, None, None, 0,

@@ -710,15 +710,6 @@ hipError_t grad_typed(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k
 }
 
 // ---- LS-HRN-exact (Algorithm 7) helpers -----------------------------------------
-// Z_full = I as the operand of the C pass (d x 64 of T): with w = 1 the pass
-// then computes C = A^T A.
-template <typename T>
-__global__ void identity_rows_kernel(int64_t d, T* __restrict__ out) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= d * kZCols) return;
-  out[idx] = (idx / kZCols == idx % kZCols) ? (T)1 : (T)0;
-}
-
 // B_K[i][j] = C[perm[i]][perm[j]] for i, j < r, else 0 (d x d).
 __global__ void gather_bk_kernel(int64_t d, const int32_t* __restrict__ perm, const int64_t* __restrict__ rank,
                                  const double* __restrict__ C, double* __restrict__ B) {
@@ -811,13 +802,6 @@ hipError_t launch_bwd_grad(int dtype, const void* A, int64_t n, int64_t d, int64
   if (dtype == 0) return grad_typed<double>(A, n, d, ld, k, w, Zfull, Hfull, hp, G, ldg, s);
   if (dtype == 1) return grad_typed<float>(A, n, d, ld, k, w, Zfull, Hfull, hp, G, ldg, s);
   return hipErrorInvalidValue;
-}
-
-hipError_t launch_identity_rows(int dtype, int64_t d, void* out, hipStream_t s) {
-  const unsigned blocks = (unsigned)((d * kZCols + 255) / 256);
-  if (dtype == 0) identity_rows_kernel<double><<<blocks, 256, 0, s>>>(d, static_cast<double*>(out));
-  else identity_rows_kernel<float><<<blocks, 256, 0, s>>>(d, static_cast<float*>(out));
-  return hipGetLastError();
 }
 
 hipError_t launch_gather_bk(int64_t d, const int32_t* perm, const int64_t* rank, const double* C, double* B,

@@ -14,6 +14,7 @@
 // and B[l / 16][l % 16]; accumulator element v of lane l is
 // C[(l / 16) + 4 * v][l % 16] (measured on gfx950; the f32 and bf16 forms
 // use row 4 * (l / 16) + v instead).
+#include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,9 +39,16 @@ struct Stage {
   double b[kPerThread];
 };
 
+__device__ __forceinline__ double to_f64(double x) { return x; }
+__device__ __forceinline__ double to_f64(float x) { return (double)x; }
+__device__ __forceinline__ double to_f64(__hip_bfloat16 x) { return (double)__bfloat162float(x); }
+
+// TI: element type of both operands in memory (FP64, or FP32 / BF16 widened
+// exactly to FP64 on load).
+template <typename TI>
 __device__ __forceinline__ void load_stage(Stage& st, int tid, int64_t m0, int64_t n0, int64_t k0, int64_t ke,
-                                           int64_t M, int64_t N, const double* __restrict__ A, int64_t sai,
-                                           int64_t sak, const double* __restrict__ B, int64_t sbk, int64_t sbj) {
+                                           int64_t M, int64_t N, const TI* __restrict__ A, int64_t sai,
+                                           int64_t sak, const TI* __restrict__ B, int64_t sbk, int64_t sbj) {
   const bool a_kfast = (sak == 1);
   const bool b_jfast = (sbj == 1);
 #pragma unroll
@@ -50,11 +58,11 @@ __device__ __forceinline__ void load_stage(Stage& st, int tid, int64_t m0, int64
     const int kk = a_kfast ? e % BK : e / BM;
     const int ii = a_kfast ? e / BK : e % BM;
     const int64_t gi = m0 + ii, gk = k0 + kk;
-    st.a[q] = (gi < M && gk < ke) ? A[gi * sai + gk * sak] : 0.0;
+    st.a[q] = (gi < M && gk < ke) ? to_f64(A[gi * sai + gk * sak]) : 0.0;
     const int kb = b_jfast ? e / BN : e % BK;
     const int jj = b_jfast ? e % BN : e / BK;
     const int64_t gj = n0 + jj, gk2 = k0 + kb;
-    st.b[q] = (gj < N && gk2 < ke) ? B[gk2 * sbk + gj * sbj] : 0.0;
+    st.b[q] = (gj < N && gk2 < ke) ? to_f64(B[gk2 * sbk + gj * sbj]) : 0.0;
   }
 }
 
@@ -91,10 +99,10 @@ __device__ __forceinline__ void store_stage(const Stage& st, int tid, double* __
 }
 
 // AK: A is contiguous in k (sak == 1); BJ: B is contiguous in j (sbj == 1).
-template <bool AK, bool BJ>
+template <bool AK, bool BJ, typename TI = double>
 __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
-                                                         const double* __restrict__ A, int64_t sai,
-                                                         int64_t sak, const double* __restrict__ B,
+                                                         const TI* __restrict__ A, int64_t sai,
+                                                         int64_t sak, const TI* __restrict__ B,
                                                          int64_t sbk, int64_t sbj, double beta,
                                                          double* __restrict__ C, int64_t ldc, int splits,
                                                          int64_t kchunk, double* __restrict__ partial,
@@ -223,6 +231,45 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const dou
     const int64_t total = M * N;
     splitk_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(M, N, splits, partial, alpha,
                                                                           beta, C, ldc, skip);
+  }
+  return hipGetLastError();
+}
+
+int gram_dense_splits(int64_t n, int64_t d) { return dgemm_choose_splits(d, d, n); }
+
+// A^T A: op(A)[i][k] = A[k][i] (strides 1, ld) and op(B)[k][j] = A[k][j]
+// (strides ld, 1), so both operand tiles are read along A's rows.
+hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, int splits,
+                             double* partial, double* B, hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  if (splits < 1) splits = 1;
+  int64_t kchunk = (n + splits - 1) / splits;
+  kchunk = std::max<int64_t>(BK, ((kchunk + BK - 1) / BK) * BK);
+  dim3 grid((unsigned)((d + BM - 1) / BM), (unsigned)((d + BN - 1) / BN), (unsigned)splits);
+  switch (dtype) {
+    case 0:
+      dgemm_kernel<false, true, double><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, static_cast<const double*>(A), 1,
+                                                                  ld, static_cast<const double*>(A), ld, 1, 0.0, B,
+                                                                  d, splits, kchunk, partial, nullptr);
+      break;
+    case 1:
+      dgemm_kernel<false, true, float><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, static_cast<const float*>(A), 1, ld,
+                                                                 static_cast<const float*>(A), ld, 1, 0.0, B, d,
+                                                                 splits, kchunk, partial, nullptr);
+      break;
+    case 2: {
+      const auto* a = static_cast<const __hip_bfloat16*>(A);
+      dgemm_kernel<false, true, __hip_bfloat16><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, a, 1, ld, a, ld, 1, 0.0, B, d,
+                                                                          splits, kchunk, partial, nullptr);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  if (splits > 1) {
+    const int64_t total = d * d;
+    splitk_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(d, d, splits, partial, 1.0, 0.0, B, d,
+                                                                          nullptr);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,169 @@
+// B = A^T A for CSR A in sum_i nnz_i^2 work: the Gram route of Algorithm 5
+// (and of Algorithm 7's exact scores), which costs the square of each row's
+// nonzero count instead of d^2 per row.
+//
+// Row i adds the outer product a_i a_i^T, i.e. a_ip a_iq at (c_p, c_q) for
+// every pair of its nonzeros.  B is cut into 128 x 128 tiles (I, J), I <= J
+// (B is symmetric); a workgroup owns one tile in LDS (FP64, 128 KB) and one
+// chunk of rows, and for each row adds the pairs with c_p in block I and
+// c_q in block J by LDS atomic adds.  Column ids are sorted within a row, so
+// the entries of a block are a contiguous run, found by counting ids below
+// the block bounds.  The tiles of all chunks are summed in chunk order into B
+// and mirrored below the diagonal.  FP32 and BF16 values give exact FP64
+// products; the order of the atomic adds inside a workgroup is not fixed, so
+// B's last bits can vary between runs.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "lev_internal.h"
+
+namespace lev {
+namespace {
+
+constexpr int kGT = 128;             // tile edge
+constexpr int kGThreads = 1024;      // 16 waves
+constexpr int kGWaves = kGThreads / 64;
+constexpr int kTargetGroups = 512;   // workgroups per launch (one per CU resident: 128 KB of LDS)
+constexpr size_t kTileBytes = sizeof(double) * kGT * kGT;
+
+__device__ __forceinline__ double val_f64(double x) { return x; }
+__device__ __forceinline__ double val_f64(float x) { return (double)x; }
+__device__ __forceinline__ double val_f64(__hip_bfloat16 x) { return (double)__bfloat162float(x); }
+
+int64_t blocks_per_side(int64_t d) { return (d + kGT - 1) / kGT; }
+int64_t tile_pairs(int64_t d) {
+  const int64_t nb = blocks_per_side(d);
+  return nb * (nb + 1) / 2;
+}
+int64_t row_chunks(int64_t n, int64_t d) {
+  const int64_t want = (kTargetGroups + tile_pairs(d) - 1) / tile_pairs(d);
+  return std::max<int64_t>(1, std::min<int64_t>(want, (n + 255) / 256));
+}
+
+// Tile pair q (0 <= q < nb (nb + 1) / 2) -> (I, J), I <= J, row-major over
+// the upper triangle.
+__device__ __forceinline__ void pair_of(int q, int nb, int& I, int& J) {
+  int i = 0, left = q;
+  while (left >= nb - i) {
+    left -= nb - i;
+    ++i;
+  }
+  I = i;
+  J = i + left;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kGThreads) void gram_csr_kernel(const T* __restrict__ vals,
+                                                             const int64_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ col_idx, int64_t n,
+                                                             int64_t d, int64_t nnz, int64_t rows_per_chunk,
+                                                             double* __restrict__ partial) {
+  extern __shared__ double tile[];  // kGT x kGT
+  const int nb = (int)((d + kGT - 1) / kGT);
+  int I, J;
+  pair_of((int)blockIdx.x, nb, I, J);
+  const int32_t I0 = I * kGT, J0 = J * kGT;
+  for (int e = threadIdx.x; e < kGT * kGT; e += kGThreads) tile[e] = 0.0;
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
+  const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
+  for (int64_t i = r0 + wave; i < r1; i += kGWaves) {
+    // row extent clamped to [0, nnz] (a malformed row_ptr gives a wrong B, no stray access)
+    const int64_t s = std::min<int64_t>(std::max<int64_t>(row_ptr[i], 0), nnz);
+    const int64_t e = std::max<int64_t>(s, std::min<int64_t>(std::max<int64_t>(row_ptr[i + 1], 0), nnz));
+    // positions of the runs [I0, I0 + kGT) and [J0, J0 + kGT) among the row's sorted ids
+    int loI = 0, hiI = 0, loJ = 0, hiJ = 0;
+    for (int64_t c0 = s; c0 < e; c0 += 64) {
+      const int64_t p = c0 + lane;
+      const int32_t c = p < e ? col_idx[p] : INT32_MAX;
+      loI += __popcll(__ballot(c < I0));
+      hiI += __popcll(__ballot(c < I0 + kGT));
+      loJ += __popcll(__ballot(c < J0));
+      hiJ += __popcll(__ballot(c < J0 + kGT));
+    }
+    const int lI = hiI - loI, lJ = hiJ - loJ;
+    if (lI == 0 || lJ == 0) continue;
+    // pairs (p, q): lanes in groups of gs (a power of two >= lJ, at most 64)
+    // over q, 64 / gs groups over p
+    const int gs = lJ >= 64 ? 64 : (1 << (32 - __clz(lJ - 1)));
+    const int gq = lane & (gs - 1), gp = lane / gs, ng = 64 / gs;
+    for (int pb = 0; pb < lI; pb += ng) {
+      const int p = pb + gp;
+      if (p >= lI) continue;
+      const int64_t pp = s + loI + p;
+      const int32_t cp = col_idx[pp];
+      const double vp = val_f64(vals[pp]);
+      if ((uint32_t)(cp - I0) >= (uint32_t)kGT) continue;  // ids >= d or unsorted rows: skipped
+      for (int qb = 0; qb < lJ; qb += gs) {
+        const int q = qb + gq;
+        if (q >= lJ) break;
+        const int64_t qq = s + loJ + q;
+        const int32_t cq = col_idx[qq];
+        if ((uint32_t)(cq - J0) >= (uint32_t)kGT || cq >= d || cp >= d) continue;
+        atomicAdd(&tile[(cp - I0) * kGT + (cq - J0)], vp * val_f64(vals[qq]));
+      }
+    }
+  }
+  __syncthreads();
+  double* out = partial + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * (kGT * kGT);
+  for (int e = threadIdx.x; e < kGT * kGT; e += kGThreads) out[e] = tile[e];
+}
+
+// B[I0 + a][J0 + b] = sum over chunks (ascending) of the tiles of pair (I, J),
+// and B[J0 + b][I0 + a] the same for I < J.
+__global__ void gram_csr_reduce_kernel(int64_t d, int64_t chunks, const double* __restrict__ partial,
+                                       double* __restrict__ B) {
+  const int nb = (int)((d + kGT - 1) / kGT);
+  int I, J;
+  pair_of((int)blockIdx.y, nb, I, J);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kGT * kGT) return;
+  const int64_t r = (int64_t)I * kGT + e / kGT, c = (int64_t)J * kGT + e % kGT;
+  if (r >= d || c >= d) return;
+  const double* src = partial + (int64_t)blockIdx.y * chunks * (kGT * kGT) + e;
+  double acc = 0.0;
+  for (int64_t q = 0; q < chunks; ++q) acc += src[q * (kGT * kGT)];
+  B[r * d + c] = acc;
+  if (I != J) B[c * d + r] = acc;
+}
+
+template <typename T>
+hipError_t launch_typed(const void* vals, const int64_t* row_ptr, const int32_t* col_idx, int64_t n, int64_t d,
+                        int64_t nnz, double* partial, double* B, hipStream_t s) {
+  const int64_t pairs = tile_pairs(d), chunks = row_chunks(n, d);
+  const int64_t rows_per_chunk = (n + chunks - 1) / chunks;
+  auto kern = gram_csr_kernel<T>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileBytes);
+  if (e != hipSuccess) return e;
+  kern<<<dim3((unsigned)pairs, (unsigned)chunks), kGThreads, kTileBytes, s>>>(
+      static_cast<const T*>(vals), row_ptr, col_idx, n, d, nnz, rows_per_chunk, partial);
+  gram_csr_reduce_kernel<<<dim3((kGT * kGT + 255) / 256, (unsigned)pairs), 256, 0, s>>>(d, chunks, partial, B);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t gram_csr_partial_elems(int64_t n, int64_t d) {
+  return (size_t)tile_pairs(d) * (size_t)row_chunks(n, d) * (size_t)(kGT * kGT);
+}
+
+hipError_t launch_gram_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
+                           int64_t n, int64_t d, int64_t nnz, double* partial, double* B, hipStream_t s) {
+  if (d <= 0) return hipSuccess;
+  if (n <= 0 || nnz <= 0) return launch_fill_zero(B, sizeof(double) * (size_t)(d * d), s);
+  switch (dtype) {
+    case 0: return launch_typed<double>(vals, row_ptr, col_idx, n, d, nnz, partial, B, s);
+    case 1: return launch_typed<float>(vals, row_ptr, col_idx, n, d, nnz, partial, B, s);
+    case 2: return launch_typed<__hip_bfloat16>(vals, row_ptr, col_idx, n, d, nnz, partial, B, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lev

@@ -109,7 +109,8 @@ constexpr double kZetaGram = 1e-5;
 constexpr double kZetaMin = 1e-10;
 constexpr int64_t kMaxRows = (1ll << 31) - 2;  // row ids + sign bit in 32 bits
 constexpr int64_t kMaxD = 1024;
-constexpr int64_t kMaxK = 64;
+constexpr int64_t kMaxK = 4096;    // JL columns (pass 2 runs one pass per 64)
+constexpr int64_t kMaxBwdK = 64;  // the backward's register tiles
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -191,20 +192,21 @@ lev_status check_params(const lev_matrix* A, const lev_params* p, bool uses_zeta
   if (p->r_cs < 1 || p->r_cs > kMaxRows) return fail(LEV_ERR_ARG, "r_cs = %lld out of range", (long long)p->r_cs);
   if (p->m < A->d) return fail(LEV_ERR_SHAPE, "m = %lld < d = %lld", (long long)p->m, (long long)A->d);
   if (p->m > (1ll << 24)) return fail(LEV_ERR_SHAPE, "m too large");
-  if (p->k < 1 || p->k > kMaxK) return fail(LEV_ERR_ARG, "k = %lld outside [1, 64]", (long long)p->k);
+  if (p->mode != LEV_MODE_JL && p->mode != LEV_MODE_EXACT && p->mode != LEV_MODE_NOJL)
+    return fail(LEV_ERR_ARG, "mode %d is not LEV_MODE_JL, LEV_MODE_EXACT or LEV_MODE_NOJL", p->mode);
+  if (p->mode == LEV_MODE_JL && (p->k < 1 || p->k > kMaxK))
+    return fail(LEV_ERR_ARG, "k = %lld outside [1, %lld]", (long long)p->k, (long long)kMaxK);
   if (!(p->zeta >= 0.0 && p->zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
   if (uses_zeta && p->zeta < kZetaMin)
     return fail(LEV_ERR_NOT_SUPPORTED, "zeta = %g is below the smallest supported rank cutoff %g", p->zeta, kZetaMin);
   if (az_variant(A->format, A->dtype, p->az_precision) < 0)
     return fail(LEV_ERR_ARG, "az_precision %d not valid for dtype %d", p->az_precision, A->dtype);
-  if (p->exact != 0 && p->exact != 1) return fail(LEV_ERR_ARG, "exact must be 0 or 1");
-  if (p->exact) {
-    if (A->format != LEV_DENSE_ROWMAJOR) return fail(LEV_ERR_NOT_SUPPORTED, "exact scores take dense A only");
-    if (A->dtype != LEV_F32 && A->dtype != LEV_F64) return fail(LEV_ERR_DTYPE, "exact scores take FP32 or FP64 A");
-    if (A->d > 64) return fail(LEV_ERR_SHAPE, "exact scores need d <= 64 (d = %lld)", (long long)A->d);
-  }
   return LEV_OK;
 }
+
+// Columns of the pass-2 operand Z: the JL columns k, or (no JL step, exact
+// scores) all d columns of R11^{-1}, of which the first r can be nonzero.
+int64_t pass2_cols(const lev_matrix* A, const lev_params* p) { return p->mode == LEV_MODE_JL ? p->k : A->d; }
 
 lev_status check_ws(const void* ws, size_t have, size_t need) {
   if (need > have) return fail(LEV_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", have, need);
@@ -514,12 +516,10 @@ BwdBufs carve_bwd(Carver& c, const lev_matrix* A, const lev_params* p) {
   return b;
 }
 
-// LS-HRN-exact (Algorithm 7): the C pass's buffers for B = A^T A, and a
-// second pivoted Cholesky (of B_K) with its outputs.
+// LS-HRN-exact (Algorithm 7): B = A^T A and its partial sums, and a second
+// pivoted Cholesky (of B_K) with its outputs.
 struct ExactBufs {
-  void* ZI;
-  void* partials;
-  int groups;
+  double* gram_partial;
   double* C64;
   RankBufs rb2;
   int32_t* perm2;
@@ -529,14 +529,15 @@ struct ExactBufs {
   double* I;
 };
 
+size_t gram_partial_elems(const lev_matrix* A) {
+  if (A->format == LEV_CSR) return lev::gram_csr_partial_elems(A->n, A->d);
+  return lev::dgemm_partial_elems(A->d, A->d, lev::gram_dense_splits(A->n, A->d));
+}
+
 ExactBufs carve_exact(Carver& c, const lev_matrix* A, const lev_params* p) {
-  const int64_t n = A->n, d = A->d, m = p->m;
-  const int dt = A->dtype == LEV_F64 ? 0 : 1;
-  const size_t es = lev::bwd_elem_size(dt);
+  const int64_t d = A->d, m = p->m;
   ExactBufs b;
-  b.groups = lev::bwd_groups(dt, n, d, d);
-  b.ZI = c.take<char>((size_t)d * 64 * es);
-  b.partials = c.take<char>((size_t)b.groups * (size_t)d * 64 * es);
+  b.gram_partial = c.take<double>(std::max<size_t>(1, gram_partial_elems(A)));
   b.C64 = c.take<double>((size_t)(d * d));
   b.rb2 = carve_rank(c, m, d);
   b.perm2 = c.take<int32_t>((size_t)d);
@@ -547,7 +548,10 @@ ExactBufs carve_exact(Carver& c, const lev_matrix* A, const lev_params* p) {
   return b;
 }
 
-lev_status check_backward_input(const lev_matrix* A) {
+lev_status check_backward_input(const lev_matrix* A, const lev_params* p) {
+  if (p->mode != LEV_MODE_JL) return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass is of the JL estimate only");
+  if (p->k > kMaxBwdK)
+    return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass takes k <= %lld", (long long)kMaxBwdK);
   if (A->format != LEV_DENSE_ROWMAJOR)
     return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass takes dense A only");
   if (A->dtype != LEV_F32 && A->dtype != LEV_F64)
@@ -646,7 +650,7 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
     carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
     return c.used;
   }
-  if (which == LEV_WS_ESTIMATE && p->exact) {
+  if (which == LEV_WS_ESTIMATE && p->mode == LEV_MODE_EXACT) {
     carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
     carve_rank(c, m, d);
     if (p->zeta < kZetaGram) carve_refine(c, m, d);
@@ -659,13 +663,14 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
     carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
     carve_rank(c, m, d);
     if (p->zeta < kZetaGram) carve_refine(c, m, d);
-    c.take<char>(state_bytes(d, m, k));
-    c.take<double>((size_t)(d * k));  // G_k
-    c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, k));
+    const int64_t kz = pass2_cols(A, p);
+    c.take<char>(state_bytes(d, m, kz));
+    c.take<double>((size_t)(d * kz));  // G_k (identity without the JL step)
+    c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, kz));
     return c.used;
   }
   if (which == LEV_WS_BACKWARD) {
-    if (check_backward_input(A) != LEV_OK) return 0;
+    if (check_backward_input(A, p) != LEV_OK) return 0;
     carve_bwd(c, A, p);
     return c.used;
   }
@@ -705,19 +710,19 @@ lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta
   return enqueue_rank(At, m, d, zeta, b, perm_out, R_out, rank_out, stream, &rf);
 }
 
-// Algorithm 7 (LS-HRN-exact) on dense FP32/FP64 A with d <= 64: the columns K
-// and the rank from Algorithm 4 on the sketch (as for Algorithm 10), then
-// B = A^T A in one pass over A (the backward's C pass with w = 1 and
-// Z_full = I), B_K = B[K, K], its pivoted Cholesky (A_K P2)^T (A_K P2) =
-// R_B^T R_B, Z = R_B^{-1} and theta~_i = ||e_i^T A_K P2 R_B^{-1}||^2 in pass
-// 2.  A_K P2 R_B^{-1} and Algorithm 7's A_K V Sigma^{-1} are both orthonormal
-// bases of range(A_K), so the row norms are the same.  The Cholesky runs with
+// Algorithm 7 (LS-HRN-exact): the columns K and the rank from Algorithm 4
+// on the sketch (as for Algorithm 10), then B = A^T A in one more pass over
+// A (Algorithm 5's Gram route: FP64 matrix cores for dense A, sum_i nnz_i^2
+// products for CSR), B_K = B[K, K], its pivoted Cholesky (A_K P2)^T (A_K P2)
+// = R_B^T R_B, Z = R_B^{-1} and theta~_i = ||e_i^T A_K P2 R_B^{-1}||^2 in
+// pass 2 over the column tiles of Z that lie below the rank.  A_K P2
+// R_B^{-1} and Algorithm 7's A_K V Sigma^{-1} are both orthonormal bases of
+// range(A_K), so the row norms are the same.  The Cholesky runs with
 // zeta = 0: B_K's rows and columns past the rank are exact zeros, where it
 // stops.
 lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant, void* theta_out, void* ws,
                           hipStream_t stream) {
   const int64_t n = A->n, d = A->d, m = p->m, r_cs = p->r_cs;
-  const int dt = A->dtype == LEV_F64 ? 0 : 1;
   hipStream_t s = stream;
   Carver c(ws);
   SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true, use_x3_transform(A, r_cs));
@@ -739,9 +744,12 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, nullptr, s));
   LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, s, refine ? &rf : nullptr));
   LEV_HIP(mark_phase(4, s));
-  LEV_HIP(lev::launch_identity_rows(dt, d, eb.ZI, s));
-  if (n > 0) {
-    LEV_HIP(lev::launch_bwd_gram(dt, A->values, n, d, A->ld, d, nullptr, eb.ZI, eb.partials, eb.groups, eb.C64, s));
+  if (A->format == LEV_CSR) {
+    LEV_HIP(lev::launch_gram_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, eb.gram_partial,
+                                 eb.C64, s));
+  } else if (n > 0) {
+    LEV_HIP(lev::launch_gram_dense(A->dtype, A->values, n, d, A->ld, lev::gram_dense_splits(n, d),
+                                   eb.gram_partial, eb.C64, s));
   } else {
     LEV_HIP(lev::launch_fill_zero(eb.C64, sizeof(double) * (size_t)(d * d), s));
   }
@@ -753,7 +761,10 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   LEV_HIP(lev::launch_identity(d, eb.I, s));
   LEV_HIP(lev::launch_form_z(variant, d, d, eb.R2, eb.rank2, eb.permc, eb.I, sv.Z64, Zpack, err, s));
   LEV_HIP(mark_phase(5, s));
-  if (n > 0) {
+  if (n > 0 && A->format == LEV_CSR) {
+    LEV_HIP(lev::launch_rownorm_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, d, Zpack, eb.rank2,
+                                    theta_out, s));
+  } else if (n > 0) {
     LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, d, Zpack, eb.rank2, theta_out, s));
   }
   LEV_HIP(mark_phase(6, s));
@@ -769,13 +780,16 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   LEV_TRY(check_ws(ws, ws_bytes, need));
   if (state_out != nullptr && (reinterpret_cast<uintptr_t>(state_out) & (kAlign - 1)) != 0)
     return fail(LEV_ERR_ARG, "state_out must be 256-byte aligned");
+  if (state_out != nullptr && p->mode != LEV_MODE_JL)
+    return fail(LEV_ERR_NOT_SUPPORTED, "only the JL estimate (LEV_MODE_JL) has a backward state");
 
-  const int64_t n = A->n, d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
+  const int64_t n = A->n, d = A->d, m = p->m, r_cs = p->r_cs;
   const int variant = az_variant(A->format, A->dtype, p->az_precision);
-  if (p->exact) {
-    if (state_out != nullptr) return fail(LEV_ERR_NOT_SUPPORTED, "exact scores have no backward state");
-    return estimate_exact(A, p, variant, theta_out, ws, stream);
-  }
+  if (p->mode == LEV_MODE_EXACT) return estimate_exact(A, p, variant, theta_out, ws, stream);
+  // JL: Z = R11^{-1} G_k (k columns, all live).  No JL step: Z = R11^{-1}
+  // [I_r 0] (d columns, the first r live).
+  const bool jl = p->mode == LEV_MODE_JL;
+  const int64_t k = pass2_cols(A, p);
   Carver c(ws);
   SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true, use_x3_transform(A, r_cs));
   RankBufs rb = carve_rank(c, m, d);
@@ -789,20 +803,22 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   int64_t* rank = sv.header + 4;
   int32_t* err = state_err(sv);
   rb.pc.err = err;
+  const int64_t* live = jl ? nullptr : rank;
 
   const lev::SeedDraws dr = lev::derive_draws(p->seed, n, r_cs);
   LEV_HIP(mark_phase(0, stream));
   LEV_HIP(lev::launch_fill_zero(sv.header + 5, sizeof(int64_t), stream));
-  LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, Gk, stream));
+  LEV_TRY(enqueue_sketch(A, p, dr, sb, sb.SA, sv.At, jl ? Gk : nullptr, stream));
   LEV_TRY(enqueue_rank(sv.At, m, d, p->zeta, rb, sv.perm, sv.R, rank, stream, refine ? &rf : nullptr));
   LEV_HIP(mark_phase(4, stream));
+  if (!jl) LEV_HIP(lev::launch_identity(d, Gk, stream));
   LEV_HIP(lev::launch_form_z(variant, d, k, sv.R, rank, sv.perm, Gk, sv.Z64, Zpack, err, stream));
   LEV_HIP(mark_phase(5, stream));
   if (n > 0 && A->format == LEV_CSR) {
-    LEV_HIP(lev::launch_rownorm_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, Zpack, theta_out,
-                                    stream));
+    LEV_HIP(lev::launch_rownorm_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, k, Zpack, live,
+                                    theta_out, stream));
   } else if (n > 0) {
-    LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, k, Zpack, rank, theta_out,
+    LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, k, Zpack, live, theta_out,
                                       stream));
   }
   LEV_HIP(mark_phase(6, stream));
@@ -816,7 +832,7 @@ lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const
                                  void* gradA_out, void* ws, size_t ws_bytes, hipStream_t stream) {
   LEV_TRY(check_matrix(A));
   LEV_TRY(check_params(A, p));
-  LEV_TRY(check_backward_input(A));
+  LEV_TRY(check_backward_input(A, p));
   if (state == nullptr) return fail(LEV_ERR_ARG, "state is null");
   if ((reinterpret_cast<uintptr_t>(state) & (kAlign - 1)) != 0)
     return fail(LEV_ERR_ARG, "state must be 256-byte aligned");

@@ -125,7 +125,11 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
 
 // Prepares the operand of pass 2: Z_full (d x k, rows indexed by original
 // column, zero off K) converted to the pass-2 compute type and laid out for
-// the MFMA B-operand; see rownorm.hip for the layouts.
+// the MFMA B-operand; see rownorm.hip for the layouts.  For k > 64 the
+// operand is a sequence of column tiles of 64 (the last one ragged), each
+// packed as if it were the whole of a k <= 64 operand: tile t starts at
+// byte pack_z_tile_offset(variant, d, k, t), and pass 2 makes one pass over
+// A per tile (ColTile below).
 // variant: 0 = FP64, 1 = FP32, 2 = BF16, 3 = BF16 hi/lo, 4 = BF16x3 (FP32 A),
 // 5 = FP32 row-major d x 64 (CSR pass 2), 6 = FP64 row-major d x 64 (CSR).
 // pack_z_bytes: workspace needed (operand + an inverse permutation);
@@ -139,23 +143,50 @@ hipError_t launch_form_z(int variant, int64_t d, int64_t k, const double* R, con
                          const int32_t* perm, double* Gk, double* Z64, void* Zpack, int32_t* err,
                          hipStream_t s);
 size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k);
+constexpr int64_t kZTile = 64;
+inline int64_t z_tiles(int64_t k) { return (k + kZTile - 1) / kZTile; }
+size_t pack_z_tile_offset(int variant, int64_t d, int64_t k, int64_t t);
+
+// One column tile of pass 2 (k > 64 runs one pass per tile of 64 columns).
+// live (device, may be null): the number of leading columns of Z that can
+// be nonzero; the pass returns at once when *live <= c0 (its tile is all
+// zero).  acc != 0: theta += the tile's squares instead of theta = them.
+struct ColTile {
+  const int64_t* live = nullptr;
+  int64_t c0 = 0;
+  int32_t acc = 0;
+};
+__device__ __forceinline__ bool col_tile_dead(const ColTile& ct) { return ct.live != nullptr && *ct.live <= ct.c0; }
 
 // Pass 2, dense: theta[i] = || A[i, :] Z_full ||^2.
 // variant as above; dtype = storage type of A (0 f64, 1 f32, 2 bf16).
+// live (device, may be null): columns >= *live of Z are known to be zero,
+// so their tiles are skipped (k > 64 only).
 hipError_t launch_rownorm_dense(int variant, int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
-                                int64_t k, const void* Zpack, const int64_t* rank, void* theta,
+                                int64_t k, const void* Zpack, const int64_t* live, void* theta,
                                 hipStream_t s);
-// Pass 2 for BF16 storage (rownorm_bf16.hip): Z_full packed as variant 2
-// (parts = 1), 3 (parts = 2) or 4 (parts = 3); theta FP32.
+// Pass 2 for BF16 storage (rownorm_bf16.hip): one tile (k <= 64) of Z_full
+// packed as variant 2 (parts = 1), 3 (parts = 2) or 4 (parts = 3); theta FP32.
 hipError_t launch_rownorm_bf16(int parts, const void* A, int64_t n, int64_t d, int64_t ld, int64_t k,
-                               const void* Zpack, void* theta, hipStream_t s);
+                               const void* Zpack, void* theta, const ColTile& ct, hipStream_t s);
 // Pass 2, CSR: theta[i] = || A[i, :] Z_full ||^2 with Z_full packed by
 // launch_pack_z as variant 5 (FP32, for F32/BF16 values) or 6 (FP64, for
-// F64 values): d rows of 64 elements (columns >= k zero).  theta is FP64 for
-// F64 values, else FP32.
+// F64 values): per tile, d rows of 64 elements (columns >= k zero).  theta
+// is FP64 for F64 values, else FP32.  live as for launch_rownorm_dense.
 hipError_t launch_rownorm_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
-                              int64_t n, int64_t d, int64_t nnz, const void* Zpack, void* theta,
-                              hipStream_t s);
+                              int64_t n, int64_t d, int64_t nnz, int64_t k, const void* Zpack,
+                              const int64_t* live, void* theta, hipStream_t s);
+
+// B (d x d, FP64) = A^T A for dense A (dtype 0 f64, 1 f32, 2 bf16) on the
+// FP64 matrix cores: the products of FP32 and BF16 elements are exact in
+// FP64.  partial: dgemm_partial_elems(d, d, splits) doubles.
+hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, int splits,
+                             double* partial, double* B, hipStream_t s);
+int gram_dense_splits(int64_t n, int64_t d);
+// B (d x d, FP64) = A^T A for CSR A in sum_i nnz_i^2 work (gram_csr.hip).
+size_t gram_csr_partial_elems(int64_t n, int64_t d);
+hipError_t launch_gram_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
+                           int64_t n, int64_t d, int64_t nnz, double* partial, double* B, hipStream_t s);
 
 // ---- backward (adjoint of w^T theta~ at a fixed sketch) ----------------------
 // dtype 0 = FP64, 1 = FP32 (A, w, Z_full, H_full and the gradient share it).
@@ -215,10 +246,8 @@ hipError_t launch_store_i64x4(int64_t* dst, int64_t a, int64_t b, int64_t c, int
 // Zero-fill helper (a kernel, so it is safe under graph capture).
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 
-// LS-HRN-exact (Algorithm 7): Z_full = I (d x 64 of the pass type; dtype 0
-// FP64, 1 FP32) for the C pass, B_K = C[K, K] (zeros past the rank), and
-// permc[j] = perm[perm2[j]].  The C pass treats w == nullptr as all ones.
-hipError_t launch_identity_rows(int dtype, int64_t d, void* out, hipStream_t s);
+// LS-HRN-exact (Algorithm 7): B_K = C[K, K] (zeros past the rank) and
+// permc[j] = perm[perm2[j]].
 hipError_t launch_gather_bk(int64_t d, const int32_t* perm, const int64_t* rank, const double* C, double* B,
                             hipStream_t s);
 hipError_t launch_compose_perm(int64_t d, const int32_t* perm, const int32_t* perm2, int32_t* permc, hipStream_t s);

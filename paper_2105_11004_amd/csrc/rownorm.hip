@@ -215,11 +215,12 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
                                                                  int64_t d, int64_t ld, int64_t nt,
                                                                  const uint4* __restrict__ Zg,
                                                                  int64_t zvecs, int64_t part_vecs,
-                                                                 void* __restrict__ theta) {
+                                                                 void* __restrict__ theta, ColTile ct) {
   using F = Frag<VAR, TA>;
   using AccT = typename Acc<VAR>::T;
   constexpr int kBatch = batch_of<VAR>();
   extern __shared__ uint4 zs[];
+  if (col_tile_dead(ct)) return;
   const uint4* Z = Zg;
   if constexpr (ZLDS) {
     for (int64_t i = threadIdx.x; i < zvecs; i += kThreads) zs[i] = Zg[i];
@@ -317,8 +318,13 @@ __global__ __launch_bounds__(kThreads) void rownorm_dense_kernel(const TA* __res
       for (int v = 0; v < 4; ++v) {
         const int64_t r = tile * 16 + (VAR == 0 ? g + 4 * v : 4 * g + v);
         if (r < n) {
-          if constexpr (VAR == 0) static_cast<double*>(theta)[r] = s[v];
-          else static_cast<float*>(theta)[r] = (float)s[v];
+          if constexpr (VAR == 0) {
+            double* th = static_cast<double*>(theta);
+            th[r] = ct.acc ? th[r] + s[v] : s[v];
+          } else {
+            float* th = static_cast<float*>(theta);
+            th[r] = ct.acc ? th[r] + (float)s[v] : (float)s[v];
+          }
         }
       }
     }
@@ -355,10 +361,11 @@ struct X3Shape<1024> {
 template <int CB, int WG>
 __global__ __launch_bounds__(WG, X3Shape<WG>::kMinWaves) void rownorm_x3_kernel(
     const float* __restrict__ A, int64_t n, int64_t d, int64_t ld, int64_t nt, const uint4* __restrict__ Zg,
-    int64_t zvecs, int64_t part_vecs, void* __restrict__ theta_out) {
+    int64_t zvecs, int64_t part_vecs, void* __restrict__ theta_out, ColTile ct) {
   constexpr int kB = X3Shape<WG>::kBatch;
   constexpr int kZPer = (X3Shape<WG>::kMaxZVecs + WG - 1) / WG;
   constexpr int kWaves = WG / 64;
+  if (col_tile_dead(ct)) return;
   float* theta = static_cast<float*>(theta_out);
   const bool theta_vec = (reinterpret_cast<uintptr_t>(theta) & 15) == 0;
   extern __shared__ uint4 zs[];
@@ -465,11 +472,16 @@ __global__ __launch_bounds__(WG, X3Shape<WG>::kMinWaves) void rownorm_x3_kernel(
       // exist and theta is 16-byte aligned
       const int64_t r0 = tile * 16 + 4 * g;
       if (theta_vec && r0 + 4 <= n) {
-        *reinterpret_cast<float4*>(theta + r0) = make_float4((float)sq[0], (float)sq[1], (float)sq[2], (float)sq[3]);
+        float4 o = make_float4((float)sq[0], (float)sq[1], (float)sq[2], (float)sq[3]);
+        if (ct.acc) {
+          const float4 p = *reinterpret_cast<const float4*>(theta + r0);
+          o.x += p.x, o.y += p.y, o.z += p.z, o.w += p.w;
+        }
+        *reinterpret_cast<float4*>(theta + r0) = o;
       } else {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          if (r0 + v < n) theta[r0 + v] = (float)sq[v];
+          if (r0 + v < n) theta[r0 + v] = ct.acc ? theta[r0 + v] + (float)sq[v] : (float)sq[v];
       }
     }
   }
@@ -477,7 +489,7 @@ __global__ __launch_bounds__(WG, X3Shape<WG>::kMinWaves) void rownorm_x3_kernel(
 
 template <int CB, int WG>
 hipError_t launch_x3(const float* a, int64_t n, int64_t d, int64_t ld, int64_t nt, const uint4* z, int64_t zvecs,
-                     int64_t part_vecs, size_t zbytes, int num_cu, void* theta, hipStream_t s) {
+                     int64_t part_vecs, size_t zbytes, int num_cu, void* theta, const ColTile& ct, hipStream_t s) {
   auto kern = rownorm_x3_kernel<CB, WG>;
   hipError_t e = hipSuccess;
   if (zbytes > 64 * 1024) {
@@ -491,13 +503,13 @@ hipError_t launch_x3(const float* a, int64_t n, int64_t d, int64_t ld, int64_t n
   const int64_t ntiles = (n + 15) / 16;
   const int64_t want = (ntiles + WG / 64 - 1) / (WG / 64);
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * std::max(per_cu, 1)));
-  kern<<<(unsigned)blocks, WG, zbytes, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta);
+  kern<<<(unsigned)blocks, WG, zbytes, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta, ct);
   return hipGetLastError();
 }
 
 template <int VAR, typename TA, int CB>
 hipError_t launch_cb(const void* A, int64_t n, int64_t d, int64_t ld, int64_t nt, const void* Zpack,
-                     size_t zbytes, void* theta, hipStream_t s) {
+                     size_t zbytes, void* theta, const ColTile& ct, hipStream_t s) {
   using F = Frag<VAR, TA>;
   const int64_t zvecs = (int64_t)(zbytes / 16);
   const int64_t part_vecs = zvecs / F::NZ;
@@ -516,9 +528,9 @@ hipError_t launch_cb(const void* A, int64_t n, int64_t d, int64_t ld, int64_t nt
       // (four column tiles need more than the 768-thread shape's 80 registers)
       if constexpr (CB < 4) {
         if (zbytes <= (size_t)X3Shape<768>::kMaxZVecs * 16)
-          return launch_x3<CB, 768>(a, n, d, ld, nt, z, zvecs, part_vecs, zbytes, num_cu, theta, s);
+          return launch_x3<CB, 768>(a, n, d, ld, nt, z, zvecs, part_vecs, zbytes, num_cu, theta, ct, s);
       }
-      return launch_x3<CB, 1024>(a, n, d, ld, nt, z, zvecs, part_vecs, zbytes, num_cu, theta, s);
+      return launch_x3<CB, 1024>(a, n, d, ld, nt, z, zvecs, part_vecs, zbytes, num_cu, theta, ct, s);
     }
   }
   if (zbytes <= kMaxLdsZ) {
@@ -531,48 +543,65 @@ hipError_t launch_cb(const void* A, int64_t n, int64_t d, int64_t ld, int64_t nt
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, zbytes);
     if (e != hipSuccess) return e;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * std::max(per_cu, 1)));
-    kern<<<(unsigned)blocks, kThreads, zbytes, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta);
+    kern<<<(unsigned)blocks, kThreads, zbytes, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta, ct);
   } else {
     auto kern = rownorm_dense_kernel<VAR, TA, CB, false>;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0);
     if (e != hipSuccess) return e;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * std::max(per_cu, 1)));
-    kern<<<(unsigned)blocks, kThreads, 0, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta);
+    kern<<<(unsigned)blocks, kThreads, 0, s>>>(a, n, d, ld, nt, z, zvecs, part_vecs, theta, ct);
   }
   return hipGetLastError();
 }
 
 template <int VAR, typename TA>
 hipError_t launch_var(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k, const void* Zpack,
-                      void* theta, hipStream_t s) {
+                      void* theta, const ColTile& ct, hipStream_t s) {
   using F = Frag<VAR, TA>;
   const int64_t nt = (d + F::CW - 1) / F::CW;
   const size_t zbytes = pack_z_operand_bytes(VAR, d, k);
   switch ((k + 15) / 16) {
-    case 1: return launch_cb<VAR, TA, 1>(A, n, d, ld, nt, Zpack, zbytes, theta, s);
-    case 2: return launch_cb<VAR, TA, 2>(A, n, d, ld, nt, Zpack, zbytes, theta, s);
-    case 3: return launch_cb<VAR, TA, 3>(A, n, d, ld, nt, Zpack, zbytes, theta, s);
-    case 4: return launch_cb<VAR, TA, 4>(A, n, d, ld, nt, Zpack, zbytes, theta, s);
+    case 1: return launch_cb<VAR, TA, 1>(A, n, d, ld, nt, Zpack, zbytes, theta, ct, s);
+    case 2: return launch_cb<VAR, TA, 2>(A, n, d, ld, nt, Zpack, zbytes, theta, ct, s);
+    case 3: return launch_cb<VAR, TA, 3>(A, n, d, ld, nt, Zpack, zbytes, theta, ct, s);
+    case 4: return launch_cb<VAR, TA, 4>(A, n, d, ld, nt, Zpack, zbytes, theta, ct, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// One column tile (k <= 64) of pass 2.
+hipError_t launch_tile(int variant, int dtype, const void* A, int64_t n, int64_t d, int64_t ld, int64_t k,
+                       const void* Zpack, void* theta, const ColTile& ct, hipStream_t s) {
+  if (variant == 0 && dtype == 0) return launch_var<0, double>(A, n, d, ld, k, Zpack, theta, ct, s);
+  if (variant == 1 && dtype == 1) return launch_var<1, float>(A, n, d, ld, k, Zpack, theta, ct, s);
+  if (variant == 1 && dtype == 2) return launch_var<1, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, ct, s);
+  // BF16 storage: the streaming kernel of rownorm_bf16.hip, Z in 1, 2 or 3 parts
+  if (variant == 2 && dtype == 2) return launch_rownorm_bf16(1, A, n, d, ld, k, Zpack, theta, ct, s);
+  if (variant == 3 && dtype == 2) return launch_rownorm_bf16(2, A, n, d, ld, k, Zpack, theta, ct, s);
+  if (variant == 4 && dtype == 2) return launch_rownorm_bf16(3, A, n, d, ld, k, Zpack, theta, ct, s);
+  if (variant == 4 && dtype == 1) return launch_var<4, float>(A, n, d, ld, k, Zpack, theta, ct, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_rownorm_dense(int variant, int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
-                                int64_t k, const void* Zpack, const int64_t* rank, void* theta,
+                                int64_t k, const void* Zpack, const int64_t* live, void* theta,
                                 hipStream_t s) {
-  (void)rank;
   if (n <= 0) return hipSuccess;
-  if (variant == 0 && dtype == 0) return launch_var<0, double>(A, n, d, ld, k, Zpack, theta, s);
-  if (variant == 1 && dtype == 1) return launch_var<1, float>(A, n, d, ld, k, Zpack, theta, s);
-  if (variant == 1 && dtype == 2) return launch_var<1, __hip_bfloat16>(A, n, d, ld, k, Zpack, theta, s);
-  // BF16 storage: the streaming kernel of rownorm_bf16.hip, Z in 1, 2 or 3 parts
-  if (variant == 2 && dtype == 2) return launch_rownorm_bf16(1, A, n, d, ld, k, Zpack, theta, s);
-  if (variant == 3 && dtype == 2) return launch_rownorm_bf16(2, A, n, d, ld, k, Zpack, theta, s);
-  if (variant == 4 && dtype == 2) return launch_rownorm_bf16(3, A, n, d, ld, k, Zpack, theta, s);
-  if (variant == 4 && dtype == 1) return launch_var<4, float>(A, n, d, ld, k, Zpack, theta, s);
-  return hipErrorInvalidValue;
+  // k > 64: one pass over A per column tile of 64, each adding its squares
+  // to theta (the first stores); a tile past the live columns returns at once
+  for (int64_t t = 0; t < z_tiles(k); ++t) {
+    ColTile ct;
+    ct.c0 = t * kZTile;
+    ct.acc = t > 0;
+    ct.live = t > 0 ? live : nullptr;
+    const int64_t kt = std::min<int64_t>(kZTile, k - ct.c0);
+    const void* zt = static_cast<const char*>(Zpack) + pack_z_tile_offset(variant, d, k, t);
+    hipError_t e = launch_tile(variant, dtype, A, n, d, ld, kt, zt, theta, ct, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace lev

@@ -84,9 +84,10 @@ struct ZChunk {
 template <int NP, int CB>
 __global__ __launch_bounds__(kThreads, 1) void rownorm_bf16s_kernel(
     const __hip_bfloat16* __restrict__ A, int64_t n, int64_t d, int64_t ld, int nt, const uint4* __restrict__ Zg,
-    int64_t part_vecs, float* __restrict__ theta, int64_t nblocks) {
+    int64_t part_vecs, float* __restrict__ theta, int64_t nblocks, ColTile ct) {
   using ZC = ZChunk<NP, CB>;
   __shared__ uint4 zs[2][ZC::kWin];
+  if (col_tile_dead(ct)) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -260,12 +261,16 @@ __global__ __launch_bounds__(kThreads, 1) void rownorm_bf16s_kernel(
           if (real && (lane & 15) == 0) {
             const int64_t r0 = row0 + 16 * h + 4 * g4;
             if (theta_vec && r0 + 4 <= n) {
-              *reinterpret_cast<float4*>(theta + r0) =
-                  make_float4((float)sq[0], (float)sq[1], (float)sq[2], (float)sq[3]);
+              float4 o = make_float4((float)sq[0], (float)sq[1], (float)sq[2], (float)sq[3]);
+              if (ct.acc) {
+                const float4 p = *reinterpret_cast<const float4*>(theta + r0);
+                o.x += p.x, o.y += p.y, o.z += p.z, o.w += p.w;
+              }
+              *reinterpret_cast<float4*>(theta + r0) = o;
             } else {
 #pragma unroll
               for (int v = 0; v < 4; ++v)
-                if (r0 + v < n) theta[r0 + v] = (float)sq[v];
+                if (r0 + v < n) theta[r0 + v] = ct.acc ? theta[r0 + v] + (float)sq[v] : (float)sq[v];
             }
           }
         }
@@ -280,7 +285,7 @@ __global__ __launch_bounds__(kThreads, 1) void rownorm_bf16s_kernel(
 
 template <int NP, int CB>
 hipError_t launch_np_cb(const __hip_bfloat16* A, int64_t n, int64_t d, int64_t ld, int nt, const uint4* Z,
-                        int64_t part_vecs, float* theta, hipStream_t s) {
+                        int64_t part_vecs, float* theta, const ColTile& ct, hipStream_t s) {
   int dev = 0, num_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -289,13 +294,13 @@ hipError_t launch_np_cb(const __hip_bfloat16* A, int64_t n, int64_t d, int64_t l
   // one workgroup per CU (its 8 waves take half of each SIMD's registers),
   // persistent over the row blocks
   const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(nblocks, num_cu));
-  rownorm_bf16s_kernel<NP, CB><<<(unsigned)grid, kThreads, 0, s>>>(A, n, d, ld, nt, Z, part_vecs, theta, nblocks);
+  rownorm_bf16s_kernel<NP, CB><<<(unsigned)grid, kThreads, 0, s>>>(A, n, d, ld, nt, Z, part_vecs, theta, nblocks, ct);
   return hipGetLastError();
 }
 
 template <int NP>
 hipError_t launch_np(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k, const void* Zpack, void* theta,
-                     hipStream_t s) {
+                     const ColTile& ct, hipStream_t s) {
   const int nt = (int)((d + 31) / 32);
   const int64_t cbn = (k + 15) / 16;
   const int64_t part_vecs = (int64_t)nt * cbn * 64;
@@ -303,10 +308,10 @@ hipError_t launch_np(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k,
   const auto* z = static_cast<const uint4*>(Zpack);
   auto* th = static_cast<float*>(theta);
   switch (cbn) {
-    case 1: return launch_np_cb<NP, 1>(a, n, d, ld, nt, z, part_vecs, th, s);
-    case 2: return launch_np_cb<NP, 2>(a, n, d, ld, nt, z, part_vecs, th, s);
-    case 3: return launch_np_cb<NP, 3>(a, n, d, ld, nt, z, part_vecs, th, s);
-    case 4: return launch_np_cb<NP, 4>(a, n, d, ld, nt, z, part_vecs, th, s);
+    case 1: return launch_np_cb<NP, 1>(a, n, d, ld, nt, z, part_vecs, th, ct, s);
+    case 2: return launch_np_cb<NP, 2>(a, n, d, ld, nt, z, part_vecs, th, ct, s);
+    case 3: return launch_np_cb<NP, 3>(a, n, d, ld, nt, z, part_vecs, th, ct, s);
+    case 4: return launch_np_cb<NP, 4>(a, n, d, ld, nt, z, part_vecs, th, ct, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -314,12 +319,12 @@ hipError_t launch_np(const void* A, int64_t n, int64_t d, int64_t ld, int64_t k,
 }  // namespace
 
 hipError_t launch_rownorm_bf16(int parts, const void* A, int64_t n, int64_t d, int64_t ld, int64_t k,
-                               const void* Zpack, void* theta, hipStream_t s) {
+                               const void* Zpack, void* theta, const ColTile& ct, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   switch (parts) {
-    case 1: return launch_np<1>(A, n, d, ld, k, Zpack, theta, s);
-    case 2: return launch_np<2>(A, n, d, ld, k, Zpack, theta, s);
-    case 3: return launch_np<3>(A, n, d, ld, k, Zpack, theta, s);
+    case 1: return launch_np<1>(A, n, d, ld, k, Zpack, theta, ct, s);
+    case 2: return launch_np<2>(A, n, d, ld, k, Zpack, theta, ct, s);
+    case 3: return launch_np<3>(A, n, d, ld, k, Zpack, theta, ct, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -113,8 +113,9 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
                                                                   const int32_t* __restrict__ col_idx,
                                                                   int64_t n, int64_t d, int64_t nnz,
                                                                   const ZT* __restrict__ Zg,
-                                                                  ZT* __restrict__ theta) {
+                                                                  ZT* __restrict__ theta, ColTile ct) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (col_tile_dead(ct)) return;
   StageEntry<ZT>* stage = reinterpret_cast<StageEntry<ZT>*>(smem);  // [kCsrWaves][64]
   ZT* Zs = reinterpret_cast<ZT*>(smem + sizeof(StageEntry<ZT>) * 64 * kCsrWaves);
   const ZT* Z = ZLDS ? Zs : Zg;
@@ -218,13 +219,13 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
       }
       __builtin_amdgcn_wave_barrier();
     }
-    if (r0 + lane < r1) theta[r0 + lane] = out;
+    if (r0 + lane < r1) theta[r0 + lane] = ct.acc ? theta[r0 + lane] + out : out;
   }
 }
 
 template <typename T, typename ZT>
 hipError_t launch_typed(const void* vals, const int64_t* row_ptr, const int32_t* col_idx, int64_t n, int64_t d,
-                        int64_t nnz, const void* Zpack, void* theta, hipStream_t s) {
+                        int64_t nnz, const void* Zpack, void* theta, const ColTile& ct, hipStream_t s) {
   int dev = 0, num_cu = 0;
   hipError_t err = hipGetDevice(&dev);
   if (err != hipSuccess) return err;
@@ -247,10 +248,10 @@ hipError_t launch_typed(const void* vals, const int64_t* row_ptr, const int32_t*
     // one workgroup per CU holds the LDS copy of Z_full; a second fits when it is small
     const int per_cu = (2 * lds <= kMaxLds) ? 2 : 1;
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * per_cu));
-    kern<<<grid, kCsrThreads, lds, s>>>(v, row_ptr, col_idx, n, d, nnz, Z, th);
+    kern<<<grid, kCsrThreads, lds, s>>>(v, row_ptr, col_idx, n, d, nnz, Z, th, ct);
   } else {
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu * 2));
-    rownorm_csr_kernel<T, ZT, false><<<grid, kCsrThreads, stage_bytes, s>>>(v, row_ptr, col_idx, n, d, nnz, Z, th);
+    rownorm_csr_kernel<T, ZT, false><<<grid, kCsrThreads, stage_bytes, s>>>(v, row_ptr, col_idx, n, d, nnz, Z, th, ct);
   }
   return hipGetLastError();
 }
@@ -258,15 +259,27 @@ hipError_t launch_typed(const void* vals, const int64_t* row_ptr, const int32_t*
 }  // namespace
 
 hipError_t launch_rownorm_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
-                              int64_t n, int64_t d, int64_t nnz, const void* Zpack, void* theta,
-                              hipStream_t s) {
+                              int64_t n, int64_t d, int64_t nnz, int64_t k, const void* Zpack,
+                              const int64_t* live, void* theta, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  switch (dtype) {
-    case 0: return launch_typed<double, double>(vals, row_ptr, col_idx, n, d, nnz, Zpack, theta, s);
-    case 1: return launch_typed<float, float>(vals, row_ptr, col_idx, n, d, nnz, Zpack, theta, s);
-    case 2: return launch_typed<__hip_bfloat16, float>(vals, row_ptr, col_idx, n, d, nnz, Zpack, theta, s);
-    default: return hipErrorInvalidValue;
+  const int variant = dtype == 0 ? 6 : 5;
+  // one pass per column tile of 64 (see launch_rownorm_dense)
+  for (int64_t t = 0; t < z_tiles(k); ++t) {
+    ColTile ct;
+    ct.c0 = t * kZTile;
+    ct.acc = t > 0;
+    ct.live = t > 0 ? live : nullptr;
+    const void* zt = static_cast<const char*>(Zpack) + pack_z_tile_offset(variant, d, k, t);
+    hipError_t e = hipErrorInvalidValue;
+    switch (dtype) {
+      case 0: e = launch_typed<double, double>(vals, row_ptr, col_idx, n, d, nnz, zt, theta, ct, s); break;
+      case 1: e = launch_typed<float, float>(vals, row_ptr, col_idx, n, d, nnz, zt, theta, ct, s); break;
+      case 2: e = launch_typed<__hip_bfloat16, float>(vals, row_ptr, col_idx, n, d, nnz, zt, theta, ct, s); break;
+      default: break;
+    }
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 }  // namespace lev

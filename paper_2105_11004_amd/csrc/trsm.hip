@@ -363,14 +363,16 @@ __device__ __forceinline__ void pack_element(int idx, int total, int d, int k, i
   }
 }
 
+// One column tile: Z64 points at the tile's first column, k is the tile's
+// width and zstride the row stride of Z64 (the full k).
 template <typename OUT, int EL, int NP>
 __global__ void pack_z_kernel(int64_t d, int64_t k, const int32_t* __restrict__ inv_perm,
-                              const double* __restrict__ Z64, OUT* __restrict__ out, int64_t nt,
+                              const double* __restrict__ Z64, int64_t zstride, OUT* __restrict__ out, int64_t nt,
                               int64_t cbn) {
   const int total = (int)(nt * cbn * 64 * EL);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  pack_element<OUT, EL, NP>(idx, total, (int)d, (int)k, (int)cbn, inv_perm, Z64, (int)k, out);
+  pack_element<OUT, EL, NP>(idx, total, (int)d, (int)k, (int)cbn, inv_perm, Z64, (int)zstride, out);
 }
 
 // CSR operand value of element idx of the d x 64 row-major Z_full.
@@ -399,10 +401,10 @@ __global__ void inverse_perm_kernel(int64_t d, const int32_t* __restrict__ perm,
 // CSR operand: Z_full row-major with rows padded to 64 columns.
 template <typename OUT>
 __global__ void pack_z_rowmajor_kernel(int64_t d, int64_t k, const int32_t* __restrict__ inv_perm,
-                                       const double* __restrict__ Z64, OUT* __restrict__ out) {
+                                       const double* __restrict__ Z64, int64_t zstride, OUT* __restrict__ out) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= d * 64) return;
-  pack_rowmajor_element<OUT>(idx, (int)k, inv_perm, Z64, (int)k, out);
+  pack_rowmajor_element<OUT>(idx, (int)k, inv_perm, Z64, (int)zstride, out);
 }
 
 constexpr int64_t chunk_cols(int variant) { return variant == 0 ? 8 : (variant == 1 ? 16 : 32); }
@@ -453,15 +455,69 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
   return hipGetLastError();
 }
 
-size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k) {
+namespace {
+
+// Bytes of one packed column tile of width kt <= 64.
+size_t pack_tile_bytes(int variant, int64_t d, int64_t kt) {
   if (variant == 5 || variant == 6) return (size_t)d * 64 * (variant == 5 ? 4 : 8);
   if (variant < 0 || variant > 4) return 0;
   const int64_t cw = chunk_cols(variant);
   const int64_t nt = (d + cw - 1) / cw;
-  const int64_t cbn = (k + 15) / 16;
+  const int64_t cbn = (kt + 15) / 16;
   const int64_t elems = nt * cbn * 64 * (cw / 4);
   const size_t esize = variant == 0 ? 8 : (variant == 1 ? 4 : 2);
   return (size_t)elems * esize * (size_t)parts(variant);
+}
+
+hipError_t pack_tile(int variant, int64_t d, int64_t kt, const int32_t* inv, const double* Z64, int64_t zstride,
+                     void* out, hipStream_t s) {
+  if (variant == 5 || variant == 6) {
+    const unsigned blocks = (unsigned)((d * 64 + 255) / 256);
+    if (variant == 5)
+      pack_z_rowmajor_kernel<float><<<blocks, 256, 0, s>>>(d, kt, inv, Z64, zstride, static_cast<float*>(out));
+    else
+      pack_z_rowmajor_kernel<double><<<blocks, 256, 0, s>>>(d, kt, inv, Z64, zstride, static_cast<double*>(out));
+    return hipGetLastError();
+  }
+  const int64_t cw = chunk_cols(variant);
+  const int64_t nt = (d + cw - 1) / cw;
+  const int64_t cbn = (kt + 15) / 16;
+  const int64_t total = nt * cbn * 64 * (cw / 4);
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  using bf = __hip_bfloat16;
+  switch (variant) {
+    case 0:
+      pack_z_kernel<double, 2, 1><<<blocks, 256, 0, s>>>(d, kt, inv, Z64, zstride, static_cast<double*>(out), nt, cbn);
+      break;
+    case 1:
+      pack_z_kernel<float, 4, 1><<<blocks, 256, 0, s>>>(d, kt, inv, Z64, zstride, static_cast<float*>(out), nt, cbn);
+      break;
+    case 2:
+      pack_z_kernel<bf, 8, 1><<<blocks, 256, 0, s>>>(d, kt, inv, Z64, zstride, static_cast<bf*>(out), nt, cbn);
+      break;
+    case 3:
+      pack_z_kernel<bf, 8, 2><<<blocks, 256, 0, s>>>(d, kt, inv, Z64, zstride, static_cast<bf*>(out), nt, cbn);
+      break;
+    case 4:
+      pack_z_kernel<bf, 8, 3><<<blocks, 256, 0, s>>>(d, kt, inv, Z64, zstride, static_cast<bf*>(out), nt, cbn);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t pack_z_tile_offset(int variant, int64_t d, int64_t k, int64_t t) {
+  (void)k;
+  return (size_t)t * pack_tile_bytes(variant, d, kZTile);  // every tile before the last is full
+}
+
+size_t pack_z_operand_bytes(int variant, int64_t d, int64_t k) {
+  if (variant < 0 || variant > 6 || k <= 0) return 0;
+  const int64_t last = k - (z_tiles(k) - 1) * kZTile;
+  return pack_z_tile_offset(variant, d, k, z_tiles(k) - 1) + pack_tile_bytes(variant, d, last);
 }
 
 size_t pack_z_bytes(int variant, int64_t d, int64_t k) {
@@ -469,48 +525,18 @@ size_t pack_z_bytes(int variant, int64_t d, int64_t k) {
   return pack_z_operand_bytes(variant, d, k) + (size_t)d * sizeof(int32_t);
 }
 
-// Zpack layout: the packed operand (as above) followed by inv_perm[d].
+// Zpack layout: the packed operand (its column tiles in order) followed by
+// inv_perm[d].
 hipError_t launch_pack_z(int variant, int64_t d, int64_t k, const int32_t* perm, const int64_t* rank,
                          const double* Z64, void* Zpack, hipStream_t s) {
-  if (variant == 5 || variant == 6) {
-    int32_t* inv = reinterpret_cast<int32_t*>(static_cast<char*>(Zpack) + pack_z_operand_bytes(variant, d, k));
-    inverse_perm_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(d, perm, rank, inv);
-    const unsigned blocks = (unsigned)((d * 64 + 255) / 256);
-    if (variant == 5)
-      pack_z_rowmajor_kernel<float><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<float*>(Zpack));
-    else
-      pack_z_rowmajor_kernel<double><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<double*>(Zpack));
-    return hipGetLastError();
-  }
-  const int64_t cw = chunk_cols(variant);
-  const int64_t nt = (d + cw - 1) / cw;
-  const int64_t cbn = (k + 15) / 16;
-  const int64_t total = nt * cbn * 64 * (cw / 4);
-  const size_t esize = variant == 0 ? 8 : (variant == 1 ? 4 : 2);
-  int32_t* inv = reinterpret_cast<int32_t*>(static_cast<char*>(Zpack) + (size_t)total * esize * parts(variant));
+  if (variant < 0 || variant > 6) return hipErrorInvalidValue;
+  char* base = static_cast<char*>(Zpack);
+  int32_t* inv = reinterpret_cast<int32_t*>(base + pack_z_operand_bytes(variant, d, k));
   inverse_perm_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(d, perm, rank, inv);
-  const unsigned blocks = (unsigned)((total + 255) / 256);
-  switch (variant) {
-    case 0:
-      pack_z_kernel<double, 2, 1><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<double*>(Zpack), nt, cbn);
-      break;
-    case 1:
-      pack_z_kernel<float, 4, 1><<<blocks, 256, 0, s>>>(d, k, inv, Z64, static_cast<float*>(Zpack), nt, cbn);
-      break;
-    case 2:
-      pack_z_kernel<__hip_bfloat16, 8, 1><<<blocks, 256, 0, s>>>(d, k, inv, Z64,
-                                                                 static_cast<__hip_bfloat16*>(Zpack), nt, cbn);
-      break;
-    case 3:
-      pack_z_kernel<__hip_bfloat16, 8, 2><<<blocks, 256, 0, s>>>(d, k, inv, Z64,
-                                                                 static_cast<__hip_bfloat16*>(Zpack), nt, cbn);
-      break;
-    case 4:
-      pack_z_kernel<__hip_bfloat16, 8, 3><<<blocks, 256, 0, s>>>(d, k, inv, Z64,
-                                                                 static_cast<__hip_bfloat16*>(Zpack), nt, cbn);
-      break;
-    default:
-      return hipErrorInvalidValue;
+  for (int64_t t = 0; t < z_tiles(k); ++t) {
+    const int64_t c0 = t * kZTile, kt = std::min<int64_t>(kZTile, k - c0);
+    hipError_t e = pack_tile(variant, d, kt, inv, Z64 + c0, k, base + pack_z_tile_offset(variant, d, k, t), s);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }

@@ -162,10 +162,24 @@ CONFIGS = {
     "csr_f32_8Mx512": dict(n=1 << 23, d=512, zero_cols=64, dtype="f32", r_cs=8192, m=1024, k=64, zeta=1e-5),
     "dense_bf16_4Mx1024": dict(n=1 << 22, d=1024, dtype="bf16", r_cs=16384, m=2048, k=64, zeta=1e-3),
     "dense_f32_1Mx256_rank192_bwd": dict(n=1 << 20, d=256, rank=192, dtype="f32", r_cs=4096, m=512, k=48, zeta=1e-5),
-    # LS-HRN-exact (Algorithm 7) at scale: a well-conditioned FP32 Gaussian
-    # (the FP32 Gram squares the conditioning of A_K); k is unused there
+    # LS-HRN-exact (Algorithm 7) at scale: an FP32 Gaussian; k is unused there
     "dense_f32_1Mx64_exact": dict(n=1 << 20, d=64, dtype="f32", r_cs=4096, m=128, k=32, zeta=1e-5),
 }
+
+# A case at the sizes the theorems ask for (the end-to-end (1 +- eps) check):
+# n = 4096, d = 8, a CountSketch of at least the OSE size for eps = 0.5,
+# delta = 1/3 ((d^2 + d) / (delta (2 eps - eps^2)^2) = 384 rows, Section 3),
+# a Gaussian stage of m = 64 r >= 30 r rows (distortion about sqrt(r / m),
+# the subspace embedding the bound of Section 5 composes with) and the JL
+# bound for eps = 0.5 (4 ln n / (eps^2 / 2 - eps^3 / 3) = 400 columns).
+THEORY_SIZED = dict(n=4096, d=8, r_cs=512, m=512, k=400, eps=0.5, delta=1 / 3)
+
+
+def theory_sized_matrix() -> np.ndarray:
+    """FP64 4096 x 8 Gaussian with lognormal(0, 1) row scales."""
+    rng = np.random.default_rng(21)
+    n, d = THEORY_SIZED["n"], THEORY_SIZED["d"]
+    return rng.standard_normal((n, d)) * rng.lognormal(0, 1, (n, 1))
 
 
 def sketch_seed(cfg_index: int) -> int:

@@ -56,10 +56,10 @@ def _mat(api, **kw):
 
 
 def _par(api, **kw):
-    base = dict(seed=1, r_cs=64, m=32, k=8, zeta=1e-5, az=0, exact=0)
+    base = dict(seed=1, r_cs=64, m=32, k=8, zeta=1e-5, az=0, mode=0)
     base.update(kw)
     return api.LevParams(base["seed"], base["r_cs"], base["m"], base["k"], base["zeta"], base["az"],
-                         base["exact"])
+                         base["mode"])
 
 
 @pytest.mark.parametrize("mat_kw,par_kw,expected", [
@@ -73,7 +73,7 @@ def _par(api, **kw):
     ({"n": -1}, {}, -2),
     ({}, {"m": 8}, -2),                          # m < d
     ({}, {"k": 0}, -1),
-    ({}, {"k": 65}, -1),
+    ({}, {"k": 4097}, -1),                       # JL columns: 1..4096
     ({}, {"r_cs": 0}, -1),
     ({}, {"zeta": 1.5}, -1),
     ({}, {"zeta": 1e-11}, -7),                   # below the smallest supported rank cutoff
@@ -85,10 +85,10 @@ def _par(api, **kw):
     ({"format": 1, "row_ptr": 8192, "nnz": 10}, {}, -1),            # nnz > 0 without col_idx
     ({"format": 1, "row_ptr": 8192, "dtype": 0}, {"az": 1}, -1),    # FP64 CSR runs in FP64 only
     ({"format": 1, "row_ptr": 8192, "nnz": 5, "col_idx": 16384}, {"az": 2}, -1),  # no BF16 products on CSR
-    ({}, {"exact": 2}, -1),
-    ({"d": 80, "ld": 80}, {"exact": 1, "m": 96}, -2),                               # exact scores: d <= 64
-    ({"dtype": 2, "ld": 16}, {"exact": 1}, -3),                                     # exact scores: FP32/FP64
-    ({"format": 1, "row_ptr": 8192, "nnz": 5, "col_idx": 16384}, {"exact": 1}, -7),  # exact scores: dense
+    ({}, {"mode": 3}, -1),
+    ({}, {"mode": -1}, -1),
+    ({"d": 2048, "ld": 2048}, {"mode": 1, "m": 4096}, -2),   # exact scores: d <= 1024 like the rest
+    ({}, {"mode": 2, "zeta": 1e-12}, -7),
 ])
 def test_estimate_rejects_bad_arguments(lib, mat_kw, par_kw, expected):
     from paper_2105_11004_amd import api
@@ -117,10 +117,16 @@ def test_workspace_checks(lib):
     assert lib.lev_rank_workspace_size(8, 16) == 0
 
 
-@pytest.mark.parametrize("mat_kw,expected", [({"format": 1, "row_ptr": 8192}, -7), ({"dtype": 2}, -3)])
-def test_backward_rejects_unsupported_input(lib, mat_kw, expected):
+@pytest.mark.parametrize("mat_kw,par_kw,expected", [
+    ({"format": 1, "row_ptr": 8192}, {}, -7),
+    ({"dtype": 2}, {}, -3),
+    ({}, {"mode": 1}, -7),       # only the JL estimate has an adjoint here
+    ({}, {"mode": 2}, -7),
+    ({}, {"k": 65}, -7),         # the backward's register tiles take k <= 64
+])
+def test_backward_rejects_unsupported_input(lib, mat_kw, par_kw, expected):
     from paper_2105_11004_amd import api
-    A, p = _mat(api, **mat_kw), _par(api)
+    A, p = _mat(api, **mat_kw), _par(api, **par_kw)
     if mat_kw.get("dtype") == 2:
         p = _par(api, az=1)
     vp = ctypes.c_void_p
@@ -128,6 +134,28 @@ def test_backward_rejects_unsupported_input(lib, mat_kw, expected):
                                    vp(1 << 20), 1 << 40, None)
     assert st == expected, lib.lev_last_error().decode()
     assert lib.lev_workspace_size(ctypes.byref(A), ctypes.byref(p), api.WS_BACKWARD) == 0
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_estimate_state_only_for_jl(lib, mode):
+    from paper_2105_11004_amd import api
+    A, p = _mat(api), _par(api, mode=mode)
+    st = lib.lev_estimate(ctypes.byref(A), ctypes.byref(p), ctypes.c_void_p(8192), ctypes.c_void_p(1 << 16),
+                          ctypes.c_void_p(1 << 20), 1 << 40, None)
+    assert st == -7, lib.lev_last_error().decode()
+
+
+def test_workspace_grows_with_column_tiles(lib):
+    """k > 64 JL columns and the d-column operand of the no-JL and exact
+    modes are sized per tile of 64 columns."""
+    from paper_2105_11004_amd import api
+    A = _mat(api, d=256, ld=256)
+    sizes = [lib.lev_workspace_size(ctypes.byref(A), ctypes.byref(_par(api, m=512, k=k)), api.WS_ESTIMATE)
+             for k in (64, 65, 128, 4096)]
+    assert 0 < sizes[0] < sizes[1] <= sizes[2] < sizes[3]
+    for mode in (1, 2):
+        assert lib.lev_workspace_size(ctypes.byref(A), ctypes.byref(_par(api, m=512, mode=mode)),
+                                      api.WS_ESTIMATE) > 0
 
 
 def test_backward_validates_state_and_workspace(lib):

@@ -462,6 +462,8 @@ def test_empty_matrix(gpu):
     assert theta.shape == (0,) and int(st.rank.item()) == 0
     theta = api.lev_estimate(A, 1, 64, 32, 8, 1e-5, exact=True)
     assert theta.shape == (0,)
+    theta = api.lev_estimate(A, 1, 64, 32, 8, 1e-5, mode="nojl")
+    assert theta.shape == (0,)
 
 
 @pytest.mark.parametrize("n,d,k,r_cs,m", [(1, 4, 1, 1, 4), (15, 8, 17, 3, 8), (33, 64, 64, 7, 64),

@@ -13,6 +13,7 @@ import scipy.stats as st
 
 from oracle import conventions as C
 from oracle import leverage as L
+from paper_2105_11004_amd import workloads as W
 
 GOLDEN = Path(__file__).parent / "golden"
 
@@ -339,6 +340,27 @@ def test_jl_step_meets_its_bound_given_the_sketch():
         assert np.all(tp >= th / sv[0] ** 2 * (1 - 1e-9)) and np.all(tp <= th / sv[-1] ** 2 * (1 + 1e-9))
         ratio = est.theta / tp
         assert np.all(np.abs(ratio - 1) <= eps)
+
+
+def test_end_to_end_bound_at_theory_sizes():
+    """Algorithm 10 composed (CountSketch, Gaussian stage, QRCP, JL step) at
+    sizes at or above what each theorem asks: every row's theta~_i within
+    (1 +- eps) of the exact theta_i, for all but a fraction <= delta of the
+    seeds (Section 5's bound, with failure probability delta)."""
+    E2E = W.THEORY_SIZED
+    n, d, eps = E2E["n"], E2E["d"], E2E["eps"]
+    assert E2E["r_cs"] >= (d * d + d) / (E2E["delta"] * (2 * eps - eps ** 2) ** 2)
+    assert E2E["m"] >= 30 * d
+    assert E2E["k"] >= 4 * math.log(n) / (eps ** 2 / 2 - eps ** 3 / 3)
+    A = W.theory_sized_matrix()
+    th, rank = L.exact_theta_svd(A, 1e-12)
+    assert rank == d
+    seeds, fails = 40, 0
+    for seed in range(seeds):
+        est = L.ls_hrn_approx(A, seed, E2E["r_cs"], E2E["m"], E2E["k"], 1e-10)
+        assert est.rank == d
+        fails += int(np.max(np.abs(est.theta / th - 1)) > eps)
+    assert fails / seeds <= E2E["delta"]
 
 
 def test_estimator_handles_zero_and_zero_rows():
