@@ -2,12 +2,14 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision auto|native|fp32|bf16|bf16x2|bf16x3]
-                    [--no-accuracy] [--no-cpu-baseline] [--exact]
+                    [--no-accuracy] [--no-cpu-baseline] [--mode jl|exact|nojl]
 
 One step = one lev_estimate call over the whole workload resident in HBM:
 the Gaussian draws and pass 1 (CountSketch S A), the Gaussian transform, the
 rank-revealing factorisation, Z = R11^{-1} G_k and pass 2 (theta~); for the
 backward workload (name ending in _bwd) also the adjoint of w^T theta~.
+--mode exact times Algorithm 7 instead (the exact scores of A_K from B =
+A_K^T A_K), --mode nojl the estimate without the JL step (Pi_2 = I).
 Prints one JSON line with rows/s, the per-phase times and rooflines (the
 headline `roofline` is the slowest phase's, measured live with the HIP
 events liblev records on its own stream), the accuracy of theta~ on sampled
@@ -17,8 +19,8 @@ CPU oracle timed on a bounded sample of the same workload.
 
 HBM traffic of the passes (rocprofv3 counters, one process per counter):
 
-    rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o fetch -- python3 bench.py --traffic-run [--workload NAME]
-    rocprofv3 --pmc WRITE_SIZE -d OUT/write -o write -- python3 bench.py --traffic-run [--workload NAME]
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT/fetch -o fetch -- python3 bench.py --traffic-run [--workload NAME]
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d OUT/write -o write -- python3 bench.py --traffic-run [--workload NAME]
     python3 bench.py --traffic-summarize OUT/fetch OUT/write [--workload NAME]
 
 A traffic run first copies a 1 GiB device buffer (a plain copy kernel that
@@ -128,13 +130,34 @@ def pass_kernels(A, precision: str) -> dict:
     return pass_kernels_for(_is_csr(A), _values(A).dtype, precision)
 
 
-def phase_work(A, cfg) -> dict:
+def expected_rank(cfg) -> int:
+    return min(cfg["d"] - cfg.get("zero_cols", 0), cfg.get("rank", cfg["d"]))
+
+
+def phase_work(A, cfg, mode: str = "jl") -> dict:
     """Algorithmic work of each phase of one estimate: bytes for the passes
     over A (HBM-bound), FP64 flops for the n-independent phases (their
-    dominant kernels are FP64 MFMA GEMMs and the pivoting that drives them)."""
+    dominant kernels are FP64 MFMA GEMMs and the pivoting that drives them).
+    Without the JL step and for the exact scores, Z has d columns of which
+    the first r are live: pass 2 reads A once per live tile of 64 columns;
+    the exact scores' Gram pass (dense: 2 n d^2 flops on the FP64 matrix
+    cores; CSR: one read of A at least) falls in the form_z phase."""
     n, d, m, r_cs, k = _n(A), cfg["d"], cfg["m"], cfg["r_cs"], cfg["k"]
     theta_es = 8 if _values(A).dtype == torch.float64 else 4
-    r = min(d, cfg.get("rank", d))
+    r = expected_rank(cfg)
+    if mode != "jl":
+        tiles = -(-r // 64)
+        if mode == "exact":
+            gram = ("hbm", a_bytes(A)) if _is_csr(A) else ("mfma_fp64", 2.0 * n * d * d)
+        else:
+            gram = ("mfma_fp64", float(r) * r * d)
+        return {
+            "pass1_countsketch": ("hbm", a_bytes(A) + 8 * (r_cs * d + m * r_cs)),
+            "gaussian_transform": ("mfma_fp64", 2.0 * m * r_cs * d),
+            "rank_revealing_qr": ("mfma_fp64", 2.0 * m * d * d + d ** 3 / 3.0),
+            "form_z": gram,
+            "pass2_rownorm": ("hbm", tiles * (a_bytes(A) + n * theta_es)),
+        }
     return {
         # pass 1 reads A once and writes S A (FP64) plus the two Gaussian
         # matrices it draws on the side (G_m m x r_cs, G_k d x k, FP64)
@@ -150,9 +173,9 @@ def phase_work(A, cfg) -> dict:
     }
 
 
-def rooflines(A, cfg, phases_ms: dict, traffic: dict) -> dict:
+def rooflines(A, cfg, phases_ms: dict, traffic: dict, mode: str = "jl") -> dict:
     out = {}
-    for name, (bound, work) in phase_work(A, cfg).items():
+    for name, (bound, work) in phase_work(A, cfg, mode).items():
         t = phases_ms[name] * 1e-3
         if bound == "hbm":
             ach = work / t / 1e9
@@ -172,7 +195,7 @@ def _host_rows(A, lo: int, hi: int) -> np.ndarray:
     return A[lo:hi].to(torch.float64).cpu().numpy()
 
 
-def cpu_baseline(A, cfg, seed, target_s: float = 10.0, exact: bool = False):
+def cpu_baseline(A, cfg, seed, target_s: float = 10.0, mode: str = "jl"):
     """Times the oracle's estimator on the first n_s rows of the workload
     (same d, sketch sizes and seed), growing n_s until about a quarter of
     target_s; when that covers the whole workload, the whole workload is
@@ -180,9 +203,12 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0, exact: bool = False):
     from oracle import leverage as L
 
     def oracle(Ah):
-        if exact:
+        if mode == "exact":
             return L.ls_hrn_exact(Ah, seed, cfg["r_cs"], cfg["m"], cfg["zeta"])
-        return L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+        if mode == "nojl":
+            return L.theta_prime(Ah, o.perm[:o.rank], o.R11)
+        return o
 
     try:
         from threadpoolctl import threadpool_info
@@ -213,8 +239,12 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0, exact: bool = False):
     dt = total / reps
     what = f"first {ns} rows of the workload" if ns < n else f"the whole workload ({n} rows), mean of {reps} runs"
     return {"value": ns / dt, "unit": "rows/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{what}, full estimator ({'sketch, QRCP, Gram of A_K, eigh, row norms' if exact else 'sketch, QRCP, Z, row norms'}), "
+            "sample": f"{what}, full estimator ({ORACLE_STEPS[mode]}), "
                       f"FP64 NumPy/SciPy, {dt:.2f} s per run"}
+
+
+ORACLE_STEPS = {"jl": "sketch, QRCP, Z, row norms", "nojl": "sketch, QRCP, R11^-1, row norms",
+                "exact": "sketch, QRCP, Gram of A_K, eigh, row norms"}
 
 
 def _stats(ratio: np.ndarray) -> dict:
@@ -223,12 +253,14 @@ def _stats(ratio: np.ndarray) -> dict:
             "frac_within_0.5": float(np.mean(np.abs(ratio - 1.0) <= 0.5))}
 
 
-def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000) -> dict:
+def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000, mode: str = "jl") -> dict:
     """theta~ of each form (name -> full theta~ on the device) on sampled
-    rows against (i) the oracle's FP64 estimator with the same sketch and
-    (ii) the exact scores (Algorithm 5's Gram route over the whole matrix,
-    streamed in row blocks, cutoff zeta); raw and sum-normalised
-    (theta~ * r / sum theta~, which uses sum theta = rank)."""
+    rows against (i) the oracle's FP64 estimator with the same sketch (the
+    JL estimate, or theta' without the JL step; for the exact scores the
+    exact scores themselves) and (ii) the exact scores (Algorithm 5's Gram
+    route over the whole matrix, streamed in row blocks, cutoff zeta); raw
+    and sum-normalised (theta~ * r / sum theta~, which uses sum theta =
+    rank)."""
     from oracle import leverage as L
 
     n = _n(A)
@@ -248,14 +280,21 @@ def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000) -> dict:
     t0 = time.perf_counter()
     exact, rho = L.theta_gram_rows(chunks, rows, max(cfg["zeta"], 1e-6))
     t_exact = time.perf_counter() - t0
+    if mode == "nojl":
+        same = L.theta_prime(Ah, o.perm[:o.rank], o.R11, rows=rows)
+    elif mode == "exact":
+        same = exact  # the exact scores of A_K are those of A when r = rank(A)
+    else:
+        same = o.theta_rows
     del Ah
     out = {"rows_sampled": int(rows.size), "oracle_rank": int(o.rank), "exact_rank": int(rho),
-           "oracle_s": {"same_sketch": t_same, "exact_gram": t_exact}, "forms": {}}
+           "oracle_s": {"same_sketch": t_same, "exact_gram": t_exact}, "mode": mode, "forms": {}}
     for name, theta in forms.items():
         th = theta.to(torch.float64)
         total = float(th.sum().item())
         got = th.cpu().numpy()[rows]
-        rel = np.abs(got - o.theta_rows) / np.maximum(np.abs(o.theta_rows), 1e-300)
+        rel = np.abs(got - same) / np.maximum(np.abs(same), 1e-300)
+        rel = rel[np.abs(same) > 0] if mode != "jl" else rel
         live = exact > 1e-300
         ratio = got[live] / exact[live]
         norm = ratio * (o.rank / total) if total > 0 else ratio
@@ -422,6 +461,10 @@ def phase_times(plan, bwd, steps: int, stream):
     return phases, spread, bms
 
 
+ALGORITHMS = {"jl": "LS-HRN-approx (Algorithm 10)", "exact": "LS-HRN-exact (Algorithm 7)",
+              "nojl": "Algorithm 10 without the JL step (Pi_2 = I)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -431,11 +474,15 @@ def main():
     ap.add_argument("--precision", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--exact", action="store_true",
-                    help="time Algorithm 7 (LS-HRN-exact) instead of Algorithm 10")
+    ap.add_argument("--mode", choices=("jl", "exact", "nojl"), default="jl",
+                    help="jl: Algorithm 10; exact: Algorithm 7 (LS-HRN-exact); nojl: Algorithm 10 without "
+                         "the JL step (Pi_2 = I)")
+    ap.add_argument("--exact", action="store_true", help="same as --mode exact")
     ap.add_argument("--traffic-run", action="store_true", help="the process a counter run profiles")
     ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.exact:
+        args.mode = "exact"
     if args.traffic_summarize:
         traffic_summarize(*args.traffic_summarize, args.workload, args.precision)
         return
@@ -454,7 +501,7 @@ def main():
     A, cfg, seed = make_workload(args.workload, dev)
     precision = resolve_precision(A, args.precision)
     plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=precision,
-                            exact=args.exact)
+                            mode=args.mode)
     bwd = None
     if args.workload.endswith("_bwd"):
         bwd = api.BackwardPlan(plan, torch.rand(A.shape[0], device=dev, dtype=A.dtype,
@@ -473,7 +520,7 @@ def main():
     phases, spread, bms = phase_times(plan, bwd, args.steps, stream)
     n = _n(A)
     traffic = traffic_for(args.workload, A, precision)
-    roofs = rooflines(A, cfg, phases, traffic)
+    roofs = rooflines(A, cfg, phases, traffic, args.mode)
     slowest = max(roofs, key=lambda k: phases[k])
     kern = pass_kernels(A, precision)
     headline = dict(roofs[slowest])
@@ -494,7 +541,7 @@ def main():
         "data": "synthetic (seeded, generated on the GPU)",
         "config": {"workload": args.workload, "n": n, "d": cfg["d"], "r_cs": cfg["r_cs"], "m": cfg["m"],
                    "k": cfg["k"], "zeta": cfg["zeta"], "precision": precision,
-                   "algorithm": "LS-HRN-exact (Algorithm 7)" if args.exact else "LS-HRN-approx (Algorithm 10)"},
+                   "algorithm": ALGORITHMS[args.mode]},
         "roofline": headline,
         "rooflines": roofs,
         "phases_ms": phases,
@@ -509,7 +556,7 @@ def main():
         out["backward_ms"] = bms
         out["backward_hbm_gbs"] = 3 * a_bytes(A) / (bms * 1e-3) / 1e9  # two reads of A, one write of the gradient
     forms = {precision: plan.theta.clone()}
-    if not args.exact and not _is_csr(A) and A.dtype == torch.bfloat16:
+    if args.mode == "jl" and not _is_csr(A) and A.dtype == torch.bfloat16:
         # the other BF16 forms on the same GPU: time and theta~
         out["bf16_forms"] = {precision: {"ms_per_step": ms, "pass2_ms": phases["pass2_rownorm"]}}
         for other in ("bf16", "bf16x2", "bf16x3"):
@@ -522,12 +569,12 @@ def main():
             out["bf16_forms"][other] = {"ms_per_step": t, "pass2_ms": ph["pass2_rownorm"]}
             forms[other] = p2.theta.clone()
             del p2
-    if not args.no_accuracy and not args.exact:
+    if not args.no_accuracy:
         print("# accuracy on sampled rows (oracle: same sketch, and exact scores)", file=sys.stderr, flush=True)
-        out["accuracy"] = accuracy_report(A, cfg, seed, forms)
+        out["accuracy"] = accuracy_report(A, cfg, seed, forms, mode=args.mode)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(A, cfg, seed, exact=args.exact)
+        out["cpu_baseline"] = cpu_baseline(A, cfg, seed, mode=args.mode)
     print(json.dumps(out), flush=True)
 
 

@@ -99,7 +99,9 @@ __device__ __forceinline__ void store_stage(const Stage& st, int tid, double* __
 }
 
 // AK: A is contiguous in k (sak == 1); BJ: B is contiguous in j (sbj == 1).
-template <bool AK, bool BJ, typename TI = double>
+// UPPER: C is symmetric (a Gram matrix): the tiles below the diagonal are
+// skipped, and with one split each upper tile is also stored transposed.
+template <bool AK, bool BJ, typename TI = double, bool UPPER = false>
 __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                          const TI* __restrict__ A, int64_t sai,
                                                          int64_t sak, const TI* __restrict__ B,
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, i
                                                          int64_t kchunk, double* __restrict__ partial,
                                                          const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip != 0) return;
+  if (UPPER && blockIdx.x > blockIdx.y) return;
   __shared__ double As[2][kLdsOp];
   __shared__ double Bs[2][kLdsOp];
 
@@ -175,6 +178,7 @@ __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, i
           if (splits == 1) {
             const double prev = (beta != 0.0) ? beta * C[gi * ldc + gj] : 0.0;
             C[gi * ldc + gj] = alpha * acc[i][j][v] + prev;
+            if (UPPER) C[gj * ldc + gi] = alpha * acc[i][j][v] + prev;
           } else {
             partial[((int64_t)blockIdx.z * M + gi) * N + gj] = acc[i][j][v];
           }
@@ -193,6 +197,23 @@ __global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, const dou
   for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * M * N + idx];
   const double prev = (beta != 0.0) ? beta * C[i * ldc + j] : 0.0;
   C[i * ldc + j] = alpha * s + prev;
+}
+
+// Gram form of the split-K sum: C[i][j] from the partial of the upper
+// tile holding (i, j) or (j, i).
+__global__ void gram_reduce_kernel(int64_t N, int splits, const double* __restrict__ partial,
+                                   double* __restrict__ C) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * N) return;
+  int64_t i = idx / N, j = idx % N;
+  if (i / BM > j / BN) {
+    const int64_t t = i;
+    i = j;
+    j = t;
+  }
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += partial[((int64_t)z * N + i) * N + j];
+  C[idx] = s;
 }
 
 }  // namespace
@@ -238,7 +259,8 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const dou
 int gram_dense_splits(int64_t n, int64_t d) { return dgemm_choose_splits(d, d, n); }
 
 // A^T A: op(A)[i][k] = A[k][i] (strides 1, ld) and op(B)[k][j] = A[k][j]
-// (strides ld, 1), so both operand tiles are read along A's rows.
+// (strides ld, 1), so both operand tiles are read along A's rows; only the
+// tiles on and above the diagonal are computed.
 hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, int splits,
                              double* partial, double* B, hipStream_t s) {
   if (d <= 0) return hipSuccess;
@@ -248,19 +270,20 @@ hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int
   dim3 grid((unsigned)((d + BM - 1) / BM), (unsigned)((d + BN - 1) / BN), (unsigned)splits);
   switch (dtype) {
     case 0:
-      dgemm_kernel<false, true, double><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, static_cast<const double*>(A), 1,
-                                                                  ld, static_cast<const double*>(A), ld, 1, 0.0, B,
-                                                                  d, splits, kchunk, partial, nullptr);
+      dgemm_kernel<false, true, double, true><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, static_cast<const double*>(A),
+                                                                        1, ld, static_cast<const double*>(A), ld, 1,
+                                                                        0.0, B, d, splits, kchunk, partial, nullptr);
       break;
     case 1:
-      dgemm_kernel<false, true, float><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, static_cast<const float*>(A), 1, ld,
-                                                                 static_cast<const float*>(A), ld, 1, 0.0, B, d,
-                                                                 splits, kchunk, partial, nullptr);
+      dgemm_kernel<false, true, float, true><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, static_cast<const float*>(A), 1,
+                                                                       ld, static_cast<const float*>(A), ld, 1, 0.0,
+                                                                       B, d, splits, kchunk, partial, nullptr);
       break;
     case 2: {
       const auto* a = static_cast<const __hip_bfloat16*>(A);
-      dgemm_kernel<false, true, __hip_bfloat16><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, a, 1, ld, a, ld, 1, 0.0, B, d,
-                                                                          splits, kchunk, partial, nullptr);
+      dgemm_kernel<false, true, __hip_bfloat16, true><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, a, 1, ld, a, ld, 1, 0.0,
+                                                                                B, d, splits, kchunk, partial,
+                                                                                nullptr);
       break;
     }
     default:
@@ -268,8 +291,7 @@ hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int
   }
   if (splits > 1) {
     const int64_t total = d * d;
-    splitk_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(d, d, splits, partial, 1.0, 0.0, B, d,
-                                                                          nullptr);
+    gram_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(d, splits, partial, B);
   }
   return hipGetLastError();
 }

@@ -4,14 +4,19 @@
 //
 // Row i adds the outer product a_i a_i^T, i.e. a_ip a_iq at (c_p, c_q) for
 // every pair of its nonzeros.  B is cut into 128 x 128 tiles (I, J), I <= J
-// (B is symmetric); a workgroup owns one tile in LDS (FP64, 128 KB) and one
-// chunk of rows, and for each row adds the pairs with c_p in block I and
-// c_q in block J by LDS atomic adds.  Column ids are sorted within a row, so
-// the entries of a block are a contiguous run, found by counting ids below
-// the block bounds.  The tiles of all chunks are summed in chunk order into B
-// and mirrored below the diagonal.  FP32 and BF16 values give exact FP64
-// products; the order of the atomic adds inside a workgroup is not fixed, so
-// B's last bits can vary between runs.
+// (B is symmetric); a workgroup owns one tile in LDS (FP64, rows padded to
+// kGS doubles so that the rows of one atomic instruction spread over the
+// banks) and one chunk of rows.  A wave takes one row at a time: column ids
+// are sorted within a row, so the entries in block I and in block J are two
+// contiguous runs, found by counting ids below the block bounds; the lanes
+// hold the runs (up to 128 entries each, two per lane) and, for each entry p
+// of run I in turn (its id and value read from the holding lane), add
+// a_ip a_iq for the entries q of run J, one per lane, by LDS atomic adds.
+// On a diagonal tile only q >= p is added (the upper triangle, mirrored when
+// the tiles are summed).  The tiles of all chunks are summed in chunk order
+// into B and mirrored below the diagonal.  FP32 and BF16 values give exact
+// FP64 products; the order of the atomic adds inside a workgroup is not
+// fixed, so B's last bits can vary between runs.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,10 +29,11 @@ namespace lev {
 namespace {
 
 constexpr int kGT = 128;             // tile edge
+constexpr int kGS = kGT + 1;         // LDS row stride of the tile, in doubles
 constexpr int kGThreads = 1024;      // 16 waves
 constexpr int kGWaves = kGThreads / 64;
-constexpr int kTargetGroups = 512;   // workgroups per launch (one per CU resident: 128 KB of LDS)
-constexpr size_t kTileBytes = sizeof(double) * kGT * kGT;
+constexpr int kTargetGroups = 512;   // workgroups per launch (one per CU resident: 129 KB of LDS)
+constexpr size_t kTileBytes = sizeof(double) * kGT * kGS;
 
 __device__ __forceinline__ double val_f64(double x) { return x; }
 __device__ __forceinline__ double val_f64(float x) { return (double)x; }
@@ -55,18 +61,27 @@ __device__ __forceinline__ void pair_of(int q, int nb, int& I, int& J) {
   J = i + left;
 }
 
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const int64_t b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((int64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kGThreads) void gram_csr_kernel(const T* __restrict__ vals,
                                                              const int64_t* __restrict__ row_ptr,
                                                              const int32_t* __restrict__ col_idx, int64_t n,
                                                              int64_t d, int64_t nnz, int64_t rows_per_chunk,
                                                              double* __restrict__ partial) {
-  extern __shared__ double tile[];  // kGT x kGT
+  extern __shared__ double tile[];  // kGT rows of kGS
   const int nb = (int)((d + kGT - 1) / kGT);
   int I, J;
   pair_of((int)blockIdx.x, nb, I, J);
+  const bool diag = I == J;
   const int32_t I0 = I * kGT, J0 = J * kGT;
-  for (int e = threadIdx.x; e < kGT * kGT; e += kGThreads) tile[e] = 0.0;
+  const int32_t Iend = (int32_t)std::min<int64_t>(d, I0 + kGT), Jend = (int32_t)std::min<int64_t>(d, J0 + kGT);
+  for (int e = threadIdx.x; e < kGT * kGS; e += kGThreads) tile[e] = 0.0;
   __syncthreads();
 
   const int lane = threadIdx.x & 63;
@@ -77,46 +92,53 @@ __global__ __launch_bounds__(kGThreads) void gram_csr_kernel(const T* __restrict
     // row extent clamped to [0, nnz] (a malformed row_ptr gives a wrong B, no stray access)
     const int64_t s = std::min<int64_t>(std::max<int64_t>(row_ptr[i], 0), nnz);
     const int64_t e = std::max<int64_t>(s, std::min<int64_t>(std::max<int64_t>(row_ptr[i + 1], 0), nnz));
-    // positions of the runs [I0, I0 + kGT) and [J0, J0 + kGT) among the row's sorted ids
+    // positions of the runs [I0, Iend) and [J0, Jend) among the row's sorted ids
     int loI = 0, hiI = 0, loJ = 0, hiJ = 0;
     for (int64_t c0 = s; c0 < e; c0 += 64) {
       const int64_t p = c0 + lane;
       const int32_t c = p < e ? col_idx[p] : INT32_MAX;
       loI += __popcll(__ballot(c < I0));
-      hiI += __popcll(__ballot(c < I0 + kGT));
+      hiI += __popcll(__ballot(c < Iend));
       loJ += __popcll(__ballot(c < J0));
-      hiJ += __popcll(__ballot(c < J0 + kGT));
+      hiJ += __popcll(__ballot(c < Jend));
     }
-    const int lI = hiI - loI, lJ = hiJ - loJ;
-    if (lI == 0 || lJ == 0) continue;
-    // pairs (p, q): lanes in groups of gs (a power of two >= lJ, at most 64)
-    // over q, 64 / gs groups over p
-    const int gs = lJ >= 64 ? 64 : (1 << (32 - __clz(lJ - 1)));
-    const int gq = lane & (gs - 1), gp = lane / gs, ng = 64 / gs;
-    for (int pb = 0; pb < lI; pb += ng) {
-      const int p = pb + gp;
-      if (p >= lI) continue;
-      const int64_t pp = s + loI + p;
-      const int32_t cp = col_idx[pp];
-      const double vp = val_f64(vals[pp]);
-      if ((uint32_t)(cp - I0) >= (uint32_t)kGT) continue;  // ids >= d or unsorted rows: skipped
-      for (int qb = 0; qb < lJ; qb += gs) {
-        const int q = qb + gq;
-        if (q >= lJ) break;
-        const int64_t qq = s + loJ + q;
-        const int32_t cq = col_idx[qq];
-        if ((uint32_t)(cq - J0) >= (uint32_t)kGT || cq >= d || cp >= d) continue;
-        atomicAdd(&tile[(cp - I0) * kGT + (cq - J0)], vp * val_f64(vals[qq]));
+    const int lI = std::min(hiI - loI, kGT), lJ = std::min(hiJ - loJ, kGT);
+    if (lI <= 0 || lJ <= 0) continue;
+    // the runs in registers: entry t of a run is held by lane t % 64, slot t / 64
+    int32_t cI[2], cJ[2];
+    double vI[2], vJ[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = lane + 64 * h;
+      const int64_t pi = s + loI + t, pj = s + loJ + t;
+      cI[h] = t < lI ? col_idx[pi] - I0 : 0;
+      vI[h] = t < lI ? val_f64(vals[pi]) : 0.0;
+      cJ[h] = t < lJ ? col_idx[pj] - J0 : -1;
+      vJ[h] = t < lJ ? val_f64(vals[pj]) : 0.0;
+      // ids outside the block (an unsorted row) are dropped
+      if ((uint32_t)cJ[h] >= (uint32_t)kGT) cJ[h] = -1;
+    }
+    for (int p = 0; p < lI; ++p) {
+      const int h = p >> 6, l = p & 63;
+      const int32_t cp = __builtin_amdgcn_readlane(h ? cI[1] : cI[0], l);
+      const double vp = readlane_f64(h ? vI[1] : vI[0], l);
+      if ((uint32_t)cp >= (uint32_t)kGT) continue;
+      double* row = tile + cp * kGS;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        // diagonal tile: the upper triangle (q >= p, i.e. c_q >= c_p) only
+        if (cJ[q] >= 0 && (!diag || cJ[q] >= cp)) atomicAdd(row + cJ[q], vp * vJ[q]);
       }
     }
   }
   __syncthreads();
   double* out = partial + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * (kGT * kGT);
-  for (int e = threadIdx.x; e < kGT * kGT; e += kGThreads) out[e] = tile[e];
+  for (int e = threadIdx.x; e < kGT * kGT; e += kGThreads) out[e] = tile[(e / kGT) * kGS + e % kGT];
 }
 
 // B[I0 + a][J0 + b] = sum over chunks (ascending) of the tiles of pair (I, J),
-// and B[J0 + b][I0 + a] the same for I < J.
+// and B[J0 + b][I0 + a] the same for I < J; a diagonal tile holds the upper
+// triangle (a <= b) only.
 __global__ void gram_csr_reduce_kernel(int64_t d, int64_t chunks, const double* __restrict__ partial,
                                        double* __restrict__ B) {
   const int nb = (int)((d + kGT - 1) / kGT);
@@ -126,7 +148,9 @@ __global__ void gram_csr_reduce_kernel(int64_t d, int64_t chunks, const double* 
   if (e >= kGT * kGT) return;
   const int64_t r = (int64_t)I * kGT + e / kGT, c = (int64_t)J * kGT + e % kGT;
   if (r >= d || c >= d) return;
-  const double* src = partial + (int64_t)blockIdx.y * chunks * (kGT * kGT) + e;
+  const int a = e / kGT, b = e % kGT;
+  const int es = (I == J && a > b) ? b * kGT + a : e;  // below the diagonal: the mirrored entry
+  const double* src = partial + (int64_t)blockIdx.y * chunks * (kGT * kGT) + es;
   double acc = 0.0;
   for (int64_t q = 0; q < chunks; ++q) acc += src[q * (kGT * kGT)];
   B[r * d + c] = acc;

@@ -238,3 +238,52 @@ def test_end_to_end_bound_at_theory_sizes(gpu):
             assert _rel(theta, o.theta).max() < 1e-10
     _log("e2e fails", fails, "of", seeds)
     assert fails / seeds <= E2E["delta"]
+
+
+# ------------------------------------------------------------------ full size
+def _cfg(name):
+    idx = list(W.CONFIGS).index(name) + 1
+    return dict(W.CONFIGS[name]), W.data_seed(idx), W.sketch_seed(idx)
+
+
+def test_exact_scores_full_size_dense_sampled(gpu):
+    """Algorithm 7 on the 2^20 x 256 rank-128 FP32 workload (1% of the rows
+    scaled by 1e3) in the benchmark's launch configuration: sampled rows
+    against the oracle's Algorithm 7 run on the whole matrix."""
+    cfg, dseed, seed = _cfg("dense_f32_1Mx256_rank128")
+    n, d = cfg["n"], cfg["d"]
+    A = W.low_rank_coherent(n, d, cfg["rank"], dseed, device=gpu)
+    plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], mode="exact")
+    theta = plan.run().cpu().numpy().astype(np.float64)
+    rows = np.sort(np.random.default_rng(61).choice(n, 3000, replace=False))
+    o = L.ls_hrn_exact(A.cpu().numpy().astype(np.float64), seed, cfg["r_cs"], cfg["m"], cfg["zeta"], rows=rows)
+    assert o.rank == cfg["rank"]
+    rel = _rel(theta[rows], o.theta_rows)
+    _log("exact dense full size max rel", rel.max(), "sum", theta.sum())
+    assert rel.max() < 1e-4 and abs(theta.sum() - o.rank) < 1e-3 * o.rank
+
+
+def test_exact_scores_full_size_csr_sampled(gpu):
+    """Algorithm 7 on the 2^23 x 512 CSR workload (64 zero columns): the
+    sketch keeps the 448 live columns, so the exact scores of A_K are those
+    of A; sampled rows against the oracle's exact scores of A (the Gram of A
+    streamed over row blocks, Algorithm 5), and sum theta = 448."""
+    cfg, dseed, seed = _cfg("csr_f32_8Mx512")
+    n, d = cfg["n"], cfg["d"]
+    A = W.sparse_power_law(n, d, cfg["zero_cols"], dseed, device=gpu)
+    plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], mode="exact")
+    theta = plan.run().cpu().numpy().astype(np.float64)
+    live_rank = d - cfg["zero_cols"]
+    _log("exact csr full size sum", theta.sum())
+    assert abs(theta.sum() - live_rank) < 1e-3 * live_rank
+    S = A.to_scipy()
+    rows = np.sort(np.random.default_rng(62).choice(n, 3000, replace=False))
+    blk = 1 << 18
+    chunks = lambda: ((lo, S[lo:lo + blk].toarray()) for lo in range(0, n, blk))  # noqa: E731
+    exact, rho = L.theta_gram_rows(chunks, rows, 1e-6)
+    assert rho == live_rank
+    live = exact > 0
+    assert np.all(theta[rows][~live] == 0)
+    rel = _rel(theta[rows][live], exact[live])
+    _log("exact csr full size max rel", rel.max())
+    assert rel.max() < 1e-4
