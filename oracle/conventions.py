@@ -30,6 +30,15 @@ its own):
   floor(e / 2) for the row-major element index e, key = a SplitMix64 word;
   two 53-bit uniforms per counter; Box-Muller in FP64, cosine branch for
   even e and sine branch for odd e.
+* SRHT (Section 3.4, "SRHT"): F = sqrt(r / t) P H D with D = diag(+-1),
+  H the r x r Walsh-Hadamard matrix scaled by 1 / sqrt(r) and P a uniform
+  sample of t of the r coordinates.  The sign of coordinate j is the top
+  bit of the SplitMix64 finaliser of key_d + j * gamma; the sample takes
+  coordinates pi(0), ..., pi(t - 1) of a keyed permutation pi of [0, r): a
+  four-round Feistel network (Luby-Rackoff) on 2h-bit words, h = max(1,
+  ceil(log2(r) / 2)), round functions from the finaliser of key_p + (round
+  * 2^32 + half) * gamma, walked along its cycle until the value is < r
+  (Black-Rogaway cycle walking), so pi is a bijection of [0, r).
 """
 
 from __future__ import annotations
@@ -48,6 +57,17 @@ P61 = (1 << 61) - 1
 # SplitMix64 (Steele, Lea, Flood 2014): state += golden gamma, then a
 # variant-13 finaliser of the new state.
 # --------------------------------------------------------------------------
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+
+
+def mix64(z: int) -> int:
+    """The SplitMix64 output finaliser (variant 13) of a 64-bit word."""
+    z &= MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
 def splitmix64_words(seed: int, count: int) -> list[int]:
     """The first ``count`` outputs of SplitMix64 started from ``seed``."""
     state = seed & MASK64
@@ -97,17 +117,51 @@ class SketchRandomness:
     sign_coef: tuple  # (c0, c1, c2, c3) in GF(p61)
     key_m: tuple    # Philox key (k0, k1) of the Gaussian transform G_m
     key_k: tuple    # Philox key (k0, k1) of the JL Gaussian G_k
+    key_d: int      # SRHT signs D
+    key_p: int      # SRHT coordinate sample P
 
 
 def derive(seed: int, n: int, r_cs: int) -> SketchRandomness:
-    w = splitmix64_words(seed, 8)
+    w = splitmix64_words(seed, 10)
     P = next_prime(max(n, 2))
     a = 1 + (w[0] % (P - 1))
     c = w[1] % P
     coef = tuple(w[2 + t] % P61 for t in range(4))
     key_m = (w[6] & MASK32, w[6] >> 32)
     key_k = (w[7] & MASK32, w[7] >> 32)
-    return SketchRandomness(seed, n, r_cs, P, a, c, coef, key_m, key_k)
+    return SketchRandomness(seed, n, r_cs, P, a, c, coef, key_m, key_k, w[8], w[9])
+
+
+# --------------------------------------------------------------------------
+# SRHT signs and coordinate sample
+# --------------------------------------------------------------------------
+def srht_sign(rnd: SketchRandomness, j: int) -> int:
+    """D_jj = +1 when the top bit of mix64(key_d + j * gamma) is clear."""
+    return -1 if mix64(rnd.key_d + j * GOLDEN_GAMMA) >> 63 else 1
+
+
+def _feistel_half_bits(r: int) -> int:
+    k = max(0, (r - 1).bit_length())  # r = 2^k
+    return max(1, (k + 1) // 2)
+
+
+def _feistel(rnd: SketchRandomness, x: int, h: int) -> int:
+    mask = (1 << h) - 1
+    left, right = x >> h, x & mask
+    for t in range(4):
+        f = mix64(rnd.key_p + ((t << 32) + right) * GOLDEN_GAMMA) & mask
+        left, right = right, left ^ f
+    return (left << h) | right
+
+
+def srht_coordinate(rnd: SketchRandomness, r: int, j: int) -> int:
+    """pi(j) for 0 <= j < r: the Feistel permutation of [0, 2^{2h}) walked
+    along its cycle until it lands in [0, r)."""
+    h = _feistel_half_bits(r)
+    y = _feistel(rnd, j, h)
+    while y >= r:
+        y = _feistel(rnd, y, h)
+    return y
 
 
 # --------------------------------------------------------------------------

@@ -15,7 +15,8 @@ Estimator LS-HRN-approx (Algorithm 10):
      column-pivoted QR of LAPACK xGEQP3 (Section 7); so does this oracle,
      through scipy.linalg.qr(pivoting=True), which calls DGEQP3.
   2. Keep A_{:,K} = A P_k.
-  3. Algorithm 8 on A_{:,K} with Pi_1 = G S: R~ from a QR of Pi_1 A_{:,K},
+  3. Algorithm 8 on A_{:,K} with Pi_1 = G S (or F S, the SRHT composition of
+     Section 4): R~ from a QR of Pi_1 A_{:,K},
      X = R~^{-1} Pi_2, theta~_i = ||e_i^T A_{:,K} X||^2.
 
 Readings of points the paper leaves open (listed with their reasons in the
@@ -164,9 +165,47 @@ def countsketch_apply(rnd: conv.SketchRandomness, A, chunk: int = 1 << 16) -> np
     return SA
 
 
-def count_gauss_sketch(rnd: conv.SketchRandomness, A, m: int):
-    """Algorithm 3: A~ = G (S A), with G = G_m / sqrt(m).  Returns (A~, SA)."""
+def fwht(X: np.ndarray) -> np.ndarray:
+    """H X for the unscaled Walsh-Hadamard matrix of Sylvester order
+    (H[i][j] = (-1)^popcount(i & j)), along axis 0 (length a power of two),
+    by the butterflies (a, b) -> (a + b, a - b) over each bit."""
+    Y = np.array(X, dtype=np.float64, copy=True)
+    r = Y.shape[0]
+    h = 1
+    while h < r:
+        Y = Y.reshape(r // (2 * h), 2, h, *Y.shape[1:])
+        a, b = Y[:, 0].copy(), Y[:, 1].copy()
+        Y[:, 0], Y[:, 1] = a + b, a - b
+        Y = Y.reshape(r, *Y.shape[3:])
+        h *= 2
+    return Y
+
+
+def srht_apply(rnd: conv.SketchRandomness, SA: np.ndarray, t: int) -> np.ndarray:
+    """F (S A) for the SRHT F = sqrt(r / t) P (H / sqrt(r)) D of Section 3.4
+    (= P H D / sqrt(t) with the unscaled H): D's signs, then H (the dense
+    Sylvester matrix of scipy for r <= 4096, the butterflies above beyond),
+    then rows pi(0), ..., pi(t - 1)."""
+    r = SA.shape[0]
+    D = np.array([conv.srht_sign(rnd, j) for j in range(r)], dtype=np.float64)
+    X = D[:, None] * SA
+    HX = sla.hadamard(r) @ X if r <= 4096 else fwht(X)
+    rows = [conv.srht_coordinate(rnd, r, j) for j in range(t)]
+    return HX[rows] / math.sqrt(t)
+
+
+SKETCHES = ("gauss", "srht")
+
+
+def count_gauss_sketch(rnd: conv.SketchRandomness, A, m: int, sketch: str = "gauss"):
+    """Algorithm 3: A~ = G (S A), with G = G_m / sqrt(m).  sketch="srht":
+    A~ = F (S A) with the m x r_cs SRHT F in place of G (the F S composition
+    of Section 4).  Returns (A~, SA)."""
+    if sketch not in SKETCHES:
+        raise ValueError(f"sketch must be one of {SKETCHES}")
     SA = countsketch_apply(rnd, A)
+    if sketch == "srht":
+        return srht_apply(rnd, SA, m), SA
     G = conv.gaussian_transform(rnd, m)
     return G @ SA, SA
 
@@ -196,9 +235,9 @@ def qrcp_sign_normalised(At: np.ndarray, zeta: float) -> RankRevealing:
     return RankRevealing(np.asarray(perm, dtype=np.int64), R, rank)
 
 
-def count_gauss_srrqr(rnd: conv.SketchRandomness, A, m: int, zeta: float):
+def count_gauss_srrqr(rnd: conv.SketchRandomness, A, m: int, zeta: float, sketch: str = "gauss"):
     """Algorithm 4: returns (P_k as column ids, R_k, k) plus the sketch."""
-    At, SA = count_gauss_sketch(rnd, A, m)
+    At, SA = count_gauss_sketch(rnd, A, m, sketch)
     rr = qrcp_sign_normalised(At, zeta)
     k = rr.rank
     return rr.perm[:k], rr.R[:k, :k], k, At, SA, rr
@@ -255,13 +294,14 @@ class Estimate:
     G_k: np.ndarray            # d x k_jl JL Gaussian (rows used: 0..rank-1)
 
 
-def ls_hrn_approx(A, seed: int, r_cs: int, m: int, k_jl: int, zeta: float, rows=None) -> Estimate:
+def ls_hrn_approx(A, seed: int, r_cs: int, m: int, k_jl: int, zeta: float, rows=None,
+                  sketch: str = "gauss") -> Estimate:
     """Algorithm 10 (LS-HRN-approx) with the readings listed in the module
     docstring.  ``rows`` restricts the final row-norm step to a subset (the
-    sketch still uses all of A)."""
+    sketch still uses all of A); sketch="srht" takes Pi_1 = F S."""
     n, d = A.shape
     rnd = conv.derive(seed, n, r_cs)
-    K, _, k, At, SA, rr = count_gauss_srrqr(rnd, A, m, zeta)
+    K, _, k, At, SA, rr = count_gauss_srrqr(rnd, A, m, zeta, sketch)
     Gk = conv.jl_gaussian(rnd, d, k_jl)
     if k == 0:
         th = np.zeros(n) if rows is None else None
@@ -283,7 +323,7 @@ class ExactEstimate:
     rank: int
 
 
-def ls_hrn_exact(A, seed: int, r_cs: int, m: int, zeta: float, rows=None) -> ExactEstimate:
+def ls_hrn_exact(A, seed: int, r_cs: int, m: int, zeta: float, rows=None, sketch: str = "gauss") -> ExactEstimate:
     """Algorithm 7 (LS-HRN-exact): the columns K and the rank k from
     Algorithm 4 on the sketch (as in ls_hrn_approx), then B = A_K^T A_K, its
     eigendecomposition B = V Sigma^2 V^T (the SVD of a symmetric positive
@@ -291,7 +331,7 @@ def ls_hrn_exact(A, seed: int, r_cs: int, m: int, zeta: float, rows=None) -> Exa
     leverage scores of A_K.  ``rows`` restricts the last step to a subset."""
     n, d = A.shape
     rnd = conv.derive(seed, n, r_cs)
-    K, _, k, _, _, rr = count_gauss_srrqr(rnd, A, m, zeta)
+    K, _, k, _, _, rr = count_gauss_srrqr(rnd, A, m, zeta, sketch)
     if k == 0:
         return ExactEstimate(np.zeros(n) if rows is None else None,
                              np.zeros(len(rows)) if rows is not None else None, rr.perm, 0)

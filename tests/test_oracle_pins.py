@@ -363,6 +363,105 @@ def test_end_to_end_bound_at_theory_sizes():
     assert fails / seeds <= E2E["delta"]
 
 
+# ------------------------------------------------------------------ SRHT
+def test_fwht_is_the_sylvester_hadamard_product():
+    """The butterflies equal the dense Walsh-Hadamard matrix (scipy's
+    Sylvester construction), which is symmetric with H H^T = r I."""
+    rng = np.random.default_rng(30)
+    for r in (1, 2, 8, 256, 2048):
+        X = rng.standard_normal((r, 3))
+        H = sla.hadamard(r)
+        np.testing.assert_allclose(L.fwht(X), H @ X, rtol=0, atol=1e-12 * r)
+        np.testing.assert_array_equal(H @ H.T, r * np.eye(r))
+    # entry definition: H[i][j] = (-1)^popcount(i & j)
+    H = sla.hadamard(32)
+    for i in range(32):
+        for j in range(32):
+            assert H[i, j] == (-1) ** bin(i & j).count("1")
+
+
+@pytest.mark.parametrize("r", [1, 2, 4, 8, 32, 128, 1024, 8192])
+def test_srht_sample_is_a_permutation(r):
+    """pi is a bijection of [0, r) for every key (Feistel rounds are
+    invertible; cycle walking keeps the bijection on the subset)."""
+    for seed in (0, 1, 2 ** 63 + 5):
+        rnd = C.derive(seed, 100, r)
+        assert sorted(C.srht_coordinate(rnd, r, j) for j in range(r)) == list(range(r))
+
+
+def test_srht_sample_and_signs_are_uniform():
+    """Each coordinate lands in the first t positions with probability t / r,
+    each ordered pair of coordinates equally often at positions (0, 1), and
+    the signs are balanced and pairwise uncorrelated (chi-square tests over
+    seeds)."""
+    r, t, seeds = 64, 16, 4000
+    hits = np.zeros(r)
+    pairs = np.zeros((r, r))
+    for seed in range(seeds):
+        rnd = C.derive(seed, 10, r)
+        pos = [C.srht_coordinate(rnd, r, j) for j in range(t)]
+        hits[pos] += 1
+        pairs[pos[0], pos[1]] += 1
+    assert st.chisquare(hits).pvalue > 1e-3
+    off = pairs[~np.eye(r, dtype=bool)]
+    assert np.all(np.diag(pairs) == 0) and st.chisquare(off).pvalue > 1e-3
+    sg = np.array([[C.srht_sign(C.derive(seed, 10, r), j) for j in range(8)] for seed in range(seeds)])
+    assert abs(sg.mean()) < 4 / math.sqrt(sg.size)
+    corr = (sg[:, :, None] * sg[:, None, :]).mean(axis=0)[~np.eye(8, dtype=bool)]
+    assert np.all(np.abs(corr) < 5 / math.sqrt(seeds))
+
+
+def test_srht_matches_its_matrix_definition():
+    """F (S A) equals sqrt(r / t) P (H / sqrt(r)) D (S A) written with the
+    dense matrices, and E[F^T F] = I (the scaling)."""
+    r, t, d = 64, 24, 5
+    rnd = C.derive(7, 500, r)
+    SA = np.random.default_rng(31).standard_normal((r, d))
+    D = np.diag([C.srht_sign(rnd, j) for j in range(r)])
+    P = np.zeros((t, r))
+    for j in range(t):
+        P[j, C.srht_coordinate(rnd, r, j)] = 1.0
+    F = math.sqrt(r / t) * P @ (sla.hadamard(r) / math.sqrt(r)) @ D
+    np.testing.assert_allclose(L.srht_apply(rnd, SA, t), F @ SA, rtol=1e-13, atol=1e-13)
+    acc = np.zeros((r, r))
+    seeds = 3000
+    for seed in range(seeds):
+        rs = C.derive(seed, 500, r)
+        Dd = np.array([C.srht_sign(rs, j) for j in range(r)], dtype=float)
+        Hd = sla.hadamard(r)[[C.srht_coordinate(rs, r, j) for j in range(t)]] * Dd / math.sqrt(t)
+        acc += Hd.T @ Hd
+    np.testing.assert_allclose(acc / seeds, np.eye(r), atol=0.12)
+
+
+def test_srht_is_an_embedding_at_the_theorem_size():
+    """SRHT theorem of Section 3.4 (Tropp): t >= 4 (sqrt(d) + sqrt(ln(r d)))^2
+    ln d rows give sigma(F U) in [sqrt(1/6), sqrt(13/6)] with probability
+    >= 1 - 3/d, for a fixed U with orthonormal columns."""
+    r, d = 4096, 6
+    t = math.ceil(4 * (math.sqrt(d) + math.sqrt(math.log(r * d))) ** 2 * math.log(d))
+    U, _ = np.linalg.qr(np.random.default_rng(32).standard_normal((r, d)))
+    fails, seeds = 0, 40
+    for seed in range(seeds):
+        sv = np.linalg.svd(L.srht_apply(C.derive(seed, 10, r), U, t), compute_uv=False)
+        fails += int(sv[0] > math.sqrt(13 / 6) or sv[-1] < math.sqrt(1 / 6))
+    assert fails / seeds <= 3 / d
+
+
+def test_srht_sketch_estimator():
+    """Algorithm 10 with Pi_1 = F S (m = 64 r rows of the SRHT): the rank is
+    found and theta~ stays within (1 +- 1/2) of theta for most seeds (the
+    same end-to-end check as for the Gaussian stage)."""
+    A = W.theory_sized_matrix()
+    th, _ = L.exact_theta_svd(A, 1e-12)
+    cfg = W.THEORY_SIZED
+    fails, seeds = 0, 20
+    for seed in range(seeds):
+        est = L.ls_hrn_approx(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], 1e-10, sketch="srht")
+        assert est.rank == cfg["d"]
+        fails += int(np.max(np.abs(est.theta / th - 1)) > cfg["eps"])
+    assert fails / seeds <= cfg["delta"]
+
+
 def test_estimator_handles_zero_and_zero_rows():
     A = np.zeros((100, 5))
     est = L.ls_hrn_approx(A, 1, 16, 10, 4, 1e-8)
