@@ -3,13 +3,15 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision auto|native|fp32|bf16|bf16x2|bf16x3]
                     [--no-accuracy] [--no-cpu-baseline] [--mode jl|exact|nojl]
+                    [--sketch gauss|srht]
 
 One step = one lev_estimate call over the whole workload resident in HBM:
 the Gaussian draws and pass 1 (CountSketch S A), the Gaussian transform, the
 rank-revealing factorisation, Z = R11^{-1} G_k and pass 2 (theta~); for the
 backward workload (name ending in _bwd) also the adjoint of w^T theta~.
 --mode exact times Algorithm 7 instead (the exact scores of A_K from B =
-A_K^T A_K), --mode nojl the estimate without the JL step (Pi_2 = I).
+A_K^T A_K), --mode nojl the estimate without the JL step (Pi_2 = I);
+--sketch srht replaces the Gaussian stage G (S A) by the SRHT F (S A).
 Prints one JSON line with rows/s, the per-phase times and rooflines (the
 headline `roofline` is the slowest phase's, measured live with the HIP
 events liblev records on its own stream), the accuracy of theta~ on sampled
@@ -134,7 +136,7 @@ def expected_rank(cfg) -> int:
     return min(cfg["d"] - cfg.get("zero_cols", 0), cfg.get("rank", cfg["d"]))
 
 
-def phase_work(A, cfg, mode: str = "jl") -> dict:
+def phase_work(A, cfg, mode: str = "jl", sketch: str = "gauss") -> dict:
     """Algorithmic work of each phase of one estimate: bytes for the passes
     over A (HBM-bound), FP64 flops for the n-independent phases (their
     dominant kernels are FP64 MFMA GEMMs and the pivoting that drives them).
@@ -145,6 +147,16 @@ def phase_work(A, cfg, mode: str = "jl") -> dict:
     n, d, m, r_cs, k = _n(A), cfg["d"], cfg["m"], cfg["r_cs"], cfg["k"]
     theta_es = 8 if _values(A).dtype == torch.float64 else 4
     r = expected_rank(cfg)
+    out = _phase_work_mode(A, cfg, mode, n, d, m, r_cs, k, theta_es, r)
+    if sketch == "srht":
+        # no G_m: pass 1 writes S A (and G_k); the SRHT reads S A once and
+        # writes A~ at least (its radix passes add the in-place round trips)
+        out["pass1_countsketch"] = ("hbm", a_bytes(A) + 8 * (r_cs * d + (d * k if mode == "jl" else 0)))
+        out["gaussian_transform"] = ("hbm", 8 * (r_cs * d + m * d))
+    return out
+
+
+def _phase_work_mode(A, cfg, mode, n, d, m, r_cs, k, theta_es, r) -> dict:
     if mode != "jl":
         tiles = -(-r // 64)
         if mode == "exact":
@@ -173,9 +185,9 @@ def phase_work(A, cfg, mode: str = "jl") -> dict:
     }
 
 
-def rooflines(A, cfg, phases_ms: dict, traffic: dict, mode: str = "jl") -> dict:
+def rooflines(A, cfg, phases_ms: dict, traffic: dict, mode: str = "jl", sketch: str = "gauss") -> dict:
     out = {}
-    for name, (bound, work) in phase_work(A, cfg, mode).items():
+    for name, (bound, work) in phase_work(A, cfg, mode, sketch).items():
         t = phases_ms[name] * 1e-3
         if bound == "hbm":
             ach = work / t / 1e9
@@ -195,7 +207,7 @@ def _host_rows(A, lo: int, hi: int) -> np.ndarray:
     return A[lo:hi].to(torch.float64).cpu().numpy()
 
 
-def cpu_baseline(A, cfg, seed, target_s: float = 10.0, mode: str = "jl"):
+def cpu_baseline(A, cfg, seed, target_s: float = 10.0, mode: str = "jl", sketch: str = "gauss"):
     """Times the oracle's estimator on the first n_s rows of the workload
     (same d, sketch sizes and seed), growing n_s until about a quarter of
     target_s; when that covers the whole workload, the whole workload is
@@ -204,8 +216,8 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0, mode: str = "jl"):
 
     def oracle(Ah):
         if mode == "exact":
-            return L.ls_hrn_exact(Ah, seed, cfg["r_cs"], cfg["m"], cfg["zeta"])
-        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"])
+            return L.ls_hrn_exact(Ah, seed, cfg["r_cs"], cfg["m"], cfg["zeta"], sketch=sketch)
+        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], sketch=sketch)
         if mode == "nojl":
             return L.theta_prime(Ah, o.perm[:o.rank], o.R11)
         return o
@@ -253,7 +265,7 @@ def _stats(ratio: np.ndarray) -> dict:
             "frac_within_0.5": float(np.mean(np.abs(ratio - 1.0) <= 0.5))}
 
 
-def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000, mode: str = "jl") -> dict:
+def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000, mode: str = "jl", sketch: str = "gauss") -> dict:
     """theta~ of each form (name -> full theta~ on the device) on sampled
     rows against (i) the oracle's FP64 estimator with the same sketch (the
     JL estimate, or theta' without the JL step; for the exact scores the
@@ -268,12 +280,12 @@ def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000, mode: str = "
     t0 = time.perf_counter()
     if _is_csr(A):
         Ah = A.to_scipy()
-        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows)
+        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows, sketch=sketch)
         blk = 1 << 20
         chunks = lambda: ((lo, Ah[lo:lo + blk].toarray()) for lo in range(0, n, blk))  # noqa: E731
     else:
         Ah = A.float().cpu().numpy() if A.dtype == torch.bfloat16 else A.cpu().numpy()
-        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows)
+        o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], rows=rows, sketch=sketch)
         blk = 1 << 16
         chunks = lambda: ((lo, Ah[lo:lo + blk]) for lo in range(0, n, blk))  # noqa: E731
     t_same = time.perf_counter() - t0
@@ -463,6 +475,7 @@ def phase_times(plan, bwd, steps: int, stream):
 
 ALGORITHMS = {"jl": "LS-HRN-approx (Algorithm 10)", "exact": "LS-HRN-exact (Algorithm 7)",
               "nojl": "Algorithm 10 without the JL step (Pi_2 = I)"}
+SKETCH_NAMES = {"gauss": "CountGauss G (S A) (Algorithm 3)", "srht": "SRHT F (S A) (Section 4)"}
 
 
 def main():
@@ -478,6 +491,8 @@ def main():
                     help="jl: Algorithm 10; exact: Algorithm 7 (LS-HRN-exact); nojl: Algorithm 10 without "
                          "the JL step (Pi_2 = I)")
     ap.add_argument("--exact", action="store_true", help="same as --mode exact")
+    ap.add_argument("--sketch", choices=("gauss", "srht"), default="gauss",
+                    help="gauss: A~ = G (S A) (Algorithm 3); srht: A~ = F (S A), the SRHT composition of Section 4")
     ap.add_argument("--traffic-run", action="store_true", help="the process a counter run profiles")
     ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
@@ -501,7 +516,7 @@ def main():
     A, cfg, seed = make_workload(args.workload, dev)
     precision = resolve_precision(A, args.precision)
     plan = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=precision,
-                            mode=args.mode)
+                            mode=args.mode, sketch=args.sketch)
     bwd = None
     if args.workload.endswith("_bwd"):
         bwd = api.BackwardPlan(plan, torch.rand(A.shape[0], device=dev, dtype=A.dtype,
@@ -520,7 +535,7 @@ def main():
     phases, spread, bms = phase_times(plan, bwd, args.steps, stream)
     n = _n(A)
     traffic = traffic_for(args.workload, A, precision)
-    roofs = rooflines(A, cfg, phases, traffic, args.mode)
+    roofs = rooflines(A, cfg, phases, traffic, args.mode, args.sketch)
     slowest = max(roofs, key=lambda k: phases[k])
     kern = pass_kernels(A, precision)
     headline = dict(roofs[slowest])
@@ -541,7 +556,7 @@ def main():
         "data": "synthetic (seeded, generated on the GPU)",
         "config": {"workload": args.workload, "n": n, "d": cfg["d"], "r_cs": cfg["r_cs"], "m": cfg["m"],
                    "k": cfg["k"], "zeta": cfg["zeta"], "precision": precision,
-                   "algorithm": ALGORITHMS[args.mode]},
+                   "algorithm": ALGORITHMS[args.mode], "sketch": SKETCH_NAMES[args.sketch]},
         "roofline": headline,
         "rooflines": roofs,
         "phases_ms": phases,
@@ -562,7 +577,8 @@ def main():
         for other in ("bf16", "bf16x2", "bf16x3"):
             if other == precision:
                 continue
-            p2 = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=other)
+            p2 = api.EstimatePlan(A, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], precision=other,
+                                  sketch=args.sketch)
             p2.run()
             t = time_steps(p2, None, max(3, args.steps // 4), stream)
             ph, _, _ = phase_times(p2, None, max(3, args.steps // 4), stream)
@@ -571,10 +587,10 @@ def main():
             del p2
     if not args.no_accuracy:
         print("# accuracy on sampled rows (oracle: same sketch, and exact scores)", file=sys.stderr, flush=True)
-        out["accuracy"] = accuracy_report(A, cfg, seed, forms, mode=args.mode)
+        out["accuracy"] = accuracy_report(A, cfg, seed, forms, mode=args.mode, sketch=args.sketch)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(A, cfg, seed, mode=args.mode)
+        out["cpu_baseline"] = cpu_baseline(A, cfg, seed, mode=args.mode, sketch=args.sketch)
     print(json.dumps(out), flush=True)
 
 

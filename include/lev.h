@@ -110,14 +110,27 @@ typedef struct {
  *           (lev_sketch ignores zeta.)
  *  az_precision -- LEV_AZ_* above.
  *  mode  -- what lev_estimate returns (LEV_MODE_* below); lev_estimate's
- *           state_out must be NULL unless mode is LEV_MODE_JL. */
+ *           state_out must be NULL unless mode is LEV_MODE_JL.
+ *  sketch -- the dense stage after the CountSketch (LEV_SKETCH_* below). */
 typedef struct {
   uint64_t seed;
   int64_t r_cs, m, k;
   double zeta;
   int32_t az_precision;
   int32_t mode;
+  int32_t sketch;
 } lev_params;
+
+/* LEV_SKETCH_GAUSS: A~ = G (S A) with the m x r_cs Gaussian G / sqrt(m)
+ *   (Algorithm 3, the CountGauss sketch).
+ * LEV_SKETCH_SRHT: A~ = F (S A) with the m x r_cs SRHT F = sqrt(r_cs / m)
+ *   P (H / sqrt(r_cs)) D of Section 3.4 (the F S composition of Section 4):
+ *   D random signs, H the Walsh-Hadamard matrix, P the first m coordinates
+ *   of a keyed permutation of [0, r_cs).  Needs r_cs a power of two and
+ *   m <= r_cs (LEV_ERR_ARG / LEV_ERR_SHAPE otherwise); the product costs
+ *   r_cs d log2(r_cs) additions instead of 2 m r_cs d flops.  The backward
+ *   pass takes LEV_SKETCH_GAUSS only. */
+enum { LEV_SKETCH_GAUSS = 0, LEV_SKETCH_SRHT = 1 };
 
 /* LEV_MODE_JL: Algorithm 10 (LS-HRN-approx): theta~_i = ||e_i^T A_K
  *   R11^{-1} Pi_2||^2 with the k-column JL Gaussian Pi_2.

@@ -47,7 +47,7 @@ class LevMatrix(ctypes.Structure):
 
 class LevParams(ctypes.Structure):
     _fields_ = [("seed", c_uint64), ("r_cs", c_int64), ("m", c_int64), ("k", c_int64),
-                ("zeta", c_double), ("az_precision", c_int32), ("mode", c_int32)]
+                ("zeta", c_double), ("az_precision", c_int32), ("mode", c_int32), ("sketch", c_int32)]
 
 
 class LevError(RuntimeError):
@@ -188,15 +188,20 @@ def _matrix(A) -> LevMatrix:
 # lev_params.mode: the JL estimate (Algorithm 10), the exact scores of A_K
 # (Algorithm 7) or the estimate without the JL step (Pi_2 = I).
 MODES = {"jl": 0, "exact": 1, "nojl": 2}
+# lev_params.sketch: the Gaussian stage G (S A) of Algorithm 3, or the SRHT
+# F (S A) (the F S composition of Section 4).
+SKETCHES = {"gauss": 0, "srht": 1}
 
 
-def _params(seed, r_cs, m, k, zeta, precision, mode="jl") -> LevParams:
+def _params(seed, r_cs, m, k, zeta, precision, mode="jl", sketch="gauss") -> LevParams:
     if precision not in AZ:
         raise ValueError(f"precision must be one of {list(AZ)}")
     if mode not in MODES:
         raise ValueError(f"mode must be one of {list(MODES)}")
+    if sketch not in SKETCHES:
+        raise ValueError(f"sketch must be one of {list(SKETCHES)}")
     return LevParams(int(seed) & ((1 << 64) - 1), int(r_cs), int(m), int(k), float(zeta), AZ[precision],
-                     MODES[mode])
+                     MODES[mode], SKETCHES[sketch])
 
 
 def _mode(mode: str, exact: bool) -> str:
@@ -279,15 +284,16 @@ def lev_workspace_size(A, seed, r_cs, m, k, zeta, precision="native", which=WS_E
     return int(lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), which))
 
 
-def lev_sketch(A, seed: int, r_cs: int, m: int, return_sa: bool = False):
-    """Algorithm 3: A~ = G (S A) (m x d, FP64); optionally also S A.  A is a
-    dense device tensor or a CSR matrix (Csr, or a torch sparse_csr tensor
-    with int64 row pointers and int32 column indices)."""
+def lev_sketch(A, seed: int, r_cs: int, m: int, return_sa: bool = False, sketch: str = "gauss"):
+    """Algorithm 3: A~ = G (S A) (m x d, FP64), or F (S A) with the SRHT F
+    (sketch="srht"); optionally also S A.  A is a dense device tensor or a
+    CSR matrix (Csr, or a torch sparse_csr tensor with int64 row pointers
+    and int32 column indices)."""
     lib = load_library()
     A = _as_csr(A)  # held until the call returns: it owns converted index arrays
     dev, (_, d) = _device(A), _shape(A)
     prec = "fp32" if (_dtype(A) == torch.bfloat16 and not _is_csr(_as_csr(A))) else "native"
-    mat, par = _matrix(A), _params(seed, r_cs, m, 1, 0.0, prec)
+    mat, par = _matrix(A), _params(seed, r_cs, m, 1, 0.0, prec, sketch=sketch)
     nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_SKETCH)
     if nbytes == 0:
         _check(lib.lev_sketch(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))
@@ -319,17 +325,18 @@ def lev_rank_estimate(At: torch.Tensor, zeta: float):
 
 def lev_estimate(A, seed: int, r_cs: int, m: int, k: int, zeta: float,
                  precision: str = "native", return_state: bool = False, exact: bool = False,
-                 mode: str = "jl"):
+                 mode: str = "jl", sketch: str = "gauss"):
     """Algorithm 10 (LS-HRN-approx): theta~ (FP64 for FP64 A, else FP32).
     A is a dense device tensor or a CSR matrix (see lev_sketch).
     mode="exact" (or exact=True) runs Algorithm 7 (LS-HRN-exact) instead:
     the exact leverage scores of the columns K the sketch selects;
     mode="nojl" the estimate without the JL step, ||e_i^T A_K R11^{-1}||^2.
-    Both ignore k and have no state."""
+    Both ignore k and have no state.  sketch="srht" takes the SRHT F (S A)
+    in place of the Gaussian stage G (S A)."""
     lib = load_library()
     A = _as_csr(A)  # held until the call returns: it owns converted index arrays
     dev, (n, d), dt = _device(A), _shape(A), _dtype(A)
-    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, _mode(mode, exact))
+    mat, par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, _mode(mode, exact), sketch)
     nbytes = lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), WS_ESTIMATE)
     if nbytes == 0:
         _check(lib.lev_estimate(ctypes.byref(mat), ctypes.byref(par), None, None, None, 0, None))
@@ -363,10 +370,10 @@ class EstimatePlan:
     """Pre-allocated workspace and outputs for repeated lev_estimate calls on
     same-shaped inputs (what the benchmark times)."""
 
-    def __init__(self, A, seed, r_cs, m, k, zeta, precision="native", exact=False, mode="jl"):
+    def __init__(self, A, seed, r_cs, m, k, zeta, precision="native", exact=False, mode="jl", sketch="gauss"):
         self.lib = load_library()
         A = _as_csr(A)  # kept in self.A: the pointers below refer to its arrays
-        self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, _mode(mode, exact))
+        self.mat, self.par = _matrix(A), _params(seed, r_cs, m, k, zeta, precision, _mode(mode, exact), sketch)
         self.nbytes = self.lib.lev_workspace_size(ctypes.byref(self.mat), ctypes.byref(self.par), WS_ESTIMATE)
         if self.nbytes == 0:
             _check(self.lib.lev_estimate(ctypes.byref(self.mat), ctypes.byref(self.par), None, None, None, 0,

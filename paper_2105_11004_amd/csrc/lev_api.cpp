@@ -194,6 +194,14 @@ lev_status check_params(const lev_matrix* A, const lev_params* p, bool uses_zeta
   if (p->m > (1ll << 24)) return fail(LEV_ERR_SHAPE, "m too large");
   if (p->mode != LEV_MODE_JL && p->mode != LEV_MODE_EXACT && p->mode != LEV_MODE_NOJL)
     return fail(LEV_ERR_ARG, "mode %d is not LEV_MODE_JL, LEV_MODE_EXACT or LEV_MODE_NOJL", p->mode);
+  if (p->sketch != LEV_SKETCH_GAUSS && p->sketch != LEV_SKETCH_SRHT)
+    return fail(LEV_ERR_ARG, "sketch %d is not LEV_SKETCH_GAUSS or LEV_SKETCH_SRHT", p->sketch);
+  if (p->sketch == LEV_SKETCH_SRHT) {
+    if ((p->r_cs & (p->r_cs - 1)) != 0)
+      return fail(LEV_ERR_ARG, "the SRHT needs r_cs a power of two (r_cs = %lld)", (long long)p->r_cs);
+    if (p->m > p->r_cs)
+      return fail(LEV_ERR_SHAPE, "the SRHT samples m <= r_cs rows (m = %lld)", (long long)p->m);
+  }
   if (p->mode == LEV_MODE_JL && (p->k < 1 || p->k > kMaxK))
     return fail(LEV_ERR_ARG, "k = %lld outside [1, %lld]", (long long)p->k, (long long)kMaxK);
   if (!(p->zeta >= 0.0 && p->zeta < 1.0)) return fail(LEV_ERR_ARG, "zeta must be in [0, 1)");
@@ -253,12 +261,14 @@ int32_t* state_err(const StateView& v) { return reinterpret_cast<int32_t*>(v.hea
 
 // ---- workspace plans -------------------------------------------------------------
 struct SketchBufs {
-  double* Gm;        // FP64 G_m (m x r_cs), or null when x3
+  double* Gm;        // FP64 G_m (m x r_cs), or null when x3 or SRHT
   double* SA;
   double* partial;
   bool x3 = false;   // the transform in FP32-level arithmetic (xgemm.hip)
   uint32_t* Gp;      // x3: G_m as three BF16 parts
   void* SAp;         // x3: (S A)^T as three BF16 parts
+  bool srht = false; // A~ = F (S A) with the SRHT F (srht.hip) instead of G_m
+  int32_t* inv;      // SRHT: the sampled coordinates (r_cs)
 };
 
 int gm_splits(int64_t m, int64_t d, int64_t r_cs) { return lev::dgemm_choose_splits(m, d, r_cs); }
@@ -272,8 +282,7 @@ bool use_x3_transform(const lev_matrix* A, int64_t r_cs) {
   return A->format == LEV_DENSE_ROWMAJOR && A->dtype == LEV_BF16 && r_cs % 8 == 0;
 }
 
-SketchBufs carve_sketch(Carver& c, int64_t n, int64_t d, int64_t m, int64_t r_cs, bool need_sa, bool x3) {
-  (void)n;
+SketchBufs carve_sketch_bufs(Carver& c, int64_t d, int64_t m, int64_t r_cs, bool need_sa, bool x3) {
   SketchBufs b;
   b.x3 = x3;
   if (x3) {
@@ -290,6 +299,24 @@ SketchBufs carve_sketch(Carver& c, int64_t n, int64_t d, int64_t m, int64_t r_cs
   b.SA = need_sa ? c.take<double>((size_t)(r_cs * d)) : nullptr;
   b.partial = c.take<double>(lev::dgemm_partial_elems(m, d, gm_splits(m, d, r_cs)));
   return b;
+}
+
+// The sketch's buffers for A and p: the SRHT needs S A (transformed in
+// place) and the sample map; the Gaussian stage G_m (FP64, or its three BF16
+// parts for the FP32-level transform) and the product's partial sums.
+SketchBufs carve_sketch(Carver& c, const lev_matrix* A, const lev_params* p) {
+  if (p->sketch == LEV_SKETCH_SRHT) {
+    SketchBufs b;
+    b.srht = true;
+    b.Gm = nullptr;
+    b.partial = nullptr;
+    b.Gp = nullptr;
+    b.SAp = nullptr;
+    b.SA = c.take<double>((size_t)(p->r_cs * A->d));
+    b.inv = c.take<int32_t>((size_t)p->r_cs);
+    return b;
+  }
+  return carve_sketch_bufs(c, A->d, p->m, p->r_cs, true, use_x3_transform(A, p->r_cs));
 }
 
 struct RankBufs {
@@ -363,6 +390,7 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
   lev::GaussDraw g{{{dr.key_m, m * r_cs, 1.0 / std::sqrt((double)m), b.Gm},
                     {dr.key_k, d * k, 1.0 / std::sqrt((double)k), Gk}}};
   if (b.x3) g.m[0].parts3 = b.Gp;  // G_m drawn straight into its three parts
+  if (b.srht) g.m[0].total = 0;     // no G_m
   LEV_HIP(mark_phase(1, s));
   if (A->n > 0 && A->format == LEV_CSR) {
     LEV_HIP(lev::launch_countsketch_csr(A->dtype, A->values, A->row_ptr, A->col_idx, A->n, d, A->nnz, dr.hash,
@@ -370,13 +398,17 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
   } else if (A->n > 0) {
     LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, g, s));
   } else {
-    if (!b.x3) LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, g.m[0].scale, b.Gm, s));
+    if (!b.x3 && !b.srht) LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, g.m[0].scale, b.Gm, s));
     if (Gk != nullptr) LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, g.m[1].scale, Gk, s));
     LEV_HIP(lev::launch_fill_zero(SA, sizeof(double) * (size_t)(r_cs * d), s));
   }
   LEV_HIP(mark_phase(2, s));
-  // A~ = G_m (S A): (m x r_cs) (r_cs x d)
-  if (b.x3 && A->n > 0) {
+  // A~ = G_m (S A): (m x r_cs) (r_cs x d), or F (S A) with the SRHT F
+  if (b.srht) {
+    if (SA != b.SA)
+      LEV_HIP(hipMemcpyAsync(b.SA, SA, sizeof(double) * (size_t)(r_cs * d), hipMemcpyDeviceToDevice, s));
+    LEV_HIP(lev::launch_srht(dr.key_d, dr.key_p, r_cs, d, m, b.SA, b.inv, At, s));
+  } else if (b.x3 && A->n > 0) {
     LEV_HIP(lev::launch_split_t3(r_cs, d, SA, b.SAp, s));
     LEV_HIP(lev::launch_xgemm(m, d, r_cs, b.Gp, b.SAp, At, d, lev::xgemm_choose_splits(m, d, r_cs), b.partial, s));
   } else if (b.x3) {
@@ -550,6 +582,8 @@ ExactBufs carve_exact(Carver& c, const lev_matrix* A, const lev_params* p) {
 
 lev_status check_backward_input(const lev_matrix* A, const lev_params* p) {
   if (p->mode != LEV_MODE_JL) return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass is of the JL estimate only");
+  if (p->sketch != LEV_SKETCH_GAUSS)
+    return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass takes the Gaussian sketch (LEV_SKETCH_GAUSS) only");
   if (p->k > kMaxBwdK)
     return fail(LEV_ERR_NOT_SUPPORTED, "the backward pass takes k <= %lld", (long long)kMaxBwdK);
   if (A->format != LEV_DENSE_ROWMAJOR)
@@ -574,8 +608,8 @@ namespace lev {
 
 SeedDraws derive_draws(uint64_t seed, int64_t n, int64_t r_cs) {
   uint64_t st = seed;
-  uint64_t w[8];
-  for (int i = 0; i < 8; ++i) w[i] = splitmix64_next(st);
+  uint64_t w[10];
+  for (int i = 0; i < 10; ++i) w[i] = splitmix64_next(st);
   SeedDraws dr;
   HashParams& h = dr.hash;
   h.n = n;
@@ -592,6 +626,8 @@ SeedDraws derive_draws(uint64_t seed, int64_t n, int64_t r_cs) {
   h.c3 = w[5] % kP61;
   dr.key_m = PhiloxKey{(uint32_t)(w[6] & 0xFFFFFFFFu), (uint32_t)(w[6] >> 32)};
   dr.key_k = PhiloxKey{(uint32_t)(w[7] & 0xFFFFFFFFu), (uint32_t)(w[7] >> 32)};
+  dr.key_d = w[8];
+  dr.key_p = w[9];
   return dr;
 }
 
@@ -647,11 +683,11 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
   const int64_t d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
   Carver c(nullptr);
   if (which == LEV_WS_SKETCH) {
-    carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
+    carve_sketch(c, A, p);
     return c.used;
   }
   if (which == LEV_WS_ESTIMATE && p->mode == LEV_MODE_EXACT) {
-    carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
+    carve_sketch(c, A, p);
     carve_rank(c, m, d);
     if (p->zeta < kZetaGram) carve_refine(c, m, d);
     c.take<char>(state_bytes(d, m, d));
@@ -660,7 +696,7 @@ size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
     return c.used;
   }
   if (which == LEV_WS_ESTIMATE) {
-    carve_sketch(c, A->n, d, m, r_cs, true, use_x3_transform(A, r_cs));
+    carve_sketch(c, A, p);
     carve_rank(c, m, d);
     if (p->zeta < kZetaGram) carve_refine(c, m, d);
     const int64_t kz = pass2_cols(A, p);
@@ -683,10 +719,10 @@ lev_status lev_sketch(const lev_matrix* A, const lev_params* p, double* At_out, 
   LEV_TRY(check_params(A, p, /*uses_zeta=*/false));
   if (At_out == nullptr) return fail(LEV_ERR_ARG, "At_out is null");
   Carver sizing(nullptr);
-  carve_sketch(sizing, A->n, A->d, p->m, p->r_cs, true, use_x3_transform(A, p->r_cs));
+  carve_sketch(sizing, A, p);
   LEV_TRY(check_ws(ws, ws_bytes, sizing.used));
   Carver c(ws);
-  SketchBufs b = carve_sketch(c, A->n, A->d, p->m, p->r_cs, true, use_x3_transform(A, p->r_cs));
+  SketchBufs b = carve_sketch(c, A, p);
   const lev::SeedDraws dr = lev::derive_draws(p->seed, A->n, p->r_cs);
   double* SA = SA_out != nullptr ? SA_out : b.SA;
   return enqueue_sketch(A, p, dr, b, SA, At_out, nullptr, stream);
@@ -725,7 +761,7 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   const int64_t n = A->n, d = A->d, m = p->m, r_cs = p->r_cs;
   hipStream_t s = stream;
   Carver c(ws);
-  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true, use_x3_transform(A, r_cs));
+  SketchBufs sb = carve_sketch(c, A, p);
   RankBufs rb = carve_rank(c, m, d);
   RefineBufs rf;
   const bool refine = p->zeta < kZetaGram;
@@ -791,7 +827,7 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   const bool jl = p->mode == LEV_MODE_JL;
   const int64_t k = pass2_cols(A, p);
   Carver c(ws);
-  SketchBufs sb = carve_sketch(c, n, d, m, r_cs, true, use_x3_transform(A, r_cs));
+  SketchBufs sb = carve_sketch(c, A, p);
   RankBufs rb = carve_rank(c, m, d);
   RefineBufs rf;
   const bool refine = p->zeta < kZetaGram;

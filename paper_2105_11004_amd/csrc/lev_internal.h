@@ -30,9 +30,11 @@ struct SeedDraws {
   HashParams hash;
   PhiloxKey key_m;  // Gaussian transform G_m
   PhiloxKey key_k;  // JL Gaussian G_k
+  uint64_t key_d;   // SRHT signs D
+  uint64_t key_p;   // SRHT coordinate sample P
 };
 
-// Host-side expansion of a seed (SplitMix64 words w0..w7).
+// Host-side expansion of a seed (SplitMix64 words w0..w9).
 SeedDraws derive_draws(uint64_t seed, int64_t n, int64_t r_cs);
 
 // ---- launch wrappers (all enqueue on `s`, return hipError_t of the launch) ----
@@ -75,6 +77,12 @@ hipError_t launch_countsketch_csr(int dtype, const void* vals, const int64_t* ro
 // rows x cols FP64 Gaussian matrix, Philox4x32-10 + Box-Muller, times scale.
 hipError_t launch_gaussian(PhiloxKey key, int64_t rows, int64_t cols, double scale, double* out,
                            hipStream_t s);
+
+// The SRHT F = P H D / sqrt(t) (srht.hip) applied to X = S A (r x d FP64,
+// r a power of two, overwritten by H D X): At (t x d) = F X.  inv: int32[r]
+// scratch (the sampled coordinates).
+hipError_t launch_srht(uint64_t key_d, uint64_t key_p, int64_t r, int64_t d, int64_t t, double* X, int32_t* inv,
+                       double* At, hipStream_t s);
 
 // FP64 GEMM on MFMA: C = alpha * op(A) op(B) + beta * C with arbitrary
 // element strides: op(A)(i,k) = A[i*sai + k*sak], op(B)(k,j) = B[k*sbk + j*sbj],

@@ -56,10 +56,10 @@ def _mat(api, **kw):
 
 
 def _par(api, **kw):
-    base = dict(seed=1, r_cs=64, m=32, k=8, zeta=1e-5, az=0, mode=0)
+    base = dict(seed=1, r_cs=64, m=32, k=8, zeta=1e-5, az=0, mode=0, sketch=0)
     base.update(kw)
     return api.LevParams(base["seed"], base["r_cs"], base["m"], base["k"], base["zeta"], base["az"],
-                         base["mode"])
+                         base["mode"], base["sketch"])
 
 
 @pytest.mark.parametrize("mat_kw,par_kw,expected", [
@@ -89,6 +89,9 @@ def _par(api, **kw):
     ({}, {"mode": -1}, -1),
     ({"d": 2048, "ld": 2048}, {"mode": 1, "m": 4096}, -2),   # exact scores: d <= 1024 like the rest
     ({}, {"mode": 2, "zeta": 1e-12}, -7),
+    ({}, {"sketch": 2}, -1),
+    ({}, {"sketch": 1, "r_cs": 96}, -1),          # the SRHT needs r_cs a power of two
+    ({}, {"sketch": 1, "r_cs": 16}, -2),          # ... and m <= r_cs
 ])
 def test_estimate_rejects_bad_arguments(lib, mat_kw, par_kw, expected):
     from paper_2105_11004_amd import api
@@ -123,6 +126,7 @@ def test_workspace_checks(lib):
     ({}, {"mode": 1}, -7),       # only the JL estimate has an adjoint here
     ({}, {"mode": 2}, -7),
     ({}, {"k": 65}, -7),         # the backward's register tiles take k <= 64
+    ({}, {"sketch": 1}, -7),     # the adjoint of the Gaussian stage only
 ])
 def test_backward_rejects_unsupported_input(lib, mat_kw, par_kw, expected):
     from paper_2105_11004_amd import api

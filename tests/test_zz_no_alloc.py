@@ -53,7 +53,7 @@ def test_noalloc_refuses_problems_beyond_its_scratch():
     lib = api.load_library()
     c = W.CONFIGS["dense_bf16_4Mx1024"]
     mat = api.LevMatrix(api.DENSE, api.BF16, c["n"], c["d"], c["d"], 0, 4096, None, None)
-    par = api.LevParams(1, c["r_cs"], c["m"], c["k"], c["zeta"], 0, 0)
+    par = api.LevParams(1, c["r_cs"], c["m"], c["k"], c["zeta"], 0, 0, 0)
     assert lib.lev_workspace_size(ctypes.byref(mat), ctypes.byref(par), api.WS_ESTIMATE) > lib.lev_noalloc_max_bytes()
     st = lib.lev_estimate_noalloc(ctypes.byref(mat), ctypes.byref(par), ctypes.c_void_p(4096), None)
     assert st == -5  # LEV_ERR_WORKSPACE
