@@ -356,6 +356,75 @@ def theta_prime(A, K: np.ndarray, R11: np.ndarray, rows=None) -> np.ndarray:
     return row_norms_sq(A[:, K], X, rows=rows)
 
 
+# ==========================================================================
+# Algorithm 6: exact scores from a Q-less sparse pivoted QR
+# ==========================================================================
+@dataclass
+class QlessQR:
+    perm: np.ndarray   # the k pivots, in order
+    R: np.ndarray      # k x k upper triangular, positive diagonal: (A P_k)^T (A P_k) = R^T R
+    rank: int
+
+
+def qless_pivoted_qr(A, zeta: float, max_rank: int) -> QlessQR:
+    """Algorithm 6 step 1: column-pivoted Gram-Schmidt without Q (the SPQR of
+    Berry, Pulatova and Stewart that Section 5 adopts).  Q_j = A_K R^{-1}
+    stays implicit: step j takes the column p of largest remaining norm^2
+    s_p (s_c = ||a_c||^2 minus the squares of its R entries so far), sets
+    r_jj = sqrt(s_p) and, from the inner products b = A^T a_p,
+    r_jc = (b_c - sum_{i<j} r_ip r_ic) / r_jj, then s_c -= r_jc^2.  It stops
+    at max_rank steps, or before a step with r_jj <= zeta * r_00 (the rank
+    rule of Section 7).  Ties in the norm go to the lowest column."""
+    d = A.shape[1]
+    if sp.issparse(A):
+        A = A.tocsc().astype(np.float64)
+        s = np.asarray(A.multiply(A).sum(axis=0)).ravel()
+
+        def AtA_col(p):
+            return np.asarray((A.T @ A[:, [p]]).todense()).ravel()
+    else:
+        A = np.asarray(A, dtype=np.float64)
+        s = np.einsum("ij,ij->j", A, A)
+
+        def AtA_col(p):
+            return A.T @ A[:, p]
+    rows = np.zeros((0, d))
+    chosen: list[int] = []
+    r00 = 0.0
+    for j in range(min(max_rank, d)):
+        cand = [c for c in range(d) if c not in chosen]
+        p = max(cand, key=lambda c: (s[c], -c))
+        rjj = math.sqrt(max(s[p], 0.0))
+        if j == 0:
+            r00 = rjj
+        if rjj <= 0.0 or rjj <= zeta * r00:
+            break
+        b = AtA_col(p)
+        row = (b - rows[:, p] @ rows) / rjj
+        row[p] = rjj
+        row[chosen] = 0.0
+        for c in cand:
+            if c != p:
+                s[c] -= row[c] ** 2
+        rows = np.vstack([rows, row])
+        chosen.append(p)
+    k = len(chosen)
+    perm = np.asarray(chosen, dtype=np.int64)
+    return QlessQR(perm, rows[:, perm] if k else np.zeros((0, 0)), k)
+
+
+def ls_qless_qr(A, zeta: float, max_rank: int, rows=None) -> tuple[np.ndarray, QlessQR]:
+    """Algorithm 6: theta_i = ||e_i^T A P_k R_k^{-1}||^2 with P_k, R_k from
+    the Q-less pivoted QR above (no sketch)."""
+    qr = qless_pivoted_qr(A, zeta, max_rank)
+    n = A.shape[0]
+    if qr.rank == 0:
+        return np.zeros(n if rows is None else len(rows)), qr
+    X = sla.solve_triangular(qr.R, np.eye(qr.rank), lower=False)
+    AK = A[:, qr.perm]
+    return row_norms_sq(AK, X, rows=rows), qr
+
+
 def qrcp_reference_small(At: np.ndarray) -> np.ndarray:
     """Businger-Golub column pivoting written out (tiny inputs): at each step
     the pivot is the remaining column of largest residual norm, recomputed

@@ -9,6 +9,7 @@ from pathlib import Path
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 import scipy.stats as st
 
 from oracle import conventions as C
@@ -361,6 +362,53 @@ def test_end_to_end_bound_at_theory_sizes():
         assert est.rank == d
         fails += int(np.max(np.abs(est.theta / th - 1)) > eps)
     assert fails / seeds <= E2E["delta"]
+
+
+# ------------------------------------------------------------------ Algorithm 6
+def test_qless_qr_pivots_and_factor():
+    """The Q-less pivoted QR picks the Businger-Golub pivots (the remaining
+    column of largest residual norm, recomputed exactly in the reference),
+    the same as DGEQP3 off near-ties, and R^T R = (A P_k)^T (A P_k) with a
+    positive, non-increasing diagonal."""
+    rng = np.random.default_rng(40)
+    for _ in range(4):
+        A = rng.standard_normal((300, 14)) * rng.uniform(0.1, 10, 14)
+        q = L.qless_pivoted_qr(A, 0.0, 14)
+        assert q.rank == 14
+        np.testing.assert_array_equal(q.perm, L.qrcp_reference_small(A))
+        np.testing.assert_array_equal(q.perm, L.qrcp_sign_normalised(A, 0.0).perm)
+        AK = A[:, q.perm]
+        np.testing.assert_allclose(q.R.T @ q.R, AK.T @ AK, rtol=0, atol=1e-12 * np.abs(AK.T @ AK).max())
+        dg = np.diag(q.R)
+        assert np.all(dg > 0) and np.all(np.diff(dg) <= 1e-12 * dg[0])
+        assert np.allclose(np.tril(q.R, -1), 0)
+
+
+def test_qless_qr_scores():
+    """Algorithm 6's scores equal the exact ones when the rank is found
+    (full rank, and rank 5 of 12 with the cutoff), the leverage of the first
+    pivots when the steps are capped, and sparse input gives the dense
+    result."""
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((400, 12)) * rng.lognormal(0, 1, (400, 1))
+    th, qa = L.ls_qless_qr(A, 1e-10, 12)
+    ex, _ = L.exact_theta_svd(A, 1e-12)
+    assert qa.rank == 12
+    np.testing.assert_allclose(th, ex, rtol=1e-10, atol=1e-14)
+    B = rng.standard_normal((400, 5)) @ rng.standard_normal((5, 12))
+    th, q = L.ls_qless_qr(B, 1e-6, 12)
+    exb, rk = L.exact_theta_svd(B, 1e-10)
+    assert q.rank == rk == 5
+    np.testing.assert_allclose(th, exb, rtol=1e-8, atol=1e-12)
+    th3, q3 = L.ls_qless_qr(A, 1e-10, 3)
+    assert q3.rank == 3
+    np.testing.assert_array_equal(q3.perm, qa.perm[:3])
+    np.testing.assert_allclose(th3, L.exact_theta_svd(A[:, q3.perm], 1e-12)[0], rtol=1e-10, atol=1e-14)
+    S = sp.random(2000, 30, density=0.2, random_state=3, format="csr")
+    ths, qs = L.ls_qless_qr(S, 1e-10, 30)
+    thd, qd = L.ls_qless_qr(S.toarray(), 1e-10, 30)
+    np.testing.assert_array_equal(qs.perm, qd.perm)
+    np.testing.assert_allclose(ths, thd, rtol=1e-10, atol=1e-14)
 
 
 # ------------------------------------------------------------------ SRHT
