@@ -157,6 +157,18 @@ def phase_work(A, cfg, mode: str = "jl", sketch: str = "gauss") -> dict:
 
 
 def _phase_work_mode(A, cfg, mode, n, d, m, r_cs, k, theta_es, r) -> dict:
+    if mode == "qless":
+        # Algorithm 6: no sketch; one pass over A for the norms and one per
+        # step (min(k, r) steps, the last one stopping at the cutoff)
+        steps = min(k, r)
+        tiles = -(-steps // 64)
+        return {
+            "pass1_countsketch": ("hbm", 0),
+            "gaussian_transform": ("hbm", 0),
+            "rank_revealing_qr": ("hbm", (steps + 1) * a_bytes(A)),
+            "form_z": ("mfma_fp64", float(steps) * steps * d),
+            "pass2_rownorm": ("hbm", tiles * (a_bytes(A) + n * theta_es)),
+        }
     if mode != "jl":
         tiles = -(-r // 64)
         if mode == "exact":
@@ -189,6 +201,8 @@ def rooflines(A, cfg, phases_ms: dict, traffic: dict, mode: str = "jl", sketch: 
     out = {}
     for name, (bound, work) in phase_work(A, cfg, mode, sketch).items():
         t = phases_ms[name] * 1e-3
+        if work == 0:
+            continue  # a phase this mode does not have
         if bound == "hbm":
             ach = work / t / 1e9
             out[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -215,6 +229,8 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0, mode: str = "jl", sketch:
     from oracle import leverage as L
 
     def oracle(Ah):
+        if mode == "qless":
+            return L.ls_qless_qr(Ah, cfg["zeta"], cfg["k"])
         if mode == "exact":
             return L.ls_hrn_exact(Ah, seed, cfg["r_cs"], cfg["m"], cfg["zeta"], sketch=sketch)
         o = L.ls_hrn_approx(Ah, seed, cfg["r_cs"], cfg["m"], cfg["k"], cfg["zeta"], sketch=sketch)
@@ -256,7 +272,8 @@ def cpu_baseline(A, cfg, seed, target_s: float = 10.0, mode: str = "jl", sketch:
 
 
 ORACLE_STEPS = {"jl": "sketch, QRCP, Z, row norms", "nojl": "sketch, QRCP, R11^-1, row norms",
-                "exact": "sketch, QRCP, Gram of A_K, eigh, row norms"}
+                "exact": "sketch, QRCP, Gram of A_K, eigh, row norms",
+                "qless": "Q-less pivoted QR of A, R^-1, row norms"}
 
 
 def _stats(ratio: np.ndarray) -> dict:
@@ -294,6 +311,8 @@ def accuracy_report(A, cfg, seed, forms: dict, n_rows: int = 2000, mode: str = "
     t_exact = time.perf_counter() - t0
     if mode == "nojl":
         same = L.theta_prime(Ah, o.perm[:o.rank], o.R11, rows=rows)
+    elif mode == "qless":
+        same, _ = L.ls_qless_qr(Ah, cfg["zeta"], cfg["k"], rows=rows)
     elif mode == "exact":
         same = exact  # the exact scores of A_K are those of A when r = rank(A)
     else:
@@ -474,7 +493,8 @@ def phase_times(plan, bwd, steps: int, stream):
 
 
 ALGORITHMS = {"jl": "LS-HRN-approx (Algorithm 10)", "exact": "LS-HRN-exact (Algorithm 7)",
-              "nojl": "Algorithm 10 without the JL step (Pi_2 = I)"}
+              "nojl": "Algorithm 10 without the JL step (Pi_2 = I)",
+              "qless": "exact scores via a Q-less pivoted QR (Algorithm 6)"}
 SKETCH_NAMES = {"gauss": "CountGauss G (S A) (Algorithm 3)", "srht": "SRHT F (S A) (Section 4)"}
 
 
@@ -487,9 +507,9 @@ def main():
     ap.add_argument("--precision", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--mode", choices=("jl", "exact", "nojl"), default="jl",
+    ap.add_argument("--mode", choices=("jl", "exact", "nojl", "qless"), default="jl",
                     help="jl: Algorithm 10; exact: Algorithm 7 (LS-HRN-exact); nojl: Algorithm 10 without "
-                         "the JL step (Pi_2 = I)")
+                         "the JL step (Pi_2 = I); qless: Algorithm 6 (Q-less pivoted QR of A, k = step cap)")
     ap.add_argument("--exact", action="store_true", help="same as --mode exact")
     ap.add_argument("--sketch", choices=("gauss", "srht"), default="gauss",
                     help="gauss: A~ = G (S A) (Algorithm 3); srht: A~ = F (S A), the SRHT composition of Section 4")
@@ -561,12 +581,12 @@ def main():
         "rooflines": roofs,
         "phases_ms": phases,
         "phases_ms_spread": spread,
-        "passes_hbm_frac": {"pass1": roofs["pass1_countsketch"]["frac"], "pass2": roofs["pass2_rownorm"]["frac"],
-                            "both": (roofs["pass1_countsketch"]["algorithmic_bytes"]
-                                     + roofs["pass2_rownorm"]["algorithmic_bytes"])
-                            / ((phases["pass1_countsketch"] + phases["pass2_rownorm"]) * 1e-3) / 1e9
-                            / HBM_PEAK_GBS},
     }
+    if "pass1_countsketch" in roofs:
+        out["passes_hbm_frac"] = {
+            "pass1": roofs["pass1_countsketch"]["frac"], "pass2": roofs["pass2_rownorm"]["frac"],
+            "both": (roofs["pass1_countsketch"]["algorithmic_bytes"] + roofs["pass2_rownorm"]["algorithmic_bytes"])
+            / ((phases["pass1_countsketch"] + phases["pass2_rownorm"]) * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if bwd is not None:
         out["backward_ms"] = bms
         out["backward_hbm_gbs"] = 3 * a_bytes(A) / (bms * 1e-3) / 1e9  # two reads of A, one write of the gradient

@@ -100,8 +100,9 @@ typedef struct {
  *  m     -- rows of the Gaussian transform G (Algorithm 3's m = ceil(gamma d)).
  *           d <= m required.
  *  k     -- columns of the JL Gaussian Pi_2 (Algorithm 8's r_2).  1..4096
- *           (the backward pass takes k <= 64).  Ignored unless mode is
- *           LEV_MODE_JL.  Pass 2 makes one pass over A per 64 columns.
+ *           (the backward pass takes k <= 64).  Pass 2 makes one pass over
+ *           A per 64 columns.  LEV_MODE_QLESS: the step cap; ignored by the
+ *           other modes.
  *  zeta  -- rank tolerance: the revealed rank is r = #{ j : R_jj > zeta R_00 }
  *           on the column-pivoted factor of the sketch (the cutoff rule of
  *           Section 7).  Supported: 1e-10 <= zeta < 1 (1e-10 is the FP64
@@ -144,8 +145,16 @@ enum { LEV_SKETCH_GAUSS = 0, LEV_SKETCH_SRHT = 1 };
  *   matrix cores, 2 n d^2 flops; CSR: sum_i nnz_i^2 products), the pivoted
  *   Cholesky B_K P2 = R_B^T R_B, and theta~_i = ||e_i^T A_K P2 R_B^{-1}||^2
  *   over ceil(r / 64) column tiles.  The CSR Gram adds its FP64 products
- *   with LDS atomics, so its last bits can differ between runs. */
-enum { LEV_MODE_JL = 0, LEV_MODE_EXACT = 1, LEV_MODE_NOJL = 2 };
+ *   with LDS atomics, so its last bits can differ between runs.
+ * LEV_MODE_QLESS: Algorithm 6: exact scores from a Q-less column-pivoted QR
+ *   of A itself (no sketch: m, r_cs and sketch are not used): step j
+ *   takes the column of largest remaining norm, forms row j of R from the
+ *   column inner products A^T a_p (one pass over A per step) and downdates
+ *   the norms; it stops before R_jj <= zeta R_00 or after k steps (k is the
+ *   step cap here, any k >= 1, at most d steps run).  Then theta_i =
+ *   ||e_i^T A P_k R_k^{-1}||^2.  The cutoff is read off downdated norms, so
+ *   zeta >= 1e-5 (LEV_ERR_NOT_SUPPORTED below).  Meant for small ranks. */
+enum { LEV_MODE_JL = 0, LEV_MODE_EXACT = 1, LEV_MODE_NOJL = 2, LEV_MODE_QLESS = 3 };
 
 /* Workspace bytes needed by lev_sketch (which = LEV_WS_SKETCH),
  * lev_estimate (LEV_WS_ESTIMATE) or lev_estimate_backward (LEV_WS_BACKWARD)

@@ -187,7 +187,7 @@ def _matrix(A) -> LevMatrix:
 
 # lev_params.mode: the JL estimate (Algorithm 10), the exact scores of A_K
 # (Algorithm 7) or the estimate without the JL step (Pi_2 = I).
-MODES = {"jl": 0, "exact": 1, "nojl": 2}
+MODES = {"jl": 0, "exact": 1, "nojl": 2, "qless": 3}
 # lev_params.sketch: the Gaussian stage G (S A) of Algorithm 3, or the SRHT
 # F (S A) (the F S composition of Section 4).
 SKETCHES = {"gauss": 0, "srht": 1}
@@ -330,8 +330,10 @@ def lev_estimate(A, seed: int, r_cs: int, m: int, k: int, zeta: float,
     A is a dense device tensor or a CSR matrix (see lev_sketch).
     mode="exact" (or exact=True) runs Algorithm 7 (LS-HRN-exact) instead:
     the exact leverage scores of the columns K the sketch selects;
-    mode="nojl" the estimate without the JL step, ||e_i^T A_K R11^{-1}||^2.
-    Both ignore k and have no state.  sketch="srht" takes the SRHT F (S A)
+    mode="nojl" the estimate without the JL step, ||e_i^T A_K R11^{-1}||^2
+    (both ignore k); mode="qless" Algorithm 6, the exact scores from a Q-less
+    pivoted QR of A itself with k as its step cap (no sketch).  Only the JL
+    estimate has a state.  sketch="srht" takes the SRHT F (S A)
     in place of the Gaussian stage G (S A)."""
     lib = load_library()
     A = _as_csr(A)  # held until the call returns: it owns converted index arrays

@@ -190,13 +190,19 @@ lev_status check_matrix(const lev_matrix* A) {
 lev_status check_params(const lev_matrix* A, const lev_params* p, bool uses_zeta = true) {
   if (p == nullptr) return fail(LEV_ERR_ARG, "params is null");
   if (p->r_cs < 1 || p->r_cs > kMaxRows) return fail(LEV_ERR_ARG, "r_cs = %lld out of range", (long long)p->r_cs);
-  if (p->m < A->d) return fail(LEV_ERR_SHAPE, "m = %lld < d = %lld", (long long)p->m, (long long)A->d);
+  const bool sketched = p->mode != LEV_MODE_QLESS;  // Algorithm 6 takes no sketch: m and sketch unused
+  if (sketched && p->m < A->d) return fail(LEV_ERR_SHAPE, "m = %lld < d = %lld", (long long)p->m, (long long)A->d);
   if (p->m > (1ll << 24)) return fail(LEV_ERR_SHAPE, "m too large");
-  if (p->mode != LEV_MODE_JL && p->mode != LEV_MODE_EXACT && p->mode != LEV_MODE_NOJL)
-    return fail(LEV_ERR_ARG, "mode %d is not LEV_MODE_JL, LEV_MODE_EXACT or LEV_MODE_NOJL", p->mode);
+  if (p->mode != LEV_MODE_JL && p->mode != LEV_MODE_EXACT && p->mode != LEV_MODE_NOJL && p->mode != LEV_MODE_QLESS)
+    return fail(LEV_ERR_ARG, "mode %d is not one of the LEV_MODE_* values", p->mode);
+  if (p->mode == LEV_MODE_QLESS) {
+    if (p->k < 1) return fail(LEV_ERR_ARG, "k (the step cap of the Q-less QR) must be >= 1");
+    if (uses_zeta && p->zeta < kZetaGram)
+      return fail(LEV_ERR_NOT_SUPPORTED, "the Q-less QR decides its rank from downdated norms: zeta >= %g", kZetaGram);
+  }
   if (p->sketch != LEV_SKETCH_GAUSS && p->sketch != LEV_SKETCH_SRHT)
     return fail(LEV_ERR_ARG, "sketch %d is not LEV_SKETCH_GAUSS or LEV_SKETCH_SRHT", p->sketch);
-  if (p->sketch == LEV_SKETCH_SRHT) {
+  if (sketched && p->sketch == LEV_SKETCH_SRHT) {
     if ((p->r_cs & (p->r_cs - 1)) != 0)
       return fail(LEV_ERR_ARG, "the SRHT needs r_cs a power of two (r_cs = %lld)", (long long)p->r_cs);
     if (p->m > p->r_cs)
@@ -678,12 +684,53 @@ size_t lev_rank_workspace_size(int64_t m, int64_t d) {
   return c.used;
 }
 
+}  // extern "C"
+
+namespace {  // helpers of the entry points below
+
+// Algorithm 6: the Q-less pivoted QR of A (qless.hip), then Z = R_k^{-1}
+// and pass 2 over the column tiles below the rank.
+struct QlessBufs {
+  double* qws;
+  int32_t* perm;
+  double* R;
+  int64_t* rank;
+  int32_t* err;
+  double* I;
+  double* Z64;
+  void* Zpack;
+};
+
+int64_t qless_steps(const lev_matrix* A, const lev_params* p) { return std::min<int64_t>(p->k, A->d); }
+
+QlessBufs carve_qless(Carver& c, const lev_matrix* A, const lev_params* p) {
+  const int64_t d = A->d;
+  QlessBufs b;
+  b.qws = c.take<double>(lev::qless_ws_doubles(A->n, d, qless_steps(A, p), A->format == LEV_CSR));
+  b.perm = c.take<int32_t>((size_t)d);
+  b.R = c.take<double>((size_t)(d * d));
+  b.rank = c.take<int64_t>(1);
+  b.err = c.take<int32_t>(1);
+  b.I = c.take<double>((size_t)(d * d));
+  b.Z64 = c.take<double>((size_t)(d * d));
+  b.Zpack = c.take<char>(lev::pack_z_bytes(az_variant(A->format, A->dtype, p->az_precision), d, d));
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
 size_t lev_workspace_size(const lev_matrix* A, const lev_params* p, int which) {
   if (check_matrix(A) != LEV_OK || check_params(A, p, which != LEV_WS_SKETCH) != LEV_OK) return 0;
   const int64_t d = A->d, m = p->m, k = p->k, r_cs = p->r_cs;
   Carver c(nullptr);
   if (which == LEV_WS_SKETCH) {
     carve_sketch(c, A, p);
+    return c.used;
+  }
+  if (which == LEV_WS_ESTIMATE && p->mode == LEV_MODE_QLESS) {
+    carve_qless(c, A, p);
     return c.used;
   }
   if (which == LEV_WS_ESTIMATE && p->mode == LEV_MODE_EXACT) {
@@ -746,6 +793,10 @@ lev_status lev_rank_estimate(const double* At, int64_t m, int64_t d, double zeta
   return enqueue_rank(At, m, d, zeta, b, perm_out, R_out, rank_out, stream, &rf);
 }
 
+}  // extern "C"
+
+namespace {  // helpers of the entry points below
+
 // Algorithm 7 (LS-HRN-exact): the columns K and the rank from Algorithm 4
 // on the sketch (as for Algorithm 10), then B = A^T A in one more pass over
 // A (Algorithm 5's Gram route: FP64 matrix cores for dense A, sum_i nnz_i^2
@@ -807,6 +858,37 @@ lev_status estimate_exact(const lev_matrix* A, const lev_params* p, int variant,
   return LEV_OK;
 }
 
+lev_status estimate_qless(const lev_matrix* A, const lev_params* p, int variant, void* theta_out, void* ws,
+                          hipStream_t s) {
+  const int64_t n = A->n, d = A->d;
+  Carver c(ws);
+  QlessBufs b = carve_qless(c, A, p);
+  const lev::QlessInput in{A->dtype, A->values, A->format == LEV_CSR ? A->row_ptr : nullptr, A->col_idx, n, d,
+                           A->ld, A->nnz};
+  LEV_HIP(mark_phase(0, s));
+  LEV_HIP(lev::launch_fill_zero(b.err, sizeof(int32_t), s));
+  LEV_HIP(mark_phase(1, s));
+  LEV_HIP(mark_phase(2, s));
+  LEV_HIP(mark_phase(3, s));
+  LEV_HIP(lev::launch_qless_qr(in, qless_steps(A, p), p->zeta, b.qws, b.perm, b.R, b.rank, s));
+  LEV_HIP(mark_phase(4, s));
+  LEV_HIP(lev::launch_identity(d, b.I, s));
+  LEV_HIP(lev::launch_form_z(variant, d, d, b.R, b.rank, b.perm, b.I, b.Z64, b.Zpack, b.err, s));
+  LEV_HIP(mark_phase(5, s));
+  if (n > 0 && A->format == LEV_CSR) {
+    LEV_HIP(lev::launch_rownorm_csr(A->dtype, A->values, A->row_ptr, A->col_idx, n, d, A->nnz, d, b.Zpack, b.rank,
+                                    theta_out, s));
+  } else if (n > 0) {
+    LEV_HIP(lev::launch_rownorm_dense(variant, A->dtype, A->values, n, d, A->ld, d, b.Zpack, b.rank, theta_out, s));
+  }
+  LEV_HIP(mark_phase(6, s));
+  return LEV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_out, void* state_out, void* ws,
                         size_t ws_bytes, hipStream_t stream) {
   LEV_TRY(check_matrix(A));
@@ -822,6 +904,7 @@ lev_status lev_estimate(const lev_matrix* A, const lev_params* p, void* theta_ou
   const int64_t n = A->n, d = A->d, m = p->m, r_cs = p->r_cs;
   const int variant = az_variant(A->format, A->dtype, p->az_precision);
   if (p->mode == LEV_MODE_EXACT) return estimate_exact(A, p, variant, theta_out, ws, stream);
+  if (p->mode == LEV_MODE_QLESS) return estimate_qless(A, p, variant, theta_out, ws, stream);
   // JL: Z = R11^{-1} G_k (k columns, all live).  No JL step: Z = R11^{-1}
   // [I_r 0] (d columns, the first r live).
   const bool jl = p->mode == LEV_MODE_JL;

@@ -185,6 +185,23 @@ hipError_t launch_rownorm_csr(int dtype, const void* vals, const int64_t* row_pt
                               int64_t n, int64_t d, int64_t nnz, int64_t k, const void* Zpack,
                               const int64_t* live, void* theta, hipStream_t s);
 
+// Algorithm 6 (qless.hip): Q-less column-pivoted QR of A itself, kmax
+// steps at most, stopping before r_jj <= zeta r_00.  Writes perm (int32[d]:
+// the pivots, then the other columns ascending), R_out (d x d, pivoted
+// order, zero past the rank) and rank (device).  ws: qless_ws_doubles
+// doubles.  row_ptr == nullptr: dense row-major A (ld), else CSR.
+struct QlessInput {
+  int dtype;  // 0 f64, 1 f32, 2 bf16
+  const void* values;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  int64_t n, d, ld, nnz;
+};
+int qless_groups(int64_t n, bool csr);
+size_t qless_ws_doubles(int64_t n, int64_t d, int64_t kmax, bool csr);
+hipError_t launch_qless_qr(const QlessInput& in, int64_t kmax, double zeta, double* ws, int32_t* perm_out,
+                           double* R_out, int64_t* rank_out, hipStream_t st);
+
 // B (d x d, FP64) = A^T A for dense A (dtype 0 f64, 1 f32, 2 bf16) on the
 // FP64 matrix cores: the products of FP32 and BF16 elements are exact in
 // FP64.  partial: dgemm_partial_elems(d, d, splits) doubles.

@@ -164,6 +164,9 @@ CONFIGS = {
     "dense_f32_1Mx256_rank192_bwd": dict(n=1 << 20, d=256, rank=192, dtype="f32", r_cs=4096, m=512, k=48, zeta=1e-5),
     # LS-HRN-exact (Algorithm 7) at scale: an FP32 Gaussian; k is unused there
     "dense_f32_1Mx64_exact": dict(n=1 << 20, d=64, dtype="f32", r_cs=4096, m=128, k=32, zeta=1e-5),
+    # Algorithm 6's regime (rank well below sqrt(d)): the recipe of the
+    # 2^20 x 256 workload at rank 16; k is the Q-less QR's step cap there
+    "dense_f32_1Mx256_rank16": dict(n=1 << 20, d=256, rank=16, dtype="f32", r_cs=4096, m=512, k=32, zeta=1e-5),
 }
 
 # A case at the sizes the theorems ask for (the end-to-end (1 +- eps) check):
