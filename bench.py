@@ -3,7 +3,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision auto|native|fp32|bf16|bf16x2|bf16x3]
                     [--no-accuracy] [--no-cpu-baseline] [--mode jl|exact|nojl]
-                    [--sketch gauss|srht]
+                    [--sketch gauss|srht] [--precondition]
 
 One step = one lev_estimate call over the whole workload resident in HBM:
 the Gaussian draws and pass 1 (CountSketch S A), the Gaussian transform, the
@@ -12,6 +12,8 @@ backward workload (name ending in _bwd) also the adjoint of w^T theta~.
 --mode exact times Algorithm 7 instead (the exact scores of A_K from B =
 A_K^T A_K), --mode nojl the estimate without the JL step (Pi_2 = I);
 --sketch srht replaces the Gaussian stage G (S A) by the SRHT F (S A).
+--precondition runs Section 6's experiment instead (kappa(A N) of
+Algorithm 11's preconditioner over the linspace spectra, and LSQR timing).
 Prints one JSON line with rows/s, the per-phase times and rooflines (the
 headline `roofline` is the slowest phase's, measured live with the HIP
 events liblev records on its own stream), the accuracy of theta~ on sampled
@@ -498,6 +500,61 @@ ALGORITHMS = {"jl": "LS-HRN-approx (Algorithm 10)", "exact": "LS-HRN-exact (Algo
 SKETCH_NAMES = {"gauss": "CountGauss G (S A) (Algorithm 3)", "srht": "SRHT F (S A) (Section 4)"}
 
 
+def precondition_report(steps: int) -> dict:
+    """Section 6's experiment on the GPU: kappa(A N) for the 50,000 x 60
+    matrices with singular values linspace(1, r, 60), r = 1e-2 ... 1e-10,
+    N from Algorithm 11 (SVD) and from the pivoted QR, 20 sketches each
+    (m = 2d, r_cs = 5 (d^2 + d)); then the time of the preconditioner and of
+    LSQR on A N (40 steps) there and on a 2^20 x 256 FP32 Gaussian."""
+    dev = torch.device("cuda:0")
+    n, d = 50000, 60
+    r_cs, m = 5 * (d * d + d), 2 * d
+    out = {"shape": [n, d], "r_cs": r_cs, "m": m, "zeta": 1e-10, "runs": 20, "kappa": {}}
+    for e in range(2, 11):
+        r = 10.0 ** -e
+        A = W.fixed_spectrum(n, np.linspace(1.0, r, d), 100 + e)
+        Ah = A.numpy()
+        Ag = A.to(dev)
+        row = {"kappa_A": float(np.linalg.cond(Ah))}
+        for method in ("svd", "qr"):
+            ks = []
+            for seed in range(20):
+                N, k = api.lev_precondition(Ag, seed, r_cs, m, 1e-10, method)
+                kk = int(k.item())
+                ks.append(float(np.linalg.cond(Ah @ N.cpu().numpy()[:, :kk])))
+            row[method] = {"min": min(ks), "mean": float(np.mean(ks)), "max": max(ks)}
+        out["kappa"][f"{r:.0e}"] = row
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            fn()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / reps
+
+    timing = {}
+    for name, A in (("50000x60_f64_r1e-6", W.fixed_spectrum(n, np.linspace(1.0, 1e-6, d), 7).to(dev)),
+                    ("1Mx256_f32_gaussian", W.dense_gaussian(1 << 20, 256, 8, dtype=torch.float32, device=dev))):
+        nn, dd = A.shape
+        rc, mm = (r_cs, m) if dd == d else (4096, 512)
+        b = torch.randn(nn, dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(9))
+        N, _ = api.lev_precondition(A, 1, rc, mm, 1e-10, "qr")
+        t_pre = timed(lambda: api.lev_precondition(A, 1, rc, mm, 1e-10, "qr"), max(2, steps // 4))
+        t_ls = timed(lambda: api.lev_lsqr(A, N, b, 40), max(2, steps // 4))
+        x, hist = api.lev_lsqr(A, N, b, 40)
+        per_step = t_ls / 40
+        timing[name] = {"precondition_ms": t_pre, "lsqr_40_steps_ms": t_ls, "lsqr_ms_per_step": per_step,
+                        "lsqr_hbm_gbs": 2 * A.numel() * A.element_size() / (per_step * 1e-3) / 1e9,
+                        "residual_estimate_first_last": [float(hist[0]), float(hist[-1])]}
+    out["timing"] = timing
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,6 +570,8 @@ def main():
     ap.add_argument("--exact", action="store_true", help="same as --mode exact")
     ap.add_argument("--sketch", choices=("gauss", "srht"), default="gauss",
                     help="gauss: A~ = G (S A) (Algorithm 3); srht: A~ = F (S A), the SRHT composition of Section 4")
+    ap.add_argument("--precondition", action="store_true",
+                    help="run Section 6's preconditioning experiment and LSQR timing instead of the estimator")
     ap.add_argument("--traffic-run", action="store_true", help="the process a counter run profiles")
     ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
@@ -529,6 +588,11 @@ def main():
         raise SystemExit("no GPU visible")
     if args.traffic_run:
         traffic_run(args.workload, args.precision)
+        return
+    if args.precondition:
+        api.load_library()
+        print(json.dumps({"report": "preconditioning (Section 6, Algorithm 11) and LSQR on A N",
+                          **precondition_report(args.steps)}), flush=True)
         return
     dev = torch.device("cuda:0")
     api.load_library()

@@ -267,6 +267,39 @@ lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const
                                  const void* w, void* gradA_out, void* ws, size_t ws_bytes,
                                  hipStream_t stream);
 
+/* ---- least squares (Section 6) ----------------------------------------------- */
+
+/* Algorithm 11 (CountGaussPrecondition): a right preconditioner N for
+ * min ||A x - b|| from the same sketch and rank-revealing step as
+ * lev_estimate (p's seed, r_cs, m, zeta and sketch; k, mode and
+ * az_precision unused).  With A~ P = Q R the factor of the sketch:
+ *  method LEV_PRECOND_QR:  N = P R11^{-1}, k = the rank r;
+ *  method LEV_PRECOND_SVD: N = V_k Sigma_k^{-1} from the SVD of A~ (taken
+ *    as the SVD of R by one-sided Jacobi, so d <= 128, else
+ *    LEV_ERR_NOT_SUPPORTED), k = #{ sigma_j > zeta sigma_1 }.
+ * N_out: d x d FP64 row-major (device), columns >= k zero; k_out: int64
+ * (device), -1 when a bounded wait of the rank-revealing step ran out.
+ * The section's theorem bounds kappa(A N) by ((1 + alpha + sqrt(k/m)) /
+ * (1 - alpha - sqrt(k/m))) ((1 + eps) / (1 - eps)) with high probability,
+ * whatever kappa(A).  Workspace: lev_precondition_workspace_size. */
+enum { LEV_PRECOND_QR = 0, LEV_PRECOND_SVD = 1 };
+size_t lev_precondition_workspace_size(const lev_matrix* A, const lev_params* p);
+lev_status lev_precondition(const lev_matrix* A, const lev_params* p, int method, double* N_out, int64_t* k_out,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* LSQR (Paige and Saunders) on the preconditioned operator A N from y = 0,
+ * iters steps, x_out = N y (d, FP64, device): with N from lev_precondition,
+ * x approaches A^+ b (SVD) or a least-squares solution (QR).  A dense
+ * (any dtype; the arithmetic is FP64), N d x d FP64 (device), b n FP64
+ * (device), resid_out (device, may be NULL): the residual-norm estimate
+ * ||A x_t - b|| after each step t < iters.  The steps stop early (the later
+ * entries repeat the last estimate) if the bidiagonalisation breaks down
+ * exactly (alpha or beta = 0).  Two passes over A per step.  CSR gives
+ * LEV_ERR_NOT_SUPPORTED.  Workspace: lev_lsqr_workspace_size. */
+size_t lev_lsqr_workspace_size(const lev_matrix* A);
+lev_status lev_lsqr(const lev_matrix* A, const double* N, const double* b, int64_t iters, double* x_out,
+                    double* resid_out, void* ws, size_t ws_bytes, hipStream_t stream);
+
 /* ---- inspection helpers (used by the tests) -------------------------------- */
 
 /* Host-only: the CountSketch hash and sign coefficients a seed expands to

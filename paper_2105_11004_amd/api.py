@@ -31,7 +31,8 @@ WS_SKETCH, WS_ESTIMATE, WS_BACKWARD = 0, 2, 3
 EXPORTED = ["lev_workspace_size", "lev_rank_workspace_size", "lev_state_size", "lev_sketch",
             "lev_rank_estimate", "lev_estimate", "lev_estimate_backward", "lev_debug_hash",
             "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params", "lev_set_phase_events",
-            "lev_status_string", "lev_last_error", "lev_noalloc_max_bytes", "lev_estimate_noalloc"]
+            "lev_status_string", "lev_last_error", "lev_noalloc_max_bytes", "lev_estimate_noalloc",
+            "lev_precondition_workspace_size", "lev_precondition", "lev_lsqr_workspace_size", "lev_lsqr"]
 LEV_PHASES = 7
 # phase 0 holds no kernels (the Gaussian draws run inside pass 1): its time is
 # the cost of two back-to-back events
@@ -89,6 +90,12 @@ def load_library(path: Path | None = None):
     lib.lev_noalloc_max_bytes.argtypes = []
     lib.lev_noalloc_max_bytes.restype = c_size_t
     lib.lev_estimate_noalloc.argtypes = [POINTER(LevMatrix), POINTER(LevParams), vp, vp]
+    lib.lev_precondition_workspace_size.argtypes = [POINTER(LevMatrix), POINTER(LevParams)]
+    lib.lev_precondition_workspace_size.restype = c_size_t
+    lib.lev_precondition.argtypes = [POINTER(LevMatrix), POINTER(LevParams), c_int, vp, vp, vp, c_size_t, vp]
+    lib.lev_lsqr_workspace_size.argtypes = [POINTER(LevMatrix)]
+    lib.lev_lsqr_workspace_size.restype = c_size_t
+    lib.lev_lsqr.argtypes = [POINTER(LevMatrix), vp, vp, c_int64, vp, vp, vp, c_size_t, vp]
     lib.lev_set_phase_events.argtypes = [vp, c_int]
     lib.lev_set_phase_events.restype = c_int
     lib.lev_status_string.argtypes = [c_int]
@@ -366,6 +373,51 @@ def lev_estimate_noalloc(A, seed: int, r_cs: int, m: int, k: int, zeta: float, p
         theta = torch.empty(n, dtype=torch.float64 if dt == torch.float64 else torch.float32, device=dev)
     _check(lib.lev_estimate_noalloc(ctypes.byref(mat), ctypes.byref(par), _ptr(theta), _stream(dev)))
     return theta
+
+
+PRECOND = {"qr": 0, "svd": 1}
+
+
+def lev_precondition(A, seed: int, r_cs: int, m: int, zeta: float, method: str = "svd", sketch: str = "gauss"):
+    """Algorithm 11: (N, k) with N the d x d FP64 right preconditioner
+    (columns past k zero) from the sketch of A; method "svd" (N = V_k
+    Sigma_k^{-1}, d <= 128) or "qr" (N = P R11^{-1}).  k stays a device
+    tensor (-1 if a bounded wait ran out)."""
+    if method not in PRECOND:
+        raise ValueError(f"method must be one of {list(PRECOND)}")
+    lib = load_library()
+    A = _as_csr(A)
+    dev, (_, d) = _device(A), _shape(A)
+    mat, par = _matrix(A), _params(seed, r_cs, m, 1, zeta, "native", sketch=sketch)
+    nbytes = lib.lev_precondition_workspace_size(ctypes.byref(mat), ctypes.byref(par))
+    if nbytes == 0:
+        _check(lib.lev_precondition(ctypes.byref(mat), ctypes.byref(par), PRECOND[method], None, None, None, 0,
+                                    None))
+    _, ws = _workspace(nbytes, dev)
+    N = torch.empty(d, d, dtype=torch.float64, device=dev)
+    k = torch.empty(1, dtype=torch.int64, device=dev)
+    _check(lib.lev_precondition(ctypes.byref(mat), ctypes.byref(par), PRECOND[method], _ptr(N), _ptr(k), ws,
+                                nbytes, _stream(dev)))
+    return N, k
+
+
+def lev_lsqr(A: torch.Tensor, N: torch.Tensor, b: torch.Tensor, iters: int):
+    """LSQR on A N from y = 0 for `iters` steps; returns x = N y (FP64, d)
+    and the residual-norm estimate after each step (FP64, iters)."""
+    lib = load_library()
+    dev, (n, d) = _device(A), _shape(A)
+    mat = _matrix(A)
+    nbytes = lib.lev_lsqr_workspace_size(ctypes.byref(mat))
+    if nbytes == 0:
+        _check(lib.lev_lsqr(ctypes.byref(mat), None, None, 0, None, None, None, 0, None))
+    _, ws = _workspace(nbytes, dev)
+    N = N.to(torch.float64).contiguous()
+    b = b.to(torch.float64).contiguous()
+    x = torch.empty(d, dtype=torch.float64, device=dev)
+    hist = torch.empty(max(int(iters), 1), dtype=torch.float64, device=dev)
+    _check(lib.lev_lsqr(ctypes.byref(mat), _ptr(N), _ptr(b), int(iters), _ptr(x), _ptr(hist), ws, nbytes,
+                        _stream(dev)))
+    return x, hist[:int(iters)]
 
 
 class EstimatePlan:

@@ -1003,6 +1003,91 @@ lev_status lev_estimate_backward(const lev_matrix* A, const lev_params* p, const
   return LEV_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Algorithm 11's buffers: the sketch, the rank-revealing step and its
+// outputs, and the preconditioner's scratch.
+struct PrecondBufs {
+  SketchBufs sb;
+  RankBufs rb;
+  RefineBufs rf;
+  double* At;
+  double* R;
+  int32_t* perm;
+  int64_t* rank;
+  int32_t* err;
+  double* work;
+};
+
+PrecondBufs carve_precond(Carver& c, const lev_matrix* A, const lev_params* p) {
+  const int64_t d = A->d, m = p->m;
+  PrecondBufs b;
+  b.sb = carve_sketch(c, A, p);
+  b.rb = carve_rank(c, m, d);
+  if (p->zeta < kZetaGram) b.rf = carve_refine(c, m, d);
+  b.At = c.take<double>((size_t)(m * d));
+  b.R = c.take<double>((size_t)(d * d));
+  b.perm = c.take<int32_t>((size_t)d);
+  b.rank = c.take<int64_t>(1);
+  b.err = c.take<int32_t>(1);
+  b.work = c.take<double>((size_t)(2 * d * d + d));
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lev_precondition_workspace_size(const lev_matrix* A, const lev_params* p) {
+  if (check_matrix(A) != LEV_OK || check_params(A, p) != LEV_OK) return 0;
+  Carver c(nullptr);
+  carve_precond(c, A, p);
+  return c.used;
+}
+
+lev_status lev_precondition(const lev_matrix* A, const lev_params* p, int method, double* N_out, int64_t* k_out,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+  LEV_TRY(check_matrix(A));
+  LEV_TRY(check_params(A, p));
+  if (method != LEV_PRECOND_QR && method != LEV_PRECOND_SVD)
+    return fail(LEV_ERR_ARG, "method must be LEV_PRECOND_QR or LEV_PRECOND_SVD");
+  if (method == LEV_PRECOND_SVD && A->d > 128)
+    return fail(LEV_ERR_NOT_SUPPORTED, "the SVD preconditioner takes d <= 128 (d = %lld)", (long long)A->d);
+  if (N_out == nullptr || k_out == nullptr) return fail(LEV_ERR_ARG, "N_out or k_out is null");
+  LEV_TRY(check_ws(ws, ws_bytes, lev_precondition_workspace_size(A, p)));
+  const int64_t d = A->d, m = p->m;
+  Carver c(ws);
+  PrecondBufs b = carve_precond(c, A, p);
+  b.rb.pc.err = b.err;
+  const lev::SeedDraws dr = lev::derive_draws(p->seed, A->n, p->r_cs);
+  const bool refine = p->zeta < kZetaGram;
+  LEV_HIP(lev::launch_fill_zero(b.err, sizeof(int32_t), stream));
+  LEV_TRY(enqueue_sketch(A, p, dr, b.sb, b.sb.SA, b.At, nullptr, stream));
+  LEV_TRY(enqueue_rank(b.At, m, d, p->zeta, b.rb, b.perm, b.R, b.rank, stream, refine ? &b.rf : nullptr));
+  LEV_HIP(lev::launch_precondition(method, d, b.R, b.rank, b.perm, p->zeta, b.work, N_out, k_out, b.err, stream));
+  LEV_HIP(lev::launch_flag_error(b.err, k_out, stream));
+  return LEV_OK;
+}
+
+size_t lev_lsqr_workspace_size(const lev_matrix* A) {
+  if (check_matrix(A) != LEV_OK || A->format != LEV_DENSE_ROWMAJOR) return 0;
+  return align_up(sizeof(double) * lev::lsqr_ws_doubles(A->n, A->d));
+}
+
+lev_status lev_lsqr(const lev_matrix* A, const double* N, const double* b, int64_t iters, double* x_out,
+                    double* resid_out, void* ws, size_t ws_bytes, hipStream_t stream) {
+  LEV_TRY(check_matrix(A));
+  if (A->format != LEV_DENSE_ROWMAJOR) return fail(LEV_ERR_NOT_SUPPORTED, "LSQR takes dense A only");
+  if (iters < 0) return fail(LEV_ERR_ARG, "iters = %lld < 0", (long long)iters);
+  if (N == nullptr || x_out == nullptr || (A->n > 0 && b == nullptr)) return fail(LEV_ERR_ARG, "null pointer argument");
+  LEV_TRY(check_ws(ws, ws_bytes, lev_lsqr_workspace_size(A)));
+  LEV_HIP(lev::launch_lsqr(A->dtype, A->values, A->n, A->d, A->ld, N, b, iters, x_out, resid_out,
+                           static_cast<double*>(ws), stream));
+  return LEV_OK;
+}
+
 size_t lev_noalloc_max_bytes(void) { return kScratchBytes; }
 
 lev_status lev_estimate_noalloc(const lev_matrix* A, const lev_params* p, void* theta_out, hipStream_t stream) {

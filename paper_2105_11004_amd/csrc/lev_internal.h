@@ -202,6 +202,20 @@ size_t qless_ws_doubles(int64_t n, int64_t d, int64_t kmax, bool csr);
 hipError_t launch_qless_qr(const QlessInput& in, int64_t kmax, double zeta, double* ws, int32_t* perm_out,
                            double* R_out, int64_t* rank_out, hipStream_t st);
 
+// Section 6 (precond.hip).  method 0: N = P R11^{-1}; 1: N = P V_R
+// Sigma^{-1} from a one-sided Jacobi SVD of R (d <= 128), keeping sigma_j >
+// zeta sigma_1.  N is d x d row-major (columns past k zero); work: 2 d^2 + d
+// doubles; k_out on the device.
+hipError_t launch_precondition(int method, int64_t d, const double* R, const int64_t* rank, const int32_t* perm,
+                               double zeta, double* work, double* N, int64_t* k_out, int32_t* err, hipStream_t s);
+hipError_t launch_flag_error(const int32_t* err, int64_t* k_out, hipStream_t s);
+// LSQR on A N (dense A of dtype 0/1/2) from y = 0, iters steps, x = N y;
+// hist (may be null): the residual-norm estimate after each step.
+int lsqr_groups(int64_t n);
+size_t lsqr_ws_doubles(int64_t n, int64_t d);
+hipError_t launch_lsqr(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, const double* N, const double* b,
+                       int64_t iters, double* x, double* hist, double* ws, hipStream_t s);
+
 // B (d x d, FP64) = A^T A for dense A (dtype 0 f64, 1 f32, 2 bf16) on the
 // FP64 matrix cores: the products of FP32 and BF16 elements are exact in
 // FP64.  partial: dgemm_partial_elems(d, d, splits) doubles.

@@ -1,0 +1,415 @@
+// Section 6: the right preconditioner of Algorithm 11 built from the
+// sketch's factor, and LSQR on the preconditioned operator A N.
+//
+// Preconditioner.  The sketch A~ = G S A is factored as A~ P = Q R by the
+// rank-revealing step; then
+//   QR:  N = P R11^{-1}                       (columns past the rank zero);
+//   SVD: N = P V_R Sigma^{-1}, R = U_R Sigma V_R^T the SVD of R, which is the
+//        V Sigma^{-1} of the SVD of A~ itself (A~ = (Q U_R) Sigma (P V_R)^T),
+//        keeping the k singular values above zeta sigma_1.
+// The SVD of R (d <= 128) is a one-sided Jacobi (Hestenes) iteration in one
+// workgroup: the columns of W = R sit in LDS, disjoint column pairs of a
+// round-robin round are orthogonalised in parallel (one wave per pair,
+// Rutishauser's rotation), V accumulates the rotations, and sweeps repeat
+// until no pair is rotated.  Singular values are the final column norms;
+// relative accuracy does not depend on kappa(R).
+//
+// LSQR (Paige and Saunders 1982) on M = A N from y = 0, with x = N y at the
+// end.  Per iteration two passes over A (dense, FP64 arithmetic on any
+// storage type) and one single-workgroup kernel:
+//   gemv:  t = A (N v) - alpha u, and per-workgroup sums of t_i^2;
+//   atv:   beta = sqrt(sum), u = t / beta, per-workgroup partials of A^T u;
+//   step:  q = N^T (A^T u) - beta v, alpha = ||q||, v = q / alpha, the
+//          rotation (rho, c, s, theta, phi), y += (phi / rho) w,
+//          w = v - (theta / rho) w, z = N v for the next gemv.
+// Scalars stay in device memory; all sums run in a fixed order.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "lev_internal.h"
+
+namespace lev {
+namespace {
+
+constexpr int kSvdThreads = 1024;
+constexpr int kSvdWaves = kSvdThreads / 64;
+constexpr int kMaxSweeps = 40;
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// Round-robin pairing of dd (even) columns: round t, pair q -> (a, b).
+__device__ __forceinline__ void rr_pair(int dd, int t, int q, int& a, int& b) {
+  auto pos = [&](int i) -> int { return i == 0 ? 0 : 1 + (i - 1 + t) % (dd - 1); };
+  a = pos(q);
+  b = pos(dd - 1 - q);
+}
+
+// W (LDS, column-major, d x d) = R; V (global, column-major) = I.
+__global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(int64_t d, const double* __restrict__ R,
+                                                                 const int64_t* __restrict__ rank,
+                                                                 const int32_t* __restrict__ perm, double zeta,
+                                                                 double* __restrict__ V, double* __restrict__ N,
+                                                                 int64_t* __restrict__ k_out) {
+  extern __shared__ double W[];
+  __shared__ int rotated;
+  __shared__ double sig[128];
+  __shared__ int order[128];
+  const int di = (int)d;
+  const int dd = di + (di & 1);  // a zero column pads an odd d
+  const int64_t r = *rank;
+  for (int e = threadIdx.x; e < dd * di; e += kSvdThreads) {
+    const int c = e / di, row = e % di;
+    W[e] = (c < di && row < r) ? R[(int64_t)row * d + c] : 0.0;  // rows past the rank are zero
+  }
+  for (int e = threadIdx.x; e < dd * di; e += kSvdThreads) V[e] = (e / di == e % di) ? 1.0 : 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double tol = 4.0 * (double)di * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int t = 0; t < dd - 1; ++t) {
+      for (int q = wave; q < dd / 2; q += kSvdWaves) {
+        int a, b;
+        rr_pair(dd, t, q, a, b);
+        double* wa = W + (int64_t)a * di;
+        double* wb = W + (int64_t)b * di;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = lane; i < di; i += 64) {
+          const double x = wa[i], y = wb[i];
+          al = fma(x, x, al);
+          be = fma(y, y, be);
+          ga = fma(x, y, ga);
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
+        const double zt = (be - al) / (2.0 * ga);
+        const double tn = (zt >= 0.0 ? 1.0 : -1.0) / (fabs(zt) + sqrt(1.0 + zt * zt));
+        const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
+        for (int i = lane; i < di; i += 64) {
+          const double x = wa[i], y = wb[i];
+          wa[i] = c * x - s * y;
+          wb[i] = s * x + c * y;
+        }
+        double* va = V + (int64_t)a * di;
+        double* vb = V + (int64_t)b * di;
+        for (int i = lane; i < di; i += 64) {
+          const double x = va[i], y = vb[i];
+          va[i] = c * x - s * y;
+          vb[i] = s * x + c * y;
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  // singular values, their descending order (ties: lower column first), k
+  for (int c = threadIdx.x; c < di; c += kSvdThreads) {
+    double nn = 0.0;
+    for (int i = 0; i < di; ++i) nn = fma(W[(int64_t)c * di + i], W[(int64_t)c * di + i], nn);
+    sig[c] = sqrt(nn);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < di; c += kSvdThreads) {
+    int rk = 0;
+    for (int c2 = 0; c2 < di; ++c2) rk += (sig[c2] > sig[c] || (sig[c2] == sig[c] && c2 < c)) ? 1 : 0;
+    order[rk] = c;
+  }
+  __syncthreads();
+  const double s1 = sig[order[0]];
+  int k = 0;
+  for (int q = 0; q < di; ++q) k += (s1 > 0.0 && sig[order[q]] > zeta * s1) ? 1 : 0;
+  // N[perm[i]][q] = V_R[i][order[q]] / sigma (rows of V_R by pivot position)
+  for (int e = threadIdx.x; e < di * di; e += kSvdThreads) {
+    const int i = e / di, q = e % di;
+    double v = 0.0;
+    if (q < k) {
+      const int c = order[q];
+      v = V[(int64_t)c * di + i] / sig[c];
+    }
+    N[(int64_t)perm[i] * d + q] = v;
+  }
+  if (threadIdx.x == 0) *k_out = k;
+}
+
+// N[perm[j]][q] = Z[j][q] (Z = R11^{-1} with zero rows past the rank).
+__global__ void scatter_rows_kernel(int64_t d, const int32_t* __restrict__ perm, const double* __restrict__ Z,
+                                    double* __restrict__ N, const int64_t* __restrict__ rank,
+                                    int64_t* __restrict__ k_out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) *k_out = *rank;
+  if (e >= d * d) return;
+  const int64_t j = e / d, q = e % d;
+  N[(int64_t)perm[j] * d + q] = Z[e];
+}
+
+// ---- LSQR -------------------------------------------------------------------------
+// st: [0] alpha, [1] beta, [2] rhobar, [3] phibar, [4] stop (0 / 1), [5] beta_1
+constexpr int kGemvThreads = 256;
+constexpr int kStepThreads = 1024;
+
+__device__ __forceinline__ double f64(double x) { return x; }
+__device__ __forceinline__ double f64(float x) { return (double)x; }
+__device__ __forceinline__ double f64(__hip_bfloat16 x) { return (double)__bfloat162float(x); }
+
+// t_i = A[i,:] z - alpha u_i (or b_i when init), partial[g] = sum of t_i^2
+// over the workgroup's rows.  A group of gs lanes (a power of two) takes a
+// row, each lane a strided set of its elements.
+template <typename T>
+__global__ __launch_bounds__(kGemvThreads) void lsqr_gemv_kernel(const T* __restrict__ A, int64_t n, int64_t d,
+                                                                 int64_t ld, const double* __restrict__ z,
+                                                                 const double* __restrict__ u,
+                                                                 const double* __restrict__ b, int init,
+                                                                 const double* __restrict__ st,
+                                                                 double* __restrict__ t, double* __restrict__ partial,
+                                                                 int gs) {
+  __shared__ double red[kGemvThreads / 64];
+  if (!init && st[4] != 0.0) return;
+  const double alpha = init ? 0.0 : st[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / gs, gl = lane % gs, per_wave = 64 / gs;
+  const int64_t rows_per_group = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_group, r1 = std::min<int64_t>(n, r0 + rows_per_group);
+  double sq = 0.0;
+  for (int64_t i = r0 + wave * per_wave + grp; i < r1; i += (int64_t)(kGemvThreads / 64) * per_wave) {
+    double acc = 0.0;
+    if (!init) {
+      const T* row = A + i * ld;
+      for (int64_t c = gl; c < d; c += gs) acc = fma(f64(row[c]), z[c], acc);
+    }
+    for (int o = gs / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, gs);
+    const double ti = init ? b[i] : acc - alpha * u[i];
+    if (gl == 0) {
+      t[i] = ti;
+      sq = fma(ti, ti, sq);
+    }
+  }
+  sq = wave_sum(sq);
+  if (lane == 0) red[wave] = sq;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kGemvThreads / 64; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
+}
+
+// beta = sqrt(sum of the gemv partials); u = t / beta; partial_g[c] = sum over
+// the workgroup's rows of u_i A[i][c].  Thread c of a row-slice takes column c.
+template <typename T>
+__global__ __launch_bounds__(kGemvThreads) void lsqr_atv_kernel(const T* __restrict__ A, int64_t n, int64_t d,
+                                                                int64_t ld, const double* __restrict__ t,
+                                                                const double* __restrict__ gpart, int ggroups,
+                                                                double* __restrict__ st, int init,
+                                                                double* __restrict__ u, double* __restrict__ partial) {
+  if (!init && st[4] != 0.0) return;
+  double s = 0.0;
+  for (int g = 0; g < ggroups; ++g) s += gpart[g];
+  const double beta = sqrt(s);
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st[1] = beta;
+    if (init) {
+      st[5] = beta;
+      st[3] = beta;  // phibar = beta_1
+    }
+  }
+  const int64_t rows_per_group = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_group, r1 = std::min<int64_t>(n, r0 + rows_per_group);
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += kGemvThreads) u[i] = t[i] * inv;
+  // columns: slices of kGemvThreads, rows in order
+  for (int64_t c0 = 0; c0 < d; c0 += kGemvThreads) {
+    const int64_t c = c0 + threadIdx.x;
+    double acc = 0.0;
+    if (c < d)
+      for (int64_t i = r0; i < r1; ++i) acc = fma(t[i] * inv, f64(A[i * ld + c]), acc);
+    if (c < d) partial[(int64_t)blockIdx.x * d + c] = acc;
+  }
+}
+
+// One LSQR step after the two passes (init: the first alpha, v, w).
+__global__ __launch_bounds__(kStepThreads) void lsqr_step_kernel(int64_t d, const double* __restrict__ N,
+                                                                 const double* __restrict__ partial, int groups,
+                                                                 double* __restrict__ st, double* __restrict__ v,
+                                                                 double* __restrict__ w, double* __restrict__ y,
+                                                                 double* __restrict__ z, double* __restrict__ hist,
+                                                                 int64_t it, int init) {
+  __shared__ double g[1024];
+  __shared__ double q[1024];
+  __shared__ double red[kStepThreads / 64];
+  if (!init && st[4] != 0.0) {
+    if (threadIdx.x == 0 && hist != nullptr) hist[it] = st[3];
+    return;
+  }
+  const int di = (int)d;
+  for (int c = threadIdx.x; c < di; c += kStepThreads) {
+    double s = 0.0;
+    for (int gg = 0; gg < groups; ++gg) s += partial[(int64_t)gg * d + c];
+    g[c] = s;
+  }
+  __syncthreads();
+  const double beta = st[1];
+  // q = N^T g - beta v
+  double sq = 0.0;
+  for (int c = threadIdx.x; c < di; c += kStepThreads) {
+    double s = 0.0;
+    for (int i = 0; i < di; ++i) s = fma(N[(int64_t)i * d + c], g[i], s);
+    const double qc = init ? s : s - beta * v[c];
+    q[c] = qc;
+    sq = fma(qc, qc, sq);
+  }
+  sq = wave_sum(sq);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+  __syncthreads();
+  double a2 = 0.0;
+  for (int wv = 0; wv < kStepThreads / 64; ++wv) a2 += red[wv];
+  const double alpha = sqrt(a2);
+  const double ia = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  double rho = 1.0, c = 1.0, s = 0.0, phi = 0.0;
+  const double rhobar = st[2], phibar = st[3];
+  if (!init) {
+    rho = hypot(rhobar, beta);
+    c = rhobar / rho;
+    s = beta / rho;
+  }
+  const double theta = s * alpha;
+  phi = c * phibar;
+  for (int cc = threadIdx.x; cc < di; cc += kStepThreads) {
+    const double vn = q[cc] * ia;
+    if (init) {
+      w[cc] = vn;
+      y[cc] = 0.0;
+    } else {
+      y[cc] = fma(phi / rho, w[cc], y[cc]);
+      w[cc] = vn - (theta / rho) * w[cc];
+    }
+    v[cc] = vn;
+  }
+  __syncthreads();
+  // z = N v for the next gemv
+  for (int r = threadIdx.x; r < di; r += kStepThreads) {
+    double acc = 0.0;
+    for (int cc = 0; cc < di; ++cc) acc = fma(N[(int64_t)r * d + cc], v[cc], acc);
+    z[r] = acc;
+  }
+  if (threadIdx.x == 0) {
+    st[0] = alpha;
+    if (init) {
+      st[2] = alpha;  // rhobar = alpha_1
+    } else {
+      st[2] = -c * alpha;
+      st[3] = s * phibar;
+      if (hist != nullptr) hist[it] = s * phibar;
+    }
+    if (alpha == 0.0 || (!init && beta == 0.0) || st[5] == 0.0) st[4] = 1.0;
+  }
+}
+
+// x = N y.
+__global__ void lsqr_finish_kernel(int64_t d, const double* __restrict__ N, const double* __restrict__ y,
+                                   double* __restrict__ x) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d) return;
+  double acc = 0.0;
+  for (int64_t c = 0; c < d; ++c) acc = fma(N[r * d + c], y[c], acc);
+  x[r] = acc;
+}
+
+template <typename T>
+hipError_t lsqr_typed(const void* Av, int64_t n, int64_t d, int64_t ld, const double* N, const double* b,
+                      int64_t iters, double* x, double* hist, double* ws, hipStream_t s) {
+  const T* A = static_cast<const T*>(Av);
+  const int groups = lsqr_groups(n);
+  double* st = ws;               // 8
+  double* u = st + 8;            // n
+  double* t = u + n;             // n
+  double* gpart = t + n;         // groups
+  double* apart = gpart + groups;  // groups * d
+  double* v = apart + (size_t)groups * d;  // d
+  double* w = v + d;
+  double* y = w + d;
+  double* z = y + d;
+  int gs = 1;
+  while (gs < 64 && gs < d) gs <<= 1;
+  hipError_t e = launch_fill_zero(st, 8 * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  // beta_1 u_1 = b; alpha_1 v_1 = M^T u_1
+  lsqr_gemv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, z, u, b, 1, st, t, gpart, gs);
+  lsqr_atv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, t, gpart, groups, st, 1, u, apart);
+  lsqr_step_kernel<<<1, kStepThreads, 0, s>>>(d, N, apart, groups, st, v, w, y, z, hist, 0, 1);
+  for (int64_t it = 0; it < iters; ++it) {
+    lsqr_gemv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, z, u, b, 0, st, t, gpart, gs);
+    lsqr_atv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, t, gpart, groups, st, 0, u, apart);
+    lsqr_step_kernel<<<1, kStepThreads, 0, s>>>(d, N, apart, groups, st, v, w, y, z, hist, it, 0);
+  }
+  lsqr_finish_kernel<<<(unsigned)((d + 255) / 256), 256, 0, s>>>(d, N, y, x);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_precondition(int method, int64_t d, const double* R, const int64_t* rank, const int32_t* perm,
+                               double zeta, double* work, double* N, int64_t* k_out, int32_t* err,
+                               hipStream_t s) {
+  if (method == 1) {
+    if (d > 128) return hipErrorInvalidValue;
+    const int64_t dd = d + (d & 1);
+    const size_t lds = sizeof(double) * (size_t)(dd * d);
+    auto kern = jacobi_svd_kernel;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    kern<<<1, kSvdThreads, lds, s>>>(d, R, rank, perm, zeta, work, N, k_out);
+    return hipGetLastError();
+  }
+  // QR: Z = R11^{-1} (trsm of the identity), rows scattered to the original columns
+  double* I = work;
+  double* Z = work + d * d;
+  hipError_t e = launch_identity(d, I, s);
+  if (e != hipSuccess) return e;
+  e = launch_trsm_z(d, d, R, rank, I, Z, err, s);
+  if (e != hipSuccess) return e;
+  scatter_rows_kernel<<<(unsigned)((d * d + 255) / 256), 256, 0, s>>>(d, perm, Z, N, rank, k_out);
+  return hipGetLastError();
+}
+
+// k = -1 when a bounded wait of the rank-revealing step ran out.
+__global__ void flag_error_kernel(const int32_t* __restrict__ err, int64_t* __restrict__ k_out) {
+  if (*err != 0) *k_out = -1;
+}
+
+hipError_t launch_flag_error(const int32_t* err, int64_t* k_out, hipStream_t s) {
+  flag_error_kernel<<<1, 1, 0, s>>>(err, k_out);
+  return hipGetLastError();
+}
+
+int lsqr_groups(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(1024, (n + 255) / 256)); }
+
+size_t lsqr_ws_doubles(int64_t n, int64_t d) {
+  return 8 + 2 * (size_t)n + (size_t)lsqr_groups(n) * (1 + (size_t)d) + 4 * (size_t)d;
+}
+
+hipError_t launch_lsqr(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, const double* N, const double* b,
+                       int64_t iters, double* x, double* hist, double* ws, hipStream_t s) {
+  switch (dtype) {
+    case 0: return lsqr_typed<double>(A, n, d, ld, N, b, iters, x, hist, ws, s);
+    case 1: return lsqr_typed<float>(A, n, d, ld, N, b, iters, x, hist, ws, s);
+    case 2: return lsqr_typed<__hip_bfloat16>(A, n, d, ld, N, b, iters, x, hist, ws, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace lev

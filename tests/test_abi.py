@@ -167,6 +167,25 @@ def test_workspace_grows_with_column_tiles(lib):
     assert lib.lev_workspace_size(ctypes.byref(A), ctypes.byref(_par(api, m=8, mode=3)), api.WS_ESTIMATE) > 0
 
 
+def test_precondition_and_lsqr_validate(lib):
+    from paper_2105_11004_amd import api
+    vp = ctypes.c_void_p
+    A, p = _mat(api, dtype=0, d=200, ld=200), _par(api, m=400, r_cs=4096, zeta=1e-10)
+    assert lib.lev_precondition_workspace_size(ctypes.byref(A), ctypes.byref(p)) > 0
+    # the SVD preconditioner takes d <= 128; unknown method; null outputs
+    assert lib.lev_precondition(ctypes.byref(A), ctypes.byref(p), 1, vp(8192), vp(8192), vp(1 << 20), 1 << 40,
+                                None) == -7
+    assert lib.lev_precondition(ctypes.byref(A), ctypes.byref(p), 2, vp(8192), vp(8192), vp(1 << 20), 1 << 40,
+                                None) == -1
+    assert lib.lev_precondition(ctypes.byref(A), ctypes.byref(p), 0, None, vp(8192), vp(1 << 20), 1 << 40,
+                                None) == -1
+    C = _mat(api, format=1, row_ptr=8192, nnz=5, col_idx=16384)
+    assert lib.lev_lsqr_workspace_size(ctypes.byref(C)) == 0
+    assert lib.lev_lsqr(ctypes.byref(C), vp(8), vp(8), 3, vp(8), None, vp(1 << 20), 1 << 40, None) == -7
+    assert lib.lev_lsqr(ctypes.byref(A), vp(8), vp(8), -1, vp(8), None, vp(1 << 20), 1 << 40, None) == -1
+    assert lib.lev_lsqr_workspace_size(ctypes.byref(A)) > 0
+
+
 def test_backward_validates_state_and_workspace(lib):
     from paper_2105_11004_amd import api
     A, p = _mat(api), _par(api)
