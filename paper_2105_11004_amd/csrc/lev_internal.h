@@ -98,12 +98,12 @@ int dgemm_choose_splits(int64_t M, int64_t N, int64_t K);
 
 // Pivoted Cholesky of the d x d Gram B (overwritten with Schur complements).
 struct PivCholState {
-  double* diag;        // d
-  double* Rrows;       // d x d: row J = row J of R in original column order
-  int32_t* piv;        // d: pivot at position J
-  int32_t* flags;      // [0] = done, [1] = pivots so far, [2..] scratch
-  double* r00;         // 1
-  int32_t* err;        // optional (may be null): bit kErrPivotWait is set when a bounded wait ran out
+  double* diag = nullptr;     // d
+  double* Rrows = nullptr;    // d x d: row J = row J of R in original column order
+  int32_t* piv = nullptr;     // d: pivot at position J
+  int32_t* flags = nullptr;   // [0] = done, [1] = pivots so far, [2..] scratch
+  double* r00 = nullptr;      // 1
+  int32_t* err = nullptr;     // optional: bit kErrPivotWait is set when a bounded wait ran out
 };
 
 // Bits of the device error word (state header, slot 5).  A bounded wait
