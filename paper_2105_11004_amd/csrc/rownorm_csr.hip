@@ -223,6 +223,201 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
   }
 }
 
+// ---- FP32 Z: rows shared out to 16-lane groups --------------------------------
+// A wave takes 64 consecutive rows.  Its four 16-lane groups each own four
+// of the 64 output columns per lane... more precisely: lane l of group g
+// owns columns 4 (l % 16) .. + 3 of the k <= 64, and a group walks one row's
+// nonzeros 16 at a time: each lane loads one (column id, value), then for
+// each of the 16 entries the group broadcasts it from its lane (DPP
+// row_newbcast, no LDS), reads the 16 bytes of Z_full's row it needs
+// (ds_read_b128: the group reads the whole 256-byte row, conflict-free) and
+// does four FMAs.  Light rows (< 64 nonzeros) go four at a time, one per
+// group, so a single-nonzero row costs a quarter of a step, not a whole
+// wave's; heavy rows are split over the four groups (each takes 16 of every
+// 64 nonzeros) and the groups' partial k-vectors are added at the end.
+// Z_full sits in LDS with a row stride of 68 floats (272 bytes: the four
+// groups' rows fall on different banks).  The squares of a row's k-vector
+// are summed over the group with four DPP steps; the group's last lane
+// stores theta.
+constexpr int kGZStride = 68;
+constexpr int kHeavy = 64;
+
+template <int U>
+__device__ __forceinline__ int row_bcast_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + U, 0xF, 0xF, false);  // row_newbcast:U
+}
+
+__device__ __forceinline__ float group_sum16(float v) {
+  // prefix within each 16-lane row; lane 15 of the row ends with the total
+  v = dpp_sum_step<0x111, 0xF>(v);
+  v = dpp_sum_step<0x112, 0xF>(v);
+  v = dpp_sum_step<0x114, 0xF>(v);
+  v = dpp_sum_step<0x118, 0xF>(v);
+  return v;
+}
+
+// y += the group's first `steps` (wave-uniform, rounded up to 4, at most 16)
+// staged entries (col, val); masked entries carry a zero value.
+__device__ __forceinline__ void group_chunk(const float* __restrict__ Zs, int col, float val, int gl, float (&y)[4],
+                                            int steps = 16) {
+#define LEV_GSTEP(U)                                                                                   \
+  {                                                                                                  \
+    const int cu = row_bcast_i<U>(col);                                                              \
+    const float vu = __int_as_float(row_bcast_i<U>(__float_as_int(val)));                            \
+    const float4 z = *reinterpret_cast<const float4*>(Zs + cu * kGZStride + 4 * gl);                 \
+    y[0] = fmaf(vu, z.x, y[0]);                                                                      \
+    y[1] = fmaf(vu, z.y, y[1]);                                                                      \
+    y[2] = fmaf(vu, z.z, y[2]);                                                                      \
+    y[3] = fmaf(vu, z.w, y[3]);                                                                      \
+  }
+  LEV_GSTEP(0) LEV_GSTEP(1) LEV_GSTEP(2) LEV_GSTEP(3)
+  if (steps > 4) { LEV_GSTEP(4) LEV_GSTEP(5) LEV_GSTEP(6) LEV_GSTEP(7) }
+  if (steps > 8) { LEV_GSTEP(8) LEV_GSTEP(9) LEV_GSTEP(10) LEV_GSTEP(11) }
+  if (steps > 12) { LEV_GSTEP(12) LEV_GSTEP(13) LEV_GSTEP(14) LEV_GSTEP(15) }
+#undef LEV_GSTEP
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* __restrict__ vals,
+                                                                      const int64_t* __restrict__ row_ptr,
+                                                                      const int32_t* __restrict__ col_idx,
+                                                                      int64_t n, int64_t d, int64_t nnz,
+                                                                      const float* __restrict__ Zg,
+                                                                      float* __restrict__ theta, ColTile ct) {
+  extern __shared__ __align__(16) float Zs[];  // d rows of kGZStride floats
+  if (col_tile_dead(ct)) return;
+  for (int64_t e = threadIdx.x; e < d * 64; e += kCsrThreads) Zs[(e / 64) * kGZStride + (e % 64)] = Zg[e];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4, gl = lane & 15;
+  const int64_t ntask = (n + 63) / 64;
+  const int64_t tstep = (int64_t)gridDim.x * kCsrWaves;
+  int64_t task = (int64_t)blockIdx.x * kCsrWaves + wave;
+  // the next task's row starts load while the current task runs
+  auto row_start = [&](int64_t tk) -> int64_t {
+    if (tk >= ntask) return 0;
+    const int64_t r = tk * 64 + lane;
+    return r <= n ? min(max(row_ptr[r], (int64_t)0), nnz) : nnz;
+  };
+  int64_t rp_next = row_start(task);
+  for (; task < ntask; task += tstep) {
+    const int64_t r0 = task * 64;
+    const int nr = (int)min((int64_t)64, n - r0);
+    // lane j: start of row r0 + j, made non-decreasing
+    int64_t rp = rp_next;
+    rp_next = row_start(task + tstep);
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t up = __shfl_up(rp, o, 64);
+      if (lane >= o) rp = max(rp, up);
+    }
+    int64_t last = min(max(row_ptr[r0 + nr], (int64_t)0), nnz);
+    last = max(last, __shfl(rp, 63, 64));
+    if (lane >= nr) rp = last;  // rows past the task's end are empty
+    // (the shuffle runs on every lane: a lane masked off by a branch does not
+    // supply its value to the others)
+    const int64_t down = __shfl_down(rp, 1, 64);
+    const int64_t rnext = lane < 63 ? down : last;
+    const int len = lane < nr ? (int)(rnext - rp) : 0;
+    const uint64_t heavy = __ballot(lane < nr && len >= kHeavy);
+
+    // light rows: group g takes rows 4 q + g; the first 32 nonzeros of the
+    // rows two steps ahead load while a step runs (a ring of three)
+    int pc[3][2];
+    float pv[3][2];
+#define LEV_LOADQ(Q, SLOT)                                                                          \
+    {                                                                                               \
+      const int jj = 4 * (Q) + g;                                                                   \
+      const int64_t ss = __shfl(rp, jj, 64);                                                        \
+      const int l0 = __shfl(len, jj, 64);                                                           \
+      const int ll = (jj < nr && l0 < kHeavy) ? l0 : 0;                                             \
+      _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                               \
+        const int t = 16 * h + gl;                                                                  \
+        const bool ok = t < ll;                                                                     \
+        const int cc = ok ? col_idx[ss + t] : 0;                                                    \
+        const float vv = ok ? to_f32<T>(vals[ss + t]) : 0.f;                                        \
+        const bool cin = (uint32_t)cc < (uint32_t)d;                                                \
+        pc[SLOT][h] = cin ? cc : 0;                                                                 \
+        pv[SLOT][h] = cin ? vv : 0.f;                                                               \
+      }                                                                                             \
+    }
+    LEV_LOADQ(0, 0)
+    LEV_LOADQ(1, 1)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      if (q + 2 < 16) LEV_LOADQ(q + 2, (q + 2) % 3)
+      const int slot = q % 3;
+      const int j = 4 * q + g;
+      const int64_t s0 = __shfl(rp, j, 64);
+      int lj = __shfl(len, j, 64);
+      const bool mine = j < nr && lj < kHeavy;
+      if (!mine) lj = 0;
+      // wave-uniform chunk count: the longest of the four groups' rows
+      int mx = lj;
+      mx = max(mx, __shfl_xor(mx, 16, 64));
+      mx = max(mx, __shfl_xor(mx, 32, 64));
+      float y[4] = {0.f, 0.f, 0.f, 0.f};
+      if (mx > 0) group_chunk(Zs, pc[slot][0], pv[slot][0], gl, y, mx);
+      if (mx > 16) group_chunk(Zs, pc[slot][1], pv[slot][1], gl, y, mx - 16);
+      for (int c0 = 32; c0 < mx; c0 += 16) {
+        const int t = c0 + gl;
+        const bool ok = t < lj;
+        const int col = ok ? col_idx[s0 + t] : 0;
+        const float v = ok ? to_f32<T>(vals[s0 + t]) : 0.f;
+        const bool cin = (uint32_t)col < (uint32_t)d;
+        group_chunk(Zs, cin ? col : 0, cin ? v : 0.f, gl, y, mx - c0);
+      }
+      const float sq = group_sum16(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+      if (mine && gl == 15) {
+        const int64_t r = r0 + j;
+        theta[r] = ct.acc ? theta[r] + sq : sq;
+      }
+    }
+#undef LEV_LOADQ
+    // heavy rows: the four groups split each row's nonzeros; the next chunk
+    // of 64 loads while the current one runs
+    uint64_t hm = heavy;
+    while (hm) {
+      const int j = __builtin_ctzll(hm);
+      hm &= hm - 1;
+      const int64_t s0 = __shfl(rp, j, 64);
+      const int lj = __shfl(len, j, 64);
+      auto load = [&](int c0, int& col, float& v) {
+        const int t = c0 + lane;
+        const bool ok = t < lj;
+        const int cc = ok ? col_idx[s0 + t] : 0;
+        const float vv = ok ? to_f32<T>(vals[s0 + t]) : 0.f;
+        const bool cin = (uint32_t)cc < (uint32_t)d;
+        col = cin ? cc : 0;
+        v = cin ? vv : 0.f;
+      };
+      int col;
+      float v;
+      load(0, col, v);
+      float y[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int c0 = 0; c0 < lj; c0 += 64) {
+        int ncol = 0;
+        float nv = 0.f;
+        if (c0 + 64 < lj) load(c0 + 64, ncol, nv);
+        group_chunk(Zs, col, v, gl, y, lj - c0);
+        col = ncol;
+        v = nv;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        y[q] += __shfl_xor(y[q], 16, 64);
+        y[q] += __shfl_xor(y[q], 32, 64);
+      }
+      const float sq = group_sum16(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+      if (lane == 15) {
+        const int64_t r = r0 + j;
+        theta[r] = ct.acc ? theta[r] + sq : sq;
+      }
+    }
+  }
+}
+
 template <typename T, typename ZT>
 hipError_t launch_typed(const void* vals, const int64_t* row_ptr, const int32_t* col_idx, int64_t n, int64_t d,
                         int64_t nnz, const void* Zpack, void* theta, const ColTile& ct, hipStream_t s) {
@@ -239,6 +434,18 @@ hipError_t launch_typed(const void* vals, const int64_t* row_ptr, const int32_t*
   const T* v = static_cast<const T*>(vals);
   const ZT* Z = static_cast<const ZT*>(Zpack);
   ZT* th = static_cast<ZT*>(theta);
+  if constexpr (sizeof(ZT) == 4) {
+    const size_t gz = (size_t)d * kGZStride * sizeof(float);
+    if (gz <= 152 * 1024) {
+      auto kern = rownorm_csr_grp_kernel<T>;
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)gz);
+      if (e != hipSuccess) return e;
+      const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)num_cu));
+      kern<<<grid, kCsrThreads, gz, s>>>(v, row_ptr, col_idx, n, d, nnz, Z, th, ct);
+      return hipGetLastError();
+    }
+  }
   if (stage_bytes + z_bytes <= kMaxLds) {
     const size_t lds = stage_bytes + z_bytes;
     auto kern = rownorm_csr_kernel<T, ZT, true>;
