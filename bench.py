@@ -118,10 +118,14 @@ def a_bytes(A) -> int:
 
 
 # kernels that carry each pass (for the traffic counters and the profiles)
-def pass_kernels_for(csr: bool, dtype: torch.dtype, precision: str) -> dict:
+def pass_kernels_for(csr: bool, dtype: torch.dtype, precision: str, d: int = 0) -> dict:
     if csr:
+        # FP32 Z whose d rows (68 floats each) fit in 152 KiB of LDS: the
+        # 16-lane group kernel; else the one-row-per-wave kernel
+        grp = dtype != torch.float64 and d * 68 * 4 <= 152 * 1024
         return {"pass1_countsketch": ("countsketch_csr_kernel", CSRC / "sketch.hip"),
-                "pass2_rownorm": ("rownorm_csr_kernel", CSRC / "rownorm_csr.hip")}
+                "pass2_rownorm": ("rownorm_csr_grp_kernel" if grp else "rownorm_csr_kernel",
+                                  CSRC / "rownorm_csr.hip")}
     if precision == "fp32" or dtype == torch.float64:
         p2 = ("rownorm_dense_kernel", CSRC / "rownorm.hip")
     elif dtype == torch.bfloat16:
@@ -132,7 +136,7 @@ def pass_kernels_for(csr: bool, dtype: torch.dtype, precision: str) -> dict:
 
 
 def pass_kernels(A, precision: str) -> dict:
-    return pass_kernels_for(_is_csr(A), _values(A).dtype, precision)
+    return pass_kernels_for(_is_csr(A), _values(A).dtype, precision, A.d if _is_csr(A) else A.shape[1])
 
 
 def expected_rank(cfg) -> int:
@@ -417,13 +421,12 @@ def traffic_summarize(fetch_dir: str, write_dir: str, workload: str, precision: 
     csr = workload.startswith("csr")
     if precision == "auto":
         precision = "bf16x3" if (dtype == torch.bfloat16 and not csr) else "native"
-    kern = pass_kernels_for(csr, dtype, precision)
-    n, d = cfg["n"], cfg["d"]
-    es = torch.empty(0, dtype=dtype).element_size()
-    theta_es = 8 if dtype == torch.float64 else 4
-    algorithmic = {} if csr else {
-        "pass2_rownorm": n * d * es + n * theta_es,
-        "pass1_countsketch": n * d * es + 8 * (cfg["r_cs"] * d + cfg["m"] * cfg["r_cs"] + d * cfg["k"])}
+    kern = pass_kernels_for(csr, dtype, precision, cfg["d"])
+    # the algorithmic bytes of the passes, from the workload itself (a CSR
+    # matrix's are those of its row_ptr, col_idx and values)
+    A, _, _ = make_workload(workload, torch.device("cuda:0") if torch.cuda.is_available() else torch.device("cpu"))
+    algorithmic = {k: w for k, (b, w) in phase_work(A, cfg).items() if b == "hbm"}
+    del A
     entry = {"copy_bytes": COPY_BYTES, "factor_read": f_read, "factor_write": f_write}
     lines = [f"# HBM traffic per launch, workload {workload}, precision {precision} "
              f"(rocprofv3 FETCH_SIZE / WRITE_SIZE, KiB per dispatch)",
