@@ -65,49 +65,81 @@ __device__ __forceinline__ void lds_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// flags[0] = done, flags[1] = pivots computed so far.
-__global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __restrict__ S, int64_t d,
-                                                              double zeta, int64_t J0,
-                                                              PivCholState st,
-                                                              int64_t* __restrict__ rank_out, int fixed,
-                                                              const double* __restrict__ ref_r00) {
-  __shared__ double bc[NB];
-  __shared__ double wv[2][kMaxD / 64];
-  __shared__ int wi[2][kMaxD / 64];
+// Max over lanes 0..7 (row shifts within the first 16-lane row), returned
+// to every lane (the workgroup's at most 8 wave candidates).
+__device__ __forceinline__ double max8_f64(double v) {
+  v = dpp_max_step<0x111, 0xF>(v);  // row_shr:1
+  v = dpp_max_step<0x112, 0xF>(v);  // row_shr:2
+  v = dpp_max_step<0x114, 0xF>(v);  // row_shr:4
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 7);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 7);
+  return __hiloint2double(hi, lo);
+}
 
-  const int c = threadIdx.x;
-  const int lane = c & 63, wave = c >> 6;
+// One panel of NB pivot steps.  Thread t owns the adjacent columns 2t and
+// 2t + 1 (at most 8 waves for d <= 1024): every pivot step runs two
+// reductions and two barriers whose cost is paid per wave, so half as many
+// waves, each with twice the column work, halve that part of the step.  The
+// lane's candidate is the larger of its two diagonals (ties to the lower
+// column), the wave's the lowest lane holding the wave max, the workgroup's
+// the lowest wave holding the overall max: ties go to the lowest column.
+// flags[0] = done, flags[1] = pivots computed so far.
+constexpr int kPanelCols = 2;
+constexpr int kPanelThreads = kMaxD / kPanelCols;
+constexpr int kPanelWaves = kPanelThreads / 64;
+
+__global__ __launch_bounds__(kPanelThreads) void pivchol_panel_kernel(const double* __restrict__ S, int64_t d,
+                                                                      double zeta, int64_t J0,
+                                                                      PivCholState st,
+                                                                      int64_t* __restrict__ rank_out, int fixed,
+                                                                      const double* __restrict__ ref_r00) {
+  __shared__ double bc[NB];
+  __shared__ double wv[2][kPanelWaves];
+  __shared__ int wi[2][kPanelWaves];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int nwaves = blockDim.x >> 6;
+  const int c0 = kPanelCols * tid;  // columns c0, c0 + 1
   if (J0 > 0 && st.flags[0] != 0) return;
 
-  double dg;
-  if (c < d) dg = (J0 == 0) ? S[(int64_t)c * d + c] : st.diag[c];
-  else dg = -INFINITY;
-  bool alive = (c < d) && (dg != -INFINITY);
+  double dg[2];
+  bool alive[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int c = c0 + q;
+    dg[q] = (c < d) ? ((J0 == 0) ? S[(int64_t)c * d + c] : st.diag[c]) : -INFINITY;
+    alive[q] = (c < d) && (dg[q] != -INFINITY);
+  }
   double r00 = ref_r00 != nullptr ? *ref_r00 : ((J0 == 0) ? 0.0 : *st.r00);
 
-  double rp[NB];
+  double rp0[NB], rp1[NB];
 #pragma unroll
-  for (int t = 0; t < NB; ++t) rp[t] = 0.0;
+  for (int t = 0; t < NB; ++t) rp0[t] = rp1[t] = 0.0;
 
   int64_t J = J0;
   bool stop = false;
   bool active = true;  // uniform across the workgroup
-  // Constant trip count (no break) so the loop unrolls fully and rp[] stays
-  // in registers.
+  // Constant trip count (no break) so the loop unrolls fully and rp0[],
+  // rp1[] stay in registers.
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     if (active && J >= d) active = false;
     if (!active) continue;
-    // the wave's largest alive diagonal (DPP max; NaN never wins) and the
-    // lowest lane holding it (ties go to the lower column)
-    // (fixed order: the only candidate of step J is column J)
-    const double mv = (alive && (!fixed || c == J)) ? dg : -INFINITY;
+    // the lane's candidate (fixed order: the only candidate of step J is
+    // column J); a NaN diagonal never wins
+    const double m0 = (alive[0] && (!fixed || c0 == J)) ? dg[0] : -INFINITY;
+    const double m1 = (alive[1] && (!fixed || c0 + 1 == J)) ? dg[1] : -INFINITY;
+    const bool second = (m1 > m0) || (m0 != m0);
+    const double mv = second ? m1 : m0;
+    const int mc = c0 + (second ? 1 : 0);
     const double wmax = wave_max_f64(mv);
     const uint64_t hit = __ballot(mv == wmax);
+    const int hl = hit != 0 ? (__ffsll((unsigned long long)hit) - 1) : 0;
+    const int hc = __builtin_amdgcn_readlane(mc, hl);
     if (lane == 0) {
       wv[j & 1][wave] = hit != 0 ? wmax : -INFINITY;
-      wi[j & 1][wave] = hit != 0 ? wave * 64 + (__ffsll((unsigned long long)hit) - 1) : 0x7fffffff;
+      wi[j & 1][wave] = hit != 0 ? hc : 0x7fffffff;
     }
     // (LDS-only barriers: the R rows this kernel stores are read by later
     // launches only, and waiting for their acknowledgement at every pivot
@@ -118,8 +150,8 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
     // columns are the lower ones)
     const double cv = lane < nwaves ? wv[j & 1][lane] : -INFINITY;
     const int ci = lane < nwaves ? wi[j & 1][lane] : 0x7fffffff;
-    const double bmax = wave_max_f64(cv);
-    const uint64_t bhit = __ballot(cv == bmax);
+    const double bmax = max8_f64(cv);
+    const uint64_t bhit = __ballot(lane < 8 && cv == bmax);
     const int bw = bhit != 0 ? (__ffsll((unsigned long long)bhit) - 1) : 0;
     const double pv = bhit != 0 ? bmax : -INFINITY;
     const int p = __builtin_amdgcn_readlane(ci, bw);
@@ -130,33 +162,49 @@ __global__ __launch_bounds__(kMaxD) void pivchol_panel_kernel(const double* __re
       continue;
     }
     const double rjj = sqrt(pv);
+    const double inv = 1.0 / rjj;
     // prefetch the pivot row of the Schur complement (symmetric: = column p)
-    const double s_pc = (c < d) ? S[(int64_t)p * d + c] : 0.0;
-    if (c == p) {
+    double s_pc[2];
 #pragma unroll
-      for (int t = 0; t < j; ++t) bc[t] = rp[t];
+    for (int q = 0; q < 2; ++q) s_pc[q] = (c0 + q < d) ? S[(int64_t)p * d + c0 + q] : 0.0;
+    if ((p >> 1) == tid) {
+#pragma unroll
+      for (int t = 0; t < j; ++t) bc[t] = (p & 1) ? rp1[t] : rp0[t];
     }
     lds_barrier();
-    double val = 0.0;
-    if (c == p) {
-      val = rjj;
-      alive = false;
-      dg = -INFINITY;
-    } else if (alive) {
-      double acc = s_pc;
+    double acc0 = s_pc[0], acc1 = s_pc[1];
 #pragma unroll
-      for (int t = 0; t < j; ++t) acc = fma(-bc[t], rp[t], acc);
-      val = acc / rjj;
-      dg = fma(-val, val, dg);
+    for (int t = 0; t < j; ++t) {
+      const double b = bc[t];
+      acc0 = fma(-b, rp0[t], acc0);
+      acc1 = fma(-b, rp1[t], acc1);
     }
-    rp[j] = val;
-    if (c < d) st.Rrows[J * d + c] = val;
-    if (c == 0) st.piv[J] = p;
+    double val[2] = {acc0 * inv, acc1 * inv};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (c0 + q == p) {
+        val[q] = rjj;
+        alive[q] = false;
+        dg[q] = -INFINITY;
+      } else if (alive[q]) {
+        dg[q] = fma(-val[q], val[q], dg[q]);
+      } else {
+        val[q] = 0.0;
+      }
+    }
+    rp0[j] = val[0];
+    rp1[j] = val[1];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (c0 + q < d) st.Rrows[J * d + c0 + q] = val[q];
+    if (tid == 0) st.piv[J] = p;
     ++J;
   }
 
-  if (c < d) st.diag[c] = dg;
-  if (c == 0) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    if (c0 + q < d) st.diag[c0 + q] = dg[q];
+  if (tid == 0) {
     *st.r00 = r00;
     st.flags[1] = (int32_t)J;
     if (stop || J >= d) {
@@ -522,7 +570,7 @@ hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState&
     pivchol_small_kernel<<<1, 64 * waves, 0, s>>>(B, (int)d, zeta, st, rank_out, fixed, ref_r00);
     return hipGetLastError();
   }
-  const int threads = (int)(((d + 63) / 64) * 64);
+  const int threads = (int)(((d + 64 * kPanelCols - 1) / (64 * kPanelCols)) * 64);
   for (int64_t J0 = 0; J0 < d; J0 += NB) {
     pivchol_panel_kernel<<<1, threads, 0, s>>>(B, d, zeta, J0, st, rank_out, fixed, ref_r00);
     if (J0 + NB < d) {
