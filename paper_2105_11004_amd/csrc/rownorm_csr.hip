@@ -224,17 +224,24 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
 }
 
 // ---- FP32 Z: rows shared out to 16-lane groups --------------------------------
-// A wave takes 64 consecutive rows.  Its four 16-lane groups each own four
-// of the 64 output columns per lane... more precisely: lane l of group g
-// owns columns 4 (l % 16) .. + 3 of the k <= 64, and a group walks one row's
-// nonzeros 16 at a time: each lane loads one (column id, value), then for
-// each of the 16 entries the group broadcasts it from its lane (DPP
+// A wave takes 64 consecutive rows.  Lane l of group g (16 lanes) owns
+// columns 4 (l % 16) .. + 3 of the k <= 64 output columns, and a group walks
+// one row's nonzeros 16 at a time: each lane loads one (column id, value),
+// then for each of the 16 entries the group broadcasts it from its lane (DPP
 // row_newbcast, no LDS), reads the 16 bytes of Z_full's row it needs
 // (ds_read_b128: the group reads the whole 256-byte row, conflict-free) and
 // does four FMAs.  Light rows (< 64 nonzeros) go four at a time, one per
 // group, so a single-nonzero row costs a quarter of a step, not a whole
-// wave's; heavy rows are split over the four groups (each takes 16 of every
-// 64 nonzeros) and the groups' partial k-vectors are added at the end.
+// wave's.  The four groups move in step, so a wave pays for the longest of
+// its four rows: the light rows of the 64 are first ordered by length class
+// (1, 2, 3-4, 5-8, ..., 33-63; counted with ballots, moved with a forward
+// lane permutation), which puts rows of similar length side by side (with
+// power-law row lengths, a third of the group steps did useful work in row
+// order).  Short chunks step one entry at a time up to four, then four at a
+// time.  Heavy rows are split over the four groups, entry c0 + 4 i + g of
+// a 64-entry chunk going to lane i of group g, so a chunk's last partial
+// stretch costs a quarter of its length, and the groups' partial k-vectors
+// are added at the end.
 // Z_full sits in LDS with a row stride of 68 floats (272 bytes: the four
 // groups' rows fall on different banks).  The squares of a row's k-vector
 // are summed over the group with four DPP steps; the group's last lane
@@ -256,8 +263,8 @@ __device__ __forceinline__ float group_sum16(float v) {
   return v;
 }
 
-// y += the group's first `steps` (wave-uniform, rounded up to 4, at most 16)
-// staged entries (col, val); masked entries carry a zero value.
+// y += the group's first `steps` (wave-uniform; rounded up to 4 past 4, at
+// most 16) staged entries (col, val); masked entries carry a zero value.
 __device__ __forceinline__ void group_chunk(const float* __restrict__ Zs, int col, float val, int gl, float (&y)[4],
                                             int steps = 16) {
 #define LEV_GSTEP(U)                                                                                   \
@@ -270,7 +277,10 @@ __device__ __forceinline__ void group_chunk(const float* __restrict__ Zs, int co
     y[2] = fmaf(vu, z.z, y[2]);                                                                      \
     y[3] = fmaf(vu, z.w, y[3]);                                                                      \
   }
-  LEV_GSTEP(0) LEV_GSTEP(1) LEV_GSTEP(2) LEV_GSTEP(3)
+  LEV_GSTEP(0)
+  if (steps > 1) LEV_GSTEP(1)
+  if (steps > 2) LEV_GSTEP(2)
+  if (steps > 3) LEV_GSTEP(3)
   if (steps > 4) { LEV_GSTEP(4) LEV_GSTEP(5) LEV_GSTEP(6) LEV_GSTEP(7) }
   if (steps > 8) { LEV_GSTEP(8) LEV_GSTEP(9) LEV_GSTEP(10) LEV_GSTEP(11) }
   if (steps > 12) { LEV_GSTEP(12) LEV_GSTEP(13) LEV_GSTEP(14) LEV_GSTEP(15) }
@@ -321,17 +331,35 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
     const int64_t rnext = lane < 63 ? down : last;
     const int len = lane < nr ? (int)(rnext - rp) : 0;
     const uint64_t heavy = __ballot(lane < nr && len >= kHeavy);
+    // light rows (empty ones included: their theta is 0) by length class;
+    // sorted position q holds row srow, its start rps and length lens;
+    // heavy rows and lanes past the task's end come last
+    const bool light = lane < nr && len < kHeavy;
+    const int cls = light ? (len <= 1 ? 0 : 32 - __builtin_clz((unsigned)(len - 1))) : 7;
+    int pos = 0, base = 0, nlight = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint64_t m = __ballot(cls == c);
+      const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (cls == c) pos = base + below;
+      base += __popcll(m);
+      if (c == 6) nlight = base;
+    }
+    const int srow = __builtin_amdgcn_ds_permute(4 * pos, lane);
+    const int64_t rps = ((int64_t)__builtin_amdgcn_ds_permute(4 * pos, (int)(rp >> 32)) << 32) |
+                        (uint32_t)__builtin_amdgcn_ds_permute(4 * pos, (int)rp);
+    const int lens = __builtin_amdgcn_ds_permute(4 * pos, light ? len : 0);
 
-    // light rows: group g takes rows 4 q + g; the first 32 nonzeros of the
-    // rows two steps ahead load while a step runs (a ring of three)
+    // light rows: group g takes sorted positions 4 q + g; the first 32
+    // nonzeros of the rows two steps ahead load while a step runs (a ring
+    // of three)
     int pc[3][2];
     float pv[3][2];
 #define LEV_LOADQ(Q, SLOT)                                                                          \
     {                                                                                               \
       const int jj = 4 * (Q) + g;                                                                   \
-      const int64_t ss = __shfl(rp, jj, 64);                                                        \
-      const int l0 = __shfl(len, jj, 64);                                                           \
-      const int ll = (jj < nr && l0 < kHeavy) ? l0 : 0;                                             \
+      const int64_t ss = __shfl(rps, jj, 64);                                                       \
+      const int ll = __shfl(lens, jj, 64);                                                          \
       _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                               \
         const int t = 16 * h + gl;                                                                  \
         const bool ok = t < ll;                                                                     \
@@ -346,13 +374,13 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
     LEV_LOADQ(1, 1)
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
+      if (4 * q >= nlight) break;  // uniform: the rest are heavy or past the end
       if (q + 2 < 16) LEV_LOADQ(q + 2, (q + 2) % 3)
       const int slot = q % 3;
       const int j = 4 * q + g;
-      const int64_t s0 = __shfl(rp, j, 64);
-      int lj = __shfl(len, j, 64);
-      const bool mine = j < nr && lj < kHeavy;
-      if (!mine) lj = 0;
+      const int64_t s0 = __shfl(rps, j, 64);
+      const int lj = __shfl(lens, j, 64);
+      const bool mine = j < nlight;
       // wave-uniform chunk count: the longest of the four groups' rows
       int mx = lj;
       mx = max(mx, __shfl_xor(mx, 16, 64));
@@ -369,14 +397,16 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
         group_chunk(Zs, cin ? col : 0, cin ? v : 0.f, gl, y, mx - c0);
       }
       const float sq = group_sum16(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+      const int sj = __shfl(srow, j, 64);
       if (mine && gl == 15) {
-        const int64_t r = r0 + j;
+        const int64_t r = r0 + sj;
         theta[r] = ct.acc ? theta[r] + sq : sq;
       }
     }
 #undef LEV_LOADQ
-    // heavy rows: the four groups split each row's nonzeros; the next chunk
-    // of 64 loads while the current one runs
+    // heavy rows: the four groups split each row's nonzeros (entry c0 + 4 i
+    // + g to lane i of group g); the next chunk of 64 loads while the
+    // current one runs
     uint64_t hm = heavy;
     while (hm) {
       const int j = __builtin_ctzll(hm);
@@ -384,7 +414,7 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
       const int64_t s0 = __shfl(rp, j, 64);
       const int lj = __shfl(len, j, 64);
       auto load = [&](int c0, int& col, float& v) {
-        const int t = c0 + lane;
+        const int t = c0 + 4 * gl + g;
         const bool ok = t < lj;
         const int cc = ok ? col_idx[s0 + t] : 0;
         const float vv = ok ? to_f32<T>(vals[s0 + t]) : 0.f;
@@ -400,7 +430,7 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
         int ncol = 0;
         float nv = 0.f;
         if (c0 + 64 < lj) load(c0 + 64, ncol, nv);
-        group_chunk(Zs, col, v, gl, y, lj - c0);
+        group_chunk(Zs, col, v, gl, y, min(16, (lj - c0 + 3) / 4));
         col = ncol;
         v = nv;
       }
