@@ -120,9 +120,9 @@ def a_bytes(A) -> int:
 # kernels that carry each pass (for the traffic counters and the profiles)
 def pass_kernels_for(csr: bool, dtype: torch.dtype, precision: str, d: int = 0) -> dict:
     if csr:
-        # FP32 Z whose d rows (68 floats each) fit in 152 KiB of LDS: the
+        # FP32 Z whose d rows (64 floats each) fit in 152 KiB of LDS: the
         # 16-lane group kernel; else the one-row-per-wave kernel
-        grp = dtype != torch.float64 and d * 68 * 4 <= 152 * 1024
+        grp = dtype != torch.float64 and d * 64 * 4 <= 152 * 1024
         return {"pass1_countsketch": ("countsketch_csr_kernel", CSRC / "sketch.hip"),
                 "pass2_rownorm": ("rownorm_csr_grp_kernel" if grp else "rownorm_csr_kernel",
                                   CSRC / "rownorm_csr.hip")}
@@ -457,6 +457,26 @@ def traffic_summarize(fetch_dir: str, write_dir: str, workload: str, precision: 
 
 
 # ---------------------------------------------------------------------------- the benchmark
+def read_ceiling(A, stream, reps: int = 5) -> dict:
+    """GB/s of liblev's plain streaming read (16-byte loads, no arithmetic
+    but a checksum) over the workload's largest device buffer (dense: A;
+    CSR: the values), timed with events on the stream it runs on: the read
+    bandwidth a pass over A could reach at best."""
+    buf = _values(A)
+    nbytes = buf.numel() * buf.element_size() // 16 * 16
+    sink = api.lev_debug_stream_read(buf, nbytes, stream=stream)
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(reps):
+        api.lev_debug_stream_read(buf, nbytes, sink, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    return {"GB/s": nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes, "ms": ms, "kernel": "stream_read_kernel",
+            "frac_of_peak": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
 def time_steps(plan, bwd, steps: int, stream) -> float:
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -662,6 +682,11 @@ def main():
         "phases_ms": phases,
         "phases_ms_spread": spread,
     }
+    # the measured ceiling: a plain streaming read of A's largest buffer
+    ceil = read_ceiling(A, stream)
+    out["read_ceiling"] = ceil
+    if headline.get("unit") == "GB/s":
+        headline["frac_of_read_ceiling"] = headline["achieved"] / ceil["GB/s"]
     if "pass1_countsketch" in roofs:
         out["passes_hbm_frac"] = {
             "pass1": roofs["pass1_countsketch"]["frac"], "pass2": roofs["pass2_rownorm"]["frac"],

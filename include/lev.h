@@ -327,6 +327,17 @@ lev_status lev_debug_buckets(uint64_t seed, int64_t n, int64_t r_cs, int64_t* bu
 lev_status lev_debug_gaussian(uint64_t seed, int which, int64_t rows, int64_t cols,
                               double* out, hipStream_t stream);
 
+/* The read ceiling the passes over A are measured against: reads `bytes`
+ * of device memory at buf (16-byte aligned, bytes a multiple of 16) once,
+ * with 16-byte loads from 256 workgroups of 1024 threads, and stores one
+ * checksum per thread into sink (device, LEV_STREAM_READ_SINK uint32; the
+ * XOR of all of them is the XOR over the 16-byte vectors of the sum of
+ * their four 32-bit words, mod 2^32).  Nothing else is read or written.
+ * LEV_ERR_ARG for a null pointer, misaligned buf or bytes not a positive
+ * multiple of 16. */
+#define LEV_STREAM_READ_SINK 262144
+lev_status lev_debug_stream_read(const void* buf, int64_t bytes, uint32_t* sink, hipStream_t stream);
+
 /* Phase timing.  Registers `count` caller-created HIP events (count must be
  * LEV_PHASES, or 0 / NULL to stop) for the calling thread; each following
  * lev_estimate call on that thread records them on its stream at the phase

@@ -32,7 +32,9 @@ EXPORTED = ["lev_workspace_size", "lev_rank_workspace_size", "lev_state_size", "
             "lev_rank_estimate", "lev_estimate", "lev_estimate_backward", "lev_debug_hash",
             "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params", "lev_set_phase_events",
             "lev_status_string", "lev_last_error", "lev_noalloc_max_bytes", "lev_estimate_noalloc",
-            "lev_precondition_workspace_size", "lev_precondition", "lev_lsqr_workspace_size", "lev_lsqr"]
+            "lev_precondition_workspace_size", "lev_precondition", "lev_lsqr_workspace_size", "lev_lsqr",
+            "lev_debug_stream_read"]
+LEV_STREAM_READ_SINK = 262144
 LEV_PHASES = 7
 # phase 0 holds no kernels (the Gaussian draws run inside pass 1): its time is
 # the cost of two back-to-back events
@@ -96,6 +98,7 @@ def load_library(path: Path | None = None):
     lib.lev_lsqr_workspace_size.argtypes = [POINTER(LevMatrix)]
     lib.lev_lsqr_workspace_size.restype = c_size_t
     lib.lev_lsqr.argtypes = [POINTER(LevMatrix), vp, vp, c_int64, vp, vp, vp, c_size_t, vp]
+    lib.lev_debug_stream_read.argtypes = [vp, c_int64, vp, vp]
     lib.lev_set_phase_events.argtypes = [vp, c_int]
     lib.lev_set_phase_events.restype = c_int
     lib.lev_status_string.argtypes = [c_int]
@@ -104,7 +107,7 @@ def load_library(path: Path | None = None):
     lib.lev_last_error.restype = ctypes.c_char_p
     for name in ("lev_sketch", "lev_rank_estimate", "lev_estimate", "lev_estimate_backward",
                  "lev_debug_hash", "lev_debug_buckets", "lev_debug_gaussian", "lev_hash_params",
-                 "lev_estimate_noalloc"):
+                 "lev_estimate_noalloc", "lev_debug_stream_read"):
         getattr(lib, name).restype = c_int
     _lib = lib
     return lib
@@ -522,6 +525,22 @@ def lev_debug_gaussian(seed: int, which: int, rows: int, cols: int, device="cuda
     _check(lib.lev_debug_gaussian(int(seed) & ((1 << 64) - 1), which, rows, cols, _ptr(out),
                                   _stream(torch.device(device))))
     return out
+
+
+def lev_debug_stream_read(buf: torch.Tensor, nbytes: int = None, sink: torch.Tensor = None,
+                          stream=None) -> torch.Tensor:
+    """One streaming read of the first nbytes (default: all, rounded down to
+    16) of a device tensor's storage; returns the per-thread checksums
+    (int32, LEV_STREAM_READ_SINK).  stream: a torch stream (default: the
+    current one)."""
+    lib = load_library()
+    if nbytes is None:
+        nbytes = buf.numel() * buf.element_size() // 16 * 16
+    if sink is None:
+        sink = torch.empty(LEV_STREAM_READ_SINK, dtype=torch.int32, device=buf.device)
+    st = (stream or torch.cuda.current_stream(buf.device)).cuda_stream
+    _check(lib.lev_debug_stream_read(_ptr(buf), int(nbytes), _ptr(sink), ctypes.c_void_p(st)))
+    return sink
 
 
 def lev_estimate_backward(A, state: State, w: torch.Tensor, seed: int, r_cs: int, m: int, k: int, zeta: float,

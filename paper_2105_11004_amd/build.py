@@ -26,7 +26,7 @@ ARCH = "gfx950"
 
 SOURCES = ["sketch.hip", "gauss.hip", "gemm.hip", "pivchol.hip", "rrqr.hip", "trsm.hip", "rownorm.hip",
            "rownorm_bf16.hip", "rownorm_csr.hip", "bwd.hip", "xgemm.hip", "gram_csr.hip", "srht.hip", "qless.hip", "precond.hip",
-           "lev_api.cpp"]
+           "probe.hip", "lev_api.cpp"]
 
 COMMON_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -1158,4 +1158,12 @@ lev_status lev_debug_gaussian(uint64_t seed, int which, int64_t rows, int64_t co
   return LEV_OK;
 }
 
+lev_status lev_debug_stream_read(const void* buf, int64_t bytes, uint32_t* sink, hipStream_t stream) {
+  if (buf == nullptr || sink == nullptr) return fail(LEV_ERR_ARG, "buf and sink must not be null");
+  if ((reinterpret_cast<uintptr_t>(buf) & 15) != 0) return fail(LEV_ERR_ARG, "buf must be 16-byte aligned");
+  if (bytes <= 0 || bytes % 16 != 0) return fail(LEV_ERR_ARG, "bytes must be a positive multiple of 16");
+  LEV_HIP(lev::launch_stream_read(buf, bytes, sink, stream));
+  return LEV_OK;
+}
+
 }  // extern "C"

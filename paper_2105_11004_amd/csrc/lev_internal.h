@@ -216,6 +216,11 @@ size_t lsqr_ws_doubles(int64_t n, int64_t d);
 hipError_t launch_lsqr(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, const double* N, const double* b,
                        int64_t iters, double* x, double* hist, double* ws, hipStream_t s);
 
+// A streaming read of `bytes` (a multiple of 16) at buf: the measured read
+// ceiling (probe.hip); sink holds stream_read_sink_len() checksums.
+int64_t stream_read_sink_len();
+hipError_t launch_stream_read(const void* buf, int64_t bytes, uint32_t* sink, hipStream_t s);
+
 // B (d x d, FP64) = A^T A for dense A (dtype 0 f64, 1 f32, 2 bf16) on the
 // FP64 matrix cores: the products of FP32 and BF16 elements are exact in
 // FP64.  partial: dgemm_partial_elems(d, d, splits) doubles.

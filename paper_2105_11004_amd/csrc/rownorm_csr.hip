@@ -242,11 +242,12 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
 // a 64-entry chunk going to lane i of group g, so a chunk's last partial
 // stretch costs a quarter of its length, and the groups' partial k-vectors
 // are added at the end.
-// Z_full sits in LDS with a row stride of 68 floats (272 bytes: the four
-// groups' rows fall on different banks).  The squares of a row's k-vector
+// Z_full sits in LDS unpadded, 256 bytes a row: a group's 16-lane read is
+// one whole row (measured on gfx950: a 68-float stride cost two bank-
+// conflict cycles per LDS instruction, 64 none).  The squares of a row's k-vector
 // are summed over the group with four DPP steps; the group's last lane
 // stores theta.
-constexpr int kGZStride = 68;
+constexpr int kGZStride = 64;
 constexpr int kHeavy = 64;
 
 template <int U>

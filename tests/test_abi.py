@@ -208,6 +208,13 @@ def test_other_calls_validate(lib):
     assert lib.lev_debug_hash(1, -5, 8, vp(8), vp(8), None) == -2
     assert lib.lev_debug_gaussian(1, 2, 4, 4, vp(8), None) == -1
     assert lib.lev_debug_buckets(1, 10, 0, vp(8), vp(8), None) == -2
+    # the read probe: null pointers, a misaligned buffer, a size that is not
+    # a positive multiple of 16 (all rejected before any device work)
+    assert lib.lev_debug_stream_read(None, 16, vp(16), None) == -1
+    assert lib.lev_debug_stream_read(vp(16), 16, None, None) == -1
+    assert lib.lev_debug_stream_read(vp(24), 16, vp(16), None) == -1
+    assert lib.lev_debug_stream_read(vp(16), 24, vp(16), None) == -1
+    assert lib.lev_debug_stream_read(vp(16), 0, vp(16), None) == -1
 
 
 def test_hash_params_match_known_primes_and_oracle(lib):

@@ -525,3 +525,18 @@ def test_accuracy_against_exact_theta_is_reported(gpu):
     bias = W.expected_bias(m, d, r_cs)
     _log("median ratio", np.median(ratio), "pred bias", bias, "within 0.5", np.mean(np.abs(ratio - 1) < 0.5))
     assert abs(np.median(ratio) / bias - 1) < 0.25
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 16, (1 << 24) + 48])
+def test_stream_read_probe_reads_every_vector(gpu, nbytes):
+    """The read-ceiling probe reads each 16-byte vector exactly once: the XOR
+    of its per-thread checksums is the XOR over the vectors of the sum of
+    their four words (mod 2^32), computed here on the host."""
+    words = np.random.default_rng(nbytes).integers(0, 1 << 32, size=nbytes // 4, dtype=np.uint64).astype(np.uint32)
+    buf = torch.from_numpy(words.view(np.int32)).to(gpu)
+    sink = api.lev_debug_stream_read(buf, nbytes)
+    torch.cuda.synchronize()
+    got = np.bitwise_xor.reduce(sink.cpu().numpy().view(np.uint32))
+    v = words.reshape(-1, 4).astype(np.uint64).sum(axis=1) & 0xFFFFFFFF
+    assert int(got) == int(np.bitwise_xor.reduce(v.astype(np.uint32)))
+
