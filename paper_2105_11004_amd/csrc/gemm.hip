@@ -256,7 +256,19 @@ hipError_t launch_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const dou
   return hipGetLastError();
 }
 
-int gram_dense_splits(int64_t n, int64_t d) { return dgemm_choose_splits(d, d, n); }
+// The Gram's K is the row count n: long, while only the tiles on and above
+// the diagonal run.  Aim for >= 2048 workgroups (eight per CU: each K step is
+// a global-load round trip that the other workgroups' MFMAs cover) with
+// >= 512 rows per split and the partials within 64 MiB (d = 64: 1024 splits;
+// d = 256: 128; d = 1024: 8).
+int gram_dense_splits(int64_t n, int64_t d) {
+  const int64_t tb = (d + BM - 1) / BM;
+  const int64_t upper = tb * (tb + 1) / 2;
+  const int64_t cap = std::max<int64_t>(1, (int64_t(64) << 20) / (8 * d * d));
+  int splits = 1;
+  while (upper * splits < 2048 && n / (splits * 2) >= 512 && splits * 2 <= cap && splits < 1024) splits *= 2;
+  return splits;
+}
 
 // A^T A: op(A)[i][k] = A[k][i] (strides 1, ld) and op(B)[k][j] = A[k][j]
 // (strides ld, 1), so both operand tiles are read along A's rows; only the
