@@ -14,10 +14,10 @@
 //
 // Tiling: 128 x 128 output tile per workgroup of 8 waves (each wave 64 rows
 // x 32 columns = 4 x 2 MFMA blocks), K in steps of 32 through
-// double-buffered LDS (3 parts x 128 rows x 32 k per operand, rows padded
-// to 80 bytes so that the 16 rows an MFMA operand read touches fall on
-// distinct banks), the next step's global loads in registers while the
-// current step's MFMAs run, optional split-K with partials reduced in a
+// double-buffered LDS (3 parts x 128 rows x 32 k per operand, the k pieces
+// of each row swizzled against bank conflicts), the next two steps' global
+// loads in registers while the current step's MFMAs run, optional split-K
+// with partials reduced in a
 // fixed order.  Workgroups that share an A tile are placed on the same XCD
 // (blockIdx % 8) so that its re-reads hit that die's L2.
 #include <hip/hip_bf16.h>
@@ -39,12 +39,23 @@ typedef float v2f __attribute__((ext_vector_type(2)));
 constexpr int TM = 128, TN = 128, TK = 32;
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kRowHalfs = 40;  // LDS row stride in BF16 elements (80 bytes)
+constexpr int kRowHalfs = 32;  // LDS row stride in BF16 elements (64 bytes, unpadded)
+// Position (in BF16 elements) of 16-byte k piece pc of tile row r in its LDS
+// row: the pieces are XOR-swizzled by (r / 2) mod 4, so that both the
+// staging stores (4 rows x 64 bytes per 16 lanes) and the MFMA operand reads
+// (16 rows at one k piece) hit distinct banks (measured on gfx950: no bank
+// conflicts, against 5 conflict cycles per LDS instruction with 80-byte
+// padded rows and 2-3 with other swizzles or paddings).
+__device__ __forceinline__ int xg_piece(int r, int pc) { return 8 * (pc ^ ((r >> 1) & 3)); }
 constexpr int kPieces = 2 * 3 * TM * (TK / 8);       // 16-byte pieces per K step (A and B)
 constexpr int kPer = kPieces / kThreads;             // 6 per thread
 constexpr int kOpHalfs = 3 * TM * kRowHalfs;         // BF16 elements per operand buffer
 
 __device__ __forceinline__ v8bf as_bf(const uint4& u) { return __builtin_bit_cast(v8bf, u); }
+
+// Workgroup barrier that orders LDS traffic only: __syncthreads() would also
+// wait for the staged loads of the next two steps.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 __device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((v2f){a, b}, v2bf));
@@ -127,35 +138,38 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
   const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
 
   // staging: piece e = tid + kThreads * q; operand e / (kPieces / 2), part,
-  // row and 16-byte k piece within the step
-  uint4 stg[kPer];
-  auto load_step = [&](int64_t k0) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + kThreads * q;
-      const int op = e / (kPieces / 2), ee = e % (kPieces / 2);
-      const int part = ee / (TM * 4), row = (ee % (TM * 4)) / 4, pc = ee % 4;
-      const int64_t gk = k0 + 8 * pc;
-      const __hip_bfloat16* base = op == 0 ? Ap + part * apstride : Bp + part * bpstride;
-      const int64_t gr = (op == 0 ? m0 : n0) + row;
-      const int64_t lim = op == 0 ? M : N;
-      // rows past the matrix and k pieces past the range read a valid
-      // address and are zeroed (K is a multiple of 8 in every use)
-      const bool ok = gr < lim && gk < ke;
-      const uint4 v = *reinterpret_cast<const uint4*>(base + (ok ? gr : 0) * ldk + (ok ? gk : 0));
-      stg[q] = ok ? v : make_uint4(0u, 0u, 0u, 0u);
-    }
-  };
-  auto store_step = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + kThreads * q;
-      const int op = e / (kPieces / 2), ee = e % (kPieces / 2);
-      const int part = ee / (TM * 4), row = (ee % (TM * 4)) / 4, pc = ee % 4;
-      __hip_bfloat16* dst = (op == 0 ? As[buf] : Bs[buf]) + (part * TM + row) * kRowHalfs + 8 * pc;
-      *reinterpret_cast<uint4*>(dst) = stg[q];
-    }
-  };
+  // row and 16-byte k piece within the step.  Two steps' pieces are in
+  // flight in registers (stgA, stgB alternate) while a third is multiplied
+  // from LDS: one step's products (≈0.6 µs of MFMA work per SIMD) do not
+  // cover an L2 round trip, two do.  Loads past the range read a valid
+  // address and are zeroed when stored to LDS, so no branch or select
+  // touches a loaded value before it is needed (either would make the
+  // compiler wait for the load there).
+#define LEV_XG_LOAD(STG, K0)                                                                          \
+  _Pragma("unroll") for (int q = 0; q < kPer; ++q) {                                                  \
+    const int e = tid + kThreads * q;                                                                 \
+    const int op = e / (kPieces / 2), ee = e % (kPieces / 2);                                         \
+    const int part = ee / (TM * 4), row = (ee % (TM * 4)) / 4, pc = ee % 4;                           \
+    const int64_t gk = (K0) + 8 * pc;                                                                 \
+    const __hip_bfloat16* base = op == 0 ? Ap + part * apstride : Bp + part * bpstride;               \
+    const int64_t gr = (op == 0 ? m0 : n0) + row;                                                     \
+    const int64_t lim = op == 0 ? M : N;                                                              \
+    const bool ok = gr < lim && gk < ke; /* else a valid address, zeroed at the store */              \
+    STG[q] = *reinterpret_cast<const uint4*>(base + (ok ? gr : 0) * ldk + (ok ? gk : 0));             \
+  }
+/* pieces outside the operand or the K range go to LDS as zeros (masked at
+   the store, where the data is needed anyway, so no earlier wait) */
+#define LEV_XG_STORE(STG, BUF, K0)                                                                    \
+  _Pragma("unroll") for (int q = 0; q < kPer; ++q) {                                                  \
+    const int e = tid + kThreads * q;                                                                 \
+    const int op = e / (kPieces / 2), ee = e % (kPieces / 2);                                         \
+    const int part = ee / (TM * 4), row = (ee % (TM * 4)) / 4, pc = ee % 4;                           \
+    const int64_t gk = (K0) + 8 * pc;                                                                 \
+    const int64_t gr = (op == 0 ? m0 : n0) + row;                                                     \
+    const bool ok = gr < (op == 0 ? M : N) && gk < ke;                                                \
+    __hip_bfloat16* dst = (op == 0 ? As[BUF] : Bs[BUF]) + (part * TM + row) * kRowHalfs + xg_piece(row, pc); \
+    *reinterpret_cast<uint4*>(dst) = ok ? STG[q] : make_uint4(0u, 0u, 0u, 0u);                        \
+  }
 
   v4f acc[4][2];
   double acc64[4][2][4];
@@ -168,57 +182,62 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
       for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
     }
 
-  int buf = 0;
-  if (kb < ke) {
-    load_step(kb);
-    store_step(0);
+  // B fragments of the wave's two column blocks (all parts), then per row
+  // block the A fragments and the six products, smallest first; the step's
+  // FP32 sums go into FP64
+#define LEV_XG_COMPUTE(BUF)                                                                           \
+  {                                                                                                   \
+    uint4 bq[2][3];                                                                                   \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j)                                                     \
+    _Pragma("unroll") for (int p = 0; p < 3; ++p)                                                     \
+      bq[j][p] = *reinterpret_cast<const uint4*>(Bs[BUF] + (p * TM + wn + 16 * j + (lane & 15)) * kRowHalfs + \
+                                                 xg_piece(wn + 16 * j + (lane & 15), lane >> 4));     \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                                   \
+      uint4 ap[3];                                                                                    \
+      _Pragma("unroll") for (int p = 0; p < 3; ++p)                                                   \
+        ap[p] = *reinterpret_cast<const uint4*>(As[BUF] + (p * TM + wm + 16 * i + (lane & 15)) * kRowHalfs + \
+                                                xg_piece(wm + 16 * i + (lane & 15), lane >> 4));      \
+      _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                                 \
+        v4f c = acc[i][j];                                                                            \
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[2]), as_bf(bq[j][0]), c, 0, 0, 0);      \
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][1]), c, 0, 0, 0);      \
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][2]), c, 0, 0, 0);      \
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][0]), c, 0, 0, 0);      \
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][1]), c, 0, 0, 0);      \
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][0]), c, 0, 0, 0);      \
+        acc[i][j] = c;                                                                                \
+      }                                                                                               \
+    }                                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i)                                                     \
+    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                                   \
+      _Pragma("unroll") for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];          \
+      acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};                                                            \
+    }                                                                                                 \
   }
+
+  // (the products are l h, m m, h l, m h, h m, h h: smallest first)
+  const int64_t nsteps = ke > kb ? (ke - kb + TK - 1) / TK : 0;
+  uint4 stgA[kPer], stgB[kPer];
+  LEV_XG_LOAD(stgA, kb)
+  LEV_XG_STORE(stgA, 0, kb)
+  LEV_XG_LOAD(stgB, kb + TK)
   __syncthreads();
-  for (int64_t k0 = kb; k0 < ke; k0 += TK) {
-    const bool more = k0 + TK < ke;  // uniform
-    if (more) load_step(k0 + TK);
-    // B fragments of the wave's two column blocks (all parts), then per row
-    // block the A fragments and the six products, smallest first
-    uint4 bq[2][3];
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int p = 0; p < 3; ++p)
-        bq[j][p] = *reinterpret_cast<const uint4*>(Bs[buf] + (p * TM + wn + 16 * j + (lane & 15)) * kRowHalfs +
-                                                   8 * (lane >> 4));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint4 ap[3];
-#pragma unroll
-      for (int p = 0; p < 3; ++p)
-        ap[p] = *reinterpret_cast<const uint4*>(As[buf] + (p * TM + wm + 16 * i + (lane & 15)) * kRowHalfs +
-                                                8 * (lane >> 4));
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        v4f c = acc[i][j];
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[2]), as_bf(bq[j][0]), c, 0, 0, 0);  // l h
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][1]), c, 0, 0, 0);  // m m
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][2]), c, 0, 0, 0);  // h l
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][0]), c, 0, 0, 0);  // m h
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][1]), c, 0, 0, 0);  // h m
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][0]), c, 0, 0, 0);  // h h
-        acc[i][j] = c;
-      }
-    }
-    // the step's FP32 sums into FP64
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
-        acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-      }
-    // the other buffer was last read before the previous barrier
-    if (more) store_step(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+  for (int64_t s = 0; s < nsteps; s += 2) {
+    // step s from buffer 0; step s + 1 is in stgB; step s + 2 into stgA
+    LEV_XG_LOAD(stgA, kb + (s + 2) * TK)
+    LEV_XG_COMPUTE(0)
+    LEV_XG_STORE(stgB, 1, kb + (s + 1) * TK)  // buffer 1 was last read before the previous barrier
+    lds_barrier();
+    if (s + 1 >= nsteps) break;  // uniform
+    // step s + 1 from buffer 1; step s + 2 is in stgA; step s + 3 into stgB
+    LEV_XG_LOAD(stgB, kb + (s + 3) * TK)
+    LEV_XG_COMPUTE(1)
+    LEV_XG_STORE(stgA, 0, kb + (s + 2) * TK)  // buffer 0 was last read before the barrier above
+    lds_barrier();
   }
+#undef LEV_XG_LOAD
+#undef LEV_XG_STORE
+#undef LEV_XG_COMPUTE
 
   // accumulator element v of lane l: row 4 (l / 16) + v, column l % 16 of
   // its 16 x 16 block
