@@ -45,6 +45,13 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// Sum over each 16-lane group, returned to every lane of the group.
+__device__ __forceinline__ double group16_sum(double x) {
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) x += __shfl_xor(x, o, 16);
+  return x;
+}
+
 // Round-robin pairing of dd (even) columns: round t, pair q -> (a, b).
 __device__ __forceinline__ void rr_pair(int dd, int t, int q, int& a, int& b) {
   auto pos = [&](int i) -> int { return i == 0 ? 0 : 1 + (i - 1 + t) % (dd - 1); };
@@ -165,36 +172,101 @@ __device__ __forceinline__ double f64(double x) { return x; }
 __device__ __forceinline__ double f64(float x) { return (double)x; }
 __device__ __forceinline__ double f64(__hip_bfloat16 x) { return (double)__bfloat162float(x); }
 
+// Four consecutive elements of a row from column c (c a multiple of 4,
+// c < d), widened to FP64; elements at or past d read as zero.  Rows are
+// 16-byte aligned with ld * sizeof(T) a multiple of 16, so a vector whose
+// first element is below d stays inside the row (FP64: each 16-byte half
+// is read only when its first element is below d).
+__device__ __forceinline__ void load4(const float* p, int64_t c, int64_t d, double (&a)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  a[0] = v.x;
+  a[1] = c + 1 < d ? (double)v.y : 0.0;
+  a[2] = c + 2 < d ? (double)v.z : 0.0;
+  a[3] = c + 3 < d ? (double)v.w : 0.0;
+}
+__device__ __forceinline__ void load4(const double* p, int64_t c, int64_t d, double (&a)[4]) {
+  const double2 lo = *reinterpret_cast<const double2*>(p);
+  const double2 hi = c + 2 < d ? *reinterpret_cast<const double2*>(p + 2) : make_double2(0.0, 0.0);
+  a[0] = lo.x;
+  a[1] = c + 1 < d ? lo.y : 0.0;
+  a[2] = hi.x;
+  a[3] = c + 3 < d ? hi.y : 0.0;
+}
+__device__ __forceinline__ void load4(const __hip_bfloat16* p, int64_t c, int64_t d, double (&a)[4]) {
+  const uint2 v = *reinterpret_cast<const uint2*>(p);
+  a[0] = (double)__uint_as_float(v.x << 16);
+  a[1] = c + 1 < d ? (double)__uint_as_float(v.x & 0xFFFF0000u) : 0.0;
+  a[2] = c + 2 < d ? (double)__uint_as_float(v.y << 16) : 0.0;
+  a[3] = c + 3 < d ? (double)__uint_as_float(v.y & 0xFFFF0000u) : 0.0;
+}
+
 // t_i = A[i,:] z - alpha u_i (or b_i when init), partial[g] = sum of t_i^2
-// over the workgroup's rows.  A group of gs lanes (a power of two) takes a
-// row, each lane a strided set of its elements.
+// over the workgroup's rows.  A 16-lane group takes a row: lane l of the
+// group reads elements 64 m + 4 l .. + 3 (one vector load per 64 columns,
+// four rows per wave-instruction, each 256 contiguous bytes), z comes from
+// LDS, and the row's sum is a four-step reduction over the group; two rows
+// per group are in flight at a time.
+constexpr int kGemvGroup = 16;
 template <typename T>
 __global__ __launch_bounds__(kGemvThreads) void lsqr_gemv_kernel(const T* __restrict__ A, int64_t n, int64_t d,
                                                                  int64_t ld, const double* __restrict__ z,
                                                                  const double* __restrict__ u,
                                                                  const double* __restrict__ b, int init,
                                                                  const double* __restrict__ st,
-                                                                 double* __restrict__ t, double* __restrict__ partial,
-                                                                 int gs) {
+                                                                 double* __restrict__ t, double* __restrict__ partial) {
   __shared__ double red[kGemvThreads / 64];
+  __shared__ __align__(16) double zs[1024 + 4];
   if (!init && st[4] != 0.0) return;
   const double alpha = init ? 0.0 : st[0];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int grp = lane / gs, gl = lane % gs, per_wave = 64 / gs;
+  const int gl = lane % kGemvGroup;
+  const int row_slot = threadIdx.x / kGemvGroup;  // 0 .. 15 in the workgroup
+  constexpr int kSlots = kGemvThreads / kGemvGroup;
   const int64_t rows_per_group = (n + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_group, r1 = std::min<int64_t>(n, r0 + rows_per_group);
-  double sq = 0.0;
-  for (int64_t i = r0 + wave * per_wave + grp; i < r1; i += (int64_t)(kGemvThreads / 64) * per_wave) {
+  if (!init)
+    for (int64_t c = threadIdx.x; c < d; c += kGemvThreads) zs[c] = z[c];
+  __syncthreads();
+  const int nm = (int)((d + 63) / 64);
+  auto row_dot = [&](int64_t i) -> double {
     double acc = 0.0;
-    if (!init) {
-      const T* row = A + i * ld;
-      for (int64_t c = gl; c < d; c += gs) acc = fma(f64(row[c]), z[c], acc);
+    for (int m = 0; m < nm; ++m) {
+      const int64_t c = 64 * m + 4 * gl;
+      if (c < d) {
+        double a[4];
+        load4(A + i * ld + c, c, d, a);
+        const double2 z0 = *reinterpret_cast<const double2*>(zs + c);
+        const double2 z1 = *reinterpret_cast<const double2*>(zs + c + 2);
+        acc = fma(a[0], z0.x, acc);
+        acc = fma(a[1], z0.y, acc);
+        acc = fma(a[2], c + 2 < d ? z1.x : 0.0, acc);
+        acc = fma(a[3], c + 3 < d ? z1.y : 0.0, acc);
+      }
     }
-    for (int o = gs / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, gs);
-    const double ti = init ? b[i] : acc - alpha * u[i];
-    if (gl == 0) {
-      t[i] = ti;
-      sq = fma(ti, ti, sq);
+    return acc;
+  };
+  double sq = 0.0;
+  for (int64_t i0 = r0; i0 < r1; i0 += 2 * kSlots) {
+    const int64_t ia = i0 + row_slot, ib = ia + kSlots;
+    double sa = 0.0, sb = 0.0;
+    if (!init) {
+      if (ia < r1) sa = row_dot(ia);
+      if (ib < r1) sb = row_dot(ib);
+      // sum over the 16 lanes of the group (lane 15 of each 16-lane row ends with it)
+      sa = group16_sum(sa);
+      sb = group16_sum(sb);
+    }
+    if (gl == kGemvGroup - 1) {
+      if (ia < r1) {
+        const double ti = init ? b[ia] : sa - alpha * u[ia];
+        t[ia] = ti;
+        sq = fma(ti, ti, sq);
+      }
+      if (ib < r1) {
+        const double ti = init ? b[ib] : sb - alpha * u[ib];
+        t[ib] = ti;
+        sq = fma(ti, ti, sq);
+      }
     }
   }
   sq = wave_sum(sq);
@@ -208,13 +280,19 @@ __global__ __launch_bounds__(kGemvThreads) void lsqr_gemv_kernel(const T* __rest
 }
 
 // beta = sqrt(sum of the gemv partials); u = t / beta; partial_g[c] = sum over
-// the workgroup's rows of u_i A[i][c].  Thread c of a row-slice takes column c.
+// the workgroup's rows of u_i A[i][c].  Per 256-column slice, lane l of a
+// wave takes columns 4 l .. 4 l + 3 (one vector load per row), the four
+// waves take every fourth row with eight rows in flight per lane, and the
+// waves' sums are added in LDS in wave order (fixed: deterministic bits).
+constexpr int kAtvCols = 256;
+constexpr int kAtvRows = 8;
 template <typename T>
 __global__ __launch_bounds__(kGemvThreads) void lsqr_atv_kernel(const T* __restrict__ A, int64_t n, int64_t d,
                                                                 int64_t ld, const double* __restrict__ t,
                                                                 const double* __restrict__ gpart, int ggroups,
                                                                 double* __restrict__ st, int init,
                                                                 double* __restrict__ u, double* __restrict__ partial) {
+  __shared__ double red[kGemvThreads / 64][kAtvCols];
   if (!init && st[4] != 0.0) return;
   double s = 0.0;
   for (int g = 0; g < ggroups; ++g) s += gpart[g];
@@ -230,13 +308,45 @@ __global__ __launch_bounds__(kGemvThreads) void lsqr_atv_kernel(const T* __restr
   const int64_t rows_per_group = (n + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_group, r1 = std::min<int64_t>(n, r0 + rows_per_group);
   for (int64_t i = r0 + threadIdx.x; i < r1; i += kGemvThreads) u[i] = t[i] * inv;
-  // columns: slices of kGemvThreads, rows in order
-  for (int64_t c0 = 0; c0 < d; c0 += kGemvThreads) {
-    const int64_t c = c0 + threadIdx.x;
-    double acc = 0.0;
-    if (c < d)
-      for (int64_t i = r0; i < r1; ++i) acc = fma(t[i] * inv, f64(A[i * ld + c]), acc);
-    if (c < d) partial[(int64_t)blockIdx.x * d + c] = acc;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int kW = kGemvThreads / 64;
+  for (int64_t c0 = 0; c0 < d; c0 += kAtvCols) {
+    const int64_t c = c0 + 4 * lane;
+    const bool live = c < d;
+    const int64_t cl = live ? c : 0;  // lanes past d read column 0 and add nothing
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = r0 + wave;
+    for (; i + kW * (kAtvRows - 1) < r1; i += kW * kAtvRows) {
+      double a[kAtvRows][4];
+      double ui[kAtvRows];
+#pragma unroll
+      for (int q = 0; q < kAtvRows; ++q) {
+        load4(A + (i + kW * q) * ld + cl, cl, d, a[q]);
+        ui[q] = live ? t[i + kW * q] * inv : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kAtvRows; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[e] = fma(ui[q], a[q][e], acc[e]);
+    }
+    for (; i < r1; i += kW) {
+      double a[4];
+      load4(A + i * ld + cl, cl, d, a);
+      const double ui = live ? t[i] * inv : 0.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] = fma(ui, a[e], acc[e]);
+    }
+    __syncthreads();  // the previous slice's sums have been read
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wave][4 * lane + e] = acc[e];
+    __syncthreads();
+    const int64_t cc = c0 + threadIdx.x;
+    if (threadIdx.x < kAtvCols && cc < d) {
+      double v = red[0][threadIdx.x];
+#pragma unroll
+      for (int w = 1; w < kW; ++w) v += red[w][threadIdx.x];
+      partial[(int64_t)blockIdx.x * d + cc] = v;
+    }
   }
 }
 
@@ -342,16 +452,14 @@ hipError_t lsqr_typed(const void* Av, int64_t n, int64_t d, int64_t ld, const do
   double* w = v + d;
   double* y = w + d;
   double* z = y + d;
-  int gs = 1;
-  while (gs < 64 && gs < d) gs <<= 1;
   hipError_t e = launch_fill_zero(st, 8 * sizeof(double), s);
   if (e != hipSuccess) return e;
   // beta_1 u_1 = b; alpha_1 v_1 = M^T u_1
-  lsqr_gemv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, z, u, b, 1, st, t, gpart, gs);
+  lsqr_gemv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, z, u, b, 1, st, t, gpart);
   lsqr_atv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, t, gpart, groups, st, 1, u, apart);
   lsqr_step_kernel<<<1, kStepThreads, 0, s>>>(d, N, apart, groups, st, v, w, y, z, hist, 0, 1);
   for (int64_t it = 0; it < iters; ++it) {
-    lsqr_gemv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, z, u, b, 0, st, t, gpart, gs);
+    lsqr_gemv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, z, u, b, 0, st, t, gpart);
     lsqr_atv_kernel<T><<<groups, kGemvThreads, 0, s>>>(A, n, d, ld, t, gpart, groups, st, 0, u, apart);
     lsqr_step_kernel<<<1, kStepThreads, 0, s>>>(d, N, apart, groups, st, v, w, y, z, hist, it, 0);
   }
