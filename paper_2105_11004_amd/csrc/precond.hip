@@ -365,9 +365,21 @@ __global__ __launch_bounds__(kStepThreads) void lsqr_step_kernel(int64_t d, cons
     return;
   }
   const int di = (int)d;
+  // g = the sum of the workgroups' partials (eight independent partial sums
+  // per column, so that eight loads are in flight, added in a fixed order)
+  constexpr int kU = 8;
   for (int c = threadIdx.x; c < di; c += kStepThreads) {
+    double sp[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) sp[u] = 0.0;
+    int gg = 0;
+    for (; gg + kU <= groups; gg += kU)
+#pragma unroll
+      for (int u = 0; u < kU; ++u) sp[u] += partial[(int64_t)(gg + u) * d + c];
+    for (; gg < groups; ++gg) sp[0] += partial[(int64_t)gg * d + c];
     double s = 0.0;
-    for (int gg = 0; gg < groups; ++gg) s += partial[(int64_t)gg * d + c];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s += sp[u];
     g[c] = s;
   }
   __syncthreads();
@@ -375,8 +387,17 @@ __global__ __launch_bounds__(kStepThreads) void lsqr_step_kernel(int64_t d, cons
   // q = N^T g - beta v
   double sq = 0.0;
   for (int c = threadIdx.x; c < di; c += kStepThreads) {
+    double sp[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) sp[u] = 0.0;
+    int i = 0;
+    for (; i + kU <= di; i += kU)
+#pragma unroll
+      for (int u = 0; u < kU; ++u) sp[u] = fma(N[(int64_t)(i + u) * d + c], g[i + u], sp[u]);
+    for (; i < di; ++i) sp[0] = fma(N[(int64_t)i * d + c], g[i], sp[0]);
     double s = 0.0;
-    for (int i = 0; i < di; ++i) s = fma(N[(int64_t)i * d + c], g[i], s);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) s += sp[u];
     const double qc = init ? s : s - beta * v[c];
     q[c] = qc;
     sq = fma(qc, qc, sq);
@@ -407,13 +428,19 @@ __global__ __launch_bounds__(kStepThreads) void lsqr_step_kernel(int64_t d, cons
       w[cc] = vn - (theta / rho) * w[cc];
     }
     v[cc] = vn;
+    g[cc] = vn;  // (g is free again: v in LDS for z below)
   }
   __syncthreads();
-  // z = N v for the next gemv
-  for (int r = threadIdx.x; r < di; r += kStepThreads) {
-    double acc = 0.0;
-    for (int cc = 0; cc < di; ++cc) acc = fma(N[(int64_t)r * d + cc], v[cc], acc);
-    z[r] = acc;
+  // z = N v for the next gemv: a wave per row, its lanes along the row
+  // (coalesced), then a wave sum
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = wv; r < di; r += kStepThreads / 64) {
+      double acc = 0.0;
+      for (int cc = lane; cc < di; cc += 64) acc = fma(N[(int64_t)r * d + cc], g[cc], acc);
+      acc = wave_sum(acc);
+      if (lane == 0) z[r] = acc;
+    }
   }
   if (threadIdx.x == 0) {
     st[0] = alpha;
