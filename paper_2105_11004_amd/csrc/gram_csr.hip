@@ -8,8 +8,12 @@
 // kGS doubles so that the rows of one atomic instruction spread over the
 // banks) and one chunk of rows.  A wave takes one row at a time: column ids
 // are sorted within a row, so the entries in block I and in block J are two
-// contiguous runs, found by counting ids below the block bounds; the lanes
-// hold the runs (up to 128 entries each, two per lane) and, for each entry p
+// contiguous runs, found by counting ids below the block bounds (a wave
+// walks 64 rows at a time with their extents in one load, and a row of at
+// most 64 entries is read once, the next row's read in flight, and its
+// pairs of run entries go one per lane, 64 per atomic instruction); a longer
+// row's lanes hold its runs (up to 128 entries each, two per lane) and, for
+// each entry p
 // of run I in turn (its id and value read from the holding lane), add
 // a_ip a_iq for the entries q of run J, one per lane, by LDS atomic adds.
 // On a diagonal tile only q >= p is added (the upper triangle, mirrored when
@@ -88,36 +92,10 @@ __global__ __launch_bounds__(kGThreads) void gram_csr_kernel(const T* __restrict
   const int wave = threadIdx.x >> 6;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t r1 = std::min<int64_t>(n, r0 + rows_per_chunk);
-  for (int64_t i = r0 + wave; i < r1; i += kGWaves) {
-    // row extent clamped to [0, nnz] (a malformed row_ptr gives a wrong B, no stray access)
-    const int64_t s = std::min<int64_t>(std::max<int64_t>(row_ptr[i], 0), nnz);
-    const int64_t e = std::max<int64_t>(s, std::min<int64_t>(std::max<int64_t>(row_ptr[i + 1], 0), nnz));
-    // positions of the runs [I0, Iend) and [J0, Jend) among the row's sorted ids
-    int loI = 0, hiI = 0, loJ = 0, hiJ = 0;
-    for (int64_t c0 = s; c0 < e; c0 += 64) {
-      const int64_t p = c0 + lane;
-      const int32_t c = p < e ? col_idx[p] : INT32_MAX;
-      loI += __popcll(__ballot(c < I0));
-      hiI += __popcll(__ballot(c < Iend));
-      loJ += __popcll(__ballot(c < J0));
-      hiJ += __popcll(__ballot(c < Jend));
-    }
-    const int lI = std::min(hiI - loI, kGT), lJ = std::min(hiJ - loJ, kGT);
-    if (lI <= 0 || lJ <= 0) continue;
-    // the runs in registers: entry t of a run is held by lane t % 64, slot t / 64
-    int32_t cI[2], cJ[2];
-    double vI[2], vJ[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int t = lane + 64 * h;
-      const int64_t pi = s + loI + t, pj = s + loJ + t;
-      cI[h] = t < lI ? col_idx[pi] - I0 : 0;
-      vI[h] = t < lI ? val_f64(vals[pi]) : 0.0;
-      cJ[h] = t < lJ ? col_idx[pj] - J0 : -1;
-      vJ[h] = t < lJ ? val_f64(vals[pj]) : 0.0;
-      // ids outside the block (an unsorted row) are dropped
-      if ((uint32_t)cJ[h] >= (uint32_t)kGT) cJ[h] = -1;
-    }
+  // The pairs of one row with its entries in registers: entry t (t < lI of
+  // run I, t < lJ of run J) held by lane t % 64, slot t / 64.
+  auto add_pairs = [&](const int32_t (&cI)[2], const double (&vI)[2], const int32_t (&cJ)[2],
+                       const double (&vJ)[2], int lI) {
     for (int p = 0; p < lI; ++p) {
       const int h = p >> 6, l = p & 63;
       const int32_t cp = __builtin_amdgcn_readlane(h ? cI[1] : cI[0], l);
@@ -129,6 +107,92 @@ __global__ __launch_bounds__(kGThreads) void gram_csr_kernel(const T* __restrict
         // diagonal tile: the upper triangle (q >= p, i.e. c_q >= c_p) only
         if (cJ[q] >= 0 && (!diag || cJ[q] >= cp)) atomicAdd(row + cJ[q], vp * vJ[q]);
       }
+    }
+  };
+  // A wave takes 64 consecutive rows at a time: their extents in one load
+  // (lane j: row i0 + j), then row by row.  A row of at most 64 entries is
+  // loaded once (ids and values, one per lane, the next row's load in
+  // flight while this row's pairs are added) and its pairs of run entries
+  // are dealt out one per lane; longer rows count and load their runs from
+  // memory in 64-entry pieces.
+  for (int64_t i0 = r0 + 64 * (int64_t)wave; i0 < r1; i0 += 64 * (int64_t)kGWaves) {
+    const int nr = (int)std::min<int64_t>(64, r1 - i0);
+    // row extents clamped to [0, nnz] and made non-decreasing (a malformed
+    // row_ptr gives a wrong B, no stray access)
+    int64_t rs = lane < nr ? std::min<int64_t>(std::max<int64_t>(row_ptr[i0 + lane], 0), nnz) : nnz;
+    int64_t re = lane < nr ? std::min<int64_t>(std::max<int64_t>(row_ptr[i0 + lane + 1], 0), nnz) : nnz;
+    re = std::max(re, rs);
+    auto load_short = [&](int j, int32_t& c, double& v) {
+      // entry `lane` of row j when the row has at most 64 entries
+      const int64_t s = ((int64_t)__builtin_amdgcn_readlane((int)(rs >> 32), j) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)rs, j);
+      const int64_t e = ((int64_t)__builtin_amdgcn_readlane((int)(re >> 32), j) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)re, j);
+      const bool ok = e - s <= 64 && s + lane < e;
+      c = ok ? col_idx[s + lane] : INT32_MAX;
+      v = ok ? val_f64(vals[s + lane]) : 0.0;
+    };
+    int32_t nc;
+    double nv;
+    load_short(0, nc, nv);
+    for (int j = 0; j < nr; ++j) {
+      const int32_t c = nc;
+      const double v = nv;
+      if (j + 1 < nr) load_short(j + 1, nc, nv);
+      const int64_t s = ((int64_t)__builtin_amdgcn_readlane((int)(rs >> 32), j) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)rs, j);
+      const int64_t e = ((int64_t)__builtin_amdgcn_readlane((int)(re >> 32), j) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane((int)re, j);
+      const int64_t len = e - s;
+      if (len == 0) continue;
+      if (len <= 64) {
+        // positions of the runs [I0, Iend) and [J0, Jend) among the sorted ids
+        const int loI = __popcll(__ballot(c < I0)), hiI = __popcll(__ballot(c < Iend));
+        const int loJ = __popcll(__ballot(c < J0)), hiJ = __popcll(__ballot(c < Jend));
+        const int lI = hiI - loI, lJ = hiJ - loJ;
+        if (lI <= 0 || lJ <= 0) continue;
+        // one lane per pair (p, q) of the two runs, 64 pairs per step: the
+        // entries come from their lanes by shuffles that every lane takes
+        // part in
+        const int np = lI * lJ;
+        for (int k0 = 0; k0 < np; k0 += 64) {
+          const int k = k0 + lane;
+          const int pp = k / lJ, qq = k - pp * lJ;
+          const bool ok = k < np;
+          const int srcp = ok ? loI + pp : 0, srcq = ok ? loJ + qq : 0;
+          const int32_t cp = __shfl(c, srcp, 64) - I0, cq = __shfl(c, srcq, 64) - J0;
+          const double vp = __shfl(v, srcp, 64), vq = __shfl(v, srcq, 64);
+          // ids outside the blocks (an unsorted row) are dropped; on a
+          // diagonal tile only the upper triangle (c_q >= c_p) is added
+          if (ok && (uint32_t)cp < (uint32_t)kGT && (uint32_t)cq < (uint32_t)kGT && (!diag || cq >= cp))
+            atomicAdd(tile + cp * kGS + cq, vp * vq);
+        }
+        continue;
+      }
+      int32_t cI[2], cJ[2];
+      double vI[2], vJ[2];
+      int loI = 0, hiI = 0, loJ = 0, hiJ = 0;
+      for (int64_t c0 = s; c0 < e; c0 += 64) {
+        const int64_t p = c0 + lane;
+        const int32_t cc = p < e ? col_idx[p] : INT32_MAX;
+        loI += __popcll(__ballot(cc < I0));
+        hiI += __popcll(__ballot(cc < Iend));
+        loJ += __popcll(__ballot(cc < J0));
+        hiJ += __popcll(__ballot(cc < Jend));
+      }
+      const int lI = std::min(hiI - loI, kGT), lJ = std::min(hiJ - loJ, kGT);
+      if (lI <= 0 || lJ <= 0) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = lane + 64 * h;
+        const int64_t pi = s + loI + t, pj = s + loJ + t;
+        cI[h] = t < lI ? col_idx[pi] - I0 : 0;
+        vI[h] = t < lI ? val_f64(vals[pi]) : 0.0;
+        cJ[h] = t < lJ ? col_idx[pj] - J0 : -1;
+        vJ[h] = t < lJ ? val_f64(vals[pj]) : 0.0;
+        if ((uint32_t)cJ[h] >= (uint32_t)kGT) cJ[h] = -1;
+      }
+      add_pairs(cI, vI, cJ, vJ, lI);
     }
   }
   __syncthreads();
