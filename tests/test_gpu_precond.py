@@ -96,6 +96,34 @@ def test_lsqr_on_preconditioned_operator(gpu, dtype):
     assert np.linalg.norm(x - xs) <= 1e-6 * np.linalg.norm(xs)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("n,d", [(3001, 37), (4099, 257)])
+def test_lsqr_ragged_columns(gpu, dtype, n, d):
+    """The passes' column layout at d not a multiple of 4 (the last vector
+    of a row half past d) and past one 256-column slice, with a row count
+    that leaves the workgroups' row ranges ragged.  Before convergence an
+    LSQR iterate moves by ~1e-8 under a rounding-level change of N (the
+    oracle alone shows it), so the comparison is at convergence (80 steps
+    at kappa(A N) ~ 5): the solution against the oracle's and the
+    least-squares one, the residual history against the oracle's."""
+    rng = np.random.default_rng(n + d)
+    A = rng.standard_normal((n, d)) * rng.uniform(0.2, 5.0, d)
+    At = _padded(A, dtype, gpu)
+    Ah = At.cpu().to(torch.float64).numpy()
+    b = rng.standard_normal(n)
+    N, k = api.lev_precondition(At, 9, 4096, 2 * d, 1e-10, "qr")
+    assert int(k.item()) == d
+    x, hist = api.lev_lsqr(At, N, torch.from_numpy(b).to(gpu), 80)
+    x = x.cpu().numpy()
+    xo, ho = P.preconditioned_lsqr(Ah, N.cpu().numpy(), b, 80)
+    xs = np.linalg.lstsq(Ah, b, rcond=None)[0]
+    rel = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    _log(dtype, n, d, "lsqr ragged vs oracle", rel, "vs lstsq", np.linalg.norm(x - xs) / np.linalg.norm(xs))
+    assert rel < 1e-9
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    np.testing.assert_allclose(hist.cpu().numpy(), ho, rtol=1e-6)
+
+
 def test_lsqr_edge_cases(gpu):
     """b = 0 stops at once with x = 0; zero steps give x = 0; the QR
     preconditioner of a rank-deficient A gives a least-squares solution."""
