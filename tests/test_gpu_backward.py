@@ -40,6 +40,11 @@ def _compare(gpu_grad, ref_grad, bar):
     (torch.float32, 8192 + 3, 48, 16, 512, 96, 1e-5),
     (torch.float32, 5000 + 7, 80, 64, 1024, 160, 1e-5),
     (torch.float64, 1000, 20, 7, 100, 40, 1e-9),
+    # the register-resident FP32 passes with one, two and three 16-column
+    # blocks of Z_full
+    (torch.float32, 4096 + 9, 64, 16, 1024, 128, 1e-5),
+    (torch.float32, 3000 + 1, 96, 32, 1024, 192, 1e-5),
+    (torch.float32, 6000 + 11, 128, 40, 2048, 256, 1e-5),
 ])
 def test_backward_matches_reference_gradient(gpu, dtype, n, d, k, r_cs, m, bar):
     _log("bwd", dtype, n, d, k)
