@@ -472,9 +472,9 @@ lev_status cholqr2(int64_t m, int64_t d, const double* X, const double* Rc, cons
 // Algorithm 4, steps 2-3: perm, R (sign-normalised, positive diagonal) and
 // the cutoff rank of the column-pivoted QR of A~.  For zeta >= kZetaGram the
 // pivoted Cholesky of the Gram decides alone; below it (rf != null) the
-// refined path of rrqr.hip: round 1 to kZetaGram, Cholesky QR twice of those
-// columns, the rest projected off them twice, round 2 on the residual's Gram
-// with the cutoff zeta * R_00 of round 1, Cholesky QR twice of the round-2
+// refined path of rrqr.hip: stage 1 to kZetaGram, Cholesky QR twice of those
+// columns, the rest projected off them twice, stage 2 on the residual's Gram
+// with the cutoff zeta * R_00 of stage 1, Cholesky QR twice of the stage-2
 // columns, R's rows as Q^T X.
 lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, const RankBufs& b,
                         int32_t* perm, double* R, int64_t* rank, hipStream_t s, RefineBufs* rf = nullptr) {
@@ -487,7 +487,7 @@ lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, con
   int32_t* err = b.pc.err;
   f.stf.err = err;
   f.st2.err = err;
-  // round 1: the columns the Gram resolves
+  // stage 1: the columns the Gram resolves
   LEV_TRY(pivchol_into(b.B, d, kZetaGram, b.pc, f.r1, f.perm1, f.R1, b.partial, s));
   LEV_HIP(lev::launch_gather_split(m, d, f.perm1, f.r1, At, f.X1, f.X2, s));
   LEV_TRY(cholqr2(m, d, f.X1, f.R1, f.r1, f, f.Q, err, s));
@@ -498,10 +498,10 @@ lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, con
   LEV_TRY(gemm_ab(m, d, d, -1.0, f.Q, d, 1, f.W2, d, 1, 1.0, f.X2, f.partial, s));
   LEV_TRY(gemm_ab(d, d, m, 1.0, f.Q, 1, d, f.X1, d, 1, 0.0, f.Rtop, f.partial, s));
   LEV_HIP(lev::launch_add2(d * d, f.Rtop, f.W1, f.W2, s));
-  // round 2: pivoting on the residual's Gram, cutoff zeta * R_00 of round 1
+  // stage 2: pivoting on the residual's Gram, cutoff zeta * R_00 of stage 1
   LEV_TRY(gemm_ab(d, d, m, 1.0, f.X2, 1, d, f.X2, d, 1, 0.0, f.Bq, f.partial, s));
   LEV_TRY(pivchol_into(f.Bq, d, zeta, f.st2, f.r2, f.perm2, f.R2, b.partial, s, 0, b.pc.r00));
-  LEV_HIP(lev::launch_gather_split(m, d, f.perm2, f.r2, f.X2, f.X1, nullptr, s));  // X1 <- the round-2 columns
+  LEV_HIP(lev::launch_gather_split(m, d, f.perm2, f.r2, f.X2, f.X1, nullptr, s));  // X1 <- the stage-2 columns
   LEV_TRY(cholqr2(m, d, f.X1, f.R2, f.r2, f, f.Q, err, s));
   LEV_TRY(gemm_ab(d, d, m, 1.0, f.Q, 1, d, f.X2, d, 1, 0.0, f.Rbot, f.partial, s));
   LEV_HIP(lev::launch_rrqr_assemble(d, f.perm1, f.r1, f.perm2, f.r2, f.Rtop, f.Rbot, perm, R, rank, s));

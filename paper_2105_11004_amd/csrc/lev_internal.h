@@ -261,7 +261,7 @@ hipError_t launch_gather_split(int64_t m, int64_t d, const int32_t* perm, const 
                                double* X1, double* X2, hipStream_t s);
 // dst += a + b
 hipError_t launch_add2(int64_t n, double* dst, const double* a, const double* b, hipStream_t s);
-// Final perm, R and rank from round 1 (perm1, r1, rows Rtop) and round 2
+// Final perm, R and rank from stage 1 (perm1, r1, rows Rtop) and stage 2
 // (perm2 as positions of perm1, r2, rows Rbot); see rrqr.hip.
 hipError_t launch_rrqr_assemble(int64_t d, const int32_t* perm1, const int64_t* rank1, const int32_t* perm2,
                                 const int64_t* rank2, const double* Rtop, const double* Rbot, int32_t* perm_out,

@@ -7,13 +7,13 @@
 // only while the residual column norms stay well above sqrt(u) * R_00: B is
 // rounded at u * R_00^2, so below that the Schur diagonal is noise.  The
 // refined path therefore runs the Gram pivoting only down to a coarse cutoff
-// tau (round 1, r1 columns), orthonormalises those columns accurately
+// tau (stage 1, r1 columns), orthonormalises those columns accurately
 // (Cholesky QR twice: Q1 with Q1^T Q1 = I to rounding), projects them out of
 // the other columns twice (block Gram-Schmidt with reorthogonalisation), and
-// pivots again on the Gram of that explicit residual (round 2, r2 more
+// pivots again on the Gram of that explicit residual (stage 2, r2 more
 // columns), whose rounding is relative to the residual's own norm, not to
 // R_00.  The rows of R come from Q^T X (accurate to rounding relative to
-// ||X||): R = [Q1^T X; Q2^T X2], Q2 from Cholesky QR twice of the round-2
+// ||X||): R = [Q1^T X; Q2^T X2], Q2 from Cholesky QR twice of the stage-2
 // columns.  In exact arithmetic every step equals the corresponding step of
 // Householder QRCP (same pivots, same R with positive diagonal), because
 // QRCP's trailing matrix after r1 steps has the Gram of the projected
@@ -57,9 +57,9 @@ __global__ void add2_kernel(int64_t n, double* __restrict__ dst, const double* _
 }
 
 // Final permutation, factor and rank from the two rounds.
-//  perm1: round 1 (pivots 0..r1-1, then the other columns); positions of
+//  perm1: stage 1 (pivots 0..r1-1, then the other columns); positions of
 //         perm1 are the column space of X = A~[:, perm1], Rtop and Rbot.
-//  perm2: round 2 pivots as positions in that space (0..r2-1 valid).
+//  perm2: stage 2 pivots as positions in that space (0..r2-1 valid).
 //  perm_out[j]: perm1[j] (j < r1), perm1[perm2[j - r1]] (r1 <= j < r), then
 //  the unselected original columns ascending.
 //  R_out[j][t] (t >= j): Rtop[j][pos(t)] for j < r1, Rbot[j - r1][pos(t)] for

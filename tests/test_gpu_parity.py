@@ -260,7 +260,7 @@ def test_estimate_fp64_wide_blocked_solve(gpu, n, d, rank, k):
     positions with the rank on the device; ranks inside the first and second
     block leave later blocks past the rank (zero rows of Z).  zeta = 1e-10,
     the paper's FP64 cutoff: exactly rank-deficient A is decided by the
-    refined path (round 2 on the explicit residual)."""
+    refined path (stage 2 on the explicit residual)."""
     _log("wide solve", n, d, rank, k)
     rng = np.random.default_rng(d + rank)
     A = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, d))
