@@ -74,6 +74,32 @@ def test_preconditioner_rank_deficient_and_wide(gpu):
         api.lev_precondition(torch.from_numpy(A).to(gpu), 4, 8192, 600, 1e-10, "svd")
 
 
+@pytest.mark.parametrize("method", ["svd", "qr"])
+def test_preconditioner_csr(gpu, method):
+    """CSR input (power-law rows, 8 zero columns, so k = 88 of 96): the
+    sketch goes through the CSR pass 1; k, kappa(A N) and N N^T against the
+    oracle's on the same scipy matrix (FP32 values, exact in FP64)."""
+    import scipy.sparse as sp
+    n, d, zc = 30000 + 7, 96, 8
+    S = W.sparse_power_law(n, d, zc, 41).to_scipy()
+    S.sort_indices()
+    vals = S.data.astype(np.float32)
+    A = api.Csr(torch.from_numpy(S.indptr.astype(np.int64)).to(gpu), torch.from_numpy(S.indices.astype(np.int32)).to(gpu),
+                torch.from_numpy(vals).to(gpu), n, d)
+    Sh = sp.csr_matrix((vals.astype(np.float64), S.indices, S.indptr), shape=(n, d))
+    N, k = api.lev_precondition(A, 13, 8192, 2 * d, 1e-10, method)
+    N, k = N.cpu().numpy(), int(k.item())
+    No, ko = P.count_gauss_precondition(Sh, 13, 8192, 2 * d, 1e-10, method)
+    assert k == ko == d - zc
+    assert np.all(N[:, k:] == 0)
+    Ad = Sh.toarray()
+    kg, ko_ = np.linalg.cond(Ad @ N[:, :k]), np.linalg.cond(Ad @ No)
+    _log("csr", method, "kappa(AN)", kg, ko_)
+    assert kg < 20 and abs(kg - ko_) <= 1e-6 * ko_
+    G, Go = N[:, :k] @ N[:, :k].T, No @ No.T
+    assert np.linalg.norm(G - Go) <= 1e-9 * np.linalg.norm(Go)
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
 def test_lsqr_on_preconditioned_operator(gpu, dtype):
     """LSQR on A N: the GPU's iterates against the oracle's recurrences run
