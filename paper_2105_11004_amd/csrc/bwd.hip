@@ -500,7 +500,14 @@ __global__ __launch_bounds__((64 * KB * gram_streams<KB, NJ>()), (KB * gram_stre
     for (int e = 0; e < 4; ++e) cacc[q][e] = v4f{0.f, 0.f, 0.f, 0.f};
 
   const int64_t ntiles = (n + 15) / 16;
-  for (int64_t tile = (int64_t)stream * gridDim.x + blockIdx.x; tile < ntiles; tile += (int64_t)gridDim.x * S) {
+  // The KB waves of a stream read the same tile; a barrier per round keeps
+  // them (and the streams) within one tile of each other, so the tile is
+  // fetched from HBM once and found in L2 by the others (drifting apart,
+  // each wave fetched its own copy: 2.8x the bytes of A).  The trip count
+  // is the workgroup's, the same for every wave.
+  for (int64_t t0 = blockIdx.x; t0 < ntiles; t0 += (int64_t)gridDim.x * S) {
+    const int64_t tile = t0 + (int64_t)stream * gridDim.x;
+    if (tile < ntiles) {
     // the tile's pieces, row i16 in the lanes: 16 j + 4 g .. + 3
     const int64_t row = tile * 16 + i16;
     const float* rp = A + (row < n ? row : 0) * ld + 4 * g;
@@ -551,6 +558,8 @@ __global__ __launch_bounds__((64 * KB * gram_streams<KB, NJ>()), (KB * gram_stre
         }
       }
     }
+    }
+    __builtin_amdgcn_s_barrier();
   }
   // C[64 q + 4 i16 + e][16 nb + 4 g + v] = cacc[q][e][v]; streams add in order
   __syncthreads();  // every wave is done with zs
