@@ -572,7 +572,12 @@ def precondition_report(steps: int) -> dict:
         t_ls = timed(lambda: api.lev_lsqr(A, N, b, 40), max(2, steps // 4))
         x, hist = api.lev_lsqr(A, N, b, 40)
         per_step = t_ls / 40
-        timing[name] = {"precondition_ms": t_pre, "lsqr_40_steps_ms": t_ls, "lsqr_ms_per_step": per_step,
+        if dd <= 128:
+            t_svd = timed(lambda: api.lev_precondition(A, 1, rc, mm, 1e-10, "svd"), max(2, steps // 4))
+        else:
+            t_svd = None
+        timing[name] = {"precondition_ms": t_pre, "precondition_svd_ms": t_svd,
+                        "lsqr_40_steps_ms": t_ls, "lsqr_ms_per_step": per_step,
                         "lsqr_hbm_gbs": 2 * A.numel() * A.element_size() / (per_step * 1e-3) / 1e9,
                         "residual_estimate_first_last": [float(hist[0]), float(hist[-1])]}
     out["timing"] = timing

@@ -60,10 +60,14 @@ __device__ __forceinline__ void rr_pair(int dd, int t, int q, int& a, int& b) {
 }
 
 // W (LDS, column-major, d x d) = R; V (global, column-major) = I.
+// VL: V kept in LDS behind W (when both fit), so a rotation's update of V
+// costs LDS round trips instead of global ones (the rounds of a sweep are
+// serial, so that latency is paid 59 times a sweep at d = 60).
+template <bool VL>
 __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(int64_t d, const double* __restrict__ R,
                                                                  const int64_t* __restrict__ rank,
                                                                  const int32_t* __restrict__ perm, double zeta,
-                                                                 double* __restrict__ V, double* __restrict__ N,
+                                                                 double* __restrict__ Vg, double* __restrict__ N,
                                                                  int64_t* __restrict__ k_out) {
   extern __shared__ double W[];
   __shared__ int rotated;
@@ -71,6 +75,7 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(int64_t d, cons
   __shared__ int order[128];
   const int di = (int)d;
   const int dd = di + (di & 1);  // a zero column pads an odd d
+  double* V = VL ? W + (int64_t)dd * di : Vg;
   const int64_t r = *rank;
   for (int e = threadIdx.x; e < dd * di; e += kSvdThreads) {
     const int c = e / di, row = e % di;
@@ -502,8 +507,10 @@ hipError_t launch_precondition(int method, int64_t d, const double* R, const int
   if (method == 1) {
     if (d > 128) return hipErrorInvalidValue;
     const int64_t dd = d + (d & 1);
-    const size_t lds = sizeof(double) * (size_t)(dd * d);
-    auto kern = jacobi_svd_kernel;
+    // V in LDS beside W when both fit (d <= 98)
+    const bool vl = 2 * sizeof(double) * (size_t)(dd * d) <= 150 * 1024;
+    const size_t lds = sizeof(double) * (size_t)(dd * d) * (vl ? 2 : 1);
+    auto kern = vl ? jacobi_svd_kernel<true> : jacobi_svd_kernel<false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

@@ -74,6 +74,24 @@ def test_preconditioner_rank_deficient_and_wide(gpu):
         api.lev_precondition(torch.from_numpy(A).to(gpu), 4, 8192, 600, 1e-10, "svd")
 
 
+@pytest.mark.parametrize("d", [97, 99, 128])
+def test_preconditioner_svd_widths(gpu, d):
+    """The Jacobi SVD with V beside W in LDS (d <= 98) and V in global
+    memory (wider), at an odd d (a zero column pads the round-robin
+    pairing): k, kappa(A N) and N N^T against the oracle's SVD."""
+    rng = np.random.default_rng(d)
+    A = rng.standard_normal((20000, d)) * np.logspace(0, -3, d)
+    N, k = api.lev_precondition(_padded(A, torch.float64, gpu), 17, 8192, 2 * d, 1e-10, "svd")
+    N, k = N.cpu().numpy(), int(k.item())
+    No, ko = P.count_gauss_precondition(A, 17, 8192, 2 * d, 1e-10, "svd")
+    assert k == ko == d
+    kg, ko_ = np.linalg.cond(A @ N), np.linalg.cond(A @ No)
+    _log("svd", d, "kappa(AN)", kg, ko_)
+    assert kg < 20 and abs(kg - ko_) <= 1e-6 * ko_
+    G, Go = N @ N.T, No @ No.T
+    assert np.linalg.norm(G - Go) <= 1e-9 * np.linalg.norm(Go)
+
+
 @pytest.mark.parametrize("method", ["svd", "qr"])
 def test_preconditioner_csr(gpu, method):
     """CSR input (power-law rows, 8 zero columns, so k = 88 of 96): the
