@@ -7,12 +7,16 @@
 //   SVD: N = P V_R Sigma^{-1}, R = U_R Sigma V_R^T the SVD of R, which is the
 //        V Sigma^{-1} of the SVD of A~ itself (A~ = (Q U_R) Sigma (P V_R)^T),
 //        keeping the k singular values above zeta sigma_1.
-// The SVD of R (d <= 128) is a one-sided Jacobi (Hestenes) iteration in one
-// workgroup: the columns of W = R sit in LDS, disjoint column pairs of a
-// round-robin round are orthogonalised in parallel (one wave per pair,
-// Rutishauser's rotation), V accumulates the rotations, and sweeps repeat
-// until no pair is rotated.  Singular values are the final column norms;
-// relative accuracy does not depend on kappa(R).
+// The SVD of R (d <= 128) is the preconditioned one-sided Jacobi method of
+// Drmac and Veselic (2008): Hestenes' iteration on W = R^T, whose columns
+// are the rows of the pivoted factor and so are already close to
+// orthogonal (few sweeps).  W sits in LDS; each round of a round-robin
+// ordering orthogonalises all its disjoint column pairs at once (a 16-lane
+// group per pair, Rutishauser's rotation), and sweeps repeat until no pair
+// is rotated.  Then W = R^T U_R = V_R Sigma: the column norms are the
+// singular values and column c over its norm is the right singular vector,
+// so N = P W Sigma^{-2} without accumulating the rotations.  Relative
+// accuracy of the singular values does not depend on kappa(R).
 //
 // LSQR (Paige and Saunders 1982) on M = A N from y = 0, with x = N y at the
 // end.  Per iteration two passes over A (dense, FP64 arithmetic on any
@@ -35,8 +39,9 @@
 namespace lev {
 namespace {
 
-constexpr int kSvdThreads = 1024;
-constexpr int kSvdWaves = kSvdThreads / 64;
+constexpr int kSvdGroup = 16;           // lanes per column pair
+constexpr int kSvdMaxThreads = 1024;    // 64 groups: every pair of a round at d <= 128
+constexpr int kSvdElems = 8;            // column elements per lane at d <= 128
 constexpr int kMaxSweeps = 40;
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -52,75 +57,102 @@ __device__ __forceinline__ double group16_sum(double x) {
   return x;
 }
 
-// Round-robin pairing of dd (even) columns: round t, pair q -> (a, b).
-__device__ __forceinline__ void rr_pair(int dd, int t, int q, int& a, int& b) {
-  auto pos = [&](int i) -> int { return i == 0 ? 0 : 1 + (i - 1 + t) % (dd - 1); };
-  a = pos(q);
-  b = pos(dd - 1 - q);
+// Round-robin pairing of dd (even) columns: in round t pair q joins the
+// columns at positions q and dd - 1 - q of the ring, where position 0
+// holds column 0 for good and position i > 0 holds column
+// 1 + (i - 1 + t) mod (dd - 1); so from one round to the next every
+// column but 0 moves to the next of 1 .. dd - 1, cyclically.
+__device__ __forceinline__ int rr_col(int dd, int t, int i) { return i == 0 ? 0 : 1 + (i - 1 + t) % (dd - 1); }
+__device__ __forceinline__ int rr_next(int dd, int c) { return c == 0 ? 0 : (c + 1 == dd ? 1 : c + 1); }
+
+// v + v of the DPP partner lane (both 32-bit halves moved).
+template <int CTRL>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return v + __hiloint2double(hi, lo);
 }
 
-// W (LDS, column-major, d x d) = R; V (global, column-major) = I.
-// VL: V kept in LDS behind W (when both fit), so a rotation's update of V
-// costs LDS round trips instead of global ones (the rounds of a sweep are
-// serial, so that latency is paid 59 times a sweep at d = 60).
-template <bool VL>
-__global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(int64_t d, const double* __restrict__ R,
-                                                                 const int64_t* __restrict__ rank,
-                                                                 const int32_t* __restrict__ perm, double zeta,
-                                                                 double* __restrict__ Vg, double* __restrict__ N,
-                                                                 int64_t* __restrict__ k_out) {
+// Sum over each 16-lane row by butterflies whose partners always sit in
+// the other half of the part summed so far, so both sides add the same two
+// values and every lane of the row ends with identical bits (the rotation
+// is then the same in every lane).  All 16 lanes must be active.
+__device__ __forceinline__ double row16_sum(double v) {
+  v = dpp_add<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v = dpp_add<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v = dpp_add<0x141>(v);  // row_half_mirror
+  v = dpp_add<0x140>(v);  // row_mirror
+  return v;
+}
+
+// One workgroup of 16 * (dd / 2) lanes (rounded up to a wave); LDS holds W
+// column-major, dd columns of d (a zero column pads an odd d).
+__global__ __launch_bounds__(kSvdMaxThreads) void jacobi_svd_kernel(int64_t d, const double* __restrict__ R,
+                                                                    const int64_t* __restrict__ rank,
+                                                                    const int32_t* __restrict__ perm, double zeta,
+                                                                    double* __restrict__ N,
+                                                                    int64_t* __restrict__ k_out) {
   extern __shared__ double W[];
   __shared__ int rotated;
   __shared__ double sig[128];
   __shared__ int order[128];
   const int di = (int)d;
-  const int dd = di + (di & 1);  // a zero column pads an odd d
-  double* V = VL ? W + (int64_t)dd * di : Vg;
+  const int dd = di + (di & 1);
   const int64_t r = *rank;
-  for (int e = threadIdx.x; e < dd * di; e += kSvdThreads) {
-    const int c = e / di, row = e % di;
-    W[e] = (c < di && row < r) ? R[(int64_t)row * d + c] : 0.0;  // rows past the rank are zero
+  // column c of W = row c of R (rows past the rank are zero)
+  for (int e = threadIdx.x; e < dd * di; e += blockDim.x) {
+    const int c = e / di, i = e - c * di;
+    W[e] = (c < di && c < r) ? R[(int64_t)c * d + i] : 0.0;
   }
-  for (int e = threadIdx.x; e < dd * di; e += kSvdThreads) V[e] = (e / di == e % di) ? 1.0 : 0.0;
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gl = threadIdx.x & (kSvdGroup - 1);
+  const int q = threadIdx.x / kSvdGroup;
+  const bool active = q < dd / 2;  // whole 16-lane rows are active or not
+  // a pair is rotated while |x . y| > tol ||x|| ||y||, tested squared
   const double tol = 4.0 * (double)di * 2.220446049250313e-16;
+  const double tol2 = tol * tol;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if (threadIdx.x == 0) rotated = 0;
     __syncthreads();
-    for (int t = 0; t < dd - 1; ++t) {
-      for (int q = wave; q < dd / 2; q += kSvdWaves) {
-        int a, b;
-        rr_pair(dd, t, q, a, b);
-        double* wa = W + (int64_t)a * di;
-        double* wb = W + (int64_t)b * di;
+    int a = rr_col(dd, 0, q), b = rr_col(dd, 0, dd - 1 - q);
+    for (int t = 0; t < dd - 1; ++t, a = rr_next(dd, a), b = rr_next(dd, b)) {
+      if (active) {
+        double* wa = W + a * di;
+        double* wb = W + b * di;
+        double x[kSvdElems], y[kSvdElems];
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < di; i += 64) {
-          const double x = wa[i], y = wb[i];
-          al = fma(x, x, al);
-          be = fma(y, y, be);
-          ga = fma(x, y, ga);
+#pragma unroll
+        for (int j = 0; j < kSvdElems; ++j) {
+          // the load's index is clamped into the column and its value
+          // zeroed after, so no load sits under a branch
+          const int i = gl + kSvdGroup * j;
+          const int ic = i < di ? i : di - 1;
+          x[j] = i < di ? wa[ic] : 0.0;
+          y[j] = i < di ? wb[ic] : 0.0;
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (ga == 0.0 || fabs(ga) <= tol * sqrt(al * be)) continue;
-        const double zt = (be - al) / (2.0 * ga);
-        const double tn = (zt >= 0.0 ? 1.0 : -1.0) / (fabs(zt) + sqrt(1.0 + zt * zt));
-        const double c = 1.0 / sqrt(1.0 + tn * tn), s = c * tn;
-        for (int i = lane; i < di; i += 64) {
-          const double x = wa[i], y = wb[i];
-          wa[i] = c * x - s * y;
-          wb[i] = s * x + c * y;
+#pragma unroll
+        for (int j = 0; j < kSvdElems; ++j) {
+          al = fma(x[j], x[j], al);
+          be = fma(y[j], y[j], be);
+          ga = fma(x[j], y[j], ga);
         }
-        double* va = V + (int64_t)a * di;
-        double* vb = V + (int64_t)b * di;
-        for (int i = lane; i < di; i += 64) {
-          const double x = va[i], y = vb[i];
-          va[i] = c * x - s * y;
-          vb[i] = s * x + c * y;
+        al = row16_sum(al);
+        be = row16_sum(be);
+        ga = row16_sum(ga);
+        if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
+          const double zt = (be - al) / (2.0 * ga);
+          const double tn = (zt >= 0.0 ? 1.0 : -1.0) / (fabs(zt) + sqrt(1.0 + zt * zt));
+          const double c = rsqrt(1.0 + tn * tn), s = c * tn;  // 1 + tn^2 in [1, 2]
+#pragma unroll
+          for (int j = 0; j < kSvdElems; ++j) {
+            const int i = gl + kSvdGroup * j;
+            if (i < di) {
+              wa[i] = c * x[j] - s * y[j];
+              wb[i] = s * x[j] + c * y[j];
+            }
+          }
+          if (gl == 0) rotated = 1;
         }
-        if (lane == 0) rotated = 1;
       }
       __syncthreads();
     }
@@ -129,13 +161,13 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(int64_t d, cons
     if (!any) break;
   }
   // singular values, their descending order (ties: lower column first), k
-  for (int c = threadIdx.x; c < di; c += kSvdThreads) {
+  for (int c = threadIdx.x; c < di; c += blockDim.x) {
     double nn = 0.0;
-    for (int i = 0; i < di; ++i) nn = fma(W[(int64_t)c * di + i], W[(int64_t)c * di + i], nn);
+    for (int i = 0; i < di; ++i) nn = fma(W[c * di + i], W[c * di + i], nn);
     sig[c] = sqrt(nn);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < di; c += kSvdThreads) {
+  for (int c = threadIdx.x; c < di; c += blockDim.x) {
     int rk = 0;
     for (int c2 = 0; c2 < di; ++c2) rk += (sig[c2] > sig[c] || (sig[c2] == sig[c] && c2 < c)) ? 1 : 0;
     order[rk] = c;
@@ -143,16 +175,16 @@ __global__ __launch_bounds__(kSvdThreads) void jacobi_svd_kernel(int64_t d, cons
   __syncthreads();
   const double s1 = sig[order[0]];
   int k = 0;
-  for (int q = 0; q < di; ++q) k += (s1 > 0.0 && sig[order[q]] > zeta * s1) ? 1 : 0;
-  // N[perm[i]][q] = V_R[i][order[q]] / sigma (rows of V_R by pivot position)
-  for (int e = threadIdx.x; e < di * di; e += kSvdThreads) {
-    const int i = e / di, q = e % di;
+  for (int c = 0; c < di; ++c) k += (s1 > 0.0 && sig[order[c]] > zeta * s1) ? 1 : 0;
+  // N[perm[i]][c] = V_R[i][order[c]] / sigma = W[i][order[c]] / sigma^2
+  for (int e = threadIdx.x; e < di * di; e += blockDim.x) {
+    const int i = e / di, c = e - i * di;
     double v = 0.0;
-    if (q < k) {
-      const int c = order[q];
-      v = V[(int64_t)c * di + i] / sig[c];
+    if (c < k) {
+      const int o = order[c];
+      v = W[o * di + i] / sig[o] / sig[o];
     }
-    N[(int64_t)perm[i] * d + q] = v;
+    N[(int64_t)perm[i] * d + c] = v;
   }
   if (threadIdx.x == 0) *k_out = k;
 }
@@ -507,14 +539,12 @@ hipError_t launch_precondition(int method, int64_t d, const double* R, const int
   if (method == 1) {
     if (d > 128) return hipErrorInvalidValue;
     const int64_t dd = d + (d & 1);
-    // V in LDS beside W when both fit (d <= 98)
-    const bool vl = 2 * sizeof(double) * (size_t)(dd * d) <= 150 * 1024;
-    const size_t lds = sizeof(double) * (size_t)(dd * d) * (vl ? 2 : 1);
-    auto kern = vl ? jacobi_svd_kernel<true> : jacobi_svd_kernel<false>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+    const size_t lds = sizeof(double) * (size_t)(dd * d);  // <= 128 KiB
+    const int threads = (int)std::max<int64_t>(64, (dd / 2 * kSvdGroup + 63) / 64 * 64);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(jacobi_svd_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    kern<<<1, kSvdThreads, lds, s>>>(d, R, rank, perm, zeta, work, N, k_out);
+    jacobi_svd_kernel<<<1, threads, lds, s>>>(d, R, rank, perm, zeta, N, k_out);
     return hipGetLastError();
   }
   // QR: Z = R11^{-1} (trsm of the identity), rows scattered to the original columns

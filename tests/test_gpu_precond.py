@@ -76,9 +76,10 @@ def test_preconditioner_rank_deficient_and_wide(gpu):
 
 @pytest.mark.parametrize("d", [97, 99, 128])
 def test_preconditioner_svd_widths(gpu, d):
-    """The Jacobi SVD with V beside W in LDS (d <= 98) and V in global
-    memory (wider), at an odd d (a zero column pads the round-robin
-    pairing): k, kappa(A N) and N N^T against the oracle's SVD."""
+    """The Jacobi SVD at odd d (a zero column pads the round-robin
+    pairing), past 64 columns (eight elements of a column per lane) and at
+    the largest d (W fills 128 KiB of LDS, 64 pairs a round): k,
+    kappa(A N) and N N^T against the oracle's SVD."""
     rng = np.random.default_rng(d)
     A = rng.standard_normal((20000, d)) * np.logspace(0, -3, d)
     N, k = api.lev_precondition(_padded(A, torch.float64, gpu), 17, 8192, 2 * d, 1e-10, "svd")
