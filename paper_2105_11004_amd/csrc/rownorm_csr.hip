@@ -230,9 +230,10 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_kernel(const T* __res
 // then for each of the 16 entries the group broadcasts it from its lane (DPP
 // row_newbcast, no LDS), reads the 16 bytes of Z_full's row it needs
 // (ds_read_b128: the group reads the whole 256-byte row, conflict-free) and
-// does four FMAs.  Light rows (< 64 nonzeros) go four at a time, one per
-// group, so a single-nonzero row costs a quarter of a step, not a whole
-// wave's.  The four groups move in step, so a wave pays for the longest of
+// does four FMAs.  A row of at most one nonzero a_ij needs no k-vector:
+// theta = a_ij^2 ||Z_full[j,:]||^2, from the squared row norms of Z_full
+// kept in LDS beside it, one row a lane.  The other light rows (2 .. 63
+// nonzeros) go four at a time, one per group.  The four groups move in step, so a wave pays for the longest of
 // its four rows: the light rows of the 64 are first ordered by length class
 // (1, 2, 3-4, 5-8, ..., 33-63; counted with ballots, moved with a forward
 // lane permutation), which puts rows of similar length side by side (with
@@ -295,9 +296,15 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
                                                                       int64_t n, int64_t d, int64_t nnz,
                                                                       const float* __restrict__ Zg,
                                                                       float* __restrict__ theta, ColTile ct) {
-  extern __shared__ __align__(16) float Zs[];  // d rows of kGZStride floats
+  extern __shared__ __align__(16) float Zs[];  // d rows of kGZStride floats, then d squared row norms
   if (col_tile_dead(ct)) return;
+  float* zn = Zs + d * kGZStride;
   for (int64_t e = threadIdx.x; e < d * 64; e += kCsrThreads) Zs[(e / 64) * kGZStride + (e % 64)] = Zg[e];
+  for (int64_t c = threadIdx.x; c < d; c += kCsrThreads) {
+    float a = 0.f;
+    for (int q = 0; q < 64; ++q) a = fmaf(Zg[c * 64 + q], Zg[c * 64 + q], a);
+    zn[c] = a;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -332,18 +339,31 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
     const int64_t rnext = lane < 63 ? down : last;
     const int len = lane < nr ? (int)(rnext - rp) : 0;
     const uint64_t heavy = __ballot(lane < nr && len >= kHeavy);
-    // light rows (empty ones included: their theta is 0) by length class;
-    // sorted position q holds row srow, its start rps and length lens;
-    // heavy rows and lanes past the task's end come last
+    // rows of at most one nonzero, one a lane (an empty row's theta is 0)
+    if (lane < nr && len <= 1) {
+      float sq = 0.f;
+      if (len == 1) {
+        const int cc = col_idx[rp];
+        const float vv = to_f32<T>(vals[rp]);
+        if ((uint32_t)cc < (uint32_t)d) sq = vv * vv * zn[cc];
+      }
+      const int64_t r = r0 + lane;
+      theta[r] = ct.acc ? theta[r] + sq : sq;
+    }
+    // the other light rows by length class; sorted position q holds row
+    // srow, its start rps and length lens; the rows just done (class 0),
+    // then the heavy rows and lanes past the task's end sort outside
+    // positions n01 .. nlight - 1
     const bool light = lane < nr && len < kHeavy;
     const int cls = light ? (len <= 1 ? 0 : 32 - __builtin_clz((unsigned)(len - 1))) : 7;
-    int pos = 0, base = 0, nlight = 0;
+    int pos = 0, base = 0, nlight = 0, n01 = 0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const uint64_t m = __ballot(cls == c);
       const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
       if (cls == c) pos = base + below;
       base += __popcll(m);
+      if (c == 0) n01 = base;
       if (c == 6) nlight = base;
     }
     const int srow = __builtin_amdgcn_ds_permute(4 * pos, lane);
@@ -351,16 +371,18 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
                         (uint32_t)__builtin_amdgcn_ds_permute(4 * pos, (int)rp);
     const int lens = __builtin_amdgcn_ds_permute(4 * pos, light ? len : 0);
 
-    // light rows: group g takes sorted positions 4 q + g; the first 32
-    // nonzeros of the rows two steps ahead load while a step runs (a ring
-    // of three)
+    // light rows of 2 .. 63 nonzeros: group g takes sorted positions
+    // n01 + 4 q + g; the first 32 nonzeros of the rows two steps ahead load
+    // while a step runs (a ring of three); a position at or past nlight
+    // (possibly past the wave) stands for an empty row
     int pc[3][2];
     float pv[3][2];
 #define LEV_LOADQ(Q, SLOT)                                                                          \
     {                                                                                               \
-      const int jj = 4 * (Q) + g;                                                                   \
-      const int64_t ss = __shfl(rps, jj, 64);                                                       \
-      const int ll = __shfl(lens, jj, 64);                                                          \
+      const int jj = n01 + 4 * (Q) + g;                                                             \
+      const int64_t ss = __shfl(rps, jj & 63, 64);                                                  \
+      const int lr = __shfl(lens, jj & 63, 64); /* on every lane, then masked */                    \
+      const int ll = jj < nlight ? lr : 0;                                                          \
       _Pragma("unroll") for (int h = 0; h < 2; ++h) {                                               \
         const int t = 16 * h + gl;                                                                  \
         const bool ok = t < ll;                                                                     \
@@ -375,13 +397,14 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
     LEV_LOADQ(1, 1)
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      if (4 * q >= nlight) break;  // uniform: the rest are heavy or past the end
+      if (n01 + 4 * q >= nlight) break;  // uniform: the rest are heavy or past the end
       if (q + 2 < 16) LEV_LOADQ(q + 2, (q + 2) % 3)
       const int slot = q % 3;
-      const int j = 4 * q + g;
-      const int64_t s0 = __shfl(rps, j, 64);
-      const int lj = __shfl(lens, j, 64);
+      const int j = n01 + 4 * q + g;
       const bool mine = j < nlight;
+      const int64_t s0 = __shfl(rps, j & 63, 64);
+      const int ljr = __shfl(lens, j & 63, 64);  // on every lane, then masked
+      const int lj = mine ? ljr : 0;
       // wave-uniform chunk count: the longest of the four groups' rows
       int mx = lj;
       mx = max(mx, __shfl_xor(mx, 16, 64));
@@ -398,7 +421,7 @@ __global__ __launch_bounds__(kCsrThreads) void rownorm_csr_grp_kernel(const T* _
         group_chunk(Zs, cin ? col : 0, cin ? v : 0.f, gl, y, mx - c0);
       }
       const float sq = group_sum16(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
-      const int sj = __shfl(srow, j, 64);
+      const int sj = __shfl(srow, j & 63, 64);
       if (mine && gl == 15) {
         const int64_t r = r0 + sj;
         theta[r] = ct.acc ? theta[r] + sq : sq;
@@ -466,7 +489,7 @@ hipError_t launch_typed(const void* vals, const int64_t* row_ptr, const int32_t*
   const ZT* Z = static_cast<const ZT*>(Zpack);
   ZT* th = static_cast<ZT*>(theta);
   if constexpr (sizeof(ZT) == 4) {
-    const size_t gz = (size_t)d * kGZStride * sizeof(float);
+    const size_t gz = (size_t)d * (kGZStride + 1) * sizeof(float);
     if (gz <= 152 * 1024) {
       auto kern = rownorm_csr_grp_kernel<T>;
       hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
