@@ -182,9 +182,26 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
       for (int v = 0; v < 4; ++v) acc64[i][j][v] = 0.0;
     }
 
+// (the empty asm pins each FP64 sum where it is written: otherwise the
+// compiler sinks all the adds below the step's last MFMA)
+#define LEV_XG_FLUSH(I)                                                                               \
+  _Pragma("unroll") for (int j = 0; j < 2; ++j)                                                       \
+  _Pragma("unroll") for (int v = 0; v < 4; ++v) {                                                     \
+    acc64[I][j][v] += (double)acc[I][j][v];                                                           \
+    asm volatile("" : "+v"(acc64[I][j][v]));                                                          \
+  }
+
   // B fragments of the wave's two column blocks (all parts), then per row
-  // block the A fragments and the six products, smallest first; the step's
-  // FP32 sums go into FP64
+  // block the A fragments and the six products, smallest first, the first
+  // from a zero accumulator.  A row block's FP32 sums go into FP64 once the
+  // next row block's products are issued (its own have finished by then),
+  // so the conversions and FP64 adds sit between MFMAs and only the last
+  // row block's wait at the end of the step; the FP64 sums take the steps
+  // in order either way.
+#define LEV_XG_AFRAG(BUF, I, DST)                                                                     \
+  _Pragma("unroll") for (int p = 0; p < 3; ++p)                                                       \
+    DST[p] = *reinterpret_cast<const uint4*>(As[BUF] + (p * TM + wm + 16 * (I) + (lane & 15)) * kRowHalfs + \
+                                             xg_piece(wm + 16 * (I) + (lane & 15), lane >> 4));
 #define LEV_XG_COMPUTE(BUF)                                                                           \
   {                                                                                                   \
     uint4 bq[2][3];                                                                                   \
@@ -192,14 +209,13 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
     _Pragma("unroll") for (int p = 0; p < 3; ++p)                                                     \
       bq[j][p] = *reinterpret_cast<const uint4*>(Bs[BUF] + (p * TM + wn + 16 * j + (lane & 15)) * kRowHalfs + \
                                                  xg_piece(wn + 16 * j + (lane & 15), lane >> 4));     \
+    uint4 ap[3], apn[3];                                                                              \
+    LEV_XG_AFRAG(BUF, 0, ap)                                                                          \
     _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                                   \
-      uint4 ap[3];                                                                                    \
-      _Pragma("unroll") for (int p = 0; p < 3; ++p)                                                   \
-        ap[p] = *reinterpret_cast<const uint4*>(As[BUF] + (p * TM + wm + 16 * i + (lane & 15)) * kRowHalfs + \
-                                                xg_piece(wm + 16 * i + (lane & 15), lane >> 4));      \
+      if (i < 3) { LEV_XG_AFRAG(BUF, i + 1, apn) }                                                    \
       _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                                 \
-        v4f c = acc[i][j];                                                                            \
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[2]), as_bf(bq[j][0]), c, 0, 0, 0);      \
+        v4f c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[2]), as_bf(bq[j][0]),                \
+                                                        (v4f{0.f, 0.f, 0.f, 0.f}), 0, 0, 0);         \
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][1]), c, 0, 0, 0);      \
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][2]), c, 0, 0, 0);      \
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[1]), as_bf(bq[j][0]), c, 0, 0, 0);      \
@@ -207,12 +223,12 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(ap[0]), as_bf(bq[j][0]), c, 0, 0, 0);      \
         acc[i][j] = c;                                                                                \
       }                                                                                               \
+      if (i > 0) { LEV_XG_FLUSH(i - 1) }                                                              \
+      /* keeps the flush of row block i - 1 among row block i's MFMAs */                              \
+      __builtin_amdgcn_sched_barrier(0);                                                              \
+      _Pragma("unroll") for (int p = 0; p < 3; ++p) ap[p] = apn[p];                                   \
     }                                                                                                 \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i)                                                     \
-    _Pragma("unroll") for (int j = 0; j < 2; ++j) {                                                   \
-      _Pragma("unroll") for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];          \
-      acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};                                                            \
-    }                                                                                                 \
+    LEV_XG_FLUSH(3)                                                                                   \
   }
 
   // (the products are l h, m m, h l, m h, h m, h h: smallest first)
@@ -238,6 +254,8 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
 #undef LEV_XG_LOAD
 #undef LEV_XG_STORE
 #undef LEV_XG_COMPUTE
+#undef LEV_XG_FLUSH
+#undef LEV_XG_AFRAG
 
   // accumulator element v of lane l: row 4 (l / 16) + v, column l % 16 of
   // its 16 x 16 block
