@@ -88,10 +88,12 @@ constexpr int kPanelCols = 2;
 constexpr int kPanelThreads = kMaxD / kPanelCols;
 constexpr int kPanelWaves = kPanelThreads / 64;
 
+// FIXED: the pivot order is the identity (step J's only candidate is column J).
+template <bool FIXED>
 __global__ __launch_bounds__(kPanelThreads) void pivchol_panel_kernel(const double* __restrict__ S, int64_t d,
                                                                       double zeta, int64_t J0,
                                                                       PivCholState st,
-                                                                      int64_t* __restrict__ rank_out, int fixed,
+                                                                      int64_t* __restrict__ rank_out,
                                                                       const double* __restrict__ ref_r00) {
   __shared__ double bc[NB];
   __shared__ double wv[2][kPanelWaves];
@@ -112,6 +114,10 @@ __global__ __launch_bounds__(kPanelThreads) void pivchol_panel_kernel(const doub
     alive[q] = (c < d) && (dg[q] != -INFINITY);
   }
   double r00 = ref_r00 != nullptr ? *ref_r00 : ((J0 == 0) ? 0.0 : *st.r00);
+  // the cutoff sqrt(pv) > zeta r00 is tested as pv > (zeta r00)^2, so that
+  // no square root stands between the pivot and the exchange of its column
+  // (if the square overflows, sqrt(pv) cannot exceed zeta r00 either)
+  double zr2 = (zeta * r00) * (zeta * r00);
 
   double rp0[NB], rp1[NB];
 #pragma unroll
@@ -120,16 +126,19 @@ __global__ __launch_bounds__(kPanelThreads) void pivchol_panel_kernel(const doub
   int64_t J = J0;
   bool stop = false;
   bool active = true;  // uniform across the workgroup
+  const int di = (int)d;  // d <= kMaxD: 32-bit offsets below
+  double* rrow = st.Rrows + J0 * d + c0;  // row J of R at this thread's columns
   // Constant trip count (no break) so the loop unrolls fully and rp0[],
   // rp1[] stay in registers.
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     if (active && J >= d) active = false;
     if (!active) continue;
-    // the lane's candidate (fixed order: the only candidate of step J is
-    // column J); a NaN diagonal never wins
-    const double m0 = (alive[0] && (!fixed || c0 == J)) ? dg[0] : -INFINITY;
-    const double m1 = (alive[1] && (!fixed || c0 + 1 == J)) ? dg[1] : -INFINITY;
+    // the lane's candidate (a column no longer alive holds -inf; fixed
+    // order: the only candidate of step J is column J); a NaN diagonal
+    // never wins
+    const double m0 = (!FIXED || c0 == J) ? dg[0] : -INFINITY;
+    const double m1 = (!FIXED || c0 + 1 == J) ? dg[1] : -INFINITY;
     const bool second = (m1 > m0) || (m0 != m0);
     const double mv = second ? m1 : m0;
     const int mc = c0 + (second ? 1 : 0);
@@ -155,23 +164,31 @@ __global__ __launch_bounds__(kPanelThreads) void pivchol_panel_kernel(const doub
     const int bw = bhit != 0 ? (__ffsll((unsigned long long)bhit) - 1) : 0;
     const double pv = bhit != 0 ? bmax : -INFINITY;
     const int p = __builtin_amdgcn_readlane(ci, bw);
-    if (J == 0 && ref_r00 == nullptr) r00 = pv > 0.0 ? sqrt(pv) : 0.0;
-    if (!(pv > 0.0) || !(sqrt(pv) > zeta * r00)) {
+    if (j == 0 && J0 == 0 && ref_r00 == nullptr) {
+      r00 = pv > 0.0 ? sqrt(pv) : 0.0;
+      zr2 = (zeta * r00) * (zeta * r00);
+    }
+    if (!(pv > 0.0) || !(pv > zr2)) {
       stop = true;
       active = false;
       continue;
     }
-    const double rjj = sqrt(pv);
-    const double inv = 1.0 / rjj;
     // prefetch the pivot row of the Schur complement (symmetric: = column p)
     double s_pc[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) s_pc[q] = (c0 + q < d) ? S[(int64_t)p * d + c0 + q] : 0.0;
+    for (int q = 0; q < 2; ++q) s_pc[q] = (c0 + q < di) ? S[p * di + c0 + q] : 0.0;
     if ((p >> 1) == tid) {
 #pragma unroll
       for (int t = 0; t < j; ++t) bc[t] = (p & 1) ? rp1[t] : rp0[t];
     }
     lds_barrier();
+    // rjj and 1 / rjj (the reciprocal estimate and two Newton steps: rjj is
+    // positive, finite and normal here, so the scaled division's special
+    // cases do not arise) while the column's entries are read and summed
+    const double rjj = sqrt(pv);
+    double inv = __builtin_amdgcn_rcp(rjj);
+    inv = fma(inv, fma(-rjj, inv, 1.0), inv);
+    inv = fma(inv, fma(-rjj, inv, 1.0), inv);
     double acc0 = s_pc[0], acc1 = s_pc[1];
 #pragma unroll
     for (int t = 0; t < j; ++t) {
@@ -179,24 +196,28 @@ __global__ __launch_bounds__(kPanelThreads) void pivchol_panel_kernel(const doub
       acc0 = fma(-b, rp0[t], acc0);
       acc1 = fma(-b, rp1[t], acc1);
     }
+    // selects, not branches: the pivot column takes rjj and leaves the
+    // candidates, live columns take their entry and downdate their diagonal,
+    // dead ones (and those past d) take 0
     double val[2] = {acc0 * inv, acc1 * inv};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      if (c0 + q == p) {
-        val[q] = rjj;
-        alive[q] = false;
-        dg[q] = -INFINITY;
-      } else if (alive[q]) {
-        dg[q] = fma(-val[q], val[q], dg[q]);
-      } else {
-        val[q] = 0.0;
-      }
+      const bool piv = c0 + q == p;
+      const double nd = fma(-val[q], val[q], dg[q]);
+      val[q] = piv ? rjj : (alive[q] ? val[q] : 0.0);
+      dg[q] = piv ? -INFINITY : (alive[q] ? nd : dg[q]);
+      alive[q] = alive[q] && !piv;
     }
     rp0[j] = val[0];
     rp1[j] = val[1];
+    if (c0 + 1 < d && ((d & 1) == 0)) {  // the pair is 16-byte aligned (d even, c0 even)
+      *reinterpret_cast<double2*>(rrow) = make_double2(val[0], val[1]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
-      if (c0 + q < d) st.Rrows[J * d + c0 + q] = val[q];
+      for (int q = 0; q < 2; ++q)
+        if (c0 + q < d) rrow[q] = val[q];
+    }
+    rrow += d;
     if (tid == 0) st.piv[J] = p;
     ++J;
   }
@@ -572,7 +593,10 @@ hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState&
   }
   const int threads = (int)(((d + 64 * kPanelCols - 1) / (64 * kPanelCols)) * 64);
   for (int64_t J0 = 0; J0 < d; J0 += NB) {
-    pivchol_panel_kernel<<<1, threads, 0, s>>>(B, d, zeta, J0, st, rank_out, fixed, ref_r00);
+    if (fixed)
+      pivchol_panel_kernel<true><<<1, threads, 0, s>>>(B, d, zeta, J0, st, rank_out, ref_r00);
+    else
+      pivchol_panel_kernel<false><<<1, threads, 0, s>>>(B, d, zeta, J0, st, rank_out, ref_r00);
     if (J0 + NB < d) {
       // S <- S - R_panel^T R_panel over the panel's NB rows (skipped once done)
       const double* Rp = st.Rrows + J0 * d;
