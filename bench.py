@@ -155,6 +155,17 @@ def phase_work(A, cfg, mode: str = "jl", sketch: str = "gauss") -> dict:
     theta_es = 8 if _values(A).dtype == torch.float64 else 4
     r = expected_rank(cfg)
     out = _phase_work_mode(A, cfg, mode, n, d, m, r_cs, k, theta_es, r)
+    if (sketch == "gauss" and not _is_csr(A) and A.dtype == torch.bfloat16 and r_cs % 8 == 0
+            and out["gaussian_transform"][1] > 0):
+        # BF16-stored dense A: the transform runs as six products of
+        # three-part BF16 splits on the BF16 matrix cores (FP32-level
+        # arithmetic), so it is priced by those products against that peak;
+        # pass 1 then writes G_m as three BF16 parts (6 bytes an entry)
+        out["gaussian_transform"] = ("mfma_bf16", 6 * 2.0 * m * r_cs * d)
+        if mode == "jl":
+            out["pass1_countsketch"] = ("hbm", a_bytes(A) + 8 * (r_cs * d + d * k) + 6 * m * r_cs)
+        else:  # no G_k
+            out["pass1_countsketch"] = ("hbm", a_bytes(A) + 8 * r_cs * d + 6 * m * r_cs)
     if sketch == "srht":
         # no G_m: pass 1 writes S A (and G_k); the SRHT reads S A once and
         # writes A~ at least (its radix passes add the in-place round trips)
@@ -216,9 +227,9 @@ def rooflines(A, cfg, phases_ms: dict, traffic: dict, mode: str = "jl", sketch: 
                          "frac": ach / HBM_PEAK_GBS, "traffic": traffic.get(name), "algorithmic_bytes": work}
         else:
             ach = work / t / 1e12
-            out[name] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                         "frac": ach / FP64_PEAK_TFLOPS, "traffic": None, "algorithmic_flops": work,
-                         "dtype": "f64"}
+            peak, dt = (BF16_PEAK_TFLOPS, "bf16") if bound == "mfma_bf16" else (FP64_PEAK_TFLOPS, "f64")
+            out[name] = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                         "frac": ach / peak, "traffic": None, "algorithmic_flops": work, "dtype": dt}
     return out
 
 
