@@ -580,6 +580,73 @@ __global__ __launch_bounds__(kMaxD) void pivchol_finalize_kernel(int64_t d, PivC
     }
 }
 
+// Rank-NB update after a panel: S <- S - R_p^T R_p, R_p the panel's NB rows
+// of R (NB x d, row-major).  One K step of NB, so a tiled GEMM would spend
+// its time on the LDS staging and barrier around a single step; here there
+// is no LDS: each wave owns a 32 x 32 block of S (2 x 2 blocks of the 16x16x4
+// FP64 MFMA), loads the R values of its operands straight into registers
+// (16 lanes read 128 contiguous bytes of one row of R_p) together with its
+// block of S, runs the NB / 4 MFMA steps and writes S - (R_p^T R_p) back,
+// the same arithmetic as the GEMM form: the product summed from zero in
+// k order, then one subtraction.  Skipped once the factorisation is done.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kSchurTile = 64;  // rows and columns of S per workgroup (4 waves)
+
+__global__ __launch_bounds__(256) void schur_update_kernel(double* __restrict__ S, int64_t d,
+                                                           const double* __restrict__ Rp,
+                                                           const int32_t* __restrict__ done) {
+  if (*done != 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, i = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.y * kSchurTile + (wave >> 1) * 32;
+  const int64_t c0 = (int64_t)blockIdx.x * kSchurTile + (wave & 1) * 32;
+  // operands of step s (contraction index k = 4 s + g): lane l supplies
+  // A[l % 16][l / 16] = R_p[k][r0 + 16 bi + l % 16] and B[l / 16][l % 16] =
+  // R_p[k][c0 + 16 bj + l % 16]; indices past d read zero
+  double av[NB / 4][2], bv[NB / 4][2];
+#pragma unroll
+  for (int st = 0; st < NB / 4; ++st)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double* row = Rp + (int64_t)(4 * st + g) * d;
+      const int64_t ri = r0 + 16 * h + i, cj = c0 + 16 * h + i;
+      av[st][h] = ri < d ? row[ri] : 0.0;
+      bv[st][h] = cj < d ? row[cj] : 0.0;
+    }
+  // S block: accumulator element v of lane l is row g + 4 v, column i
+  double sv[2][2][4];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + 16 * bi + g + 4 * v, c = c0 + 16 * bj + i;
+        sv[bi][bj][v] = (r < d && c < d) ? S[r * d + c] : 0.0;
+      }
+  v4d acc[2][2];
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < NB / 4; ++st)
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj)
+        acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st][bi], bv[st][bj], acc[bi][bj], 0, 0, 0);
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + 16 * bi + g + 4 * v, c = c0 + 16 * bj + i;
+        if (r < d && c < d) S[r * d + c] = sv[bi][bj][v] - acc[bi][bj][v];
+      }
+}
+
 }  // namespace
 
 hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState& st, int64_t* rank_out,
@@ -600,8 +667,9 @@ hipError_t launch_pivchol(double* B, int64_t d, double zeta, const PivCholState&
     if (J0 + NB < d) {
       // S <- S - R_panel^T R_panel over the panel's NB rows (skipped once done)
       const double* Rp = st.Rrows + J0 * d;
-      hipError_t e = launch_dgemm(d, d, NB, -1.0, Rp, 1, d, Rp, d, 1, 1.0, B, d, 1, nullptr,
-                                  st.flags, s);
+      const unsigned tiles = (unsigned)((d + kSchurTile - 1) / kSchurTile);
+      schur_update_kernel<<<dim3(tiles, tiles), 256, 0, s>>>(B, d, Rp, st.flags);
+      hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
   }
