@@ -431,6 +431,53 @@ __global__ __launch_bounds__(1024) void form_z_kernel(int64_t d, int64_t k, cons
   store_operand<VARIANT, KB>(lds, inv, di, total, Zpack);
 }
 
+// The update between diagonal blocks: G[0:j0, :] -= R[0:j0, j0:j0+kb] Z_q,
+// Z_q = Z64[j0:j0+kb, :] (kb <= 256).  A tiled GEMM of this shape (a few
+// hundred rows, k <= 64 columns) has only a dozen workgroups, so here each
+// workgroup owns one 16 x 16 block of G and its four waves split the
+// contraction in quarters of at most 64 (16 FP64 MFMA steps each, operands
+// loaded straight into registers, no LDS staging); the quarters are added
+// in wave order through LDS and the sum subtracted from G.
+constexpr int kUpdK = kTrsmR / 4;  // contraction quarter per wave
+
+__global__ __launch_bounds__(256) void trsm_update_kernel(int64_t j0, int64_t kb, int64_t d, int64_t k,
+                                                          const double* __restrict__ R,
+                                                          const double* __restrict__ Z64,
+                                                          double* __restrict__ G) {
+  __shared__ double part[3][4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, i = lane & 15;
+  const int64_t m0 = (int64_t)blockIdx.y * 16, n0 = (int64_t)blockIdx.x * 16;
+  // step s of this wave: contraction index kk = wave * kUpdK + 4 s + g; lane
+  // l supplies A[l % 16][l / 16] = R[m0 + i][j0 + kk] and B[l / 16][l % 16] =
+  // Z_q[kk][n0 + i] (zero past the block, the rows or the columns)
+  const int64_t row = m0 + i, col = n0 + i;
+  double av[kUpdK / 4], bv[kUpdK / 4];
+#pragma unroll
+  for (int st = 0; st < kUpdK / 4; ++st) {
+    const int64_t kk = (int64_t)wave * kUpdK + 4 * st + g;
+    const bool in_k = kk < kb;
+    av[st] = (in_k && row < j0) ? R[row * d + j0 + kk] : 0.0;
+    bv[st] = (in_k && col < k) ? Z64[(j0 + kk) * k + col] : 0.0;
+  }
+  v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int st = 0; st < kUpdK / 4; ++st) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st], acc, 0, 0, 0);
+  if (wave > 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[wave - 1][v][lane] = acc[v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+  // accumulator element v of lane l: row g + 4 v, column i of the block
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double sum = ((acc[v] + part[0][v][lane]) + part[1][v][lane]) + part[2][v][lane];
+    const int64_t r = m0 + g + 4 * v;
+    if (r < j0 && col < k) G[r * k + col] -= sum;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* rank, double* G, double* Z64,
@@ -447,8 +494,9 @@ hipError_t launch_trsm_z(int64_t d, int64_t k, const double* R, const int64_t* r
     trsm_blocked_kernel<<<grid, 1024, 0, s>>>(d, k, j0, R, rank, G, Z64, err);
     if (j0 > 0) {
       const int64_t kb = std::min<int64_t>(kTrsmR, d - j0);
-      hipError_t e = launch_dgemm(j0, k, kb, -1.0, R + j0, d, 1, Z64 + j0 * k, k, 1, 1.0, G, k, 1, nullptr,
-                                  nullptr, s);
+      const dim3 ugrid((unsigned)((k + 15) / 16), (unsigned)((j0 + 15) / 16));
+      trsm_update_kernel<<<ugrid, 256, 0, s>>>(j0, kb, d, k, R, Z64, G);
+      hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
   }
