@@ -270,17 +270,6 @@ int gram_dense_splits(int64_t n, int64_t d) {
   return splits;
 }
 
-// Splits of the sketch's Gram A~^T A~ (m rows) on the upper tiles: about
-// two workgroups per CU, each split keeping at least 64 of the rows, as
-// for the full products above.
-int gram_sketch_splits(int64_t m, int64_t d) {
-  const int64_t tb = (d + BM - 1) / BM;
-  const int64_t upper = tb * (tb + 1) / 2;
-  int splits = 1;
-  while (upper * splits < 512 && m / (splits * 2) >= 64 && splits < 64) splits *= 2;
-  return splits;
-}
-
 // A^T A: op(A)[i][k] = A[k][i] (strides 1, ld) and op(B)[k][j] = A[k][j]
 // (strides ld, 1), so both operand tiles are read along A's rows; only the
 // tiles on and above the diagonal are computed.
