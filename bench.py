@@ -160,12 +160,13 @@ def phase_work(A, cfg, mode: str = "jl", sketch: str = "gauss") -> dict:
         # BF16-stored dense A: the transform runs as six products of
         # three-part BF16 splits on the BF16 matrix cores (FP32-level
         # arithmetic), so it is priced by those products against that peak;
-        # pass 1 then writes G_m as three BF16 parts (6 bytes an entry)
+        # pass 1 then writes G_m as three BF16 parts (6 bytes an entry) and
+        # S A as FP32 (the split starts from its FP32 value)
         out["gaussian_transform"] = ("mfma_bf16", 6 * 2.0 * m * r_cs * d)
         if mode == "jl":
-            out["pass1_countsketch"] = ("hbm", a_bytes(A) + 8 * (r_cs * d + d * k) + 6 * m * r_cs)
+            out["pass1_countsketch"] = ("hbm", a_bytes(A) + 4 * r_cs * d + 8 * d * k + 6 * m * r_cs)
         else:  # no G_k
-            out["pass1_countsketch"] = ("hbm", a_bytes(A) + 8 * r_cs * d + 6 * m * r_cs)
+            out["pass1_countsketch"] = ("hbm", a_bytes(A) + 4 * r_cs * d + 6 * m * r_cs)
     if sketch == "srht":
         # no G_m: pass 1 writes S A (and G_k); the SRHT reads S A once and
         # writes A~ at least (its radix passes add the in-place round trips)

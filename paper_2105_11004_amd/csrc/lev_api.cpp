@@ -397,12 +397,16 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
                     {dr.key_k, d * k, 1.0 / std::sqrt((double)k), Gk}}};
   if (b.x3) g.m[0].parts3 = b.Gp;  // G_m drawn straight into its three parts
   if (b.srht) g.m[0].total = 0;     // no G_m
+  // the split-form transform reads S A only through its FP32 value: pass 1
+  // stores it as float (in the internal buffer; a caller's SA_out keeps FP64)
+  const bool sa32 = b.x3 && SA == b.SA && A->n > 0 && A->format != LEV_CSR;
+  void* sa_buf = SA;
   LEV_HIP(mark_phase(1, s));
   if (A->n > 0 && A->format == LEV_CSR) {
     LEV_HIP(lev::launch_countsketch_csr(A->dtype, A->values, A->row_ptr, A->col_idx, A->n, d, A->nnz, dr.hash,
                                         SA, g, s));
   } else if (A->n > 0) {
-    LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, SA, g, s));
+    LEV_HIP(lev::launch_countsketch_dense(A->dtype, A->values, A->n, d, A->ld, dr.hash, sa_buf, sa32, g, s));
   } else {
     if (!b.x3 && !b.srht) LEV_HIP(lev::launch_gaussian(dr.key_m, m, r_cs, g.m[0].scale, b.Gm, s));
     if (Gk != nullptr) LEV_HIP(lev::launch_gaussian(dr.key_k, d, k, g.m[1].scale, Gk, s));
@@ -415,7 +419,7 @@ lev_status enqueue_sketch(const lev_matrix* A, const lev_params* p, const lev::S
       LEV_HIP(hipMemcpyAsync(b.SA, SA, sizeof(double) * (size_t)(r_cs * d), hipMemcpyDeviceToDevice, s));
     LEV_HIP(lev::launch_srht(dr.key_d, dr.key_p, r_cs, d, m, b.SA, b.inv, At, s));
   } else if (b.x3 && A->n > 0) {
-    LEV_HIP(lev::launch_split_t3(r_cs, d, SA, b.SAp, s));
+    LEV_HIP(lev::launch_split_t3(r_cs, d, sa_buf, sa32, b.SAp, s));
     LEV_HIP(lev::launch_xgemm(m, d, r_cs, b.Gp, b.SAp, At, d, lev::xgemm_choose_splits(m, d, r_cs), b.partial, s));
   } else if (b.x3) {
     LEV_HIP(lev::launch_fill_zero(At, sizeof(double) * (size_t)(m * d), s));

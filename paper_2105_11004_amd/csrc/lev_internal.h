@@ -63,10 +63,12 @@ struct GaussDraw {
   GaussMatrix m[2];
 };
 
-// Pass 1, dense: SA (r_cs x d, FP64, ld = d) = S A, plus the draw g.
-// dtype: 0 = f64, 1 = f32, 2 = bf16.
+// Pass 1, dense: SA (r_cs x d, ld = d) = S A, plus the draw g.  The sums
+// are taken in FP64; sa_f32: SA is stored as float (rounded once at the
+// store), otherwise as double.  dtype: 0 = f64, 1 = f32, 2 = bf16.
 hipError_t launch_countsketch_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
-                                    const HashParams& hp, double* SA, const GaussDraw& g, hipStream_t s);
+                                    const HashParams& hp, void* SA, bool sa_f32, const GaussDraw& g,
+                                    hipStream_t s);
 // Pass 1, CSR (row_ptr int64[n+1], col_idx int32[nnz], vals[nnz]), plus the
 // draw g.  Row extents are clamped to [0, nnz] and to d entries, column ids
 // >= d skipped.
@@ -271,8 +273,9 @@ hipError_t launch_full_rank_flag(int64_t d, const int64_t* rank, int32_t* flag, 
 
 // ---- the Gaussian transform in FP32-level arithmetic (xgemm.hip) -------------
 // out (3 parts of N x K BF16, rows contiguous in k) = the three-part split
-// of SA^T (SA K x N FP64 row-major); K even.
-hipError_t launch_split_t3(int64_t K, int64_t N, const double* SA, void* out, hipStream_t s);
+// of SA^T (SA K x N row-major, float when sa_f32, else double, split from
+// its FP32 value either way); K even.
+hipError_t launch_split_t3(int64_t K, int64_t N, const void* SA, bool sa_f32, void* out, hipStream_t s);
 // C (M x N FP64, row stride ldc) = A B^T from three-part operands: Ap 3
 // parts of M x K, Bp 3 parts of N x K (BF16, rows of K elements, K a
 // multiple of 8), the six products above 2^-24 on BF16 MFMAs, FP32 within a

@@ -197,10 +197,10 @@ __device__ __forceinline__ void side_draw(const GaussDraw& g) {
 // chunk, so each wave reads NV contiguous KB-sized segments of a row.
 // Wave w takes rows t = w, w + 4, ... of the staged row list, U at a time,
 // with the next U rows in flight while the current ones are added.
-template <typename T, int NV, int U>
+template <typename T, int NV, int U, typename OutT>
 __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __restrict__ A, int64_t d,
                                                                      int64_t ld, HashParams hp,
-                                                                     double* __restrict__ SA, GaussDraw g) {
+                                                                     OutT* __restrict__ SA, GaussDraw g) {
   constexpr int E = Vec16<T>::E;
   constexpr int kCols = 64 * NV * E;
   __shared__ uint32_t entries[kChunk];
@@ -293,28 +293,28 @@ __global__ __launch_bounds__(kThreads) void countsketch_dense_kernel(const T* __
       double s = red[0][cidx];
 #pragma unroll
       for (int w = 1; w < kWaves; ++w) s += red[w][cidx];
-      SA[b * d + col] = s;
+      SA[b * d + col] = (OutT)s;
     }
   }
 }
 
-template <typename T>
+template <typename T, typename OutT>
 hipError_t launch_dense_typed(const void* A, int64_t n, int64_t d, int64_t ld, const HashParams& hp,
-                              double* SA, const GaussDraw& g, hipStream_t s) {
+                              OutT* SA, const GaussDraw& g, hipStream_t s) {
   (void)n;
   constexpr int E = Vec16<T>::E;
   const T* a = static_cast<const T*>(A);
   const int64_t per_vec_row = 64 * E;
   if (d <= per_vec_row) {
     dim3 grid((unsigned)hp.r_cs, 1);
-    countsketch_dense_kernel<T, 1, 4><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
+    countsketch_dense_kernel<T, 1, 4, OutT><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   } else if (d <= 2 * per_vec_row) {
     dim3 grid((unsigned)hp.r_cs, 1);
-    countsketch_dense_kernel<T, 2, 2><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
+    countsketch_dense_kernel<T, 2, 2, OutT><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   } else {
     const int64_t cols = 4 * per_vec_row;
     dim3 grid((unsigned)hp.r_cs, (unsigned)((d + cols - 1) / cols));
-    countsketch_dense_kernel<T, 4, 1><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
+    countsketch_dense_kernel<T, 4, 1, OutT><<<grid, kThreads, 0, s>>>(a, d, ld, hp, SA, g);
   }
   return hipGetLastError();
 }
@@ -479,11 +479,18 @@ hipError_t launch_bucket_lists(const HashParams& hp, int64_t* off, int32_t* rows
 }
 
 hipError_t launch_countsketch_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld,
-                                    const HashParams& hp, double* SA, const GaussDraw& g, hipStream_t s) {
+                                    const HashParams& hp, void* SA, bool sa_f32, const GaussDraw& g,
+                                    hipStream_t s) {
+  // FP32 S A only for BF16 input (the split-form transform's operand)
+  if (sa_f32) {
+    if (dtype != 2) return hipErrorInvalidValue;
+    return launch_dense_typed<__hip_bfloat16>(A, n, d, ld, hp, static_cast<float*>(SA), g, s);
+  }
+  double* sa = static_cast<double*>(SA);
   switch (dtype) {
-    case 0: return launch_dense_typed<double>(A, n, d, ld, hp, SA, g, s);
-    case 1: return launch_dense_typed<float>(A, n, d, ld, hp, SA, g, s);
-    case 2: return launch_dense_typed<__hip_bfloat16>(A, n, d, ld, hp, SA, g, s);
+    case 0: return launch_dense_typed<double>(A, n, d, ld, hp, sa, g, s);
+    case 1: return launch_dense_typed<float>(A, n, d, ld, hp, sa, g, s);
+    case 2: return launch_dense_typed<__hip_bfloat16>(A, n, d, ld, hp, sa, g, s);
     default: return hipErrorInvalidValue;
   }
 }

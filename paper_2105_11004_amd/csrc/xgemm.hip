@@ -71,11 +71,13 @@ __device__ __forceinline__ void split3_pair(float x0, float x1, uint32_t& h, uin
 }
 
 // out part p (N x K, BF16, row-major: contiguous in k) = split(SA^T), SA
-// K x N FP64 row-major.  A 64 x 64 tile goes through LDS (as FP32: the
-// split starts from the FP32 value) so that both the reads (along j) and
-// the writes (pairs of k along k) are coalesced.
+// K x N row-major (FP64, or FP32 as pass 1 stores it for this transform).
+// A 64 x 64 tile goes through LDS (as FP32: the split starts from the FP32
+// value) so that both the reads (along j) and the writes (pairs of k along
+// k) are coalesced.
 constexpr int kT = 64;
-__global__ __launch_bounds__(256) void split_t3_kernel(int64_t K, int64_t N, const double* __restrict__ SA,
+template <typename TS>
+__global__ __launch_bounds__(256) void split_t3_kernel(int64_t K, int64_t N, const TS* __restrict__ SA,
                                                        uint32_t* __restrict__ out) {
   __shared__ float tile[kT][kT + 1];
   const int64_t Kp = (K + 1) / 2;
@@ -300,10 +302,13 @@ size_t xgemm_partial_elems(int64_t M, int64_t N, int splits) {
 
 size_t split3_elems(int64_t rows, int64_t K) { return (size_t)rows * (size_t)((K + 1) / 2) * 2; }
 
-hipError_t launch_split_t3(int64_t K, int64_t N, const double* SA, void* out, hipStream_t s) {
+hipError_t launch_split_t3(int64_t K, int64_t N, const void* SA, bool sa_f32, void* out, hipStream_t s) {
   if (K <= 0 || N <= 0) return hipSuccess;
   const dim3 grid((unsigned)((K + kT - 1) / kT), (unsigned)((N + kT - 1) / kT));
-  split_t3_kernel<<<grid, 256, 0, s>>>(K, N, SA, static_cast<uint32_t*>(out));
+  if (sa_f32)
+    split_t3_kernel<float><<<grid, 256, 0, s>>>(K, N, static_cast<const float*>(SA), static_cast<uint32_t*>(out));
+  else
+    split_t3_kernel<double><<<grid, 256, 0, s>>>(K, N, static_cast<const double*>(SA), static_cast<uint32_t*>(out));
   return hipGetLastError();
 }
 
