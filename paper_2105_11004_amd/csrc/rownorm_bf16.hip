@@ -218,9 +218,15 @@ __global__ __launch_bounds__(kThreads, 1) void rownorm_bf16s_kernel(
       // the step's operands (ring slot u); the slot is refilled with step pre
       // (g + P, clamped to the last step) once the MFMAs have read it, so no
       // copy of a value still in flight is needed
+      // (one uniform branch around all the masking, so that its arithmetic
+      // is not hoisted into the steps of whole chunks)
       uint4 a[kTiles];
 #pragma unroll
-      for (int h = 0; h < kTiles; ++h) a[h] = whole_d ? aring[slot][h] : mask_a(aring[slot][h], t);
+      for (int h = 0; h < kTiles; ++h) a[h] = aring[slot][h];
+      if (!whole_d) {
+#pragma unroll
+        for (int h = 0; h < kTiles; ++h) a[h] = mask_a(a[h], t);
+      }
       // chunk t: lo parts first (smallest terms first)
       const uint4* zb = zs[grp] + (u % kW) * ZC::Q;
 #pragma unroll

@@ -147,6 +147,30 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
   // address and are zeroed when stored to LDS, so no branch or select
   // touches a loaded value before it is needed (either would make the
   // compiler wait for the load there).
+  // Per staged piece q (operand q / 3 by construction: tid < kThreads and
+  // kPieces / 2 = 3 kThreads): its operand row pointer at its k piece (the
+  // row clamped to a valid one) and its place in an LDS buffer.  Whole
+  // tiles and whole K steps (uniform tests) load and store with no
+  // predicate; the masked forms below take the rest.
+  const bool rows_full = m0 + TM <= M && n0 + TN <= N;
+  const __hip_bfloat16* qptr[kPer];
+  int qlds[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int e = tid + kThreads * q;
+    const int op = e / (kPieces / 2), ee = e % (kPieces / 2);
+    const int part = ee / (TM * 4), row = (ee % (TM * 4)) / 4, pc = ee % 4;
+    const __hip_bfloat16* base = op == 0 ? Ap + part * apstride : Bp + part * bpstride;
+    const int64_t gr = (op == 0 ? m0 : n0) + row;
+    qptr[q] = base + (gr < (op == 0 ? M : N) ? gr : 0) * ldk + 8 * pc;
+    qlds[q] = (part * TM + row) * kRowHalfs + xg_piece(row, pc);
+  }
+#define LEV_XG_FAST(K0) (rows_full && (K0) + TK <= ke)
+#define LEV_XG_LOAD_FAST(STG, K0)                                                                     \
+  _Pragma("unroll") for (int q = 0; q < kPer; ++q) STG[q] = *reinterpret_cast<const uint4*>(qptr[q] + (K0));
+#define LEV_XG_STORE_FAST(STG, BUF)                                                                   \
+  _Pragma("unroll") for (int q = 0; q < kPer; ++q)                                                    \
+    *reinterpret_cast<uint4*>((q < kPer / 2 ? As[BUF] : Bs[BUF]) + qlds[q]) = STG[q];
 #define LEV_XG_LOAD(STG, K0)                                                                          \
   _Pragma("unroll") for (int q = 0; q < kPer; ++q) {                                                  \
     const int e = tid + kThreads * q;                                                                 \
@@ -236,23 +260,40 @@ __global__ __launch_bounds__(kThreads, 1) void xgemm_kernel(int64_t M, int64_t N
   // (the products are l h, m m, h l, m h, h m, h h: smallest first)
   const int64_t nsteps = ke > kb ? (ke - kb + TK - 1) / TK : 0;
   uint4 stgA[kPer], stgB[kPer];
-  LEV_XG_LOAD(stgA, kb)
-  LEV_XG_STORE(stgA, 0, kb)
-  LEV_XG_LOAD(stgB, kb + TK)
+#define LEV_XG_LOAD_ANY(STG, K0)                                                                      \
+  if (LEV_XG_FAST(K0)) {                                                                              \
+    LEV_XG_LOAD_FAST(STG, K0)                                                                         \
+  } else {                                                                                            \
+    LEV_XG_LOAD(STG, K0)                                                                              \
+  }
+#define LEV_XG_STORE_ANY(STG, BUF, K0)                                                                \
+  if (LEV_XG_FAST(K0)) {                                                                              \
+    LEV_XG_STORE_FAST(STG, BUF)                                                                       \
+  } else {                                                                                            \
+    LEV_XG_STORE(STG, BUF, K0)                                                                        \
+  }
+  LEV_XG_LOAD_ANY(stgA, kb)
+  LEV_XG_STORE_ANY(stgA, 0, kb)
+  LEV_XG_LOAD_ANY(stgB, kb + TK)
   __syncthreads();
   for (int64_t s = 0; s < nsteps; s += 2) {
     // step s from buffer 0; step s + 1 is in stgB; step s + 2 into stgA
-    LEV_XG_LOAD(stgA, kb + (s + 2) * TK)
+    LEV_XG_LOAD_ANY(stgA, kb + (s + 2) * TK)
     LEV_XG_COMPUTE(0)
-    LEV_XG_STORE(stgB, 1, kb + (s + 1) * TK)  // buffer 1 was last read before the previous barrier
+    LEV_XG_STORE_ANY(stgB, 1, kb + (s + 1) * TK)  // buffer 1 was last read before the previous barrier
     lds_barrier();
     if (s + 1 >= nsteps) break;  // uniform
     // step s + 1 from buffer 1; step s + 2 is in stgA; step s + 3 into stgB
-    LEV_XG_LOAD(stgB, kb + (s + 3) * TK)
+    LEV_XG_LOAD_ANY(stgB, kb + (s + 3) * TK)
     LEV_XG_COMPUTE(1)
-    LEV_XG_STORE(stgA, 0, kb + (s + 2) * TK)  // buffer 0 was last read before the barrier above
+    LEV_XG_STORE_ANY(stgA, 0, kb + (s + 2) * TK)  // buffer 0 was last read before the barrier above
     lds_barrier();
   }
+#undef LEV_XG_LOAD_ANY
+#undef LEV_XG_STORE_ANY
+#undef LEV_XG_LOAD_FAST
+#undef LEV_XG_STORE_FAST
+#undef LEV_XG_FAST
 #undef LEV_XG_LOAD
 #undef LEV_XG_STORE
 #undef LEV_XG_COMPUTE
