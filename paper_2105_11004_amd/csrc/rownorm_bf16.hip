@@ -172,15 +172,28 @@ __global__ __launch_bounds__(kThreads, 1) void rownorm_bf16s_kernel(
   Cursor cur{(int64_t)blockIdx.x, 0};
   Cursor pre = cur;
   int64_t pre_g = 0;
+  // the refill cursor's row pointers, recomputed only when it moves to the
+  // next row block (every nt steps), not at every step
+  const __hip_bfloat16* prp[kTiles];
+#pragma unroll
+  for (int h = 0; h < kTiles; ++h) prp[h] = row_ptr(pre.blk, h);
+  auto advance_pre = [&]() {
+    if (pre_g + 1 < total) {
+      ++pre_g;
+      if (++pre.t == nt) {
+        pre.t = 0;
+        pre.blk += gridDim.x;
+#pragma unroll
+        for (int h = 0; h < kTiles; ++h) prp[h] = row_ptr(pre.blk, h);
+      }
+    }
+  };
   LEV_LOAD_ZWIN(0)
 #pragma unroll
   for (int u = 0; u < kP; ++u) {
 #pragma unroll
-    for (int h = 0; h < kTiles; ++h) aring[u][h] = load_a(row_ptr(pre.blk, h), pre.t);
-    if (pre_g + 1 < total) {
-      advance(pre);
-      ++pre_g;
-    }
+    for (int h = 0; h < kTiles; ++h) aring[u][h] = load_a(prp[h], pre.t);
+    advance_pre();
   }
   LEV_STORE_ZWIN(0)
   int zt = next_t(0);  // first chunk of window 1
@@ -241,11 +254,8 @@ __global__ __launch_bounds__(kThreads, 1) void rownorm_bf16s_kernel(
             acc[h][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(a[h]), as_bf(z[p]), acc[h][cb], 0, 0, 0);
       }
 #pragma unroll
-      for (int h = 0; h < kTiles; ++h) aring[slot][h] = load_a(row_ptr(pre.blk, h), pre.t);
-      if (pre_g + 1 < total) {
-        advance(pre);
-        ++pre_g;
-      }
+      for (int h = 0; h < kTiles; ++h) aring[slot][h] = load_a(prp[h], pre.t);
+      advance_pre();
       if (t == nt - 1) {
         // theta of the wave's rows: accumulator element v of lane l is row
         // 4 (l / 16) + v of its tile, column 16 cb + l % 16
