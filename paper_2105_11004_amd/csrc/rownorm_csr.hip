@@ -253,7 +253,9 @@ constexpr int kHeavy = 64;
 
 template <int U>
 __device__ __forceinline__ int row_bcast_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, 0x150 + U, 0xF, 0xF, false);  // row_newbcast:U
+  // every lane reads a valid lane of its row and all rows and banks are on, so
+  // the old value is never used (bound_ctrl set: no copy of it is made)
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + U, 0xF, 0xF, true);  // row_newbcast:U
 }
 
 __device__ __forceinline__ float group_sum16(float v) {
