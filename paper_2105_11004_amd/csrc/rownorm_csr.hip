@@ -44,9 +44,11 @@ __device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 x) {
 
 // Sum over the 64 lanes (row shifts within 16-lane rows, then row
 // broadcasts; lane 63 ends with the total), returned to every lane.
+// (with every row on, a lane whose source is outside its row reads 0 either
+// way; bound_ctrl says so, so no zeroed copy of the old value is made)
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ float dpp_sum_step(float v) {
-  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, ROWMASK == 0xF));
 }
 __device__ __forceinline__ float wave_sum(float v) {
   v = dpp_sum_step<0x111, 0xF>(v);
@@ -59,8 +61,8 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp_sum_step(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, ROWMASK == 0xF);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, ROWMASK == 0xF);
   return v + __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double wave_sum(double v) {
