@@ -99,8 +99,14 @@ __device__ __forceinline__ void store_stage(const Stage& st, int tid, double* __
 }
 
 // AK: A is contiguous in k (sak == 1); BJ: B is contiguous in j (sbj == 1).
-// UPPER: C is symmetric (a Gram matrix): the tiles below the diagonal are
-// skipped, and with one split each upper tile is also stored transposed.
+// UPPER: C is symmetric (a Gram matrix): only the tiles on and above the
+// diagonal run, on a one-dimensional grid of (upper tiles) x splits
+// workgroups (workgroup w = split w / T, upper tile w % T in row order, T
+// the number of upper tiles), so that consecutive workgroups, which go to
+// consecutive XCDs, spread the triangle evenly over them (on a square grid
+// the XCD of a tile is its row index mod 8, and the triangle loads the low
+// XCDs up to twice as much as the high ones); with one split each upper tile
+// is also stored transposed.
 template <bool AK, bool BJ, typename TI = double, bool UPPER = false>
 __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                          const TI* __restrict__ A, int64_t sai,
@@ -110,13 +116,25 @@ __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, i
                                                          int64_t kchunk, double* __restrict__ partial,
                                                          const int32_t* __restrict__ skip) {
   if (skip != nullptr && *skip != 0) return;
-  if (UPPER && blockIdx.x > blockIdx.y) return;
   __shared__ double As[2][kLdsOp];
   __shared__ double Bs[2][kLdsOp];
 
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int64_t n0 = (int64_t)blockIdx.y * BN;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  int64_t bi = blockIdx.x, bj = blockIdx.y, bz = blockIdx.z;
+  if constexpr (UPPER) {
+    const int64_t tb = (M + BM - 1) / BM;  // M == N
+    const int64_t T = tb * (tb + 1) / 2;
+    bz = (int64_t)blockIdx.x / T;
+    int64_t t = (int64_t)blockIdx.x % T, I = 0;
+    while (t >= tb - I) {  // row I of the triangle holds tb - I tiles
+      t -= tb - I;
+      ++I;
+    }
+    bi = I;
+    bj = I + t;
+  }
+  const int64_t m0 = bi * BM;
+  const int64_t n0 = bj * BN;
+  const int64_t kb = bz * kchunk;
   const int64_t ke = std::min<int64_t>(K, kb + kchunk);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void dgemm_kernel(int64_t M, int64_t N, i
             C[gi * ldc + gj] = alpha * acc[i][j][v] + prev;
             if (UPPER) C[gj * ldc + gi] = alpha * acc[i][j][v] + prev;
           } else {
-            partial[((int64_t)blockIdx.z * M + gi) * N + gj] = acc[i][j][v];
+            partial[(bz * M + gi) * N + gj] = acc[i][j][v];
           }
         }
       }
@@ -201,19 +219,36 @@ __global__ void splitk_reduce_kernel(int64_t M, int64_t N, int splits, const dou
 
 // Gram form of the split-K sum: C[i][j] from the partial of the upper
 // tile holding (i, j) or (j, i).
-__global__ void gram_reduce_kernel(int64_t N, int splits, const double* __restrict__ partial,
-                                   double* __restrict__ C) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N * N) return;
-  int64_t i = idx / N, j = idx % N;
-  if (i / BM > j / BN) {
-    const int64_t t = i;
-    i = j;
-    j = t;
+// C = the sum of the split partials of the upper tiles, mirrored below the
+// diagonal: workgroup t takes upper tile (I, J) (row order over the
+// triangle), sums its partials in split order with reads along j, writes
+// the tile and, through LDS, its transpose with writes along j as well.
+// Diagonal tiles keep each element as summed.
+__global__ __launch_bounds__(1024) void gram_reduce_kernel(int64_t N, int splits, const double* __restrict__ partial,
+                                                           double* __restrict__ C) {
+  __shared__ double tile[BM][BM + 1];
+  const int64_t tb = (N + BM - 1) / BM;
+  int64_t t = blockIdx.x, I = 0;
+  while (t >= tb - I) {
+    t -= tb - I;
+    ++I;
   }
-  double s = 0.0;
-  for (int z = 0; z < splits; ++z) s += partial[((int64_t)z * N + i) * N + j];
-  C[idx] = s;
+  const int64_t J = I + t, i0 = I * BM, j0 = J * BM;
+  const int jj = threadIdx.x % BM, r0 = threadIdx.x / BM;  // 16 rows per pass
+  for (int ii = r0; ii < BM; ii += 1024 / BM) {
+    const int64_t gi = i0 + ii, gj = j0 + jj;
+    double acc = 0.0;
+    if (gi < N && gj < N)
+      for (int z = 0; z < splits; ++z) acc += partial[((int64_t)z * N + gi) * N + gj];
+    tile[ii][jj] = acc;
+  }
+  __syncthreads();
+  for (int ii = r0; ii < BM; ii += 1024 / BM) {
+    const int64_t gi = i0 + ii, gj = j0 + jj;
+    if (gi < N && gj < N) C[gi * N + gj] = tile[ii][jj];
+    const int64_t ti = j0 + ii, tj = i0 + jj;  // row j0 + ii of the tile below the diagonal
+    if (I < J && ti < N && tj < N) C[ti * N + tj] = tile[jj][ii];
+  }
 }
 
 }  // namespace
@@ -279,7 +314,8 @@ hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int
   if (splits < 1) splits = 1;
   int64_t kchunk = (n + splits - 1) / splits;
   kchunk = std::max<int64_t>(BK, ((kchunk + BK - 1) / BK) * BK);
-  dim3 grid((unsigned)((d + BM - 1) / BM), (unsigned)((d + BN - 1) / BN), (unsigned)splits);
+  const int64_t tb = (d + BM - 1) / BM;
+  const dim3 grid((unsigned)(tb * (tb + 1) / 2 * splits));  // upper tiles x splits (see dgemm_kernel)
   switch (dtype) {
     case 0:
       dgemm_kernel<false, true, double, true><<<grid, kThreads, 0, s>>>(d, d, n, 1.0, static_cast<const double*>(A),
@@ -301,11 +337,20 @@ hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int
     default:
       return hipErrorInvalidValue;
   }
-  if (splits > 1) {
-    const int64_t total = d * d;
-    gram_reduce_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(d, splits, partial, B);
-  }
+  if (splits > 1) gram_reduce_kernel<<<(unsigned)(tb * (tb + 1) / 2), 1024, 0, s>>>(d, splits, partial, B);
   return hipGetLastError();
+}
+
+// Splits of the sketch's Gram A~^T A~ (m rows) on the upper tiles: as many
+// as keep every workgroup in one round at two per CU with at least 64 of the
+// rows each, and at least two, so that the sums always go through the
+// partials and the lower half is the mirror of the upper one.
+int gram_sketch_splits(int64_t m, int64_t d) {
+  const int64_t tb = (d + BM - 1) / BM;
+  const int64_t upper = tb * (tb + 1) / 2;
+  int splits = 2;
+  while (upper * (splits + 1) <= 512 && m / (splits + 1) >= 64 && splits < 64) ++splits;
+  return splits;
 }
 
 }  // namespace lev

@@ -334,7 +334,7 @@ struct RankBufs {
 RankBufs carve_rank(Carver& c, int64_t m, int64_t d) {
   RankBufs b;
   b.B = c.take<double>((size_t)(d * d));
-  b.partial = c.take<double>(lev::dgemm_partial_elems(d, d, lev::dgemm_choose_splits(d, d, m)));
+  b.partial = c.take<double>(lev::dgemm_partial_elems(d, d, lev::gram_sketch_splits(m, d)));
   b.pc.diag = c.take<double>((size_t)d);
   b.pc.Rrows = c.take<double>((size_t)(d * d));
   b.pc.piv = c.take<int32_t>((size_t)d);
@@ -482,9 +482,8 @@ lev_status cholqr2(int64_t m, int64_t d, const double* X, const double* Rc, cons
 // columns, R's rows as Q^T X.
 lev_status enqueue_rank(const double* At, int64_t m, int64_t d, double zeta, const RankBufs& b,
                         int32_t* perm, double* R, int64_t* rank, hipStream_t s, RefineBufs* rf = nullptr) {
-  // Gram B = A~^T A~ (d x d)
-  const int splits = lev::dgemm_choose_splits(d, d, m);
-  LEV_HIP(lev::launch_dgemm(d, d, m, 1.0, At, 1, d, At, d, 1, 0.0, b.B, d, splits, b.partial, nullptr, s));
+  // Gram B = A~^T A~ (d x d): the tiles on and above the diagonal, mirrored
+  LEV_HIP(lev::launch_gram_dense(LEV_F64, At, m, d, d, lev::gram_sketch_splits(m, d), b.partial, b.B, s));
   if (zeta >= kZetaGram || rf == nullptr) return pivchol_into(b.B, d, zeta, b.pc, rank, perm, R, b.partial, s);
 
   RefineBufs& f = *rf;

@@ -229,6 +229,8 @@ hipError_t launch_stream_read(const void* buf, int64_t bytes, uint32_t* sink, hi
 hipError_t launch_gram_dense(int dtype, const void* A, int64_t n, int64_t d, int64_t ld, int splits,
                              double* partial, double* B, hipStream_t s);
 int gram_dense_splits(int64_t n, int64_t d);
+// Splits (>= 2) for the sketch's Gram through launch_gram_dense (FP64 A~, m rows).
+int gram_sketch_splits(int64_t m, int64_t d);
 // B (d x d, FP64) = A^T A for CSR A in sum_i nnz_i^2 work (gram_csr.hip).
 size_t gram_csr_partial_elems(int64_t n, int64_t d);
 hipError_t launch_gram_csr(int dtype, const void* vals, const int64_t* row_ptr, const int32_t* col_idx,
