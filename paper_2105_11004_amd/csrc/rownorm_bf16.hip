@@ -142,17 +142,25 @@ __global__ __launch_bounds__(kThreads, 1) void rownorm_bf16s_kernel(
   // window's chunk c = q / Q, i.e. chunk (t0 + c) mod nt of the sequence
   // (vector j of this thread, one value per call: passing the staging array
   // by reference lets the compiler move it to LDS)
-  auto load_zvec = [&](int t0, int j) -> uint4 {
+  // (the part of the index that depends on the thread and j only is
+  // computed once: zk[j] = (p * part_vecs + rem) * 4 + c, c < kW = 4)
+  static_assert(kW <= 4, "the chunk of a window is kept in two bits of zk");
+  int zk[ZC::kPer];
+#pragma unroll
+  for (int j = 0; j < ZC::kPer; ++j) {
     int q = tid + j * kThreads;
     if (q >= ZC::kWin) q = ZC::kWin - 1;  // (duplicate of a valid vector, not stored)
     const int c = q / ZC::Q, qq = q % ZC::Q;
     const int p = qq / (CB * 64), rem = qq % (CB * 64);
-    // chunk c of the window, wrapped at nt (c < kW = 4)
-    int t = t0 + c;
+    zk[j] = (int)(p * part_vecs + rem) * 4 + c;
+  }
+  auto load_zvec = [&](int t0, int j) -> uint4 {
+    // chunk c of the window, wrapped at nt
+    int t = t0 + (zk[j] & 3);
     t = t >= nt ? t - nt : t;
     t = t >= nt ? t - nt : t;
     t = t >= nt ? t - nt : t;
-    return Zg[p * part_vecs + (int64_t)t * CB * 64 + rem];
+    return Zg[(zk[j] >> 2) + t * (CB * 64)];
   };
 #define LEV_LOAD_ZWIN(T0)                                                  \
   _Pragma("unroll") for (int j = 0; j < ZC::kPer; ++j) zstage[j] = load_zvec((T0), j);
